@@ -1,0 +1,403 @@
+"""Seeded synthetic inputs for the LOCC crop-collision path.
+
+This module only draws inputs: procedural non-convex shapes sampled on their
+surfaces, sphere shapes, rigid poses, object pairs, environments, request
+streams and network weights.  It holds none of the method's arithmetic (no
+crop box, no membership test, no network); both the HIP library and the CPU
+oracle consume what it returns.
+
+The paper trains and tests on household-object meshes (Google Scanned Objects,
+YCB, EGAD; Sec. IV) with K=1500 surface points per object (Sec. III).  None of
+those datasets or trained weights is available here, so procedural shapes of
+the same physical scale (components of 0.02-0.08 m semi-axes) stand in for
+them, with 1024/2048/4096 stored points and Gaussian-initialised weights.
+
+Every generator is deterministic in its seed.  A workload's master seed is
+split with ``numpy.random.SeedSequence(master).spawn(5)`` into the streams
+[shapes, poses, spheres/environments, calibration, requests]; weights always
+come from ``numpy.random.default_rng(seed)`` on their own.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+STREAM_SHAPES, STREAM_POSES, STREAM_ENVS, STREAM_CALIB, STREAM_REQUESTS = range(5)
+
+
+def streams(master: int):
+    """Five independent generators split from one master seed."""
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(master).spawn(5)]
+
+
+# ----------------------------------------------------------------------------
+# shapes
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ShapeLibrary:
+    """Surface point clouds of S shapes, concatenated.
+
+    pts     float32 [sum N_s, 6]: x, y, z, nx, ny, nz in the shape's own frame
+    offsets int64   [S + 1]: shape s owns rows offsets[s]:offsets[s+1]
+    radius  float32 [S]: sphere radius for sphere shapes, NaN otherwise
+    """
+    pts: np.ndarray
+    offsets: np.ndarray
+    radius: np.ndarray
+
+    @property
+    def n_shapes(self) -> int:
+        return len(self.offsets) - 1
+
+    def shape_points(self, s: int) -> np.ndarray:
+        return self.pts[self.offsets[s]:self.offsets[s + 1]]
+
+    @staticmethod
+    def concat(libs) -> "ShapeLibrary":
+        pts = np.concatenate([lb.pts for lb in libs])
+        counts = np.concatenate([np.diff(lb.offsets) for lb in libs])
+        offsets = np.zeros(len(counts) + 1, np.int64)
+        np.cumsum(counts, out=offsets[1:])
+        return ShapeLibrary(pts, offsets, np.concatenate([lb.radius for lb in libs]))
+
+
+def uniform_quaternions(rng, n: int) -> np.ndarray:
+    """Uniform random rotations (Shoemake's subgroup algorithm), (w, x, y, z), float64."""
+    u1, u2, u3 = rng.random((3, n))
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    t2, t3 = 2.0 * np.pi * u2, 2.0 * np.pi * u3
+    return np.stack([b * np.cos(t3), a * np.sin(t2), a * np.cos(t2), b * np.sin(t3)], axis=1)
+
+
+def _scipy_rot(q_wxyz: np.ndarray) -> Rotation:
+    q = np.asarray(q_wxyz, np.float64)
+    return Rotation.from_quat(np.concatenate([q[..., 1:], q[..., :1]], axis=-1))
+
+
+def _unit_sphere(rng, n):
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+class _Ellipsoid:
+    def __init__(self, rng, centre_half_width):
+        self.ax = rng.uniform(0.02, 0.08, 3)
+        self.c = rng.uniform(-centre_half_width, centre_half_width, 3)
+        self.rot = _scipy_rot(uniform_quaternions(rng, 1)[0])
+        a, b, c = self.ax
+        p = 1.6075  # Knud Thomsen's surface-area approximation
+        self.area = 4 * np.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3) ** (1 / p)
+
+    def sample(self, rng, n):
+        a, b, c = self.ax
+        out_p, out_n, have = [], [], 0
+        gmax = max(b * c, a * c, a * b)
+        while have < n:
+            u = _unit_sphere(rng, 2 * n + 16)
+            g = np.sqrt((b * c * u[:, 0]) ** 2 + (a * c * u[:, 1]) ** 2 + (a * b * u[:, 2]) ** 2)
+            keep = rng.random(len(u)) * gmax <= g  # area-element rejection
+            u = u[keep]
+            x = u * self.ax
+            nrm = x / self.ax ** 2
+            nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+            out_p.append(x)
+            out_n.append(nrm)
+            have += len(x)
+        x = np.concatenate(out_p)[:n]
+        nrm = np.concatenate(out_n)[:n]
+        return self.rot.apply(x) + self.c, self.rot.apply(nrm)
+
+    def strictly_inside(self, p):
+        loc = self.rot.inv().apply(p - self.c)
+        return np.sum((loc / self.ax) ** 2, axis=1) < 1.0
+
+
+class _Box:
+    def __init__(self, rng, centre_half_width):
+        self.h = rng.uniform(0.02, 0.08, 3)
+        self.c = rng.uniform(-centre_half_width, centre_half_width, 3)
+        self.rot = _scipy_rot(uniform_quaternions(rng, 1)[0])
+        hx, hy, hz = self.h
+        self.area = 8 * (hx * hy + hy * hz + hx * hz)
+
+    def sample(self, rng, n):
+        h = self.h
+        face_area = np.array([h[1] * h[2], h[1] * h[2], h[0] * h[2], h[0] * h[2], h[0] * h[1], h[0] * h[1]])
+        face = rng.choice(6, size=n, p=face_area / face_area.sum())
+        axis, sign = face // 2, np.where(face % 2 == 0, 1.0, -1.0)
+        x = rng.uniform(-1.0, 1.0, (n, 3)) * h
+        x[np.arange(n), axis] = sign * h[axis]
+        nrm = np.zeros((n, 3))
+        nrm[np.arange(n), axis] = sign
+        return self.rot.apply(x) + self.c, self.rot.apply(nrm)
+
+    def strictly_inside(self, p):
+        loc = self.rot.inv().apply(p - self.c)
+        return np.all(np.abs(loc) < self.h, axis=1)
+
+
+def union_shape(rng, n_points: int, n_comp: int, box_fraction: float) -> np.ndarray:
+    """Surface samples of a union of ellipsoids and boxes, float32 [n_points, 6].
+
+    A component is picked in proportion to its (approximate) area, a point is
+    drawn uniformly on its surface, and the point is dropped if it lies
+    strictly inside another component, so only the union's outer surface is
+    kept.  Points come out in i.i.d. order.  The cloud is re-centred on its
+    axis-aligned bounding-box centre (in float64) before rounding to float32.
+    """
+    comps = [(_Box if rng.random() < box_fraction else _Ellipsoid)(rng, 0.02) for _ in range(n_comp)]
+    areas = np.array([c.area for c in comps])
+    pts, nrms, have = [], [], 0
+    while have < n_points:
+        m = 2 * (n_points - have) + 64
+        which = rng.choice(n_comp, size=m, p=areas / areas.sum())
+        p = np.empty((m, 3))
+        nr = np.empty((m, 3))
+        for ci, comp in enumerate(comps):
+            sel = which == ci
+            if sel.any():
+                p[sel], nr[sel] = comp.sample(rng, int(sel.sum()))
+        keep = np.ones(m, bool)
+        for ci, comp in enumerate(comps):
+            others = which != ci
+            keep[others] &= ~comp.strictly_inside(p[others])
+        pts.append(p[keep])
+        nrms.append(nr[keep])
+        have += int(keep.sum())
+    p = np.concatenate(pts)[:n_points]
+    nr = np.concatenate(nrms)[:n_points]
+    p -= 0.5 * (p.min(axis=0) + p.max(axis=0))
+    nr /= np.linalg.norm(nr, axis=1, keepdims=True)
+    return np.concatenate([p, nr], axis=1).astype(np.float32)
+
+
+def sphere_shape(rng, radius: float, n_points: int) -> np.ndarray:
+    """Sphere of the given (float32) radius: the 6 axis poles first, then uniform points."""
+    r = float(np.float32(radius))
+    poles = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float64)
+    u = np.concatenate([poles, _unit_sphere(rng, n_points - 6)])
+    p = np.clip(u * r, -r, r)
+    return np.concatenate([p, u], axis=1).astype(np.float32)
+
+
+def shape_library(rng, n_shapes: int, n_points: int, comp_range=(3, 3), box_fraction=0.0) -> ShapeLibrary:
+    clouds = [union_shape(rng, n_points, int(rng.integers(comp_range[0], comp_range[1] + 1)), box_fraction)
+              for _ in range(n_shapes)]
+    offsets = np.arange(n_shapes + 1, dtype=np.int64) * n_points
+    return ShapeLibrary(np.concatenate(clouds), offsets, np.full(n_shapes, np.nan, np.float32))
+
+
+def sphere_library(rng, n_shapes: int, n_points: int, radii=None) -> ShapeLibrary:
+    if radii is None:
+        radii = rng.uniform(0.02, 0.08, n_shapes)
+    radii = np.asarray(radii, np.float32)
+    clouds = [sphere_shape(rng, r, n_points) for r in radii]
+    offsets = np.arange(n_shapes + 1, dtype=np.int64) * n_points
+    return ShapeLibrary(np.concatenate(clouds), offsets, radii)
+
+
+# ----------------------------------------------------------------------------
+# poses and pairs
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Scene:
+    """Objects placed in the world plus the pairs to test.
+
+    pos   float32 [n, 3]   position of the object frame origin
+    quat  float32 [n, 4]   orientation, Hamilton quaternion (w, x, y, z)
+    shape int32   [n]      index into the shape library
+    pairs int32   [P, 2]   (i, j) object indices; order is the caller's
+    """
+    lib: ShapeLibrary
+    pos: np.ndarray
+    quat: np.ndarray
+    shape: np.ndarray
+    pairs: np.ndarray
+
+    @property
+    def n_objects(self) -> int:
+        return len(self.pos)
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.pairs)
+
+    def subset(self, pair_rows) -> "Scene":
+        return Scene(self.lib, self.pos, self.quat, self.shape, np.ascontiguousarray(self.pairs[pair_rows]))
+
+
+def _world_extent(lib: ShapeLibrary, shape: int, q_wxyz) -> tuple[np.ndarray, np.ndarray]:
+    """Min / max of the rotated point cloud relative to the object origin."""
+    p = _scipy_rot(np.asarray(q_wxyz, np.float64)).apply(lib.shape_points(shape)[:, :3].astype(np.float64))
+    return p.min(axis=0), p.max(axis=0)
+
+
+def overlapping_pair_poses(rng, lib: ShapeLibrary, shape_a, shape_b, spread: float = 1.0):
+    """Poses for object pairs whose world-frame bounding boxes overlap.
+
+    Position a is uniform in [-spread, spread]^3, both orientations are
+    uniform, and position b is uniform in the box of offsets for which the
+    two world-frame bounding boxes of the rotated clouds intersect.
+    """
+    n = len(shape_a)
+    qa = uniform_quaternions(rng, n).astype(np.float32)
+    qb = uniform_quaternions(rng, n).astype(np.float32)
+    ta = rng.uniform(-spread, spread, (n, 3)).astype(np.float32)
+    tb = np.empty_like(ta)
+    for k in range(n):
+        lo_a, hi_a = _world_extent(lib, int(shape_a[k]), qa[k])
+        lo_b, hi_b = _world_extent(lib, int(shape_b[k]), qb[k])
+        tb[k] = ta[k] + rng.uniform(lo_a - hi_b, hi_a - lo_b)
+    return ta, qa, tb, qb
+
+
+def _interleave_pairs(rng, n_pairs: int, swap_fraction: float = 0.5) -> np.ndarray:
+    """Pairs (2k, 2k+1), each reversed to (2k+1, 2k) with the given probability."""
+    pairs = np.stack([2 * np.arange(n_pairs), 2 * np.arange(n_pairs) + 1], axis=1).astype(np.int32)
+    swap = rng.random(n_pairs) < swap_fraction
+    pairs[swap] = pairs[swap][:, ::-1]
+    return pairs
+
+
+def _pack_pair_scene(lib, ta, qa, tb, qb, sa, sb, pairs):
+    n = len(ta)
+    pos = np.empty((2 * n, 3), np.float32)
+    quat = np.empty((2 * n, 4), np.float32)
+    shape = np.empty(2 * n, np.int32)
+    pos[0::2], pos[1::2] = ta, tb
+    quat[0::2], quat[1::2] = qa, qb
+    shape[0::2], shape[1::2] = sa, sb
+    return Scene(lib, pos, quat, shape, pairs)
+
+
+def sphere_pair_poses(rng, radii_a, radii_b, gap_std: float = 0.020):
+    """Sphere pairs at centre distance r_a + r_b + g, g ~ N(0, gap_std).
+
+    The gap spread follows the paper's distance manipulation, which draws the
+    target separation from a zero-mean normal with 0.020 m deviation
+    (Sec. III-A).  Gaps are clipped so the centres stay apart.
+    """
+    n = len(radii_a)
+    ra = np.asarray(radii_a, np.float64)
+    rb = np.asarray(radii_b, np.float64)
+    gap = np.maximum(rng.normal(0.0, gap_std, n), -0.5 * (ra + rb))
+    d = ra + rb + gap
+    ta = rng.uniform(-1.0, 1.0, (n, 3))
+    tb = ta + _unit_sphere(rng, n) * d[:, None]
+    qa = uniform_quaternions(rng, n).astype(np.float32)
+    qb = uniform_quaternions(rng, n).astype(np.float32)
+    return ta.astype(np.float32), qa, tb.astype(np.float32), qb
+
+
+def sphere_labels(scene: Scene, rows=None) -> dict:
+    """Closed-form sphere-sphere contact for sphere pairs (float64).
+
+    For centres c_i, c_j and radii r_i, r_j at distance d: flag = d < r_i + r_j,
+    depth = r_i + r_j - d, normal = (c_j - c_i) / d and contact point
+    c_i + normal (r_i + d - r_j) / 2 (midpoint of the two deepest points).
+    """
+    pairs = scene.pairs if rows is None else scene.pairs[rows]
+    i, j = pairs[:, 0], pairs[:, 1]
+    ci = scene.pos[i].astype(np.float64)
+    cj = scene.pos[j].astype(np.float64)
+    ri = scene.lib.radius[scene.shape[i]].astype(np.float64)
+    rj = scene.lib.radius[scene.shape[j]].astype(np.float64)
+    d = np.linalg.norm(cj - ci, axis=1)
+    n = (cj - ci) / d[:, None]
+    return dict(flag=d < ri + rj, depth=ri + rj - d, normal=n, point=ci + n * ((ri + d - rj) / 2)[:, None])
+
+
+# ----------------------------------------------------------------------------
+# workloads
+# ----------------------------------------------------------------------------
+
+def small_workload(master: int = 0, n_points: int = 1024, n_nonconvex_pairs: int = 64, n_sphere_pairs: int = 16):
+    """Plain, CPU-checkable case: 64 pairs of 3-ellipsoid unions + 16 sphere pairs.
+
+    Object k uses shape k; non-convex pairs join shapes (2k, 2k+1); sphere
+    pairs follow them.  Pair order is reversed for about half the pairs.
+    """
+    g = streams(master)
+    ns = 2 * n_nonconvex_pairs
+    lib_nc = shape_library(g[STREAM_SHAPES], ns, n_points, (3, 3), 0.0)
+    lib_sp = sphere_library(g[STREAM_ENVS], 2 * n_sphere_pairs, n_points)
+    lib = ShapeLibrary.concat([lib_nc, lib_sp])
+    sa = np.arange(0, ns, 2)
+    sb = sa + 1
+    ta, qa, tb, qb = overlapping_pair_poses(g[STREAM_POSES], lib, sa, sb)
+    spa = ns + np.arange(0, 2 * n_sphere_pairs, 2)
+    spb = spa + 1
+    sta, sqa, stb, sqb = sphere_pair_poses(g[STREAM_ENVS], lib.radius[spa], lib.radius[spb])
+    n = n_nonconvex_pairs + n_sphere_pairs
+    pairs = _interleave_pairs(g[STREAM_POSES], n)
+    return _pack_pair_scene(lib, np.concatenate([ta, sta]), np.concatenate([qa, sqa]),
+                            np.concatenate([tb, stb]), np.concatenate([qb, sqb]),
+                            np.concatenate([sa, spa]).astype(np.int32), np.concatenate([sb, spb]).astype(np.int32),
+                            pairs)
+
+
+def scale_library(master: int = 1, n_shapes: int = 32, n_points: int = 2048) -> ShapeLibrary:
+    """32 shapes, each a union of 3-6 ellipsoids and boxes (half each on average)."""
+    return shape_library(streams(master)[STREAM_SHAPES], n_shapes, n_points, (3, 6), 0.5)
+
+
+def scale_workload(master: int = 1, n_pairs: int = 16384, n_shapes: int = 32, n_points: int = 2048):
+    """At-scale case: pairs of shapes drawn with replacement from a 32-shape library.
+
+    2 * n_pairs objects; pair k joins objects (2k, 2k+1), order reversed for
+    about half of the pairs.
+    """
+    g = streams(master)
+    lib = scale_library(master, n_shapes, n_points)
+    sa = g[STREAM_POSES].integers(0, n_shapes, n_pairs).astype(np.int32)
+    sb = g[STREAM_POSES].integers(0, n_shapes, n_pairs).astype(np.int32)
+    ta, qa, tb, qb = overlapping_pair_poses(g[STREAM_POSES], lib, sa, sb)
+    pairs = _interleave_pairs(g[STREAM_POSES], n_pairs)
+    return _pack_pair_scene(lib, ta, qa, tb, qb, sa, sb, pairs)
+
+
+# ----------------------------------------------------------------------------
+# network weights
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Widths:
+    """Encoder 6 -> h1 -> h2 (per point), head 2*h2 -> hh -> hh -> 8 (per pair)."""
+    h1: int
+    h2: int
+    hh: int
+
+    def layer_shapes(self):
+        return [(self.h1, 6), (self.h2, self.h1), (self.hh, 2 * self.h2), (self.hh, self.hh), (8, self.hh)]
+
+    def n_floats(self) -> int:
+        return sum(o * i + o for o, i in self.layer_shapes())
+
+
+SMALL_WIDTHS = Widths(64, 128, 256)
+SCALE_WIDTHS = Widths(128, 256, 512)
+
+
+def gaussian_weights(widths: Widths, seed: int = 0, bias_std: float = 0.0):
+    """He-initialised weights, W ~ N(0, 2 / fan_in), float32.
+
+    Drawn from ``default_rng(seed)`` in the order W1, b1, W2, b2, H1, c1, H2,
+    c2, H3, c3 (W row-major [out][in]).  Biases are zero unless bias_std > 0.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for o, i in widths.layer_shapes():
+        out.append((rng.standard_normal((o, i)) * math.sqrt(2.0 / i)).astype(np.float32))
+        b = rng.standard_normal(o) * bias_std if bias_std > 0 else np.zeros(o)
+        out.append(b.astype(np.float32))
+    return out
+
+
+def flatten_weights(layers) -> np.ndarray:
+    return np.concatenate([np.asarray(a, np.float32).ravel() for a in layers])

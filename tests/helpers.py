@@ -1,0 +1,90 @@
+"""Shared test helpers: constructed-weight networks, sphere scenes and error metrics."""
+
+import json
+import os
+
+import numpy as np
+
+from paper_2304_09439_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+FIELDS = {"logit": slice(0, 1), "point": slice(1, 4), "normal": slice(4, 7), "depth": slice(7, 8)}
+
+
+def sphere_cases():
+    with open(os.path.join(GOLDEN, "sphere_contact_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+def sphere_probe_weights(widths: I.Widths, beta: float = 4.0):
+    """Weights under which the network computes the sphere-sphere contact exactly.
+
+    Encoder: unit 0 = ReLU(x + 1), unit 1 = ReLU(1 - x), passed through layer 2,
+    so the per-object max-pool gives (1 + max x, 1 - min x) over the crop.
+    Head: g0 = f_a[0] = 1 + max_a x, g1 = f_b[1] = 1 - min_b x, and
+      logit = beta (g0 + g1 - 2), point_x = (g0 - g1) / 2, normal = (1, 0, 0),
+      depth = g0 + g1 - 2 = max_a x - min_b x.
+    For spheres on the x axis with both x-poles in the crop that is
+    ra + rb - d and (ra + d - rb) / 2.
+    """
+    h1, h2, hh = widths.h1, widths.h2, widths.hh
+    W1 = np.zeros((h1, 6), np.float32); b1 = np.zeros(h1, np.float32)
+    W1[0, 0], b1[0] = 1, 1
+    W1[1, 0], b1[1] = -1, 1
+    W2 = np.zeros((h2, h1), np.float32); b2 = np.zeros(h2, np.float32)
+    W2[0, 0] = W2[1, 1] = 1
+    H1 = np.zeros((hh, 2 * h2), np.float32); c1 = np.zeros(hh, np.float32)
+    H1[0, 0] = 1
+    H1[1, h2 + 1] = 1
+    H2 = np.zeros((hh, hh), np.float32); c2 = np.zeros(hh, np.float32)
+    H2[0, 0] = H2[1, 1] = 1
+    H3 = np.zeros((8, hh), np.float32); c3 = np.zeros(8, np.float32)
+    H3[0, :2], c3[0] = beta, -2 * beta
+    H3[1, :2] = 0.5, -0.5
+    c3[4] = 1
+    H3[7, :2], c3[7] = 1, -2
+    return I.flatten_weights([W1, b1, W2, b2, H1, c1, H2, c2, H3, c3])
+
+
+def sphere_case_scene(cases, n_points=1024, seed=5, swap_every_other=True):
+    """One pair per case: sphere a at the origin (identity), sphere b at (d, 0, 0)
+    turned by theta about x (its x-poles stay on the axis exactly)."""
+    rng = np.random.default_rng(seed)
+    radii = []
+    for c in cases:
+        radii += [c["ra"], c["rb"]]
+    lib = I.sphere_library(rng, len(radii), n_points, radii)
+    n = len(cases)
+    pos = np.zeros((2 * n, 3), np.float32)
+    quat = np.zeros((2 * n, 4), np.float32)
+    quat[:, 0] = 1
+    for k, c in enumerate(cases):
+        pos[2 * k + 1, 0] = c["d"]
+        th = c["theta"]
+        quat[2 * k + 1] = [np.cos(th / 2), np.sin(th / 2), 0, 0]
+    pairs = np.stack([2 * np.arange(n), 2 * np.arange(n) + 1], axis=1).astype(np.int32)
+    if swap_every_other:
+        pairs[1::2] = pairs[1::2, ::-1]
+    return I.Scene(lib, pos, quat, np.arange(2 * n, dtype=np.int32), pairs)
+
+
+def field_errors(out: np.ndarray, ref: np.ndarray) -> dict:
+    """Per-field relative error: max over pairs of |y_f - ref_f| / max(|ref_f|, RMS |ref_f|)."""
+    errs = {}
+    for name, sl in FIELDS.items():
+        d = np.linalg.norm(np.asarray(out, np.float64)[:, sl] - ref[:, sl], axis=1)
+        r = np.linalg.norm(ref[:, sl], axis=1)
+        rms = np.sqrt(np.mean(r ** 2)) if len(r) else 1.0
+        errs[name] = float(np.max(d / np.maximum(r, max(rms, 1e-30)))) if len(r) else 0.0
+    return errs
+
+
+def flag_agreement(logit_out, logit_ref, band: float = 0.0):
+    """Fraction of pairs whose (logit > 0) agrees; pairs with |ref| < band * RMS(ref) excluded."""
+    logit_out = np.asarray(logit_out, np.float64).ravel()
+    logit_ref = np.asarray(logit_ref, np.float64).ravel()
+    keep = np.abs(logit_ref) >= band * np.sqrt(np.mean(logit_ref ** 2))
+    if not keep.any():
+        return 1.0
+    return float(np.mean((logit_out[keep] > 0) == (logit_ref[keep] > 0)))
