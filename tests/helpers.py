@@ -27,21 +27,30 @@ def sphere_probe_weights(widths: I.Widths, beta: float = 4.0):
       depth = g0 + g1 - 2 = max_a x - min_b x.
     For spheres on the x axis with both x-poles in the crop that is
     ra + rb - d and (ra + d - rb) / 2.
+    Three more units have negative pre-activations (ReLU(-x - 1),
+    ReLU(-f_a[0]), ReLU(-g1[0])) and feed the outputs, so a missing hidden
+    ReLU changes point_x or point_y.
     """
     h1, h2, hh = widths.h1, widths.h2, widths.hh
     W1 = np.zeros((h1, 6), np.float32); b1 = np.zeros(h1, np.float32)
     W1[0, 0], b1[0] = 1, 1
     W1[1, 0], b1[1] = -1, 1
+    W1[2, 0], b1[2] = -1, -1
     W2 = np.zeros((h2, h1), np.float32); b2 = np.zeros(h2, np.float32)
     W2[0, 0] = W2[1, 1] = 1
+    W2[0, 2] = 1
     H1 = np.zeros((hh, 2 * h2), np.float32); c1 = np.zeros(hh, np.float32)
     H1[0, 0] = 1
     H1[1, h2 + 1] = 1
+    H1[2, 0] = -1
     H2 = np.zeros((hh, hh), np.float32); c2 = np.zeros(hh, np.float32)
     H2[0, 0] = H2[1, 1] = 1
+    H2[0, 2] = 1
+    H2[2, 0] = -1
     H3 = np.zeros((8, hh), np.float32); c3 = np.zeros(8, np.float32)
     H3[0, :2], c3[0] = beta, -2 * beta
     H3[1, :2] = 0.5, -0.5
+    H3[2, 2] = 1
     c3[4] = 1
     H3[7, :2], c3[7] = 1, -2
     return I.flatten_weights([W1, b1, W2, b2, H1, c1, H2, c2, H3, c3])

@@ -287,3 +287,21 @@ def test_sphere_crop_box_closed_form():
             far = np.minimum(np.abs(pts - lo), np.abs(pts - hi)).min(axis=1) > 1e-12
             expect = np.all((pts >= lo) & (pts <= hi), axis=1)
             np.testing.assert_array_equal(mask[far], expect[far])
+
+
+def test_b_side_rows_are_radial_for_spheres(small_scene):
+    """Encoder rows of a sphere b, in a's frame: normal = (point - centre_b) / r_b.
+    The centre of b in a's frame comes from scipy, not from the oracle."""
+    sc = small_scene
+    geoms, _, _ = O.crop(sc.lib.pts, sc.lib.offsets, sc.pos, sc.quat, sc.shape, sc.pairs, K=64)
+    checked = 0
+    for g in geoms:
+        rb = sc.lib.radius[sc.shape[g.b]]
+        if np.isnan(rb) or len(g.rows_b) == 0:
+            continue
+        qa = sc.quat[g.a].astype(np.float64)
+        ra = Rotation.from_quat([qa[1], qa[2], qa[3], qa[0]])
+        cb = ra.inv().apply(sc.pos[g.b].astype(np.float64) - sc.pos[g.a])
+        np.testing.assert_allclose(g.rows_b[:, 3:6], (g.rows_b[:, :3] - cb) / rb, atol=2e-5)
+        checked += 1
+    assert checked >= 8
