@@ -1,0 +1,179 @@
+/*
+ * locc.h - C-ABI of the LOCC crop-collision library for AMD MI355X (gfx950).
+ *
+ * The library evaluates, for many pairs of rigid objects at once, the local
+ * object crop collision network of Son & Kim (arXiv 2304.09439).  The paper
+ * poses the problem as evaluating the collision between two objects directly
+ * from their shapes and poses (Sec. III), with an Object Collision Net that
+ * takes the shapes and poses of the two objects (Sec. II) and a dataset of
+ * tuples (shape 1, shape 2, pose 1, pose 2, label) (Sec. III-A).  Here the
+ * shapes are uploaded once as surface point clouds with normals and each
+ * call passes poses and object pairs.
+ *
+ * Per pair (i, j) the library computes, in the frame of a = min(i, j):
+ *   - the relative pose of b = max(i, j) and a crop box: a's axis-aligned box
+ *     intersected with the axis-aligned hull of b's transformed box, widened
+ *     by a margin on every face (the paper pads the colliding region so that
+ *     nothing in contact is missed; Sec. III, appendix "Architecture
+ *     Details").  Pose composition and the membership test run in float64,
+ *     with no fused multiply-add, so crop sets are reproducible bit for bit;
+ *   - the first K stored points of each object inside the box (count before
+ *     the cap is returned), as (xyz, normal) rows in a's frame;
+ *   - a per-point MLP 6 -> h1 -> h2 (ReLU) max-pooled per object, and a head
+ *     MLP 2*h2 -> hh -> hh -> 8 (ReLU on hidden layers, last layer linear;
+ *     the appendix applies ReLU across all layers and ends in a linear layer);
+ *   - the contact record below, mapped to the world by a's pose.
+ *
+ * Pointers named h_* are host memory, d_* are device memory of the context's
+ * device.  `stream` is a hipStream_t (NULL = the default stream).  Every call
+ * returns a locc_status; on failure locc_last_error() describes it.  Calls on
+ * one context must not overlap in time (one context per host thread).
+ */
+#ifndef LOCC_H
+#define LOCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define LOCC_API __attribute__((visibility("default")))
+#else
+#define LOCC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LOCC_OK = 0,
+  LOCC_ERR_INVALID_ARG = -1, /* null pointer, negative size, bad layout: nothing was touched */
+  LOCC_ERR_OOM = -2,         /* device allocation failed */
+  LOCC_ERR_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
+  LOCC_ERR_NOT_READY = -4,   /* detect before shapes and weights were uploaded */
+  LOCC_ERR_RANGE = -5,       /* a size exceeds a library limit */
+  LOCC_ERR_BUSY = -6,        /* serving: request does not fit the memory budget now; retry */
+  LOCC_ERR_UNSUPPORTED = -7  /* widths / K / precision combination not compiled in */
+} locc_status;
+
+typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2 } locc_precision;
+
+/* Network and crop configuration, fixed for the life of a context.
+ *   K       crop cap per object, multiple of 32, 32..256
+ *   enc_h1  encoder hidden width, enc_h2 encoder output width (per object)
+ *   head_h  head hidden width; the head input is 2 * enc_h2
+ *   pad_m   crop margin added to every face of the box, metres (>= 0)
+ *   precision  arithmetic of the encoder and head (locc_precision);
+ *              the crop geometry is float64 in every precision
+ * Compiled width sets: (h1, h2, hh) = (64, 128, 256) and (128, 256, 512). */
+typedef struct {
+  int32_t K;
+  int32_t enc_h1;
+  int32_t enc_h2;
+  int32_t head_h;
+  double pad_m;
+  int32_t precision;
+  int32_t reserved; /* must be 0 */
+} locc_config;
+
+/* One rigid object: position of its frame origin, shape id, and orientation
+ * as a Hamilton quaternion (w, x, y, z) rotating object-frame vectors into
+ * the world.  The quaternion is used as given (not renormalised).  32 bytes. */
+typedef struct {
+  float p[3];
+  int32_t shape;
+  float q[4];
+} locc_object;
+
+/* Result per pair, 32 bytes:
+ *   logit   collision logit; flag = logit > 0 (sigmoid(logit) > 0.5)
+ *   point   contact point, world frame
+ *   normal  contact normal in the world frame, from the caller's first object
+ *           towards its second; not normalised
+ *   depth   penetration depth (positive = overlapping)
+ * An invalid pair (index out of range, i == j, shape id out of range) gets
+ * all-NaN fields, counts of -1, and increments the device error counter. */
+typedef struct {
+  float logit;
+  float point[3];
+  float normal[3];
+  float depth;
+} locc_contact;
+
+typedef struct locc_ctx locc_ctx;
+
+/* Library version string, e.g. "locc 0.1.0 gfx950". Static storage. */
+LOCC_API const char* locc_version(void);
+
+/* Message of the last failed call on this host thread (static thread-local
+ * storage, valid until the next failing call). */
+LOCC_API const char* locc_last_error(void);
+
+/* Create a context on HIP device `device` with configuration `cfg` (copied).
+ * Allocates nothing large; uploads and the first detect allocate.
+ * Errors: INVALID_ARG (null, bad K/pad), UNSUPPORTED (widths/precision), HIP. */
+LOCC_API locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out);
+
+/* Free every device buffer of the context and the context itself. NULL is a no-op. */
+LOCC_API void locc_destroy(locc_ctx* ctx);
+
+/* Network weights, float32, host memory, copied synchronously (the caller may
+ * free h_weights on return).  Order W1, b1, W2, b2, H1, c1, H2, c2, H3, c3;
+ * each W row-major [out][in]:
+ *   W1 [h1][6]  W2 [h2][h1]  H1 [hh][2 h2]  H2 [hh][hh]  H3 [8][hh].
+ * n_floats must equal the total.  The encoder input row is
+ * (x, y, z, nx, ny, nz) in a's frame; the head input is [f_a, f_b].
+ * Low precisions quantise from these values (per-layer scales for FP8).
+ * Errors: INVALID_ARG (null, wrong n_floats, non-finite value), OOM, HIP. */
+LOCC_API locc_status locc_upload_weights(locc_ctx* ctx, const float* h_weights, size_t n_floats);
+
+/* Shape library: n_shapes point clouds in their own frames, host memory,
+ * copied synchronously; replaces any previous library.  Shape s owns rows
+ * h_offsets[s] .. h_offsets[s+1]-1 of h_points, each row
+ * (x, y, z, nx, ny, nz) float32.  Offsets start at 0 and never decrease;
+ * every shape has at least one point; total < 2^31.  The per-shape
+ * axis-aligned box is the min/max of the stored xyz.  Shape ids are 0..n-1.
+ * Errors: INVALID_ARG (null, bad offsets, empty shape, non-finite value),
+ * RANGE (too many points), OOM, HIP. */
+LOCC_API locc_status locc_upload_shapes(locc_ctx* ctx, int32_t n_shapes, const int64_t* h_offsets,
+                               const float* h_points);
+
+/* The whole path for n_pairs pairs, asynchronous on `stream`.
+ *   d_objs    [n_objs] locc_object, device
+ *   d_pairs   [n_pairs][2] int32 object indices (i, j), device
+ *   d_out     [n_pairs] locc_contact, device, written
+ *   d_counts  [n_pairs][2] int32, device, or NULL: members of object i and of
+ *             object j inside the crop box before the cap at K (-1 if invalid)
+ * Device buffers belong to the caller and must stay valid until the stream
+ * has run the work.  n_pairs == 0 is a no-op.  The library's own workspace
+ * grows on demand (this may allocate; the call then synchronises the
+ * device once).
+ * Errors (nothing enqueued): INVALID_ARG, NOT_READY, RANGE, OOM, HIP. */
+LOCC_API locc_status locc_detect(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                        int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, void* stream);
+
+/* Crop step only (parity hook).  Same inputs as locc_detect; writes
+ *   d_idx     [n_pairs][2][K] int32: the selected point indices of object i
+ *             and of object j in stored order, -1 padded (-1 everywhere for
+ *             invalid pairs)
+ *   d_counts  [n_pairs][2] int32 as in locc_detect (required here). */
+LOCC_API locc_status locc_debug_crop(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                            int32_t n_pairs, int32_t* d_idx, int32_t* d_counts, void* stream);
+
+/* Network intermediates (parity hook).  Runs the whole path and also writes
+ *   d_z  [n_pairs][2 h2] float32 pooled features [f_a, f_b] (a = min(i, j))
+ *   d_y  [n_pairs][8] float32 raw head output in a's frame
+ * Either may be NULL. */
+LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                               int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, float* d_z, float* d_y,
+                               void* stream);
+
+/* Number of invalid pairs seen by all detect calls since the last reset;
+ * synchronises `stream`.  reset != 0 clears the counter afterwards. */
+LOCC_API locc_status locc_device_errors(locc_ctx* ctx, void* stream, int64_t* h_n_bad, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOCC_H */

@@ -1,0 +1,218 @@
+"""ctypes binding of liblocc.so (C-ABI in include/locc.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors on the context's device; the
+stream is torch's current stream unless one is given.  If the library is not
+built this module raises on first use; there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblocc.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_NOT_READY, ERR_RANGE, ERR_BUSY, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "RANGE", -6: "BUSY",
+                -7: "UNSUPPORTED"}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+
+EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
+           "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("enc_h1", ctypes.c_int32), ("enc_h2", ctypes.c_int32),
+                ("head_h", ctypes.c_int32), ("pad_m", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class LoccError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"locc {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load liblocc.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_09439_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    L.locc_version.restype = ctypes.c_char_p
+    L.locc_version.argtypes = []
+    L.locc_last_error.restype = ctypes.c_char_p
+    L.locc_last_error.argtypes = []
+    L.locc_create.restype = ctypes.c_int
+    L.locc_create.argtypes = [ctypes.POINTER(Config), ctypes.c_int, ctypes.POINTER(vp)]
+    L.locc_destroy.restype = None
+    L.locc_destroy.argtypes = [vp]
+    L.locc_upload_weights.restype = ctypes.c_int
+    L.locc_upload_weights.argtypes = [vp, vp, ctypes.c_size_t]
+    L.locc_upload_shapes.restype = ctypes.c_int
+    L.locc_upload_shapes.argtypes = [vp, i32, vp, vp]
+    L.locc_detect.restype = ctypes.c_int
+    L.locc_detect.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+    L.locc_debug_crop.restype = ctypes.c_int
+    L.locc_debug_crop.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+    L.locc_debug_forward.restype = ctypes.c_int
+    L.locc_debug_forward.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
+    L.locc_device_errors.restype = ctypes.c_int
+    L.locc_device_errors.argtypes = [vp, vp, i64p, ctypes.c_int]
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        raise LoccError(status, load().locc_last_error().decode(errors="replace"))
+
+
+def version() -> str:
+    return load().locc_version().decode()
+
+
+def pack_objects(pos, quat, shape) -> np.ndarray:
+    """Objects as float32 [n, 8] rows (px, py, pz, shape-id bits, qw, qx, qy, qz): the locc_object layout."""
+    pos = np.asarray(pos, np.float32)
+    quat = np.asarray(quat, np.float32)
+    n = len(pos)
+    out = np.empty((n, 8), np.float32)
+    out[:, 0:3] = pos
+    out[:, 3] = np.asarray(shape, np.int32).view(np.float32)
+    out[:, 4:8] = quat
+    return out
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Context:
+    """One library context: configuration, resident shapes and weights."""
+
+    def __init__(self, K: int, widths, pad: float = 0.01, precision: str = "fp32", device: int = 0):
+        L = load()
+        h1, h2, hh = widths
+        self.cfg = Config(K, h1, h2, hh, pad, PRECISIONS[precision], 0)
+        self.K, self.h1, self.h2, self.hh = K, h1, h2, hh
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(L.locc_create(ctypes.byref(self.cfg), device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().locc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------- uploads
+    def upload_shapes(self, offsets, points):
+        off = np.ascontiguousarray(offsets, np.int64)
+        pts = np.ascontiguousarray(points, np.float32)
+        if pts.ndim != 2 or pts.shape[1] != 6:
+            raise ValueError("points must be float32 [N, 6]")
+        _check(load().locc_upload_shapes(self._h, len(off) - 1, off.ctypes.data, pts.ctypes.data))
+
+    def upload_weights(self, flat):
+        w = np.ascontiguousarray(flat, np.float32)
+        _check(load().locc_upload_weights(self._h, w.ctypes.data, w.size))
+
+    # ------------------------------------------------------------- device calls
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(int(s.cuda_stream))
+
+    def _check_dev(self, name, t, dtype, shape_tail):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.device.index != self.device:
+            raise ValueError(f"{name}: expected a tensor on cuda:{self.device}")
+        if t.dtype != dtype or not t.is_contiguous() or tuple(t.shape[1:]) != tuple(shape_tail):
+            raise ValueError(f"{name}: expected contiguous {dtype} [n, {', '.join(map(str, shape_tail))}], "
+                             f"got {t.dtype} {tuple(t.shape)}")
+
+    def _inputs(self, objs, pairs):
+        import torch
+        self._check_dev("objs", objs, torch.float32, (8,))
+        self._check_dev("pairs", pairs, torch.int32, (2,))
+        return objs.shape[0], pairs.shape[0]
+
+    def detect(self, objs, pairs, out=None, counts=None, stream=None, want_counts=True):
+        """Contacts [P, 8] float32 and counts [P, 2] int32 (torch, on the device)."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        dev = objs.device
+        if out is None:
+            out = torch.empty((P, 8), dtype=torch.float32, device=dev)
+        if counts is None and want_counts:
+            counts = torch.empty((P, 2), dtype=torch.int32, device=dev)
+        _check(load().locc_detect(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
+                                  self._stream(stream)))
+        return out, counts
+
+    def debug_crop(self, objs, pairs, stream=None):
+        """Selected indices [P, 2, K] and counts [P, 2] (caller order)."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        idx = torch.empty((P, 2, self.K), dtype=torch.int32, device=objs.device)
+        counts = torch.empty((P, 2), dtype=torch.int32, device=objs.device)
+        _check(load().locc_debug_crop(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(idx), _ptr(counts),
+                                      self._stream(stream)))
+        return idx, counts
+
+    def debug_forward(self, objs, pairs, stream=None):
+        """Contacts, counts, pooled features z [P, 2 h2] and raw head output y [P, 8]."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        dev = objs.device
+        out = torch.empty((P, 8), dtype=torch.float32, device=dev)
+        counts = torch.empty((P, 2), dtype=torch.int32, device=dev)
+        z = torch.empty((P, 2 * self.h2), dtype=torch.float32, device=dev)
+        y = torch.empty((P, 8), dtype=torch.float32, device=dev)
+        _check(load().locc_debug_forward(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
+                                         _ptr(z), _ptr(y), self._stream(stream)))
+        return out, counts, z, y
+
+    def device_errors(self, reset: bool = False, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(load().locc_device_errors(self._h, self._stream(stream), ctypes.byref(n), int(reset)))
+        return n.value
+
+
+def context_for_scene(scene, K, widths, weights_flat, pad=0.01, precision="fp32", device=0):
+    """Create a context, upload the scene's shape library and the weights."""
+    ctx = Context(K, widths, pad, precision, device)
+    ctx.upload_shapes(scene.lib.offsets, scene.lib.pts)
+    ctx.upload_weights(weights_flat)
+    return ctx
+
+
+def scene_tensors(scene, device=0):
+    """(objects [n, 8] float32, pairs [P, 2] int32) of a scene, on the device."""
+    import torch
+    objs = torch.from_numpy(pack_objects(scene.pos, scene.quat, scene.shape)).to(f"cuda:{device}")
+    pairs = torch.from_numpy(np.ascontiguousarray(scene.pairs, np.int32)).to(f"cuda:{device}")
+    return objs, pairs

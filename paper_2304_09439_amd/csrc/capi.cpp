@@ -1,0 +1,313 @@
+// C-ABI of the LOCC library: argument checks, resident shape library and
+// weights, workspace, and the launch sequence of the path.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "locc_internal.h"
+
+using namespace locc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+locc_status fail(locc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? LOCC_ERR_OOM : LOCC_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+  } while (0)
+
+bool widths_supported(int h1, int h2, int hh) {
+  return (h1 == 64 && h2 == 128 && hh == 256) || (h1 == 128 && h2 == 256 && hh == 512);
+}
+
+size_t weight_floats(int h1, int h2, int hh) {
+  return (size_t)h1 * 6 + h1 + (size_t)h2 * h1 + h2 + (size_t)hh * 2 * h2 + hh + (size_t)hh * hh + hh +
+         (size_t)8 * hh + 8;
+}
+
+}  // namespace
+
+struct locc_ctx {
+  locc_config cfg{};
+  int device = 0;
+  int n_cu = 0;
+  // shape library
+  int32_t n_shapes = 0;
+  int64_t n_points = 0;
+  ShapeDesc* d_shapes = nullptr;
+  float* d_points = nullptr;  // SoA: x, y, z, nx, ny, nz, each n_points floats
+  // weights
+  float* d_wfp32 = nullptr;
+  bool have_weights = false;
+  // workspace
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned long long* d_err = nullptr;
+
+  DeviceLibrary lib() const {
+    const float* b = d_points;
+    const size_t n = (size_t)n_points;
+    return DeviceLibrary{d_shapes, n_shapes, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n};
+  }
+};
+
+namespace {
+
+locc_status ensure_workspace(locc_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return LOCC_OK;
+  if (c->d_ws) HIP_TRY(hipFree(c->d_ws));  // implicit device synchronisation
+  c->d_ws = nullptr;
+  c->ws_bytes = 0;
+  size_t want = bytes + bytes / 4;
+  HIP_TRY(hipMalloc(&c->d_ws, want));
+  c->ws_bytes = want;
+  return LOCC_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Workspace {
+  PairMeta* meta;
+  float* rows;
+  float* z;
+};
+
+locc_status carve(locc_ctx* c, int n_pairs, Workspace* w) {
+  const size_t P = (size_t)n_pairs;
+  const size_t meta = align256(P * sizeof(PairMeta));
+  const size_t rows = align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float));
+  const size_t z = align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
+  locc_status st = ensure_workspace(c, meta + rows + z);
+  if (st != LOCC_OK) return st;
+  char* b = static_cast<char*>(c->d_ws);
+  w->meta = reinterpret_cast<PairMeta*>(b);
+  w->rows = reinterpret_cast<float*>(b + meta);
+  w->z = reinterpret_cast<float*>(b + meta + rows);
+  return LOCC_OK;
+}
+
+locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                       int32_t n_pairs) {
+  if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
+  if (n_objs < 0 || n_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "negative count (n_objs=%d, n_pairs=%d)",
+                                             n_objs, n_pairs);
+  if (n_pairs > 0 && (!objs || !pairs)) return fail(LOCC_ERR_INVALID_ARG, "null objects or pairs");
+  if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
+  if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
+  return LOCC_OK;
+}
+
+locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                     int32_t n_pairs, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
+                     hipStream_t s) {
+  if (n_pairs == 0) return LOCC_OK;
+  Workspace w{};
+  locc_status st = carve(c, n_pairs, &w);
+  if (st != LOCC_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
+              nullptr, counts, w.meta, w.rows, c->d_err};
+  HIP_TRY(launch_crop(ca, s));
+  const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
+  NetArgs na{w.rows, w.meta, objs, n_pairs, c->cfg.K, z_out ? z_out : w.z, y_out, out};
+  HIP_TRY(launch_encoder_fp32(net, na, c->n_cu, s));
+  HIP_TRY(launch_head_fp32(net, na, s));
+  return LOCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* locc_version(void) { return "locc 0.1.0 gfx950"; }
+
+const char* locc_last_error(void) { return g_last_error.c_str(); }
+
+locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
+  if (!cfg || !out) return fail(LOCC_ERR_INVALID_ARG, "null cfg or out");
+  *out = nullptr;
+  if (cfg->K < 32 || cfg->K > kMaxK || cfg->K % 32 != 0)
+    return fail(LOCC_ERR_INVALID_ARG, "K=%d: must be a multiple of 32 in [32, %d]", cfg->K, kMaxK);
+  if (!(cfg->pad_m >= 0.0) || !std::isfinite(cfg->pad_m))
+    return fail(LOCC_ERR_INVALID_ARG, "pad_m must be finite and >= 0");
+  if (cfg->reserved != 0) return fail(LOCC_ERR_INVALID_ARG, "reserved field must be 0");
+  if (cfg->precision < LOCC_FP32 || cfg->precision > LOCC_FP8)
+    return fail(LOCC_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
+  if (!widths_supported(cfg->enc_h1, cfg->enc_h2, cfg->head_h))
+    return fail(LOCC_ERR_UNSUPPORTED, "widths (%d, %d, %d) not compiled in", cfg->enc_h1, cfg->enc_h2,
+                cfg->head_h);
+  if (cfg->precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "precision %d not available", cfg->precision);
+  if (device < 0) return fail(LOCC_ERR_INVALID_ARG, "device %d", device);
+  int n_dev = 0;
+  HIP_TRY(hipGetDeviceCount(&n_dev));
+  if (device >= n_dev) return fail(LOCC_ERR_INVALID_ARG, "device %d of %d", device, n_dev);
+  HIP_TRY(hipSetDevice(device));
+  int n_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+  locc_ctx* c = new locc_ctx();
+  c->cfg = *cfg;
+  c->device = device;
+  c->n_cu = n_cu;
+  hipError_t e = hipMalloc(&c->d_err, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    locc_destroy(c);
+    return fail(LOCC_ERR_HIP, "error counter: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return LOCC_OK;
+}
+
+void locc_destroy(locc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipFree(c->d_shapes);
+  (void)hipFree(c->d_points);
+  (void)hipFree(c->d_wfp32);
+  (void)hipFree(c->d_ws);
+  (void)hipFree(c->d_err);
+  delete c;
+}
+
+locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
+  if (!c || !h) return fail(LOCC_ERR_INVALID_ARG, "null context or weights");
+  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
+  const size_t want = weight_floats(h1, h2, hh);
+  if (n != want) return fail(LOCC_ERR_INVALID_ARG, "weights: %zu floats given, %zu expected", n, want);
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(h[k])) return fail(LOCC_ERR_INVALID_ARG, "weights: non-finite value at %zu", k);
+  const float* W1 = h;
+  const float* b1 = W1 + (size_t)h1 * 6;
+  const float* W2 = b1 + h1;
+  const float* b2 = W2 + (size_t)h2 * h1;
+  const float* H1 = b2 + h2;
+  const float* c1 = H1 + (size_t)hh * 2 * h2;
+  const float* H2 = c1 + hh;
+  const float* c2 = H2 + (size_t)hh * hh;
+  const float* H3 = c2 + hh;
+  const float* c3 = H3 + (size_t)8 * hh;
+  std::vector<float> pack(fp32_pack_floats(h1, h2, hh));
+  fp32_pack(W1, b1, W2, b2, H1, c1, H2, c2, H3, c3, h1, h2, hh, pack.data());
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->d_wfp32) HIP_TRY(hipMalloc(&c->d_wfp32, pack.size() * sizeof(float)));
+  HIP_TRY(hipMemcpy(c->d_wfp32, pack.data(), pack.size() * sizeof(float), hipMemcpyHostToDevice));
+  c->have_weights = true;
+  return LOCC_OK;
+}
+
+locc_status locc_upload_shapes(locc_ctx* c, int32_t n_shapes, const int64_t* off, const float* pts) {
+  if (!c || !off || !pts) return fail(LOCC_ERR_INVALID_ARG, "null context, offsets or points");
+  if (n_shapes <= 0) return fail(LOCC_ERR_INVALID_ARG, "n_shapes=%d", n_shapes);
+  if (off[0] != 0) return fail(LOCC_ERR_INVALID_ARG, "offsets[0]=%lld, must be 0", (long long)off[0]);
+  for (int s = 0; s < n_shapes; ++s) {
+    const int64_t n = off[s + 1] - off[s];
+    if (n <= 0) return fail(LOCC_ERR_INVALID_ARG, "shape %d has %lld points", s, (long long)n);
+    if (n > kMaxShapePoints)
+      return fail(LOCC_ERR_RANGE, "shape %d has %lld points (max %d)", s, (long long)n, kMaxShapePoints);
+  }
+  const int64_t total = off[n_shapes];
+  if (total >= (int64_t)INT32_MAX) return fail(LOCC_ERR_RANGE, "%lld points in total", (long long)total);
+  std::vector<float> soa((size_t)total * 6);
+  std::vector<ShapeDesc> desc(n_shapes);
+  for (int s = 0; s < n_shapes; ++s) {
+    ShapeDesc d{};
+    d.off = (int32_t)off[s];
+    d.n = (int32_t)(off[s + 1] - off[s]);
+    for (int k = 0; k < 3; ++k) {
+      d.lo[k] = INFINITY;
+      d.hi[k] = -INFINITY;
+    }
+    for (int64_t r = off[s]; r < off[s + 1]; ++r) {
+      const float* row = pts + r * 6;
+      for (int k = 0; k < 6; ++k) {
+        if (!std::isfinite(row[k]))
+          return fail(LOCC_ERR_INVALID_ARG, "shape %d point %lld: non-finite value", s, (long long)(r - off[s]));
+        soa[(size_t)k * total + r] = row[k];
+      }
+      for (int k = 0; k < 3; ++k) {
+        d.lo[k] = row[k] < d.lo[k] ? row[k] : d.lo[k];
+        d.hi[k] = row[k] > d.hi[k] ? row[k] : d.hi[k];
+      }
+    }
+    desc[s] = d;
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  (void)hipFree(c->d_shapes);
+  (void)hipFree(c->d_points);
+  c->d_shapes = nullptr;
+  c->d_points = nullptr;
+  c->n_shapes = 0;
+  c->n_points = 0;
+  HIP_TRY(hipMalloc(&c->d_shapes, sizeof(ShapeDesc) * n_shapes));
+  HIP_TRY(hipMalloc(&c->d_points, sizeof(float) * soa.size()));
+  HIP_TRY(hipMemcpy(c->d_shapes, desc.data(), sizeof(ShapeDesc) * n_shapes, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_points, soa.data(), sizeof(float) * soa.size(), hipMemcpyHostToDevice));
+  c->n_shapes = n_shapes;
+  c->n_points = total;
+  return LOCC_OK;
+}
+
+locc_status locc_detect(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                        int32_t n_pairs, locc_contact* out, int32_t* counts, void* stream) {
+  locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
+  if (st != LOCC_OK) return st;
+  if (n_pairs > 0 && !out) return fail(LOCC_ERR_INVALID_ARG, "null output");
+  return run_path(c, objs, n_objs, pairs, n_pairs, out, counts, nullptr, nullptr,
+                  static_cast<hipStream_t>(stream));
+}
+
+locc_status locc_debug_forward(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                               int32_t n_pairs, locc_contact* out, int32_t* counts, float* z, float* y,
+                               void* stream) {
+  locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
+  if (st != LOCC_OK) return st;
+  if (n_pairs > 0 && !out) return fail(LOCC_ERR_INVALID_ARG, "null output");
+  return run_path(c, objs, n_objs, pairs, n_pairs, out, counts, z, y, static_cast<hipStream_t>(stream));
+}
+
+locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                            int32_t n_pairs, int32_t* idx, int32_t* counts, void* stream) {
+  if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
+  if (n_objs < 0 || n_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "negative count");
+  if (n_pairs > 0 && (!objs || !pairs || !idx || !counts))
+    return fail(LOCC_ERR_INVALID_ARG, "null objects, pairs, idx or counts");
+  if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
+  if (n_pairs == 0) return LOCC_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
+              idx, counts, nullptr, nullptr, c->d_err};
+  HIP_TRY(launch_crop(ca, static_cast<hipStream_t>(stream)));
+  return LOCC_OK;
+}
+
+locc_status locc_device_errors(locc_ctx* c, void* stream, int64_t* n_bad, int reset) {
+  if (!c || !n_bad) return fail(LOCC_ERR_INVALID_ARG, "null context or output");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+  unsigned long long v = 0;
+  HIP_TRY(hipMemcpy(&v, c->d_err, sizeof v, hipMemcpyDeviceToHost));
+  *n_bad = (int64_t)v;
+  if (reset) HIP_TRY(hipMemset(c->d_err, 0, sizeof(unsigned long long)));
+  return LOCC_OK;
+}
+
+}  // extern "C"

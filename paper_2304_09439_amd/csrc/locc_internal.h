@@ -1,0 +1,107 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "locc.h"
+
+namespace locc {
+
+// Per-shape descriptor in device memory: rows [off, off + n) of the SoA point
+// arrays, and the axis-aligned box of the stored xyz (min / max).  32 bytes.
+struct ShapeDesc {
+  int32_t off;
+  int32_t n;
+  float lo[3];
+  float hi[3];
+};
+static_assert(sizeof(ShapeDesc) == 32, "ShapeDesc layout");
+
+// Per-pair record written by the crop step and read by the network steps.
+//   a        canonical first object (min(i, j)), or -1 for an invalid pair
+//   swapped  1 if the caller gave (b, a)
+//   m_a, m_b number of valid encoder rows (min(count, K)) per object
+struct PairMeta {
+  int32_t a;
+  int32_t swapped;
+  int32_t m_a;
+  int32_t m_b;
+};
+static_assert(sizeof(PairMeta) == 16, "PairMeta layout");
+
+// Largest point count per shape (the crop step keeps one 64-bit membership
+// mask per 64 points of each object in LDS).
+constexpr int kMaxShapePoints = 16384;
+constexpr int kMaxK = 256;
+// Encoder input rows: 8 floats (x, y, z, nx, ny, nz, 1, 0) stored in the
+// order (e0, e2, e4, e6, e1, e3, e5, e7) so that each half-wave of a 32x32x2
+// MFMA operand load reads one float4.
+constexpr int kRowFloats = 8;
+
+struct DeviceLibrary {
+  const ShapeDesc* shapes;
+  int32_t n_shapes;
+  const float* px;
+  const float* py;
+  const float* pz;
+  const float* nx;
+  const float* ny;
+  const float* nz;
+};
+
+struct CropArgs {
+  const locc_object* objs;
+  int32_t n_objs;
+  const int32_t* pairs;
+  int32_t n_pairs;
+  DeviceLibrary lib;
+  int32_t K;
+  double pad;
+  int32_t* idx_out;      // [P][2][K] caller order, may be null
+  int32_t* counts_out;   // [P][2] caller order, may be null
+  PairMeta* meta;        // [P], may be null
+  float* rows;           // [P][2K][8], may be null
+  unsigned long long* err_counter;
+};
+
+hipError_t launch_crop(const CropArgs& a, hipStream_t s);
+
+// FP32 network weights packed in MFMA fragment order (see net_fp32.hip).
+struct Fp32Net {
+  int h1, h2, hh;
+  const float* w1pack;  // [h1/32][4][64]
+  const float* w2pack;  // [4 waves][h2/128][h1/2][64]
+  const float* b2;      // [h2]
+  const float* h1pack;  // [hh/32][h2][64]   (k-steps = 2*h2 / 2)
+  const float* c1;      // [hh]
+  const float* h2pack;  // [hh/32][hh/2][64]
+  const float* c2;      // [hh]
+  const float* h3;      // [8][hh] plain row-major
+  const float* c3;      // [8]
+};
+
+struct NetArgs {
+  const float* rows;      // [P][2K][8]
+  const PairMeta* meta;   // [P]
+  const locc_object* objs;
+  int32_t n_pairs;
+  int32_t K;
+  float* z;               // [P][2 h2] workspace (always written)
+  float* y_dbg;           // [P][8] or null
+  locc_contact* out;      // [P]
+};
+
+hipError_t launch_encoder_fp32(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s);
+hipError_t launch_head_fp32(const Fp32Net& w, const NetArgs& a, hipStream_t s);
+
+// Host-side packing of row-major FP32 weights into the fragment layouts above.
+size_t fp32_pack_floats(int h1, int h2, int hh);
+void fp32_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
+               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
+               int h2, int hh, float* dst);
+Fp32Net fp32_view(const float* dev_base, int h1, int h2, int hh);
+
+}  // namespace locc

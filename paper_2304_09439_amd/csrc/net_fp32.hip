@@ -1,0 +1,343 @@
+// FP32 network of the LOCC path: per-point encoder with per-object max-pool,
+// then the pair head and the world-frame epilogue.
+//
+// Encoder (per pair, 2K rows of (x, y, z, nx, ny, nz) in a's frame):
+//   h1 = ReLU(W1 r + b1), h2 = ReLU(W2 h1 + b2), f = max over the valid rows
+// of each object (0 when none); the paper's shape encoder is likewise a
+// per-point MLP whose features are max-pooled (Sec. III, appendix).
+// Head (per pair): y = H3 ReLU(H2 ReLU(H1 [f_a, f_b] + c1) + c2) + c3, the
+// paper's predictor being an MLP on the pooled crop features that ends in a
+// linear layer (appendix).  Outputs: logit y0, contact point R_a y[1:4] + t_a,
+// normal sgn R_a y[4:7], depth y7.
+//
+// MFMA v_mfma_f32_32x32x2_f32 operand layout (lane l of a wave64):
+//   A[i][k]: i = l % 32, k = l / 32;   B[k][j]: j = l % 32, k = l / 32;
+//   D[i][j] in 16 registers r: j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4.
+// Encoder: layer 1 is computed transposed (h1^T = [W1 | b1] [r; 1]), so each
+// lane ends up holding 16 features of ONE point per 32-feature tile.  Those
+// registers are exactly layer 2's A operand if layer 2's reduction index is
+// permuted to F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4; the host packs
+// W2 in that order.  Both layers stay in registers; W2's slice for the wave
+// (h2 / 4 output columns) is loaded once per workgroup and reused for every
+// pair the persistent workgroup processes.
+#include "locc_internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace locc {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f32x16 mfma32x32x2(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+__host__ __device__ constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) + 4 * g + r % 4; }
+
+// -------------------------------------------------------------------- encoder
+template <int H1, int H2>
+__global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs A) {
+  constexpr int FT = H1 / 32;   // 32-feature tiles of layer 1
+  constexpr int KS = H1 / 2;    // layer-2 k-steps
+  constexpr int CT = H2 / 128;  // 32-column tiles per wave
+  static_assert(H1 % 32 == 0 && H2 % 128 == 0, "widths");
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 5;
+  const int K = A.K;
+
+  float w1f[FT][4];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) w1f[ft][s] = W.w1pack[(ft * 4 + s) * 64 + lane];
+  float w2f[CT][KS];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) w2f[ct][s] = W.w2pack[((wave * CT + ct) * KS + s) * 64 + lane];
+  float bias2[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) bias2[ct] = W.b2[(wave * CT + ct) * 32 + (lane & 31)];
+
+  for (int p = blockIdx.x; p < A.n_pairs; p += gridDim.x) {
+    const PairMeta mt = A.meta[p];
+    float* zp = A.z + (size_t)p * 2 * H2;
+    if (mt.a < 0) {
+      if (lane < 32)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          zp[(wave * CT + ct) * 32 + lane] = __builtin_nanf("");
+          zp[H2 + (wave * CT + ct) * 32 + lane] = __builtin_nanf("");
+        }
+      continue;
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int m = side ? mt.m_b : mt.m_a;
+      float run[CT];
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) run[ct] = 0.f;
+      const float* rbase = A.rows + ((size_t)p * 2 * K + side * K) * kRowFloats;
+      for (int r0 = 0; r0 < m; r0 += 32) {
+        const float4 xv = *reinterpret_cast<const float4*>(rbase + (r0 + (lane & 31)) * kRowFloats + 4 * g);
+        const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+        f32x16 acc1[FT];
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft) {
+          acc1[ft] = f32x16{};
+#pragma unroll
+          for (int s = 0; s < 4; ++s) acc1[ft] = mfma32x32x2(w1f[ft][s], xs[s], acc1[ft]);
+        }
+        f32x16 acc2[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
+#pragma unroll
+        for (int ft = 0; ft < FT; ++ft)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const float h = fmaxf(acc1[ft][r], 0.f);
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h, w2f[ct][ft * 16 + r], acc2[ct]);
+          }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+            const float v = fmaxf(acc2[ct][r] + bias2[ct], 0.f);
+            if (row < m) run[ct] = fmaxf(run[ct], v);
+          }
+      }
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        run[ct] = fmaxf(run[ct], __shfl_xor(run[ct], 32, 64));
+        if (lane < 32) zp[side * H2 + (wave * CT + ct) * 32 + lane] = run[ct];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------- head
+constexpr int kHeadPairs = 32;
+
+template <int Z, int HH>
+__global__ __launch_bounds__(256, 1) void head_fp32_kernel(Fp32Net W, NetArgs A) {
+  constexpr int LZ = Z + 1;    // odd row strides: conflict-free column reads
+  constexpr int LG = HH + 1;
+  constexpr int CTH = HH / 128;
+  extern __shared__ float smem[];
+  float* zt = smem;                      // [32][LZ], later reused for g2 [32][LG]
+  float* gt = smem + kHeadPairs * (LZ > LG ? LZ : LG);  // [32][LG]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 5;
+  const int p0 = blockIdx.x * kHeadPairs;
+
+  for (int e = tid; e < kHeadPairs * Z; e += 256) {
+    const int i = e / Z, k = e - i * Z;
+    const int p = p0 + i;
+    float v = 0.f;
+    if (p < A.n_pairs) {
+      v = A.z[(size_t)p * Z + k];
+      if (v != v) v = 0.f;  // invalid pair: its outputs are NaN-ed in the epilogue
+    }
+    zt[i * LZ + k] = v;
+  }
+  __syncthreads();
+
+  // layer 1: g1 = ReLU(zt H1^T + c1) -> gt ; layer 2: g2 = ReLU(gt H2^T + c2) -> zt
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const float* src = layer == 0 ? zt : gt;
+    float* dst = layer == 0 ? gt : zt;
+    const int LS = layer == 0 ? LZ : LG;
+    const int LD = LG;
+    const int KS = (layer == 0 ? Z : HH) / 2;
+    const float* pack = layer == 0 ? W.h1pack : W.h2pack;
+    const float* bias = layer == 0 ? W.c1 : W.c2;
+    f32x16 acc[CTH];
+#pragma unroll
+    for (int ct = 0; ct < CTH; ++ct) acc[ct] = f32x16{};
+    const float* arow = src + (lane & 31) * LS + g;
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const float av = arow[2 * s];
+#pragma unroll
+      for (int ct = 0; ct < CTH; ++ct)
+        acc[ct] = mfma32x32x2(av, pack[((size_t)(wave * CTH + ct) * KS + s) * 64 + lane], acc[ct]);
+    }
+    __syncthreads();  // everyone is done reading dst's previous contents (layer 1 read zt)
+#pragma unroll
+    for (int ct = 0; ct < CTH; ++ct) {
+      const int col = (wave * CTH + ct) * 32 + (lane & 31);
+      const float bc = bias[col];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = 8 * (r >> 2) + 4 * g + (r & 3);
+        dst[row * LD + col] = fmaxf(acc[ct][r] + bc, 0.f);
+      }
+    }
+    __syncthreads();
+  }
+
+  // layer 3 (8 outputs per pair): one thread per (pair, output)
+  __shared__ float ys[kHeadPairs][8];
+  {
+    const int i = tid >> 3, o = tid & 7;
+    const float* h3 = W.h3 + (size_t)o * HH;
+    const float* g2 = zt + i * LG;
+    float acc = 0.f;
+    for (int k = 0; k < HH; ++k) acc += g2[k] * h3[k];
+    ys[i][o] = acc + W.c3[o];
+  }
+  __syncthreads();
+
+  if (tid < kHeadPairs) {
+    const int p = p0 + tid;
+    if (p < A.n_pairs) {
+      const PairMeta mt = A.meta[p];
+      float out[8];
+      const float* y = ys[tid];
+      if (mt.a < 0) {
+        for (int k = 0; k < 8; ++k) out[k] = __builtin_nanf("");
+      } else {
+        const locc_object o = A.objs[mt.a];
+        const double w = o.q[0], x = o.q[1], yq = o.q[2], zq = o.q[3];
+        const double R[9] = {1.0 - 2.0 * (yq * yq + zq * zq), 2.0 * (x * yq - w * zq), 2.0 * (x * zq + w * yq),
+                             2.0 * (x * yq + w * zq), 1.0 - 2.0 * (x * x + zq * zq), 2.0 * (yq * zq - w * x),
+                             2.0 * (x * zq - w * yq), 2.0 * (yq * zq + w * x), 1.0 - 2.0 * (x * x + yq * yq)};
+        const double sg = mt.swapped ? -1.0 : 1.0;
+        out[0] = y[0];
+        for (int r = 0; r < 3; ++r) {
+          out[1 + r] = (float)(R[3 * r] * y[1] + R[3 * r + 1] * y[2] + R[3 * r + 2] * y[3] + (double)o.p[r]);
+          out[4 + r] = (float)(sg * (R[3 * r] * y[4] + R[3 * r + 1] * y[5] + R[3 * r + 2] * y[6]));
+        }
+        out[7] = y[7];
+      }
+      float4* dst = reinterpret_cast<float4*>(A.out + p);
+      dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+      dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+      if (A.y_dbg) {
+        float4* yd = reinterpret_cast<float4*>(A.y_dbg + (size_t)p * 8);
+        const float nan = __builtin_nanf("");
+        yd[0] = mt.a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[0], y[1], y[2], y[3]);
+        yd[1] = mt.a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[4], y[5], y[6], y[7]);
+      }
+    }
+  }
+}
+
+template <int Z, int HH>
+size_t head_smem_bytes() {
+  constexpr int LZ = Z + 1, LG = HH + 1;
+  return sizeof(float) * kHeadPairs * ((LZ > LG ? LZ : LG) + LG);
+}
+
+template <int H1, int H2>
+hipError_t run_encoder(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s) {
+  int grid = a.n_pairs < n_cu ? a.n_pairs : n_cu;
+  hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2>), dim3(grid), dim3(256), 0, s, w, a);
+  return hipGetLastError();
+}
+
+template <int Z, int HH>
+hipError_t run_head(const Fp32Net& w, const NetArgs& a, hipStream_t s) {
+  const size_t smem = head_smem_bytes<Z, HH>();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_fp32_kernel<Z, HH>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  const int grid = (a.n_pairs + kHeadPairs - 1) / kHeadPairs;
+  hipLaunchKernelGGL((head_fp32_kernel<Z, HH>), dim3(grid), dim3(256), smem, s, w, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_encoder_fp32(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (w.h1 == 64 && w.h2 == 128) return run_encoder<64, 128>(w, a, n_cu, s);
+  if (w.h1 == 128 && w.h2 == 256) return run_encoder<128, 256>(w, a, n_cu, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_head_fp32(const Fp32Net& w, const NetArgs& a, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (w.h2 == 128 && w.hh == 256) return run_head<256, 256>(w, a, s);
+  if (w.h2 == 256 && w.hh == 512) return run_head<512, 512>(w, a, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------- host packing
+namespace {
+struct PackLayout {
+  size_t w1, w2, b2, h1, c1, h2, c2, h3, c3, total;
+};
+size_t align64(size_t n) { return (n + 63) & ~size_t(63); }
+PackLayout pack_layout(int h1, int h2, int hh) {
+  PackLayout L{};
+  size_t o = 0;
+  L.w1 = o; o = align64(o + (size_t)8 * h1);
+  L.w2 = o; o = align64(o + (size_t)h2 * h1);
+  L.b2 = o; o = align64(o + h2);
+  L.h1 = o; o = align64(o + (size_t)hh * 2 * h2);
+  L.c1 = o; o = align64(o + hh);
+  L.h2 = o; o = align64(o + (size_t)hh * hh);
+  L.c2 = o; o = align64(o + hh);
+  L.h3 = o; o = align64(o + (size_t)8 * hh);
+  L.c3 = o; o = align64(o + 8);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+size_t fp32_pack_floats(int h1, int h2, int hh) { return pack_layout(h1, h2, hh).total; }
+
+void fp32_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
+               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
+               int h2, int hh, float* dst) {
+  const PackLayout L = pack_layout(h1, h2, hh);
+  std::memset(dst, 0, sizeof(float) * L.total);
+  // layer 1 A operand: [W1 | b1 | 0][f][c], f = 32 ft + l % 32, c = 2 s + l / 32
+  for (int ft = 0; ft < h1 / 32; ++ft)
+    for (int s = 0; s < 4; ++s)
+      for (int l = 0; l < 64; ++l) {
+        const int f = 32 * ft + l % 32, c = 2 * s + l / 32;
+        dst[L.w1 + (ft * 4 + s) * 64 + l] = c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f);
+      }
+  // layer 2 B operand, reduction index permuted to layer 1's output layout
+  const int CT = h2 / 128, KS = h1 / 2;
+  for (int w = 0; w < 4; ++w)
+    for (int ct = 0; ct < CT; ++ct)
+      for (int s = 0; s < KS; ++s)
+        for (int l = 0; l < 64; ++l) {
+          const int col = (w * CT + ct) * 32 + l % 32;
+          const int f = perm_feature(s / 16, l / 32, s % 16);
+          dst[L.w2 + ((size_t)(w * CT + ct) * KS + s) * 64 + l] = W2[(size_t)col * h1 + f];
+        }
+  std::memcpy(dst + L.b2, b2, sizeof(float) * h2);
+  // head layers: B[k][j] = H[j][k]; lane l holds H[32 ct + l % 32][2 s + l / 32]
+  auto pack_head = [&](const float* H, int in, int out, size_t at) {
+    const int ks = in / 2;
+    for (int ct = 0; ct < out / 32; ++ct)
+      for (int s = 0; s < ks; ++s)
+        for (int l = 0; l < 64; ++l)
+          dst[at + ((size_t)ct * ks + s) * 64 + l] = H[(size_t)(32 * ct + l % 32) * in + 2 * s + l / 32];
+  };
+  pack_head(H1, 2 * h2, hh, L.h1);
+  std::memcpy(dst + L.c1, c1, sizeof(float) * hh);
+  pack_head(H2, hh, hh, L.h2);
+  std::memcpy(dst + L.c2, c2, sizeof(float) * hh);
+  std::memcpy(dst + L.h3, H3, sizeof(float) * 8 * hh);
+  std::memcpy(dst + L.c3, c3, sizeof(float) * 8);
+}
+
+Fp32Net fp32_view(const float* base, int h1, int h2, int hh) {
+  const PackLayout L = pack_layout(h1, h2, hh);
+  return Fp32Net{h1, h2, hh, base + L.w1, base + L.w2, base + L.b2, base + L.h1,
+                 base + L.c1, base + L.h2, base + L.c2, base + L.h3, base + L.c3};
+}
+
+}  // namespace locc
