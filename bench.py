@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the LOCC crop-collision path on one MI355X.
+
+One step = the whole path (crop, encoder, head, world mapping) over one batch
+of synthetic pairs resident in HBM.  Prints one JSON line with pair-queries/s,
+per-step latency percentiles, the roofline of the dominant kernel (timed with
+HIP events on its launch stream inside the library) and the CPU FP64 oracle
+timed on this host on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32]
+
+Counter post-processing (turns rocprofv3 --pmc CSV output into a summary):
+  python bench.py --summarize-counters FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME
+"""
+
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair-CD queries/sec at 1 GPU (BF16 batched vs FP32 plain); p99 step latency"
+UNIT = "pair-queries/s"
+
+# MI355X published peaks
+PEAK_HBM_GBPS = 8000.0
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+CSRC = os.path.join(ROOT, "paper_2304_09439_amd", "csrc")
+KERNEL_SOURCES = {
+    "crop": ["crop.hip"],
+    "encoder_fp32": ["net_fp32.hip"],
+    "head_fp32": ["net_fp32.hip"],
+}
+
+
+def workload(name: str):
+    from paper_2304_09439_amd import inputs as I
+    if name == "scale":
+        scene = I.scale_workload()
+        return dict(scene=scene, K=128, widths=I.SCALE_WIDTHS, n_points=2048, n_shapes=32,
+                    desc="16384 object pairs, 32 procedural shapes (3-6 ellipsoids/boxes) x 2048 surface points, "
+                         "K=128, encoder 6-128-256, head 512-512-512-8")
+    if name == "small":
+        scene = I.small_workload()
+        return dict(scene=scene, K=64, widths=I.SMALL_WIDTHS, n_points=1024, n_shapes=160,
+                    desc="80 object pairs (64 three-ellipsoid unions + 16 spheres) x 1024 surface points, "
+                         "K=64, encoder 6-64-128, head 256-256-256-8")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def per_pair_work(K, widths, n_points):
+    """Algorithmic work per pair (fixed 2K encoder rows; padding excluded)."""
+    h1, h2, hh = widths.h1, widths.h2, widths.hh
+    enc_flops = 2 * (2 * K) * (6 * h1 + h1 * h2)
+    head_flops = 2 * (2 * h2 * hh + hh * hh + 8 * hh)
+    crop_bytes = 2 * n_points * 12 + 2 * K * 24 + 2 * 32 + 8 + 8   # scan xyz, gather rows, poses, pair, counts
+    return dict(enc_flops=enc_flops, head_flops=head_flops, crop_bytes=crop_bytes, contact_bytes=32)
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []) + ["locc_internal.h"]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str, workload_name: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and parts[0] in ("source_sha256", "hbm_bytes_per_launch"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_sha256") != source_hash(kernel) or "hbm_bytes_per_launch" not in vals:
+        return None
+    return float(vals["hbm_bytes_per_launch"])
+
+
+# ------------------------------------------------------------------ CPU baseline
+
+_CPU = {}
+
+
+def _cpu_chunk(rows):
+    from threadpoolctl import threadpool_limits
+    from oracle import locc_oracle as O
+    c = _CPU
+    with threadpool_limits(1):
+        O.detect_scene(c["scene"], c["w"], c["widths"], c["K"], rows=rows)
+    return len(rows)
+
+
+def cpu_baseline(scene, w, widths, K, n_pairs):
+    """The oracle on the first n_pairs pairs over a fork pool (one BLAS thread per worker)."""
+    import multiprocessing as mp
+    import numpy as np
+    _CPU.update(scene=scene, w=w, widths=(widths.h1, widths.h2, widths.hh), K=K)
+    n_pairs = min(n_pairs, scene.n_pairs)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    chunks = np.array_split(np.arange(n_pairs), max(workers * 4, 1))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        done = sum(pool.map(_cpu_chunk, chunks))
+    dt = time.perf_counter() - t0
+    return dict(value=done / dt, unit=UNIT, cores=workers, kind="oracle",
+                sample=f"first {done} pairs of the same workload, float64 NumPy oracle (crop + network + "
+                       f"outputs), {workers} worker processes x 1 BLAS thread, {dt:.2f} s wall")
+
+
+# ------------------------------------------------------------------ GPU run
+
+def run(args):
+    import numpy as np
+    from paper_2304_09439_amd import inputs as I
+
+    W = workload(args.workload)
+    scene, K, widths = W["scene"], W["K"], W["widths"]
+    w = I.flatten_weights(I.gaussian_weights(widths, seed=0))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, w, widths, K, args.cpu_pairs)   # before the GPU is touched
+
+    import torch
+    from paper_2304_09439_amd import binding as B
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wd = (widths.h1, widths.h2, widths.hh)
+    ctx = B.context_for_scene(scene, K, wd, w, precision=args.precision)
+    objs, pairs = B.scene_tensors(scene)
+    P = scene.n_pairs
+    out = torch.empty((P, 8), dtype=torch.float32, device="cuda")
+    counts = torch.empty((P, 2), dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.detect(objs, pairs, out, counts)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs", file=sys.stderr,
+          flush=True)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.detect(objs, pairs, out, counts)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    kt = ctx.profile_read()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    n_bad = ctx.device_errors()
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)   # one elementwise kernel: copy_mib read + copy_mib written
+        torch.cuda.synchronize()
+    ctx.close()
+
+    ms_per_step = 1000.0 * wall / args.steps
+    work = per_pair_work(K, widths, W["n_points"])
+    kernels = {}
+    for name, (launches, total_ms) in sorted(kt.items()):
+        avg = total_ms / max(launches, 1)
+        entry = dict(avg_ms=round(avg, 4), launches=int(launches))
+        if name == "crop":
+            achieved = work["crop_bytes"] * P / (avg * 1e-3) / 1e9
+            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+                         frac=round(achieved / PEAK_HBM_GBPS, 4))
+        elif name.startswith("encoder") or name.startswith("head"):
+            flops = work["enc_flops" if name.startswith("encoder") else "head_flops"] * P
+            prec = name.split("_")[-1]
+            achieved = flops / (avg * 1e-3) / 1e12
+            entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
+                         frac=round(achieved / PEAK_TFLOPS[prec], 4))
+        traffic = counter_traffic(name, args.workload)
+        entry["traffic"] = traffic
+        kernels[name] = entry
+    dominant = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    d = kernels[dominant]
+    roofline = dict(kernel=dominant, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
+                    frac=d["frac"], traffic=d["traffic"])
+    line = dict(
+        metric=METRIC, value=round(P / (ms_per_step * 1e-3), 1), unit=UNIT, n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype=args.precision.replace("fp", "f") if args.precision == "fp32" else args.precision,
+        data="synthetic",
+        config=dict(workload=W["desc"], pairs=P, K=K, points_per_shape=W["n_points"], shapes=W["n_shapes"],
+                    precision=args.precision, geometry="f64",
+                    path="per-step: crop, encoder and head kernels on one stream"),
+        p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
+        p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+        roofline=roofline, kernels=kernels, cpu_baseline=cpu, device_errors=int(n_bad),
+    )
+    print(json.dumps(line), flush=True)
+
+
+# ------------------------------------------------------------------ counters
+
+def _counter_means(directory):
+    """{kernel name: mean counter value per dispatch} from rocprofv3 counter CSV files."""
+    import csv
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {directory}")
+    acc = {}
+    for f in files:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Kernel_Name") or row.get("Kernel-Name") or ""
+                val = float(row.get("Counter_Value") or row.get("Counter-Value") or 0.0)
+                disp = row.get("Dispatch_Id") or row.get("Dispatch-Id") or str(len(acc))
+                acc.setdefault(name, {}).setdefault(disp, 0.0)
+                acc[name][disp] += val
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
+def summarize_counters(args):
+    fetch = _counter_means(args.summarize_counters[0])
+    write = _counter_means(args.summarize_counters[1])
+
+    def pick(table, needle):
+        hits = [(k, v) for k, v in table.items() if needle in k]
+        if not hits:
+            raise SystemExit(f"no kernel matching {needle!r}; kernels: {list(table)}")
+        return max(hits, key=lambda kv: kv[1])
+
+    copy_bytes = args.copy_mib * (1 << 20)
+    ck, cf = pick(fetch, args.copy_kernel)
+    _, cw = pick(write, args.copy_kernel)
+    f_scale = copy_bytes / (cf * 1024.0)   # counters are KiB per dispatch
+    w_scale = copy_bytes / (cw * 1024.0)
+    kk, kf = pick(fetch, args.kernel_match)
+    _, kw = pick(write, args.kernel_match)
+    fetch_b = kf * 1024.0 * f_scale
+    write_b = kw * 1024.0 * w_scale
+    print(f"kernel {args.kernel} ({kk})")
+    print(f"source_sha256 {source_hash(args.kernel)}")
+    print(f"copy_kernel {ck} copy_bytes {copy_bytes}")
+    print(f"fetch_scale {f_scale:.4f} write_scale {w_scale:.4f}")
+    print(f"fetch_kib_per_dispatch {kf:.1f} write_kib_per_dispatch {kw:.1f}")
+    print(f"hbm_bytes_per_launch {fetch_b + write_b:.0f}")
+    print(f"hbm_fetch_bytes_per_launch {fetch_b:.0f} hbm_write_bytes_per_launch {write_b:.0f}")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="scale", choices=["scale", "small"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pairs", type=int, default=16384)
+    ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--kernel", default="encoder_fp32")
+    ap.add_argument("--kernel-match", default="encoder_fp32_kernel")
+    ap.add_argument("--copy-kernel", default="neg_kernel")
+    args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(args)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the LOCC path has no "
+              f"multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only; launch it without a multi-rank launcher", file=sys.stderr)
+        sys.exit(2)
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

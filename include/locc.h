@@ -168,6 +168,26 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
                                int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, float* d_z, float* d_y,
                                void* stream);
 
+/* Per-kernel timing.  While enabled, every kernel the context launches is
+ * bracketed by two HIP events recorded on its launch stream; reading
+ * synchronises on the recorded events and returns, per kernel name, the
+ * number of launches and their summed duration in milliseconds (the same
+ * per-dispatch durations a kernel-trace profiler reports, plus event
+ * overhead).  locc_profile(ctx, 1) clears the totals and starts recording,
+ * locc_profile(ctx, 0) stops.  Kernel names: "crop", "encoder_fp32",
+ * "head_fp32" (and the names of kernels added later). */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} locc_kernel_time;
+
+LOCC_API locc_status locc_profile(locc_ctx* ctx, int enable);
+
+/* Copies up to `capacity` entries into h_out (host) and sets *h_count to the
+ * number of kernels seen.  Errors: INVALID_ARG, HIP. */
+LOCC_API locc_status locc_profile_read(locc_ctx* ctx, locc_kernel_time* h_out, int32_t capacity, int32_t* h_count);
+
 /* Number of invalid pairs seen by all detect calls since the last reset;
  * synchronises `stream`.  reset != 0 clears the counter afterwards. */
 LOCC_API locc_status locc_device_errors(locc_ctx* ctx, void* stream, int64_t* h_n_bad, int reset);

@@ -22,13 +22,18 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_READY
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
-           "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors")
+           "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
+           "locc_profile", "locc_profile_read")
 
 
 class Config(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("enc_h1", ctypes.c_int32), ("enc_h2", ctypes.c_int32),
                 ("head_h", ctypes.c_int32), ("pad_m", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
 class LoccError(RuntimeError):
@@ -69,6 +74,10 @@ def load() -> ctypes.CDLL:
     L.locc_debug_forward.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
     L.locc_device_errors.restype = ctypes.c_int
     L.locc_device_errors.argtypes = [vp, vp, i64p, ctypes.c_int]
+    L.locc_profile.restype = ctypes.c_int
+    L.locc_profile.argtypes = [vp, ctypes.c_int]
+    L.locc_profile_read.restype = ctypes.c_int
+    L.locc_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(ctypes.c_int32)]
     _lib = L
     return L
 
@@ -195,6 +204,18 @@ class Context:
         _check(load().locc_debug_forward(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
                                          _ptr(z), _ptr(y), self._stream(stream)))
         return out, counts, z, y
+
+    def profile(self, enable: bool):
+        """Start (clearing totals) or stop per-kernel event timing."""
+        _check(load().locc_profile(self._h, int(enable)))
+
+    def profile_read(self) -> dict:
+        """{kernel name: (launches, total_ms)} recorded while profiling was on."""
+        cap = 32
+        buf = (KernelTime * cap)()
+        n = ctypes.c_int32()
+        _check(load().locc_profile_read(self._h, buf, cap, ctypes.byref(n)))
+        return {buf[k].name.decode(): (buf[k].launches, buf[k].total_ms) for k in range(min(n.value, cap))}
 
     def device_errors(self, reset: bool = False, stream=None) -> int:
         n = ctypes.c_int64()

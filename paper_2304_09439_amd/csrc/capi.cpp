@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,15 @@ struct locc_ctx {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   unsigned long long* d_err = nullptr;
+  // event timing of each launch (locc_profile)
+  struct Pending {
+    std::string name;
+    hipEvent_t start, stop;
+  };
+  bool profiling = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, std::pair<int64_t, double>> totals;
 
   DeviceLibrary lib() const {
     const float* b = d_points;
@@ -71,6 +81,49 @@ struct locc_ctx {
 };
 
 namespace {
+
+hipError_t take_event(locc_ctx* c, hipEvent_t* e) {
+  if (!c->event_pool.empty()) {
+    *e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Launch `launch()` on stream s, bracketed by events while profiling is on.
+template <class F>
+hipError_t timed(locc_ctx* c, const char* name, hipStream_t s, F&& launch) {
+  if (!c->profiling) return launch();
+  locc_ctx::Pending pd{name, nullptr, nullptr};
+  hipError_t e = take_event(c, &pd.start);
+  if (e == hipSuccess) e = take_event(c, &pd.stop);
+  if (e == hipSuccess) e = hipEventRecord(pd.start, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(pd.stop, s);
+  if (e != hipSuccess) return e;
+  c->pending.push_back(pd);
+  return hipSuccess;
+}
+
+hipError_t drain_profile(locc_ctx* c) {
+  for (auto& pd : c->pending) {
+    hipError_t e = hipEventSynchronize(pd.stop);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pd.start, pd.stop);
+    if (e != hipSuccess) return e;
+    auto& t = c->totals[pd.name];
+    t.first += 1;
+    t.second += ms;
+    c->event_pool.push_back(pd.start);
+    c->event_pool.push_back(pd.stop);
+  }
+  c->pending.clear();
+  return hipSuccess;
+}
 
 locc_status ensure_workspace(locc_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return LOCC_OK;
@@ -126,11 +179,11 @@ locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const
   HIP_TRY(hipSetDevice(c->device));
   CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
               nullptr, counts, w.meta, w.rows, c->d_err};
-  HIP_TRY(launch_crop(ca, s));
+  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
   const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
   NetArgs na{w.rows, w.meta, objs, n_pairs, c->cfg.K, z_out ? z_out : w.z, y_out, out};
-  HIP_TRY(launch_encoder_fp32(net, na, c->n_cu, s));
-  HIP_TRY(launch_head_fp32(net, na, s));
+  HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+  HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
   return LOCC_OK;
 }
 
@@ -180,6 +233,8 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
 void locc_destroy(locc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  (void)drain_profile(c);
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   (void)hipFree(c->d_shapes);
   (void)hipFree(c->d_points);
   (void)hipFree(c->d_wfp32);
@@ -295,7 +350,37 @@ locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs
   HIP_TRY(hipSetDevice(c->device));
   CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
               idx, counts, nullptr, nullptr, c->d_err};
-  HIP_TRY(launch_crop(ca, static_cast<hipStream_t>(stream)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
+  return LOCC_OK;
+}
+
+locc_status locc_profile(locc_ctx* c, int enable) {
+  if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(drain_profile(c));
+  if (enable) c->totals.clear();
+  c->profiling = enable != 0;
+  return LOCC_OK;
+}
+
+locc_status locc_profile_read(locc_ctx* c, locc_kernel_time* out, int32_t capacity, int32_t* count) {
+  if (!c || !count || capacity < 0 || (capacity > 0 && !out))
+    return fail(LOCC_ERR_INVALID_ARG, "null context, output or count");
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(drain_profile(c));
+  int32_t n = 0;
+  for (const auto& kv : c->totals) {
+    if (n < capacity) {
+      locc_kernel_time& t = out[n];
+      std::memset(&t, 0, sizeof t);
+      std::snprintf(t.name, sizeof t.name, "%s", kv.first.c_str());
+      t.launches = kv.second.first;
+      t.total_ms = kv.second.second;
+    }
+    ++n;
+  }
+  *count = n;
   return LOCC_OK;
 }
 
