@@ -64,7 +64,9 @@ typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2 } locc_precision;
  *   head_h  head hidden width; the head input is 2 * enc_h2
  *   pad_m   crop margin added to every face of the box, metres (>= 0)
  *   precision  arithmetic of the encoder and head (locc_precision);
- *              the crop geometry is float64 in every precision
+ *              the crop geometry is float64 in every precision.
+ *              LOCC_FP32 runs the per-step path (crop, encoder, head
+ *              kernels); LOCC_BF16 runs one fused persistent kernel
  * Compiled width sets: (h1, h2, hh) = (64, 128, 256) and (128, 256, 512). */
 typedef struct {
   int32_t K;
@@ -168,6 +170,23 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
                                int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, float* d_z, float* d_y,
                                void* stream);
 
+/* Work schedule of the fused persistent kernel (BF16 / FP8 contexts):
+ *   wg_per_cu  workgroups per compute unit (1 .. 2); grid = CUs x wg_per_cu
+ *   claim      pairs a workgroup takes from the queue at a time (1 .. 64)
+ *   dynamic    1: pairs are claimed from a device-side atomic queue;
+ *              0: static round robin (workgroup w takes claims w, w + grid, ...)
+ * Results do not depend on the schedule: every pair is computed on its own.
+ * Errors: INVALID_ARG (null, out of range). */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t claim;
+  int32_t dynamic;
+  int32_t reserved; /* must be 0 */
+} locc_schedule;
+
+LOCC_API locc_status locc_set_schedule(locc_ctx* ctx, const locc_schedule* sched);
+LOCC_API locc_status locc_get_schedule(const locc_ctx* ctx, locc_schedule* sched);
+
 /* Per-kernel timing.  While enabled, every kernel the context launches is
  * bracketed by two HIP events recorded on its launch stream; reading
  * synchronises on the recorded events and returns, per kernel name, the
@@ -175,7 +194,7 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
  * per-dispatch durations a kernel-trace profiler reports, plus event
  * overhead).  locc_profile(ctx, 1) clears the totals and starts recording,
  * locc_profile(ctx, 0) stops.  Kernel names: "crop", "encoder_fp32",
- * "head_fp32" (and the names of kernels added later). */
+ * "head_fp32" (FP32 per-step path), "fused_bf16" (BF16 fused path). */
 typedef struct {
   char name[32];
   int64_t launches;

@@ -23,12 +23,17 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
            "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
-           "locc_profile", "locc_profile_read")
+           "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule")
 
 
 class Config(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("enc_h1", ctypes.c_int32), ("enc_h2", ctypes.c_int32),
                 ("head_h", ctypes.c_int32), ("pad_m", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("wg_per_cu", ctypes.c_int32), ("claim", ctypes.c_int32), ("dynamic", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
 
 
@@ -78,6 +83,10 @@ def load() -> ctypes.CDLL:
     L.locc_profile.argtypes = [vp, ctypes.c_int]
     L.locc_profile_read.restype = ctypes.c_int
     L.locc_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(ctypes.c_int32)]
+    L.locc_set_schedule.restype = ctypes.c_int
+    L.locc_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    L.locc_get_schedule.restype = ctypes.c_int
+    L.locc_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     _lib = L
     return L
 
@@ -204,6 +213,15 @@ class Context:
         _check(load().locc_debug_forward(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
                                          _ptr(z), _ptr(y), self._stream(stream)))
         return out, counts, z, y
+
+    def set_schedule(self, wg_per_cu: int = 2, claim: int = 1, dynamic: bool = True):
+        sc = Schedule(wg_per_cu, claim, int(dynamic), 0)
+        _check(load().locc_set_schedule(self._h, ctypes.byref(sc)))
+
+    def get_schedule(self) -> dict:
+        sc = Schedule()
+        _check(load().locc_get_schedule(self._h, ctypes.byref(sc)))
+        return dict(wg_per_cu=sc.wg_per_cu, claim=sc.claim, dynamic=bool(sc.dynamic))
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "fused.h"
 #include "locc_internal.h"
 
 using namespace locc;
@@ -58,7 +59,11 @@ struct locc_ctx {
   float* d_points = nullptr;  // SoA: x, y, z, nx, ny, nz, each n_points floats
   // weights
   float* d_wfp32 = nullptr;
+  unsigned char* d_wbf16 = nullptr;
   bool have_weights = false;
+  // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
+  locc_schedule sched{kFusedWgPerCu, 1, 1, 0};
+  unsigned int* d_queue = nullptr;
   // workspace
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -169,14 +174,50 @@ locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, con
   return LOCC_OK;
 }
 
+int fused_grid(const locc_ctx* c, int n_pairs) {
+  const int claim = c->sched.claim;
+  const int tiles = (n_pairs + claim - 1) / claim;
+  const int grid = c->n_cu * c->sched.wg_per_cu;
+  return tiles < grid ? tiles : grid;
+}
+
+locc_status run_fused(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
+                      locc_contact* out, int32_t* counts, float* z_out, float* y_out, hipStream_t s) {
+  FusedArgs fa{};
+  fa.objs = objs;
+  fa.n_objs = n_objs;
+  fa.pairs = pairs;
+  fa.n_pairs = n_pairs;
+  fa.lib = c->lib();
+  fa.K = c->cfg.K;
+  fa.pad = c->cfg.pad_m;
+  bf16_bind(fa, c->d_wbf16, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
+  fa.out = out;
+  fa.counts = counts;
+  fa.z_dbg = z_out;
+  fa.y_dbg = y_out;
+  fa.err_counter = c->d_err;
+  fa.queue = c->d_queue;
+  fa.claim = c->sched.claim;
+  fa.dynamic = c->sched.dynamic;
+  const int grid = fused_grid(c, n_pairs);
+  HIP_TRY(timed(c, "fused_bf16", s, [&] {
+    return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, s);
+  }));
+  return LOCC_OK;
+}
+
 locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
                      int32_t n_pairs, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
                      hipStream_t s) {
   if (n_pairs == 0) return LOCC_OK;
   Workspace w{};
-  locc_status st = carve(c, n_pairs, &w);
-  if (st != LOCC_OK) return st;
+  if (c->cfg.precision == LOCC_FP32) {
+    locc_status st = carve(c, n_pairs, &w);
+    if (st != LOCC_OK) return st;
+  }
   HIP_TRY(hipSetDevice(c->device));
+  if (c->cfg.precision == LOCC_BF16) return run_fused(c, objs, n_objs, pairs, n_pairs, out, counts, z_out, y_out, s);
   CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
               nullptr, counts, w.meta, w.rows, c->d_err};
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
@@ -208,7 +249,7 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (!widths_supported(cfg->enc_h1, cfg->enc_h2, cfg->head_h))
     return fail(LOCC_ERR_UNSUPPORTED, "widths (%d, %d, %d) not compiled in", cfg->enc_h1, cfg->enc_h2,
                 cfg->head_h);
-  if (cfg->precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "precision %d not available", cfg->precision);
+  if (cfg->precision == LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "precision %d not available", cfg->precision);
   if (device < 0) return fail(LOCC_ERR_INVALID_ARG, "device %d", device);
   int n_dev = 0;
   HIP_TRY(hipGetDeviceCount(&n_dev));
@@ -222,6 +263,9 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   c->n_cu = n_cu;
   hipError_t e = hipMalloc(&c->d_err, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&c->d_queue, 2 * sizeof(unsigned int));
+  if (e == hipSuccess) e = hipMemset(c->d_queue, 0, 2 * sizeof(unsigned int));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     locc_destroy(c);
     return fail(LOCC_ERR_HIP, "error counter: %s", hipGetErrorString(e));
@@ -238,6 +282,8 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_shapes);
   (void)hipFree(c->d_points);
   (void)hipFree(c->d_wfp32);
+  (void)hipFree(c->d_wbf16);
+  (void)hipFree(c->d_queue);
   (void)hipFree(c->d_ws);
   (void)hipFree(c->d_err);
   delete c;
@@ -265,6 +311,13 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   HIP_TRY(hipSetDevice(c->device));
   if (!c->d_wfp32) HIP_TRY(hipMalloc(&c->d_wfp32, pack.size() * sizeof(float)));
   HIP_TRY(hipMemcpy(c->d_wfp32, pack.data(), pack.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (c->cfg.precision == LOCC_BF16) {
+    const Bf16Layout L = bf16_layout(h1, h2, hh);
+    std::vector<unsigned char> bpack(L.total);
+    bf16_pack(W1, b1, W2, b2, H1, c1, H2, c2, H3, c3, h1, h2, hh, bpack.data());
+    if (!c->d_wbf16) HIP_TRY(hipMalloc(&c->d_wbf16, L.total));
+    HIP_TRY(hipMemcpy(c->d_wbf16, bpack.data(), L.total, hipMemcpyHostToDevice));
+  }
   c->have_weights = true;
   return LOCC_OK;
 }
@@ -352,6 +405,23 @@ locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs
               idx, counts, nullptr, nullptr, c->d_err};
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
+  return LOCC_OK;
+}
+
+locc_status locc_set_schedule(locc_ctx* c, const locc_schedule* sc) {
+  if (!c || !sc) return fail(LOCC_ERR_INVALID_ARG, "null context or schedule");
+  if (sc->wg_per_cu < 1 || sc->wg_per_cu > kFusedWgPerCu)
+    return fail(LOCC_ERR_INVALID_ARG, "wg_per_cu=%d: must be 1..%d", sc->wg_per_cu, kFusedWgPerCu);
+  if (sc->claim < 1 || sc->claim > 64) return fail(LOCC_ERR_INVALID_ARG, "claim=%d: must be 1..64", sc->claim);
+  if (sc->dynamic != 0 && sc->dynamic != 1) return fail(LOCC_ERR_INVALID_ARG, "dynamic must be 0 or 1");
+  if (sc->reserved != 0) return fail(LOCC_ERR_INVALID_ARG, "reserved field must be 0");
+  c->sched = *sc;
+  return LOCC_OK;
+}
+
+locc_status locc_get_schedule(const locc_ctx* c, locc_schedule* sc) {
+  if (!c || !sc) return fail(LOCC_ERR_INVALID_ARG, "null context or schedule");
+  *sc = c->sched;
   return LOCC_OK;
 }
 

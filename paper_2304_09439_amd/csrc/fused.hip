@@ -1,0 +1,435 @@
+// Fused persistent kernel of the LOCC path in BF16: crop, encoder, head and
+// world mapping for all pairs in one launch.
+//
+// Each workgroup (4 wave64) claims pairs from a device queue (or a static
+// round robin).  For every claimed pair it runs the float64 crop of
+// geometry.h (scan, ordered first-K selection), gathers the encoder rows into
+// LDS as bf16, and runs the per-point encoder with a per-object max-pool
+// (Sec. III: per-point MLP features, max-pooled; appendix: ReLU on every
+// layer).  The pooled features [f_a, f_b] go into an LDS tile; every 32
+// pairs (and once at the end) the head MLP runs on the tile (appendix: MLP
+// predictor ending in a linear layer) and the contacts are written.
+//
+// Matrix cores: v_mfma_f32_32x32x8_bf16 for encoder layer 1 (inputs x, y, z,
+// nx, ny, nz, 1, 0: the bias rides in the 7th input), v_mfma_f32_32x32x16_bf16
+// for encoder layer 2 and the head, FP32 accumulation.  Lane layouts (wave64):
+//   A[i][k]: i = l % 32, k = (K/2) (l / 32) + e;  B[k][j]: j = l % 32, same k;
+//   D[i][j]: j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4 for register r.
+// Encoder layer 1 is computed transposed (features x points), so each lane
+// holds 16 features of one point per 32-feature tile; those registers are
+// layer 2's A operand once layer 2's reduction index is permuted to
+// F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4 (the host packs W2 so).
+// Wave w owns h2/4 encoder output columns; its W2 slice (64 VGPRs at h2 =
+// 256) is loaded once and stays in registers for the whole kernel.
+//
+// The queue is self-cleaning: the last workgroup to finish resets it, so
+// consecutive launches (and graph replays) need no memset.
+#include "fused.h"
+#include "geometry.h"
+
+#include <cstring>
+
+namespace locc {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  const __bf16 h = (__bf16)f;  // round to nearest even
+  return __builtin_bit_cast(unsigned short, h);
+}
+
+__device__ __forceinline__ f32x16 mfma_k8(s16x4 a, s16x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma_k16(u16x8 a, u16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+template <int H1, int H2, int HH>
+struct Smem {
+  static constexpr int T = kFusedTile;
+  static constexpr int ZS = (2 * H2 > HH ? 2 * H2 : HH) + 8;  // row stride (bf16) of the z / g2 tile
+  static constexpr int GS = HH + 8;                           // row stride of the g1 tile
+  union {
+    struct {
+      CropShared crop;
+      unsigned short rows[2 * kMaxK * 8];  // encoder rows (x, y, z, nx, ny, nz, 1, 0), bf16
+    } c;
+    unsigned short g[T * GS];
+  } u;
+  unsigned short z[T * ZS];
+  float y[4][T][8];
+  int32_t pair[T];
+  int32_t a[T];
+  int32_t swapped[T];
+  int32_t claim;
+};
+
+// One head layer on the tile: dst = ReLU(src W^T + bias), bf16 in / out.
+// Wave w computes output column tiles [w CTH, (w+1) CTH); B fragments stream
+// from global memory (L2) one k-step ahead.
+template <int KDIM, int SS, int DS, int CTH>
+__device__ __forceinline__ void head_layer(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
+                                           const unsigned short* src, unsigned short* dst) {
+  constexpr int KS = KDIM / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
+  const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
+  const unsigned short* arow = src + l32 * SS + 8 * g;
+  f32x16 acc[CTH];
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) acc[c] = f32x16{};
+  u16x8 bcur[CTH];
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) bcur[c] = bp[(size_t)c * KS * 64];
+#pragma unroll 1
+  for (int s = 0; s < KS; ++s) {
+    u16x8 bnext[CTH];
+    const int sn = s + 1 < KS ? s + 1 : s;
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bnext[c] = bp[((size_t)c * KS + sn) * 64];
+    const u16x8 av = *reinterpret_cast<const u16x8*>(arow + 16 * s);
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) acc[c] = mfma_k16(av, bcur[c], acc[c]);
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bcur[c] = bnext[c];
+  }
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) {
+    const int col = (wave * CTH + c) * 32 + l32;
+    const float bc = bias[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * g + (r & 3);
+      dst[row * DS + col] = bf16_bits(fmaxf(acc[c][r] + bc, 0.f));
+    }
+  }
+}
+
+// Head on the first n rows of the z tile, then the world-frame epilogue.
+template <int H1, int H2, int HH>
+__device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& S, int n) {
+  using S_t = Smem<H1, H2, HH>;
+  constexpr int T = S_t::T, ZS = S_t::ZS, GS = S_t::GS, CTH = HH / 128, KS3 = HH / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  for (int e = tid; e < (T - n) * ZS; e += 256) S.z[n * ZS + e] = 0;
+  __syncthreads();
+  head_layer<2 * H2, ZS, GS, CTH>(A.h1p, A.c1, S.z, S.u.g);
+  __syncthreads();
+  head_layer<HH, GS, ZS, CTH>(A.h2p, A.c2, S.u.g, S.z);
+  __syncthreads();
+  // layer 3 (8 outputs, padded to 32 columns), reduction split over the 4 waves
+  {
+    f32x16 acc = f32x16{};
+    const u16x8* bp = reinterpret_cast<const u16x8*>(A.h3p) + lane;
+    const unsigned short* arow = S.z + l32 * ZS + 8 * g;
+#pragma unroll
+    for (int s = wave * (KS3 / 4); s < (wave + 1) * (KS3 / 4); ++s)
+      acc = mfma_k16(*reinterpret_cast<const u16x8*>(arow + 16 * s), bp[(size_t)s * 64], acc);
+    if (l32 < 8)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S.y[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
+  }
+  __syncthreads();
+  for (int t = tid; t < T * 8; t += 256) {
+    const int i = t >> 3, j = t & 7;
+    S.y[0][i][j] = ((S.y[0][i][j] + S.y[1][i][j]) + S.y[2][i][j]) + S.y[3][i][j] + A.c3[j];
+  }
+  __syncthreads();
+  if (tid < n) {
+    const int p = S.pair[tid];
+    const int a = S.a[tid];
+    const float* y = S.y[0][tid];
+    float out[8];
+    if (a < 0) {
+      for (int k = 0; k < 8; ++k) out[k] = __builtin_nanf("");
+    } else {
+      const locc_object o = A.objs[a];
+      const double w = o.q[0], x = o.q[1], yq = o.q[2], zq = o.q[3];
+      const double R[9] = {1.0 - 2.0 * (yq * yq + zq * zq), 2.0 * (x * yq - w * zq), 2.0 * (x * zq + w * yq),
+                           2.0 * (x * yq + w * zq), 1.0 - 2.0 * (x * x + zq * zq), 2.0 * (yq * zq - w * x),
+                           2.0 * (x * zq - w * yq), 2.0 * (yq * zq + w * x), 1.0 - 2.0 * (x * x + yq * yq)};
+      const double sg = S.swapped[tid] ? -1.0 : 1.0;
+      out[0] = y[0];
+      for (int r = 0; r < 3; ++r) {
+        out[1 + r] = (float)(R[3 * r] * y[1] + R[3 * r + 1] * y[2] + R[3 * r + 2] * y[3] + (double)o.p[r]);
+        out[4 + r] = (float)(sg * (R[3 * r] * y[4] + R[3 * r + 1] * y[5] + R[3 * r + 2] * y[6]));
+      }
+      out[7] = y[7];
+    }
+    float4* dst = reinterpret_cast<float4*>(A.out + p);
+    dst[0] = make_float4(out[0], out[1], out[2], out[3]);
+    dst[1] = make_float4(out[4], out[5], out[6], out[7]);
+    if (A.y_dbg) {
+      float4* yd = reinterpret_cast<float4*>(A.y_dbg + (size_t)p * 8);
+      const float nan = __builtin_nanf("");
+      yd[0] = a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[0], y[1], y[2], y[3]);
+      yd[1] = a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[4], y[5], y[6], y[7]);
+    }
+  }
+  __syncthreads();
+}
+
+template <int H1, int H2, int HH>
+__global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArgs A) {
+  using S_t = Smem<H1, H2, HH>;
+  constexpr int T = S_t::T, ZS = S_t::ZS;
+  constexpr int FT = H1 / 32;    // layer-1 feature tiles
+  constexpr int KS2 = H1 / 16;   // layer-2 k-steps
+  constexpr int CT = H2 / 128;   // encoder column tiles per wave
+  static_assert(H1 % 32 == 0 && H2 % 128 == 0 && HH % 128 == 0, "widths");
+  __shared__ S_t S;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 5;
+  const int l32 = lane & 31;
+  const int K = A.K;
+  const int P = A.n_pairs;
+
+  // this wave's W2 slice, layer-1 weights and layer-2 bias stay in registers
+  u16x8 w2f[CT][KS2];
+  float bias2[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+    for (int s = 0; s < KS2; ++s)
+      w2f[ct][s] = reinterpret_cast<const u16x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
+    bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
+  }
+  s16x4 w1f[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) w1f[ft] = reinterpret_cast<const s16x4*>(A.w1p)[(size_t)ft * 64 + lane];
+
+  int slot = 0;
+  for (int iter = 0;; ++iter) {
+    if (tid == 0)
+      S.claim = A.dynamic ? (int)atomicAdd(A.queue, (unsigned)A.claim) : (blockIdx.x + iter * gridDim.x) * A.claim;
+    __syncthreads();
+    const int base = S.claim;
+    __syncthreads();  // S.claim is rewritten by the next claim
+    if (base >= P) break;
+    const int n_claim = P - base < A.claim ? P - base : A.claim;
+
+    for (int c = 0; c < n_claim; ++c) {
+      const int p = base + c;
+      // ---------------------------------------------------------------- crop
+      int a = -1, swapped = 0;
+      locc_object oa, ob;
+      ShapeDesc da, db;
+      const bool valid = geo_fetch(A.objs, A.n_objs, A.pairs, p, A.lib, a, swapped, oa, ob, da, db);
+      int m_a = 0, m_b = 0;
+      if (valid) {  // uniform over the workgroup
+        PairGeom gm;
+        geo_pair(oa, ob, da, db, A.pad, gm);
+        geo_scan_select(gm, da, db, A.lib, K, S.u.c.crop);
+        const int n_a = S.u.c.crop.count[0], n_b = S.u.c.crop.count[1];
+        m_a = n_a < K ? n_a : K;
+        m_b = n_b < K ? n_b : K;
+        if (tid == 0 && A.counts) {
+          A.counts[2 * p + swapped] = n_a;
+          A.counts[2 * p + 1 - swapped] = n_b;
+        }
+        // gather rows, zero-padded to the next multiple of 32 per object
+        const int ra = (m_a + 31) & ~31, rb = (m_b + 31) & ~31;
+        for (int e = tid; e < ra + rb; e += 256) {
+          const int s = e >= ra;
+          const int r = s ? e - ra : e;
+          const int m = s ? m_b : m_a;
+          u16x8 row = {0, 0, 0, 0, 0, 0, 0, 0};
+          if (r < m) {
+            float v[6];
+            geo_row(gm, A.lib, (s ? db : da).off + S.u.c.crop.sel[s][r], s, v);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) row[k] = bf16_bits(v[k]);
+            row[6] = 0x3f80;  // 1.0
+          }
+          *reinterpret_cast<u16x8*>(&S.u.c.rows[(s * K + r) * 8]) = row;
+        }
+      } else if (tid == 0) {
+        if (A.counts) {
+          A.counts[2 * p] = -1;
+          A.counts[2 * p + 1] = -1;
+        }
+        atomicAdd(A.err_counter, 1ull);
+      }
+      if (tid == 0) {
+        S.pair[slot] = p;
+        S.a[slot] = valid ? a : -1;
+        S.swapped[slot] = swapped;
+      }
+      __syncthreads();
+
+      // ------------------------------------------------------------- encoder
+      for (int side = 0; side < 2; ++side) {
+        const int m = side ? m_b : m_a;
+        float run[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) run[ct] = 0.f;
+        for (int r0 = 0; r0 < m; r0 += 32) {
+          const s16x4 xb = *reinterpret_cast<const s16x4*>(&S.u.c.rows[(side * K + r0 + l32) * 8 + 4 * g]);
+          f32x16 acc2[CT];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
+          // layer-1 tiles one at a time (the next one issued a step ahead) keep
+          // only two 32x32 layer-1 accumulators live
+          f32x16 acc1 = mfma_k8(w1f[0], xb, f32x16{});
+#pragma unroll
+          for (int ft = 0; ft < FT; ++ft) {
+            f32x16 acc1n = acc1;
+            if (ft + 1 < FT) acc1n = mfma_k8(w1f[ft + 1 < FT ? ft + 1 : ft], xb, f32x16{});
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+              u16x8 av;
+#pragma unroll
+              for (int e = 0; e < 8; ++e) av[e] = bf16_bits(fmaxf(acc1[8 * hf + e], 0.f));
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av, w2f[ct][2 * ft + hf], acc2[ct]);
+            }
+            acc1 = acc1n;
+          }
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+              const float v = fmaxf(acc2[ct][r] + bias2[ct], 0.f);
+              if (row < m) run[ct] = fmaxf(run[ct], v);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          run[ct] = fmaxf(run[ct], __shfl_xor(run[ct], 32, 64));
+          if (lane < 32) {
+            const int col = side * H2 + (wave * CT + ct) * 32 + lane;
+            S.z[slot * ZS + col] = bf16_bits(run[ct]);
+            if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? run[ct] : __builtin_nanf("");
+          }
+        }
+      }
+      ++slot;
+      __syncthreads();  // rows and crop scratch are reused by the next pair
+      if (slot == T) {
+        head_tile<H1, H2, HH>(A, S, T);
+        slot = 0;
+      }
+    }
+  }
+  if (slot > 0) head_tile<H1, H2, HH>(A, S, slot);
+
+  if (A.dynamic && tid == 0) {
+    __threadfence();
+    if (atomicAdd(A.queue + 1, 1u) == gridDim.x - 1) {  // last workgroup out resets the queue
+      atomicExch(A.queue, 0u);
+      atomicExch(A.queue + 1, 0u);
+    }
+  }
+}
+
+template <int H1, int H2, int HH>
+hipError_t run_fused(const FusedArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- host packing
+unsigned short host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);  // quiet NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) + 4 * g + r % 4; }
+
+}  // namespace
+
+Bf16Layout bf16_layout(int h1, int h2, int hh) {
+  Bf16Layout L{};
+  size_t o = 0;
+  L.w1 = o; o = align256(o + (size_t)h1 * 8 * 2);
+  L.w2 = o; o = align256(o + (size_t)h2 * h1 * 2);
+  L.b2 = o; o = align256(o + (size_t)h2 * 4);
+  L.h1 = o; o = align256(o + (size_t)hh * 2 * h2 * 2);
+  L.c1 = o; o = align256(o + (size_t)hh * 4);
+  L.h2 = o; o = align256(o + (size_t)hh * hh * 2);
+  L.c2 = o; o = align256(o + (size_t)hh * 4);
+  L.h3 = o; o = align256(o + (size_t)32 * hh * 2);
+  L.c3 = o; o = align256(o + 8 * 4);
+  L.total = o;
+  return L;
+}
+
+void bf16_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
+               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
+               int h2, int hh, unsigned char* dst) {
+  const Bf16Layout L = bf16_layout(h1, h2, hh);
+  std::memset(dst, 0, L.total);
+  auto u16 = [&](size_t off) { return reinterpret_cast<unsigned short*>(dst + off); };
+  auto f32 = [&](size_t off) { return reinterpret_cast<float*>(dst + off); };
+  // encoder layer 1, A operand of 32x32x8: [W1 | b1 | 0][32 ft + l % 32][4 (l / 32) + e]
+  for (int ft = 0; ft < h1 / 32; ++ft)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 4; ++e) {
+        const int f = 32 * ft + l % 32, c = 4 * (l / 32) + e;
+        u16(L.w1)[((size_t)ft * 64 + l) * 4 + e] = host_bf16(c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f));
+      }
+  // encoder layer 2, B operand of 32x32x16, reduction index permuted to layer 1's output layout
+  const int CT = h2 / 128, KS2 = h1 / 16;
+  for (int w = 0; w < 4; ++w)
+    for (int ct = 0; ct < CT; ++ct)
+      for (int s = 0; s < KS2; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int col = (w * CT + ct) * 32 + l % 32;
+            const int f = perm_feature(s / 2, l / 32, 8 * (s % 2) + e);
+            u16(L.w2)[(((size_t)(w * CT + ct) * KS2 + s) * 64 + l) * 8 + e] = host_bf16(W2[(size_t)col * h1 + f]);
+          }
+  std::memcpy(f32(L.b2), b2, sizeof(float) * h2);
+  // head layers, B operand of 32x32x16: lane l holds H[32 ct + l % 32][16 s + 8 (l / 32) + e]
+  auto pack_head = [&](const float* H, int in, int out, int out_pad, size_t at) {
+    const int ks = in / 16;
+    for (int ct = 0; ct < out_pad / 32; ++ct)
+      for (int s = 0; s < ks; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 8; ++e) {
+            const int row = 32 * ct + l % 32;
+            const float v = row < out ? H[(size_t)row * in + 16 * s + 8 * (l / 32) + e] : 0.f;
+            u16(at)[(((size_t)ct * ks + s) * 64 + l) * 8 + e] = host_bf16(v);
+          }
+  };
+  pack_head(H1, 2 * h2, hh, hh, L.h1);
+  std::memcpy(f32(L.c1), c1, sizeof(float) * hh);
+  pack_head(H2, hh, hh, hh, L.h2);
+  std::memcpy(f32(L.c2), c2, sizeof(float) * hh);
+  pack_head(H3, hh, 8, 32, L.h3);
+  std::memcpy(f32(L.c3), c3, sizeof(float) * 8);
+}
+
+void bf16_bind(FusedArgs& a, const unsigned char* base, int h1, int h2, int hh) {
+  const Bf16Layout L = bf16_layout(h1, h2, hh);
+  a.w1p = reinterpret_cast<const unsigned short*>(base + L.w1);
+  a.w2p = reinterpret_cast<const unsigned short*>(base + L.w2);
+  a.b2 = reinterpret_cast<const float*>(base + L.b2);
+  a.h1p = reinterpret_cast<const unsigned short*>(base + L.h1);
+  a.c1 = reinterpret_cast<const float*>(base + L.c1);
+  a.h2p = reinterpret_cast<const unsigned short*>(base + L.h2);
+  a.c2 = reinterpret_cast<const float*>(base + L.c2);
+  a.h3p = reinterpret_cast<const unsigned short*>(base + L.h3);
+  a.c3 = reinterpret_cast<const float*>(base + L.c3);
+}
+
+hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (h1 == 64 && h2 == 128 && hh == 256) return run_fused<64, 128, 256>(a, grid, s);
+  if (h1 == 128 && h2 == 256 && hh == 512) return run_fused<128, 256, 512>(a, grid, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace locc

@@ -1,0 +1,222 @@
+// Device-side crop geometry shared by the crop kernel and the fused kernel.
+//
+// The paper keeps, for each object of a pair, the parts that lie in the
+// other object's box widened by a margin so that nothing in contact is
+// missed (Sec. III, appendix "Architecture Details").  In the frame of
+// a = min(i, j) the box used here is
+//   (AABB_a  intersect  axis-aligned hull of T_ab AABB_b) widened by pad,
+// and the first K stored points of each object inside it are kept.
+//
+// Everything is float64 with contraction disabled, evaluated in exactly this
+// order (so the selected index sets are reproducible bit for bit):
+//   R from quaternion (w,x,y,z): diag 1 - 2(s + t), off-diagonal 2(u -+ v)
+//   R_ab[i][j] = (Ra[0][i] Rb[0][j] + Ra[1][i] Rb[1][j]) + Ra[2][i] Rb[2][j]
+//   t_ab[i]    = (Ra[0][i] d0 + Ra[1][i] d1) + Ra[2][i] d2,  d = t_b - t_a
+//   c'_i = ((R[i][0] c0 + R[i][1] c1) + R[i][2] c2) + t_i,
+//   e'_i = (|R[i][0]| e0 + |R[i][1]| e1) + |R[i][2]| e2
+//   lo_i = max(lo_a_i, c'_i - e'_i) - pad,  hi_i = min(hi_a_i, c'_i + e'_i) + pad
+//   b point: q_i = ((R[i][0] p0 + R[i][1] p1) + R[i][2] p2) + t_i
+// max / min propagate NaN; membership is the closed box; NaN is never inside.
+#pragma once
+
+#include "locc_internal.h"
+
+namespace locc {
+
+constexpr int kMaxBlocks = kMaxShapePoints / 64;
+
+struct PairGeom {
+  double R[9];  // R_ab, row-major
+  double t[3];  // t_ab
+  double lo[3], hi[3];
+};
+
+// Shared-memory scratch of the scan / ordered selection for one pair.
+struct CropShared {
+  unsigned long long mask[2][kMaxBlocks];
+  int32_t sel[2][kMaxK];
+  int32_t count[2];
+};
+
+__device__ __forceinline__ double geo_nan_max(double u, double v) {
+  return (u != u || v != v) ? u + v : (u > v ? u : v);
+}
+__device__ __forceinline__ double geo_nan_min(double u, double v) {
+  return (u != u || v != v) ? u + v : (u < v ? u : v);
+}
+
+// Rotation matrix R[3*r + c] of a quaternion given as (w, x, y, z).
+__device__ __forceinline__ void geo_quat_to_rot(const float* qf, double* R) {
+#pragma clang fp contract(off)
+  const double w = qf[0], x = qf[1], y = qf[2], z = qf[3];
+  const double xx = x * x, yy = y * y, zz = z * z;
+  const double xy = x * y, xz = x * z, yz = y * z;
+  const double wx = w * x, wy = w * y, wz = w * z;
+  R[0] = 1.0 - 2.0 * (yy + zz);
+  R[1] = 2.0 * (xy - wz);
+  R[2] = 2.0 * (xz + wy);
+  R[3] = 2.0 * (xy + wz);
+  R[4] = 1.0 - 2.0 * (xx + zz);
+  R[5] = 2.0 * (yz - wx);
+  R[6] = 2.0 * (xz - wy);
+  R[7] = 2.0 * (yz + wx);
+  R[8] = 1.0 - 2.0 * (xx + yy);
+}
+
+// Relative pose of b in a's frame and the crop box.
+__device__ __forceinline__ void geo_pair(const locc_object& oa, const locc_object& ob, const ShapeDesc& da,
+                                         const ShapeDesc& db, double pad, PairGeom& g) {
+#pragma clang fp contract(off)
+  double Ra[9], Rb[9];
+  geo_quat_to_rot(oa.q, Ra);
+  geo_quat_to_rot(ob.q, Rb);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g.R[3 * r + c] = (Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c]) + Ra[6 + r] * Rb[6 + c];
+  const double d0 = (double)ob.p[0] - (double)oa.p[0];
+  const double d1 = (double)ob.p[1] - (double)oa.p[1];
+  const double d2 = (double)ob.p[2] - (double)oa.p[2];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) g.t[r] = (Ra[r] * d0 + Ra[3 + r] * d1) + Ra[6 + r] * d2;
+  double cb[3], eb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cb[k] = 0.5 * ((double)db.lo[k] + (double)db.hi[k]);
+    eb[k] = 0.5 * ((double)db.hi[k] - (double)db.lo[k]);
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const double c = ((g.R[3 * r] * cb[0] + g.R[3 * r + 1] * cb[1]) + g.R[3 * r + 2] * cb[2]) + g.t[r];
+    const double e = (fabs(g.R[3 * r]) * eb[0] + fabs(g.R[3 * r + 1]) * eb[1]) + fabs(g.R[3 * r + 2]) * eb[2];
+    g.lo[r] = geo_nan_max((double)da.lo[r], c - e) - pad;
+    g.hi[r] = geo_nan_min((double)da.hi[r], c + e) + pad;
+  }
+}
+
+// b point in a's frame.
+__device__ __forceinline__ void geo_xform(const PairGeom& g, double x, double y, double z, double* q) {
+#pragma clang fp contract(off)
+  q[0] = ((g.R[0] * x + g.R[1] * y) + g.R[2] * z) + g.t[0];
+  q[1] = ((g.R[3] * x + g.R[4] * y) + g.R[5] * z) + g.t[1];
+  q[2] = ((g.R[6] * x + g.R[7] * y) + g.R[8] * z) + g.t[2];
+}
+
+// b normal in a's frame (rotation only).
+__device__ __forceinline__ void geo_rotate(const PairGeom& g, double x, double y, double z, double* q) {
+#pragma clang fp contract(off)
+  q[0] = (g.R[0] * x + g.R[1] * y) + g.R[2] * z;
+  q[1] = (g.R[3] * x + g.R[4] * y) + g.R[5] * z;
+  q[2] = (g.R[6] * x + g.R[7] * y) + g.R[8] * z;
+}
+
+__device__ __forceinline__ bool geo_inside(const PairGeom& g, double q0, double q1, double q2) {
+  return (g.lo[0] <= q0) & (q0 <= g.hi[0]) & (g.lo[1] <= q1) & (q1 <= g.hi[1]) & (g.lo[2] <= q2) &
+         (q2 <= g.hi[2]);
+}
+
+__device__ __forceinline__ int geo_wave_inclusive_scan(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(v, d, 64);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Membership scan and ordered first-K selection for one pair, by a
+// workgroup of 256 threads (4 wave64).  Waves 0-1 scan object a, waves 2-3
+// object b, one 64-bit ballot per 64 consecutive points kept in LDS; after
+// one barrier one wave per object turns the ballots into ordered positions
+// (prefix of popcounts + rank inside the ballot) and stores the first K
+// indices.  Ends with a barrier; S.sel / S.count are then valid.
+__device__ __forceinline__ void geo_scan_select(const PairGeom& g, const ShapeDesc& da, const ShapeDesc& db,
+                                                const DeviceLibrary& lib, int K, CropShared& S) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int side = wave >> 1;
+  const ShapeDesc ds = side ? db : da;
+  const int nblk = (ds.n + 63) >> 6;
+  for (int blk = wave & 1; blk < nblk; blk += 2) {
+    const int k = (blk << 6) + lane;
+    bool in = false;
+    if (k < ds.n) {
+      const int gi = ds.off + k;
+      const double x = lib.px[gi], y = lib.py[gi], z = lib.pz[gi];
+      if (side) {
+        double q[3];
+        geo_xform(g, x, y, z, q);
+        in = geo_inside(g, q[0], q[1], q[2]);
+      } else {
+        in = geo_inside(g, x, y, z);
+      }
+    }
+    const unsigned long long m = __ballot(in);
+    if (lane == 0) S.mask[side][blk] = m;
+  }
+  __syncthreads();
+  if ((wave & 1) == 0) {
+    int carry = 0;
+    for (int base = 0; base < nblk; base += 64) {
+      const int blk = base + lane;
+      unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
+      const int c = __popcll(m);
+      const int incl = geo_wave_inclusive_scan(c, lane);
+      int pos = carry + incl - c;
+      while (m != 0ull && pos < K) {
+        const int bit = __builtin_ctzll(m);
+        S.sel[side][pos] = (blk << 6) + bit;
+        m &= m - 1ull;
+        ++pos;
+      }
+      carry += __shfl(incl, 63, 64);
+    }
+    if (lane == 0) S.count[side] = carry;
+  }
+  __syncthreads();
+}
+
+// Encoder input row (x, y, z, nx, ny, nz) in a's frame of stored point gi of
+// object `side` (0 = a as stored, 1 = b transformed in float64, then rounded).
+__device__ __forceinline__ void geo_row(const PairGeom& g, const DeviceLibrary& lib, int gi, int side, float* v) {
+  if (side) {
+    double q[3], n[3];
+    geo_xform(g, lib.px[gi], lib.py[gi], lib.pz[gi], q);
+    geo_rotate(g, lib.nx[gi], lib.ny[gi], lib.nz[gi], n);
+    v[0] = (float)q[0];
+    v[1] = (float)q[1];
+    v[2] = (float)q[2];
+    v[3] = (float)n[0];
+    v[4] = (float)n[1];
+    v[5] = (float)n[2];
+  } else {
+    v[0] = lib.px[gi];
+    v[1] = lib.py[gi];
+    v[2] = lib.pz[gi];
+    v[3] = lib.nx[gi];
+    v[4] = lib.ny[gi];
+    v[5] = lib.nz[gi];
+  }
+}
+
+// Validate pair p and fetch its canonical objects and shapes.  Returns false
+// for an invalid pair (index out of range, i == j, shape id out of range).
+__device__ __forceinline__ bool geo_fetch(const locc_object* objs, int n_objs, const int32_t* pairs, int p,
+                                          const DeviceLibrary& lib, int& a, int& swapped, locc_object& oa,
+                                          locc_object& ob, ShapeDesc& da, ShapeDesc& db) {
+  const int i = pairs[2 * p];
+  const int j = pairs[2 * p + 1];
+  if (!(i >= 0 && i < n_objs && j >= 0 && j < n_objs && i != j)) return false;
+  a = i < j ? i : j;
+  const int b = i < j ? j : i;
+  swapped = i > j;
+  oa = objs[a];
+  ob = objs[b];
+  if (!(oa.shape >= 0 && oa.shape < lib.n_shapes && ob.shape >= 0 && ob.shape < lib.n_shapes)) return false;
+  da = lib.shapes[oa.shape];
+  db = lib.shapes[ob.shape];
+  return true;
+}
+
+}  // namespace locc

@@ -1,0 +1,161 @@
+"""GPU parity of the fused persistent BF16 kernel against the CPU FP64 oracle.
+
+Crop counts must match bit for bit.  Network outputs must match within 2e-2
+(per field, relative to max(|ref|, RMS |ref|)), with collision-flag agreement
+>= 99.9% on pairs whose reference logit is not within 2e-2 RMS of zero.
+Results must not depend on the schedule or on the rest of the batch.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import locc_oracle as O
+from paper_2304_09439_amd import binding as B
+from paper_2304_09439_amd import inputs as I
+
+from helpers import field_errors, flag_agreement
+
+pytestmark = pytest.mark.gpu
+
+SW, LW = I.SMALL_WIDTHS, I.SCALE_WIDTHS
+SMALL = (SW.h1, SW.h2, SW.hh)
+SCALE = (LW.h1, LW.h2, LW.hh)
+BF16_TOL = 2e-2
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    B.load()
+    return t
+
+
+@pytest.fixture(scope="module")
+def scale_scene():
+    return I.scale_workload()
+
+
+def _weights(widths, bias=0.1):
+    return I.flatten_weights(I.gaussian_weights(widths, seed=0, bias_std=bias))
+
+
+def _forward(torch, scene, K, widths, w, sched=None):
+    ctx = B.context_for_scene(scene, K, widths, w, precision="bf16")
+    if sched:
+        ctx.set_schedule(**sched)
+    objs, pairs = B.scene_tensors(scene)
+    out, counts, z, y = ctx.debug_forward(objs, pairs)
+    torch.cuda.synchronize()
+    n_bad = ctx.device_errors()
+    ctx.close()
+    return out.cpu().numpy(), counts.cpu().numpy(), z.cpu().numpy(), y.cpu().numpy(), n_bad
+
+
+def _check(out, counts, z, y, ref, label):
+    np.testing.assert_array_equal(counts, ref["counts"])
+    ez = float(np.max(np.abs(z - ref["z"])) / np.abs(ref["z"]).max())
+    ey = field_errors(y, ref["y"])
+    ec = field_errors(out, ref["contacts"])
+    fr = flag_agreement(out[:, 0], ref["contacts"][:, 0])
+    fb = flag_agreement(out[:, 0], ref["contacts"][:, 0], band=BF16_TOL)
+    say(f"  {label}: z {ez:.2e}  y {ey}  world {ec}  flag raw {fr:.4f} banded {fb:.4f}")
+    assert ez < BF16_TOL
+    assert max(ey.values()) < BF16_TOL and max(ec.values()) < BF16_TOL
+    assert fb >= 0.999
+
+
+@pytest.mark.parametrize("bias", [0.0, 0.1])
+def test_bf16_fused_matches_oracle_small(torch, small_scene, bias):
+    w = _weights(SW, bias)
+    say(f"bf16 fused parity: small workload, bias_std={bias}")
+    out, counts, z, y, n_bad = _forward(torch, small_scene, 64, SMALL, w)
+    assert n_bad == 0
+    _check(out, counts, z, y, O.detect_scene(small_scene, w, SMALL, 64), "small")
+
+
+def test_bf16_fused_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene):
+    sc = scale_scene
+    w = _weights(LW, bias=0.0)
+    say("bf16 fused parity: 16384 pairs, sampled oracle")
+    out, counts, z, y, n_bad = _forward(torch, sc, 128, SCALE, w)
+    assert n_bad == 0
+    rows = np.sort(np.random.default_rng(321).choice(sc.n_pairs, 192, replace=False))
+    ref = O.detect_scene(sc, w, SCALE, 128, rows=rows)
+    _check(out[rows], counts[rows], z[rows], y[rows], ref, "scale sample")
+
+
+SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True), dict(wg_per_cu=1, claim=1, dynamic=True),
+             dict(wg_per_cu=2, claim=4, dynamic=True), dict(wg_per_cu=2, claim=3, dynamic=False),
+             dict(wg_per_cu=1, claim=64, dynamic=False)]
+
+
+def test_bf16_results_do_not_depend_on_the_schedule(torch, small_scene):
+    w = _weights(SW)
+    say("bf16 fused: schedule independence")
+    runs = [_forward(torch, small_scene, 64, SMALL, w, s) for s in SCHEDULES]
+    for r in runs[1:]:
+        np.testing.assert_array_equal(r[0], runs[0][0])
+        np.testing.assert_array_equal(r[1], runs[0][1])
+
+
+def test_bf16_pair_results_are_the_same_alone_and_in_the_mix(torch, scale_scene):
+    sc = scale_scene
+    w = _weights(LW)
+    say("bf16 fused: alone vs mixed")
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision="bf16")
+    objs, pairs = B.scene_tensors(sc)
+    full, fcounts = ctx.detect(objs, pairs)
+    rows = np.sort(np.random.default_rng(5).choice(sc.n_pairs, 300, replace=False))
+    sub = torch.from_numpy(sc.pairs[rows]).cuda()
+    alone, acounts = ctx.detect(objs, sub)
+    one, _ = ctx.detect(objs, sub[7:8].contiguous())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(alone.cpu().numpy(), full.cpu().numpy()[rows])
+    np.testing.assert_array_equal(acounts.cpu().numpy(), fcounts.cpu().numpy()[rows])
+    np.testing.assert_array_equal(one.cpu().numpy()[0], full.cpu().numpy()[rows[7]])
+    ctx.close()
+
+
+def test_bf16_repeated_launches_are_identical(torch, scale_scene):
+    sc = scale_scene
+    w = _weights(LW)
+    say("bf16 fused: repeated launches (queue reset)")
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision="bf16")
+    objs, pairs = B.scene_tensors(sc)
+    outs = [ctx.detect(objs, pairs)[0].clone() for _ in range(5)]
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    assert ctx.device_errors() == 0
+    ctx.close()
+
+
+def test_bf16_invalid_pairs_and_ragged_batches(torch, small_scene):
+    w = _weights(SW)
+    say("bf16 fused: invalid pairs, ragged batches")
+    ctx = B.context_for_scene(small_scene, 64, SMALL, w, precision="bf16")
+    objs, pairs = B.scene_tensors(small_scene)
+    ref_out, ref_counts = ctx.detect(objs, pairs)
+    bad = torch.tensor([[0, 0], [-1, 3], [3, small_scene.n_objects], [1, 0]], dtype=torch.int32, device="cuda")
+    ctx.device_errors(reset=True)
+    out, counts = ctx.detect(objs, bad)
+    assert ctx.device_errors() == 3
+    out, counts = out.cpu().numpy(), counts.cpu().numpy()
+    for p in range(3):
+        assert np.isnan(out[p]).all() and list(counts[p]) == [-1, -1]
+    assert np.isfinite(out[3]).all()
+    for n in (0, 1, 31, 33, 65):
+        o, c = ctx.detect(objs, pairs[:n].contiguous())
+        torch.cuda.synchronize()
+        assert o.shape == (n, 8)
+        if n:
+            assert torch.equal(o, ref_out[:n]) and torch.equal(c, ref_counts[:n])
+    ctx.close()
