@@ -7,7 +7,7 @@ per-step latency percentiles, the roofline of the dominant kernel (timed with
 HIP events on its launch stream inside the library) and the CPU FP64 oracle
 timed on this host on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32]
+  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32,bf16]
 
 Counter post-processing (turns rocprofv3 --pmc CSV output into a summary):
   python bench.py --summarize-counters FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME
@@ -19,7 +19,6 @@ import argparse
 import glob
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -36,9 +35,14 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 CSRC = os.path.join(ROOT, "paper_2304_09439_amd", "csrc")
 KERNEL_SOURCES = {
-    "crop": ["crop.hip"],
+    "crop": ["crop.hip", "geometry.h"],
     "encoder_fp32": ["net_fp32.hip"],
     "head_fp32": ["net_fp32.hip"],
+    "fused_bf16": ["fused.hip", "fused.h", "geometry.h"],
+}
+PATH_DESC = {
+    "fp32": "per-step FP32: crop, encoder and head kernels on one stream",
+    "bf16": "batched BF16: one persistent fused crop+encoder+head launch per step",
 }
 
 
@@ -124,34 +128,49 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
 
 # ------------------------------------------------------------------ GPU run
 
-def run(args):
+def kernel_entries(kt, work, P, workload_name):
+    kernels = {}
+    for name, (launches, total_ms) in sorted(kt.items()):
+        avg = total_ms / max(launches, 1)
+        entry = dict(avg_ms=round(avg, 4), launches=int(launches))
+        if name == "crop":
+            achieved = work["crop_bytes"] * P / (avg * 1e-3) / 1e9
+            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+                         frac=round(achieved / PEAK_HBM_GBPS, 4))
+        else:
+            if name.startswith("encoder"):
+                flops = work["enc_flops"] * P
+            elif name.startswith("head"):
+                flops = work["head_flops"] * P
+            else:  # fused: the whole network
+                flops = (work["enc_flops"] + work["head_flops"]) * P
+                gbps = (work["crop_bytes"] + work["contact_bytes"]) * P / (avg * 1e-3) / 1e9
+                entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
+            prec = name.split("_")[-1]
+            achieved = flops / (avg * 1e-3) / 1e12
+            entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
+                         frac=round(achieved / PEAK_TFLOPS[prec], 4))
+        entry["traffic"] = counter_traffic(name, workload_name)
+        kernels[name] = entry
+    return kernels
+
+
+def time_path(args, scene, K, widths, w, precision, work, workload_name):
     import numpy as np
-    from paper_2304_09439_amd import inputs as I
-
-    W = workload(args.workload)
-    scene, K, widths = W["scene"], W["K"], W["widths"]
-    w = I.flatten_weights(I.gaussian_weights(widths, seed=0))
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, w, widths, K, args.cpu_pairs)   # before the GPU is touched
-
     import torch
     from paper_2304_09439_amd import binding as B
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     wd = (widths.h1, widths.h2, widths.hh)
-    ctx = B.context_for_scene(scene, K, wd, w, precision=args.precision)
+    ctx = B.context_for_scene(scene, K, wd, w, precision=precision)
     objs, pairs = B.scene_tensors(scene)
     P = scene.n_pairs
     out = torch.empty((P, 8), dtype=torch.float32, device="cuda")
     counts = torch.empty((P, 2), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
-
     for _ in range(args.warmup):
         ctx.detect(objs, pairs, out, counts)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs", file=sys.stderr,
-          flush=True)
-
+    print(f"[bench] {precision}: warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs",
+          file=sys.stderr, flush=True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     ctx.profile(True)
     torch.cuda.synchronize()
@@ -166,49 +185,56 @@ def run(args):
     kt = ctx.profile_read()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     n_bad = ctx.device_errors()
+    ctx.close()
+    ms = 1000.0 * wall / args.steps
+    kernels = kernel_entries(kt, work, P, workload_name)
+    return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
+                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+                kernels=kernels, device_errors=int(n_bad), path=PATH_DESC[precision])
+
+
+def run(args):
+    from paper_2304_09439_amd import inputs as I
+
+    W = workload(args.workload)
+    scene, K, widths = W["scene"], W["K"], W["widths"]
+    w = I.flatten_weights(I.gaussian_weights(widths, seed=0))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, w, widths, K, args.cpu_pairs)   # before the GPU is touched
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    work = per_pair_work(K, widths, W["n_points"])
+    precisions = args.precision.split(",")
+    paths = {p: time_path(args, scene, K, widths, w, p, work, args.workload) for p in precisions}
     if args.copy_mib:
         n = args.copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.neg(src, out=dst)   # one elementwise kernel: copy_mib read + copy_mib written
         torch.cuda.synchronize()
-    ctx.close()
 
-    ms_per_step = 1000.0 * wall / args.steps
-    work = per_pair_work(K, widths, W["n_points"])
-    kernels = {}
-    for name, (launches, total_ms) in sorted(kt.items()):
-        avg = total_ms / max(launches, 1)
-        entry = dict(avg_ms=round(avg, 4), launches=int(launches))
-        if name == "crop":
-            achieved = work["crop_bytes"] * P / (avg * 1e-3) / 1e9
-            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
-                         frac=round(achieved / PEAK_HBM_GBPS, 4))
-        elif name.startswith("encoder") or name.startswith("head"):
-            flops = work["enc_flops" if name.startswith("encoder") else "head_flops"] * P
-            prec = name.split("_")[-1]
-            achieved = flops / (avg * 1e-3) / 1e12
-            entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
-                         frac=round(achieved / PEAK_TFLOPS[prec], 4))
-        traffic = counter_traffic(name, args.workload)
-        entry["traffic"] = traffic
-        kernels[name] = entry
+    primary = "bf16" if "bf16" in paths else precisions[0]
+    main_path = paths[primary]
+    kernels = main_path["kernels"]
     dominant = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     d = kernels[dominant]
     roofline = dict(kernel=dominant, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=d["traffic"])
     line = dict(
-        metric=METRIC, value=round(P / (ms_per_step * 1e-3), 1), unit=UNIT, n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype=args.precision.replace("fp", "f") if args.precision == "fp32" else args.precision,
-        data="synthetic",
-        config=dict(workload=W["desc"], pairs=P, K=K, points_per_shape=W["n_points"], shapes=W["n_shapes"],
-                    precision=args.precision, geometry="f64",
-                    path="per-step: crop, encoder and head kernels on one stream"),
-        p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
-        p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
-        roofline=roofline, kernels=kernels, cpu_baseline=cpu, device_errors=int(n_bad),
+        metric=METRIC, value=main_path["value"], unit=UNIT, n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=main_path["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32" if primary == "fp32" else primary, data="synthetic",
+        config=dict(workload=W["desc"], pairs=scene.n_pairs, K=K, points_per_shape=W["n_points"],
+                    shapes=W["n_shapes"], precision=primary, geometry="f64", path=PATH_DESC[primary]),
+        p50_step_ms=main_path["p50_step_ms"], p99_step_ms=main_path["p99_step_ms"],
+        roofline=roofline, kernels=kernels, cpu_baseline=cpu, device_errors=main_path["device_errors"],
+        paths={p: {k: v for k, v in r.items()} for p, r in paths.items()},
     )
+    if "fp32" in paths and primary != "fp32":
+        line["speedup_vs_fp32_plain"] = round(main_path["value"] / paths["fp32"]["value"], 3)
     print(json.dumps(line), flush=True)
 
 
@@ -266,7 +292,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale", choices=["scale", "small"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--precision", default="fp32,bf16",
+                    help="comma list of paths to time: fp32 (per-step) and/or bf16 (fused); bf16 is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")

@@ -89,6 +89,16 @@ def field_errors(out: np.ndarray, ref: np.ndarray) -> dict:
     return errs
 
 
+def normwise_errors(out: np.ndarray, ref: np.ndarray) -> dict:
+    """Per-field normwise relative error over all pairs: ||y_f - ref_f||_F / ||ref_f||_F."""
+    errs = {}
+    for name, sl in FIELDS.items():
+        d = np.linalg.norm(np.asarray(out, np.float64)[:, sl] - ref[:, sl])
+        r = np.linalg.norm(ref[:, sl])
+        errs[name] = float(d / max(r, 1e-30))
+    return errs
+
+
 def flag_agreement(logit_out, logit_ref, band: float = 0.0):
     """Fraction of pairs whose (logit > 0) agrees; pairs with |ref| < band * RMS(ref) excluded."""
     logit_out = np.asarray(logit_out, np.float64).ravel()
