@@ -170,18 +170,22 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
                                int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, float* d_z, float* d_y,
                                void* stream);
 
-/* Work schedule of the fused persistent kernel (BF16 / FP8 contexts):
- *   wg_per_cu  workgroups per compute unit (1 .. 2); grid = CUs x wg_per_cu
+/* Work schedule of the BF16 path:
+ *   wg_per_cu  workgroups per compute unit of the persistent network kernel
+ *              (1 .. 2); grid = CUs x wg_per_cu
  *   claim      pairs a workgroup takes from the queue at a time (1 .. 64)
  *   dynamic    1: pairs are claimed from a device-side atomic queue;
  *              0: static round robin (workgroup w takes claims w, w + grid, ...)
+ *   split      0: one persistent kernel does crop, encoder and head;
+ *              1: a crop kernel writes bf16 encoder rows to a library
+ *              workspace, then the persistent kernel runs encoder and head
  * Results do not depend on the schedule: every pair is computed on its own.
  * Errors: INVALID_ARG (null, out of range). */
 typedef struct {
   int32_t wg_per_cu;
   int32_t claim;
   int32_t dynamic;
-  int32_t reserved; /* must be 0 */
+  int32_t split;
 } locc_schedule;
 
 LOCC_API locc_status locc_set_schedule(locc_ctx* ctx, const locc_schedule* sched);
@@ -194,7 +198,8 @@ LOCC_API locc_status locc_get_schedule(const locc_ctx* ctx, locc_schedule* sched
  * per-dispatch durations a kernel-trace profiler reports, plus event
  * overhead).  locc_profile(ctx, 1) clears the totals and starts recording,
  * locc_profile(ctx, 0) stops.  Kernel names: "crop", "encoder_fp32",
- * "head_fp32" (FP32 per-step path), "fused_bf16" (BF16 fused path). */
+ * "head_fp32" (FP32 per-step path), "fused_bf16" (BF16, one launch),
+ * "crop" and "encoder_head_bf16" (BF16 split schedule). */
 typedef struct {
   char name[32];
   int64_t launches;

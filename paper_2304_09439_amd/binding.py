@@ -34,7 +34,7 @@ class Config(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("claim", ctypes.c_int32), ("dynamic", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("split", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -214,14 +214,14 @@ class Context:
                                          _ptr(z), _ptr(y), self._stream(stream)))
         return out, counts, z, y
 
-    def set_schedule(self, wg_per_cu: int = 2, claim: int = 1, dynamic: bool = True):
-        sc = Schedule(wg_per_cu, claim, int(dynamic), 0)
+    def set_schedule(self, wg_per_cu: int = 2, claim: int = 1, dynamic: bool = True, split: bool = False):
+        sc = Schedule(wg_per_cu, claim, int(dynamic), int(split))
         _check(load().locc_set_schedule(self._h, ctypes.byref(sc)))
 
     def get_schedule(self) -> dict:
         sc = Schedule()
         _check(load().locc_get_schedule(self._h, ctypes.byref(sc)))
-        return dict(wg_per_cu=sc.wg_per_cu, claim=sc.claim, dynamic=bool(sc.dynamic))
+        return dict(wg_per_cu=sc.wg_per_cu, claim=sc.claim, dynamic=bool(sc.dynamic), split=bool(sc.split))
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""

@@ -62,7 +62,7 @@ struct locc_ctx {
   unsigned char* d_wbf16 = nullptr;
   bool have_weights = false;
   // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
-  locc_schedule sched{kFusedWgPerCu, 1, 1, 0};
+  locc_schedule sched{kFusedWgPerCu, 4, 1, 1};  // measured best on the 16384-pair workload: split, claim 4
   unsigned int* d_queue = nullptr;
   // workspace
   void* d_ws = nullptr;
@@ -149,6 +149,23 @@ struct Workspace {
   float* z;
 };
 
+struct SplitWorkspace {
+  PairMeta* meta;
+  unsigned short* rows;
+};
+
+locc_status carve_split(locc_ctx* c, int n_pairs, SplitWorkspace* w) {
+  const size_t P = (size_t)n_pairs;
+  const size_t meta = align256(P * sizeof(PairMeta));
+  const size_t rows = align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
+  locc_status st = ensure_workspace(c, meta + rows);
+  if (st != LOCC_OK) return st;
+  char* b = static_cast<char*>(c->d_ws);
+  w->meta = reinterpret_cast<PairMeta*>(b);
+  w->rows = reinterpret_cast<unsigned short*>(b + meta);
+  return LOCC_OK;
+}
+
 locc_status carve(locc_ctx* c, int n_pairs, Workspace* w) {
   const size_t P = (size_t)n_pairs;
   const size_t meta = align256(P * sizeof(PairMeta));
@@ -201,8 +218,24 @@ locc_status run_fused(locc_ctx* c, const locc_object* objs, int32_t n_objs, cons
   fa.claim = c->sched.claim;
   fa.dynamic = c->sched.dynamic;
   const int grid = fused_grid(c, n_pairs);
+  if (c->sched.split) {
+    SplitWorkspace w{};
+    locc_status st = carve_split(c, n_pairs, &w);
+    if (st != LOCC_OK) return st;
+    CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
+                nullptr, counts, w.meta, nullptr, w.rows, c->d_err};
+    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
+    fa.rows_bf16 = w.rows;
+    fa.meta = w.meta;
+    fa.counts = nullptr;        // written by the crop kernel
+    fa.err_counter = nullptr;   // counted by the crop kernel
+    HIP_TRY(timed(c, "encoder_head_bf16", s, [&] {
+      return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, true, s);
+    }));
+    return LOCC_OK;
+  }
   HIP_TRY(timed(c, "fused_bf16", s, [&] {
-    return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, s);
+    return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, false, s);
   }));
   return LOCC_OK;
 }
@@ -219,7 +252,7 @@ locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const
   HIP_TRY(hipSetDevice(c->device));
   if (c->cfg.precision == LOCC_BF16) return run_fused(c, objs, n_objs, pairs, n_pairs, out, counts, z_out, y_out, s);
   CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
-              nullptr, counts, w.meta, w.rows, c->d_err};
+              nullptr, counts, w.meta, w.rows, nullptr, c->d_err};
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
   const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
   NetArgs na{w.rows, w.meta, objs, n_pairs, c->cfg.K, z_out ? z_out : w.z, y_out, out};
@@ -402,7 +435,7 @@ locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs
   if (n_pairs == 0) return LOCC_OK;
   HIP_TRY(hipSetDevice(c->device));
   CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
-              idx, counts, nullptr, nullptr, c->d_err};
+              idx, counts, nullptr, nullptr, nullptr, c->d_err};
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
   return LOCC_OK;
@@ -414,7 +447,7 @@ locc_status locc_set_schedule(locc_ctx* c, const locc_schedule* sc) {
     return fail(LOCC_ERR_INVALID_ARG, "wg_per_cu=%d: must be 1..%d", sc->wg_per_cu, kFusedWgPerCu);
   if (sc->claim < 1 || sc->claim > 64) return fail(LOCC_ERR_INVALID_ARG, "claim=%d: must be 1..64", sc->claim);
   if (sc->dynamic != 0 && sc->dynamic != 1) return fail(LOCC_ERR_INVALID_ARG, "dynamic must be 0 or 1");
-  if (sc->reserved != 0) return fail(LOCC_ERR_INVALID_ARG, "reserved field must be 0");
+  if (sc->split != 0 && sc->split != 1) return fail(LOCC_ERR_INVALID_ARG, "split must be 0 or 1");
   c->sched = *sc;
   return LOCC_OK;
 }

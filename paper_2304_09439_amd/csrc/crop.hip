@@ -9,6 +9,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
+template <int U>
 __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
   __shared__ CropShared S;
   const int p = blockIdx.x;
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
   }
   PairGeom g;
   geo_pair(oa, ob, da, db, A.pad, g);
-  geo_scan_select(g, da, db, A.lib, K, S);
+  geo_scan_select<U>(g, da, db, A.lib, K, S);
 
   const int n_a = S.count[0], n_b = S.count[1];
   const int m_a = n_a < K ? n_a : K;
@@ -72,13 +73,41 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
       dst[1] = hi4;
     }
   }
+  if (A.rows_bf16) {
+    // bf16 rows (x, y, z, nx, ny, nz, 1, 0), zero-padded to a multiple of 32 per object
+    const int ra = (m_a + 31) & ~31, rb = (m_b + 31) & ~31;
+    for (int e = tid; e < ra + rb; e += kThreads) {
+      const int s = e >= ra;
+      const int r = s ? e - ra : e;
+      const int m = s ? m_b : m_a;
+      unsigned short row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (r < m) {
+        float v[6];
+        geo_row(g, A.lib, (s ? db : da).off + S.sel[s][r], s, v);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) row[k] = __builtin_bit_cast(unsigned short, (__bf16)v[k]);
+        row[6] = 0x3f80;  // 1.0
+      }
+      uint4 packed;
+      packed.x = row[0] | ((unsigned)row[1] << 16);
+      packed.y = row[2] | ((unsigned)row[3] << 16);
+      packed.z = row[4] | ((unsigned)row[5] << 16);
+      packed.w = row[6] | ((unsigned)row[7] << 16);
+      *reinterpret_cast<uint4*>(A.rows_bf16 + ((size_t)p * 2 * K + s * K + r) * 8) = packed;
+    }
+  }
 }
 
 }  // namespace
 
-hipError_t launch_crop(const CropArgs& a, hipStream_t s) {
+hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll) {
   if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(crop_kernel, dim3(a.n_pairs), dim3(kThreads), 0, s, a);
+  switch (unroll) {
+    case 2: hipLaunchKernelGGL(crop_kernel<2>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(crop_kernel<4>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(crop_kernel<8>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -29,6 +29,9 @@ struct FusedArgs {
   float* z_dbg;      // [P][2 h2] or null
   float* y_dbg;      // [P][8] or null
   unsigned long long* err_counter;
+  // split schedule: rows and per-pair records produced by the crop kernel
+  const unsigned short* rows_bf16;  // [P][2K][8]
+  const PairMeta* meta;             // [P]
   // schedule
   unsigned int* queue;  // [2]: next unclaimed pair, finished workgroups (both 0 between launches)
   int32_t claim;        // pairs claimed at once
@@ -49,6 +52,8 @@ void bf16_bind(FusedArgs& a, const unsigned char* dev_base, int h1, int h2, int 
 constexpr int kFusedWgPerCu = 2;
 constexpr int kFusedTile = 32;
 
-hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s);
+// precropped = false: crop, encoder and head in one kernel; true: encoder and
+// head only, reading rows_bf16 / meta written by the crop kernel.
+hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, bool precropped, hipStream_t s);
 
 }  // namespace locc

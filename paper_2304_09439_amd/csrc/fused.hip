@@ -24,6 +24,11 @@
 //
 // The queue is self-cleaning: the last workgroup to finish resets it, so
 // consecutive launches (and graph replays) need no memset.
+//
+// Split schedule (PRE = true): the crop runs in its own high-occupancy kernel
+// (crop.hip, bf16 rows + per-pair records in HBM) and this kernel runs only
+// the encoder and head; the crop's dependent loads then overlap across many
+// more resident workgroups than the encoder's register budget allows.
 #include "fused.h"
 #include "geometry.h"
 
@@ -36,6 +41,15 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// ReLU of 8 packed bf16 values: as int16 every negative bf16 (sign bit set)
+// is below 0 and the positive ones keep their order, so max(v, 0) in int16
+// is ReLU in bf16 (two values per v_pk_max_i16).
+__device__ __forceinline__ u16x8 bf16x8_relu(u16x8 v) {
+  const s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+  return __builtin_bit_cast(u16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, v), z));
+}
 
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   const __bf16 h = (__bf16)f;  // round to nearest even
@@ -174,7 +188,7 @@ __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& 
   __syncthreads();
 }
 
-template <int H1, int H2, int HH>
+template <int H1, int H2, int HH, bool PRE>
 __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArgs A) {
   using S_t = Smem<H1, H2, HH>;
   constexpr int T = S_t::T, ZS = S_t::ZS;
@@ -216,18 +230,45 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
     if (base >= P) break;
     const int n_claim = P - base < A.claim ? P - base : A.claim;
 
+    // split schedule: each thread carries up to two 16-byte encoder rows of
+    // the next pair in registers, loaded while the current pair computes
+    uint4 nxt[2];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (tid + 256 * i < 2 * K)
+          nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)base * 2 * K + tid + 256 * i];
+    }
     for (int c = 0; c < n_claim; ++c) {
       const int p = base + c;
       // ---------------------------------------------------------------- crop
       int a = -1, swapped = 0;
+      int m_a = 0, m_b = 0;
+      bool valid;
+      if constexpr (PRE) {
+        const PairMeta mt = A.meta[p];
+        a = mt.a;
+        swapped = mt.swapped;
+        valid = a >= 0;
+        m_a = valid ? mt.m_a : 0;
+        m_b = valid ? mt.m_b : 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          if (tid + 256 * i < 2 * K) reinterpret_cast<uint4*>(S.u.c.rows)[tid + 256 * i] = nxt[i];
+        if (c + 1 < n_claim) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            if (tid + 256 * i < 2 * K)
+              nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)(p + 1) * 2 * K + tid + 256 * i];
+        }
+      } else {
       locc_object oa, ob;
       ShapeDesc da, db;
-      const bool valid = geo_fetch(A.objs, A.n_objs, A.pairs, p, A.lib, a, swapped, oa, ob, da, db);
-      int m_a = 0, m_b = 0;
+      valid = geo_fetch(A.objs, A.n_objs, A.pairs, p, A.lib, a, swapped, oa, ob, da, db);
       if (valid) {  // uniform over the workgroup
         PairGeom gm;
         geo_pair(oa, ob, da, db, A.pad, gm);
-        geo_scan_select(gm, da, db, A.lib, K, S.u.c.crop);
+        geo_scan_select<4>(gm, da, db, A.lib, K, S.u.c.crop);
         const int n_a = S.u.c.crop.count[0], n_b = S.u.c.crop.count[1];
         m_a = n_a < K ? n_a : K;
         m_b = n_b < K ? n_b : K;
@@ -258,6 +299,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
         }
         atomicAdd(A.err_counter, 1ull);
       }
+      }
       if (tid == 0) {
         S.pair[slot] = p;
         S.a[slot] = valid ? a : -1;
@@ -266,11 +308,15 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       __syncthreads();
 
       // ------------------------------------------------------------- encoder
+      // max-pool of the raw layer-2 sums; bias and ReLU are applied once per
+      // column afterwards: fl(max_r a_r + b) = max_r fl(a_r + b) because
+      // rounding is monotone, and ReLU is monotone (an empty set gives
+      // max(-inf + b, 0) = 0)
       for (int side = 0; side < 2; ++side) {
         const int m = side ? m_b : m_a;
         float run[CT];
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) run[ct] = 0.f;
+        for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
         for (int r0 = 0; r0 < m; r0 += 32) {
           const s16x4 xb = *reinterpret_cast<const s16x4*>(&S.u.c.rows[(side * K + r0 + l32) * 8 + 4 * g]);
           f32x16 acc2[CT];
@@ -287,28 +333,35 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
             for (int hf = 0; hf < 2; ++hf) {
               u16x8 av;
 #pragma unroll
-              for (int e = 0; e < 8; ++e) av[e] = bf16_bits(fmaxf(acc1[8 * hf + e], 0.f));
+              for (int e = 0; e < 8; ++e) av[e] = bf16_bits(acc1[8 * hf + e]);
+              av = bf16x8_relu(av);
 #pragma unroll
               for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av, w2f[ct][2 * ft + hf], acc2[ct]);
             }
             acc1 = acc1n;
           }
+          if (r0 + 32 <= m) {
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
+            for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
-              const float v = fmaxf(acc2[ct][r] + bias2[ct], 0.f);
-              if (row < m) run[ct] = fmaxf(run[ct], v);
-            }
+              for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+          } else {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+                if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+              }
+          }
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-          run[ct] = fmaxf(run[ct], __shfl_xor(run[ct], 32, 64));
+          const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) + bias2[ct], 0.f);
           if (lane < 32) {
             const int col = side * H2 + (wave * CT + ct) * 32 + lane;
-            S.z[slot * ZS + col] = bf16_bits(run[ct]);
-            if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? run[ct] : __builtin_nanf("");
+            S.z[slot * ZS + col] = bf16_bits(f);
+            if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? f : __builtin_nanf("");
           }
         }
       }
@@ -332,8 +385,11 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
 }
 
 template <int H1, int H2, int HH>
-hipError_t run_fused(const FusedArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH>), dim3(grid), dim3(256), 0, s, a);
+hipError_t run_fused(const FusedArgs& a, int grid, bool pre, hipStream_t s) {
+  if (pre)
+    hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -425,10 +481,10 @@ void bf16_bind(FusedArgs& a, const unsigned char* base, int h1, int h2, int hh) 
   a.c3 = reinterpret_cast<const float*>(base + L.c3);
 }
 
-hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s) {
+hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, bool pre, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  if (h1 == 64 && h2 == 128 && hh == 256) return run_fused<64, 128, 256>(a, grid, s);
-  if (h1 == 128 && h2 == 256 && hh == 512) return run_fused<128, 256, 512>(a, grid, s);
+  if (h1 == 64 && h2 == 128 && hh == 256) return run_fused<64, 128, 256>(a, grid, pre, s);
+  if (h1 == 128 && h2 == 256 && hh == 512) return run_fused<128, 256, 512>(a, grid, pre, s);
   return hipErrorInvalidValue;
 }
 

@@ -124,12 +124,109 @@ __device__ __forceinline__ int geo_wave_inclusive_scan(int v, int lane) {
   return v;
 }
 
+// Float32 screening of the float64 membership test (same result, fewer
+// instructions).
+//  * a points are float32, so p >= lo (float64) holds iff p >= the smallest
+//    float >= lo, and p <= hi iff p <= the largest float <= hi: the a-side
+//    test is exact in float32 with outward-rounded bounds.
+//  * b points: q' = fma(R'_i2, z, fma(R'_i1, y, fma(R'_i0, x, t'_i))) with
+//    R', t' the float32 roundings of R_ab, t_ab differs from the float64 q_i
+//    by less than 2^-21 S_i, S_i = sum_j |R_ij| max|p_j| + |t_i|.  With the
+//    margin E_i = 2^-19 S_i + 2^-20 (|lo_i| + |hi_i|) (which also covers the
+//    rounding of the bounds to float32), q' inside [lo + E, hi - E] on every
+//    axis implies membership and q' outside [lo - E, hi + E] on some axis
+//    implies non-membership; only the points in between take the exact
+//    float64 test.  NaN bounds make every point undecided, and the exact
+//    test then rejects it.
+struct PairScreen {
+  float alo[3], ahi[3];           // exact a-side bounds
+  float R[9], t[3];               // float32 R_ab, t_ab
+  float in_lo[3], in_hi[3];       // definitely inside
+  float out_lo[3], out_hi[3];     // definitely outside beyond these
+};
+
+// One float32 step towards +inf (up) or -inf (down) from a finite f.
+__device__ __forceinline__ float geo_f32_step(float f, bool up) {
+  if (f == 0.f) return up ? __int_as_float(1) : -__int_as_float(1);
+  const int b = __float_as_int(f);
+  return __int_as_float((f > 0.f) == up ? b + 1 : b - 1);
+}
+__device__ __forceinline__ float geo_f32_ceil(double v) {  // smallest float >= v
+  float f = (float)v;
+  if ((double)f < v) f = geo_f32_step(f, true);
+  return f;
+}
+__device__ __forceinline__ float geo_f32_floor(double v) {  // largest float <= v
+  float f = (float)v;
+  if ((double)f > v) f = geo_f32_step(f, false);
+  return f;
+}
+// Wave-uniform float, kept in a scalar register.
+__device__ __forceinline__ float geo_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ void geo_screen(const PairGeom& g, const ShapeDesc& db, PairScreen& sc) {
+#pragma clang fp contract(off)
+  double P[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P[k] = fmax(fabs((double)db.lo[k]), fabs((double)db.hi[k]));
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    sc.alo[i] = geo_f32_ceil(g.lo[i]);
+    sc.ahi[i] = geo_f32_floor(g.hi[i]);
+    const double S = fabs(g.R[3 * i]) * P[0] + fabs(g.R[3 * i + 1]) * P[1] + fabs(g.R[3 * i + 2]) * P[2] + fabs(g.t[i]);
+    const double E = 0x1p-19 * S + 0x1p-20 * (fabs(g.lo[i]) + fabs(g.hi[i]));
+    sc.in_lo[i] = (float)(g.lo[i] + E);
+    sc.in_hi[i] = (float)(g.hi[i] - E);
+    sc.out_lo[i] = (float)(g.lo[i] - E);
+    sc.out_hi[i] = (float)(g.hi[i] + E);
+    sc.t[i] = (float)g.t[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sc.R[k] = (float)g.R[k];
+  // every thread of the workgroup holds the same values: scalar registers
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    sc.alo[i] = geo_uniform(sc.alo[i]);
+    sc.ahi[i] = geo_uniform(sc.ahi[i]);
+    sc.in_lo[i] = geo_uniform(sc.in_lo[i]);
+    sc.in_hi[i] = geo_uniform(sc.in_hi[i]);
+    sc.out_lo[i] = geo_uniform(sc.out_lo[i]);
+    sc.out_hi[i] = geo_uniform(sc.out_hi[i]);
+    sc.t[i] = geo_uniform(sc.t[i]);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sc.R[k] = geo_uniform(sc.R[k]);
+}
+
+__device__ __forceinline__ bool geo_member_a(const PairScreen& sc, float x, float y, float z) {
+  return (sc.alo[0] <= x) & (x <= sc.ahi[0]) & (sc.alo[1] <= y) & (y <= sc.ahi[1]) & (sc.alo[2] <= z) &
+         (z <= sc.ahi[2]);
+}
+
+__device__ __forceinline__ bool geo_member_b(const PairGeom& g, const PairScreen& sc, float x, float y, float z) {
+  const float q0 = __builtin_fmaf(sc.R[2], z, __builtin_fmaf(sc.R[1], y, __builtin_fmaf(sc.R[0], x, sc.t[0])));
+  const float q1 = __builtin_fmaf(sc.R[5], z, __builtin_fmaf(sc.R[4], y, __builtin_fmaf(sc.R[3], x, sc.t[1])));
+  const float q2 = __builtin_fmaf(sc.R[8], z, __builtin_fmaf(sc.R[7], y, __builtin_fmaf(sc.R[6], x, sc.t[2])));
+  const bool in = (sc.in_lo[0] <= q0) & (q0 <= sc.in_hi[0]) & (sc.in_lo[1] <= q1) & (q1 <= sc.in_hi[1]) &
+                  (sc.in_lo[2] <= q2) & (q2 <= sc.in_hi[2]);
+  const bool out = (q0 < sc.out_lo[0]) | (q0 > sc.out_hi[0]) | (q1 < sc.out_lo[1]) | (q1 > sc.out_hi[1]) |
+                   (q2 < sc.out_lo[2]) | (q2 > sc.out_hi[2]);
+  if (in | out) return in;
+  double q[3];
+  geo_xform(g, x, y, z, q);
+  return geo_inside(g, q[0], q[1], q[2]);
+}
+
 // Membership scan and ordered first-K selection for one pair, by a
 // workgroup of 256 threads (4 wave64).  Waves 0-1 scan object a, waves 2-3
-// object b, one 64-bit ballot per 64 consecutive points kept in LDS; after
+// object b, one 64-bit ballot per 64 consecutive points kept in LDS (each
+// wave issues the loads of kScanUnroll blocks before testing them); after
 // one barrier one wave per object turns the ballots into ordered positions
 // (prefix of popcounts + rank inside the ballot) and stores the first K
 // indices.  Ends with a barrier; S.sel / S.count are then valid.
+template <int kScanUnroll>
 __device__ __forceinline__ void geo_scan_select(const PairGeom& g, const ShapeDesc& da, const ShapeDesc& db,
                                                 const DeviceLibrary& lib, int K, CropShared& S) {
   const int tid = threadIdx.x;
@@ -138,37 +235,53 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom& g, const ShapeDe
   const int side = wave >> 1;
   const ShapeDesc ds = side ? db : da;
   const int nblk = (ds.n + 63) >> 6;
-  for (int blk = wave & 1; blk < nblk; blk += 2) {
-    const int k = (blk << 6) + lane;
-    bool in = false;
-    if (k < ds.n) {
-      const int gi = ds.off + k;
-      const double x = lib.px[gi], y = lib.py[gi], z = lib.pz[gi];
-      if (side) {
-        double q[3];
-        geo_xform(g, x, y, z, q);
-        in = geo_inside(g, q[0], q[1], q[2]);
-      } else {
-        in = geo_inside(g, x, y, z);
+  PairScreen sc;
+  geo_screen(g, db, sc);
+  for (int blk0 = wave & 1; blk0 < nblk; blk0 += 2 * kScanUnroll) {
+    float x[kScanUnroll], y[kScanUnroll], z[kScanUnroll];
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const int k = ((blk0 + 2 * u) << 6) + lane;
+      x[u] = y[u] = z[u] = 0.f;
+      if (k < ds.n) {
+        const int gi = ds.off + k;
+        x[u] = lib.px[gi];
+        y[u] = lib.py[gi];
+        z[u] = lib.pz[gi];
       }
     }
-    const unsigned long long m = __ballot(in);
-    if (lane == 0) S.mask[side][blk] = m;
+#pragma unroll
+    for (int u = 0; u < kScanUnroll; ++u) {
+      const int blk = blk0 + 2 * u;
+      const int k = (blk << 6) + lane;
+      bool in = false;
+      if (k < ds.n) in = side ? geo_member_b(g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
+      const unsigned long long m = __ballot(in);
+      if (lane == 0 && blk < nblk) S.mask[side][blk] = m;
+    }
   }
   __syncthreads();
   if ((wave & 1) == 0) {
+    // prefix of popcounts over blocks (lane = block within a chunk of 64),
+    // then the blocks that still have room below K are written one at a time
+    // by the whole wave: member bit l of block b goes to start(b) + rank of
+    // bit l among the block's set bits.
     int carry = 0;
     for (int base = 0; base < nblk; base += 64) {
       const int blk = base + lane;
-      unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
+      const unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
       const int c = __popcll(m);
       const int incl = geo_wave_inclusive_scan(c, lane);
-      int pos = carry + incl - c;
-      while (m != 0ull && pos < K) {
-        const int bit = __builtin_ctzll(m);
-        S.sel[side][pos] = (blk << 6) + bit;
-        m &= m - 1ull;
-        ++pos;
+      const int excl = carry + incl - c;
+      const int nb = nblk - base < 64 ? nblk - base : 64;
+      for (int j = 0; j < nb; ++j) {
+        const int start = __shfl(excl, j, 64);
+        if (start >= K) break;
+        const unsigned long long mj = S.mask[side][base + j];
+        if ((mj >> lane) & 1ull) {
+          const int pos = start + __popcll(mj & ((1ull << lane) - 1ull));
+          if (pos < K) S.sel[side][pos] = ((base + j) << 6) + lane;
+        }
       }
       carry += __shfl(incl, 63, 64);
     }

@@ -64,10 +64,13 @@ struct CropArgs {
   int32_t* counts_out;   // [P][2] caller order, may be null
   PairMeta* meta;        // [P], may be null
   float* rows;           // [P][2K][8], may be null
+  unsigned short* rows_bf16;  // [P][2K][8] bf16 (x, y, z, nx, ny, nz, 1, 0), rows up to the next
+                              // multiple of 32 of each object's count written, may be null
   unsigned long long* err_counter;
 };
 
-hipError_t launch_crop(const CropArgs& a, hipStream_t s);
+// unroll: blocks of 64 points whose loads a wave issues together (2, 4 or 8)
+hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll = 8);
 
 // FP32 network weights packed in MFMA fragment order (see net_fp32.hip).
 struct Fp32Net {

@@ -99,7 +99,8 @@ def test_bf16_fused_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene)
 
 SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True), dict(wg_per_cu=1, claim=1, dynamic=True),
              dict(wg_per_cu=2, claim=4, dynamic=True), dict(wg_per_cu=2, claim=3, dynamic=False),
-             dict(wg_per_cu=1, claim=64, dynamic=False)]
+             dict(wg_per_cu=1, claim=64, dynamic=False), dict(wg_per_cu=2, claim=1, dynamic=True, split=True),
+             dict(wg_per_cu=2, claim=8, dynamic=False, split=True)]
 
 
 def test_bf16_results_do_not_depend_on_the_schedule(torch, small_scene):
