@@ -179,6 +179,7 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
  *   split      0: one persistent kernel does crop, encoder and head;
  *              1: a crop kernel writes bf16 encoder rows to a library
  *              workspace, then the persistent kernel runs encoder and head
+ *   crop_unroll  also used by the FP32 path's crop kernel
  * Results do not depend on the schedule: every pair is computed on its own.
  * Errors: INVALID_ARG (null, out of range). */
 typedef struct {
@@ -186,10 +187,55 @@ typedef struct {
   int32_t claim;
   int32_t dynamic;
   int32_t split;
+  int32_t crop_unroll; /* 2, 4 or 8: 64-point blocks whose loads a crop wave issues together */
+  int32_t reserved[3]; /* must be 0 */
 } locc_schedule;
 
 LOCC_API locc_status locc_set_schedule(locc_ctx* ctx, const locc_schedule* sched);
 LOCC_API locc_status locc_get_schedule(const locc_ctx* ctx, locc_schedule* sched);
+
+/* Picks the fastest schedule for this context on the given workload (which
+ * must be valid input for locc_detect): every candidate (split or fused,
+ * workgroups per CU, claim size, queue kind, crop unroll) is timed with HIP
+ * events on `stream` (one warm-up and three timed launches each), the best
+ * is installed with locc_set_schedule and returned.  With cache_path set, a
+ * text file of earlier results keyed by device, configuration and the
+ * power-of-two bucket of n_pairs is read first (a hit skips the timing) and
+ * appended to after a miss.  d_out / d_counts receive the outputs of the
+ * timed runs.  Synchronises `stream`.  *h_best_ms may be NULL.
+ * Errors: as locc_detect, plus HIP. */
+LOCC_API locc_status locc_autotune(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                                   int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, void* stream,
+                                   const char* cache_path, locc_schedule* h_best, double* h_best_ms);
+
+/* Grows the library workspace to hold max_pairs pairs (synchronous; may
+ * allocate).  Needed before graph capture, which must not allocate.
+ * Errors: INVALID_ARG, OOM, HIP. */
+LOCC_API locc_status locc_reserve(locc_ctx* ctx, int32_t max_pairs);
+
+/* locc_detect with the pair count read from device memory at run time:
+ * *d_n_pairs (int32, device) pairs of d_pairs are processed, clamped to
+ * [0, max_pairs]; buffers are sized for max_pairs.  Every kernel of the step
+ * is launched for the capacity and idles past the actual count, so the same
+ * launch sequence (or captured graph) serves steps whose pair counts differ.
+ * The workspace must already hold max_pairs (locc_reserve), else RANGE. */
+LOCC_API locc_status locc_detect_device_count(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                              const int32_t* d_pairs, const int32_t* d_n_pairs, int32_t max_pairs,
+                                              locc_contact* d_out, int32_t* d_counts, void* stream);
+
+/* One simulation step's detect captured once as a HIP graph and replayed.
+ * The graph keeps the device pointers given here: the caller updates the
+ * objects, pairs and *d_n_pairs in place between launches (for example with
+ * asynchronous copies on the launch stream before locc_graph_launch).
+ * Capture uses a stream of the library's own, reserves the workspace first,
+ * and records no memset node.  The schedule in force at capture time is the
+ * one replayed.  Errors: INVALID_ARG, NOT_READY, OOM, HIP. */
+typedef struct locc_graph locc_graph;
+LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                        const int32_t* d_pairs, const int32_t* d_n_pairs, int32_t max_pairs,
+                                        locc_contact* d_out, int32_t* d_counts, locc_graph** out);
+LOCC_API locc_status locc_graph_launch(locc_graph* graph, void* stream);
+LOCC_API void locc_graph_destroy(locc_graph* graph);
 
 /* Per-kernel timing.  While enabled, every kernel the context launches is
  * bracketed by two HIP events recorded on its launch stream; reading

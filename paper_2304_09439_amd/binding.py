@@ -23,7 +23,9 @@ PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
            "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
-           "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule")
+           "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
+           "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
+           "locc_graph_destroy")
 
 
 class Config(ctypes.Structure):
@@ -34,7 +36,11 @@ class Config(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("claim", ctypes.c_int32), ("dynamic", ctypes.c_int32),
-                ("split", ctypes.c_int32)]
+                ("split", ctypes.c_int32), ("crop_unroll", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self):
+        return dict(wg_per_cu=self.wg_per_cu, claim=self.claim, dynamic=bool(self.dynamic), split=bool(self.split),
+                    crop_unroll=self.crop_unroll)
 
 
 class KernelTime(ctypes.Structure):
@@ -87,6 +93,19 @@ def load() -> ctypes.CDLL:
     L.locc_set_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
     L.locc_get_schedule.restype = ctypes.c_int
     L.locc_get_schedule.argtypes = [vp, ctypes.POINTER(Schedule)]
+    L.locc_autotune.restype = ctypes.c_int
+    L.locc_autotune.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, ctypes.c_char_p, ctypes.POINTER(Schedule),
+                                ctypes.POINTER(ctypes.c_double)]
+    L.locc_reserve.restype = ctypes.c_int
+    L.locc_reserve.argtypes = [vp, i32]
+    L.locc_detect_device_count.restype = ctypes.c_int
+    L.locc_detect_device_count.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp, vp]
+    L.locc_graph_capture.restype = ctypes.c_int
+    L.locc_graph_capture.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp, ctypes.POINTER(vp)]
+    L.locc_graph_launch.restype = ctypes.c_int
+    L.locc_graph_launch.argtypes = [vp, vp]
+    L.locc_graph_destroy.restype = None
+    L.locc_graph_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -214,14 +233,46 @@ class Context:
                                          _ptr(z), _ptr(y), self._stream(stream)))
         return out, counts, z, y
 
-    def set_schedule(self, wg_per_cu: int = 2, claim: int = 1, dynamic: bool = True, split: bool = False):
-        sc = Schedule(wg_per_cu, claim, int(dynamic), int(split))
+    def set_schedule(self, wg_per_cu: int = 2, claim: int = 4, dynamic: bool = True, split: bool = True,
+                     crop_unroll: int = 8):
+        sc = Schedule(wg_per_cu, claim, int(dynamic), int(split), crop_unroll)
         _check(load().locc_set_schedule(self._h, ctypes.byref(sc)))
 
     def get_schedule(self) -> dict:
         sc = Schedule()
         _check(load().locc_get_schedule(self._h, ctypes.byref(sc)))
-        return dict(wg_per_cu=sc.wg_per_cu, claim=sc.claim, dynamic=bool(sc.dynamic), split=bool(sc.split))
+        return sc.as_dict()
+
+    def autotune(self, objs, pairs, cache_path=None, stream=None):
+        """Time every schedule on this workload, install and return the fastest: (schedule dict, ms)."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        out = torch.empty((P, 8), dtype=torch.float32, device=objs.device)
+        counts = torch.empty((P, 2), dtype=torch.int32, device=objs.device)
+        sc = Schedule()
+        ms = ctypes.c_double()
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(load().locc_autotune(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
+                                    self._stream(stream), path, ctypes.byref(sc), ctypes.byref(ms)))
+        return sc.as_dict(), ms.value
+
+    def reserve(self, max_pairs: int):
+        _check(load().locc_reserve(self._h, int(max_pairs)))
+
+    def detect_device_count(self, objs, pairs, n_dev, out, counts=None, stream=None):
+        """Detect on the first *n_dev pairs (n_dev: int32 [1] device tensor); pairs/out sized for the capacity."""
+        n_objs, cap = self._inputs(objs, pairs)
+        _check(load().locc_detect_device_count(self._h, _ptr(objs), n_objs, _ptr(pairs), _ptr(n_dev), cap,
+                                               _ptr(out), _ptr(counts), self._stream(stream)))
+        return out, counts
+
+    def capture_graph(self, objs, pairs, n_dev, out, counts=None) -> "Graph":
+        """Capture one step (device pair count) as a HIP graph over these buffers."""
+        n_objs, cap = self._inputs(objs, pairs)
+        g = ctypes.c_void_p()
+        _check(load().locc_graph_capture(self._h, _ptr(objs), n_objs, _ptr(pairs), _ptr(n_dev), cap, _ptr(out),
+                                         _ptr(counts), ctypes.byref(g)))
+        return Graph(self, g, (objs, pairs, n_dev, out, counts))
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""
@@ -239,6 +290,27 @@ class Context:
         n = ctypes.c_int64()
         _check(load().locc_device_errors(self._h, self._stream(stream), ctypes.byref(n), int(reset)))
         return n.value
+
+
+class Graph:
+    """A captured step; keeps its context and buffers alive."""
+
+    def __init__(self, ctx, handle, buffers):
+        self.ctx, self._h, self._buffers = ctx, handle, buffers
+
+    def launch(self, stream=None):
+        _check(load().locc_graph_launch(self._h, self.ctx._stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().locc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def context_for_scene(scene, K, widths, weights_flat, pad=0.01, precision="fp32", device=0):

@@ -62,8 +62,10 @@ struct locc_ctx {
   unsigned char* d_wbf16 = nullptr;
   bool have_weights = false;
   // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
-  locc_schedule sched{kFusedWgPerCu, 4, 1, 1};  // measured best on the 16384-pair workload: split, claim 4
+  locc_schedule sched{kFusedWgPerCu, 4, 1, 1, 8, {0, 0, 0}};  // split, claim 4: best on 16384 pairs
   unsigned int* d_queue = nullptr;
+  hipStream_t capture_stream = nullptr;  // created on first graph capture
+  bool capturing = false;
   // workspace
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -132,6 +134,8 @@ hipError_t drain_profile(locc_ctx* c) {
 
 locc_status ensure_workspace(locc_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return LOCC_OK;
+  if (c->capturing)
+    return fail(LOCC_ERR_RANGE, "workspace of %zu bytes too small for %zu during graph capture", c->ws_bytes, bytes);
   if (c->d_ws) HIP_TRY(hipFree(c->d_ws));  // implicit device synchronisation
   c->d_ws = nullptr;
   c->ws_bytes = 0;
@@ -143,40 +147,42 @@ locc_status ensure_workspace(locc_ctx* c, size_t bytes) {
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// Workspace of one launch, carved from the context's buffer:
+//   FP32 path: PairMeta [P], float rows [P][2K][8], pooled features z [P][2 h2]
+//   BF16 split: PairMeta [P], bf16 rows [P][2K][8]
+//   BF16 fused: nothing
 struct Workspace {
-  PairMeta* meta;
-  float* rows;
-  float* z;
+  PairMeta* meta = nullptr;
+  float* rows = nullptr;
+  float* z = nullptr;
+  unsigned short* rows_bf16 = nullptr;
 };
 
-struct SplitWorkspace {
-  PairMeta* meta;
-  unsigned short* rows;
-};
-
-locc_status carve_split(locc_ctx* c, int n_pairs, SplitWorkspace* w) {
+size_t workspace_bytes(const locc_ctx* c, int n_pairs) {
   const size_t P = (size_t)n_pairs;
   const size_t meta = align256(P * sizeof(PairMeta));
-  const size_t rows = align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
-  locc_status st = ensure_workspace(c, meta + rows);
-  if (st != LOCC_OK) return st;
-  char* b = static_cast<char*>(c->d_ws);
-  w->meta = reinterpret_cast<PairMeta*>(b);
-  w->rows = reinterpret_cast<unsigned short*>(b + meta);
-  return LOCC_OK;
+  if (c->cfg.precision == LOCC_FP32)
+    return meta + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)) +
+           align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
+  if (c->sched.split) return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
+  return 0;
 }
 
 locc_status carve(locc_ctx* c, int n_pairs, Workspace* w) {
-  const size_t P = (size_t)n_pairs;
-  const size_t meta = align256(P * sizeof(PairMeta));
-  const size_t rows = align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float));
-  const size_t z = align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
-  locc_status st = ensure_workspace(c, meta + rows + z);
+  const size_t bytes = workspace_bytes(c, n_pairs);
+  if (bytes == 0) return LOCC_OK;
+  locc_status st = ensure_workspace(c, bytes);
   if (st != LOCC_OK) return st;
+  const size_t P = (size_t)n_pairs;
   char* b = static_cast<char*>(c->d_ws);
   w->meta = reinterpret_cast<PairMeta*>(b);
-  w->rows = reinterpret_cast<float*>(b + meta);
-  w->z = reinterpret_cast<float*>(b + meta + rows);
+  b += align256(P * sizeof(PairMeta));
+  if (c->cfg.precision == LOCC_FP32) {
+    w->rows = reinterpret_cast<float*>(b);
+    w->z = reinterpret_cast<float*>(b + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)));
+  } else {
+    w->rows_bf16 = reinterpret_cast<unsigned short*>(b);
+  }
   return LOCC_OK;
 }
 
@@ -198,13 +204,32 @@ int fused_grid(const locc_ctx* c, int n_pairs) {
   return tiles < grid ? tiles : grid;
 }
 
-locc_status run_fused(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
-                      locc_contact* out, int32_t* counts, float* z_out, float* y_out, hipStream_t s) {
+// One step of the path for n_pairs pairs (the capacity when n_dev is set).
+locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
+                     const int32_t* n_dev, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
+                     hipStream_t s) {
+  if (n_pairs == 0) return LOCC_OK;
+  Workspace w{};
+  locc_status st = carve(c, n_pairs, &w);
+  if (st != LOCC_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  const int unroll = c->sched.crop_unroll;
+  if (c->cfg.precision == LOCC_FP32) {
+    CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
+                nullptr, counts, w.meta, w.rows, nullptr, c->d_err};
+    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
+    const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
+    NetArgs na{w.rows, w.meta, objs, n_pairs, n_dev, c->cfg.K, z_out ? z_out : w.z, y_out, out};
+    HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+    HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
+    return LOCC_OK;
+  }
   FusedArgs fa{};
   fa.objs = objs;
   fa.n_objs = n_objs;
   fa.pairs = pairs;
   fa.n_pairs = n_pairs;
+  fa.n_pairs_dev = n_dev;
   fa.lib = c->lib();
   fa.K = c->cfg.K;
   fa.pad = c->cfg.pad_m;
@@ -218,50 +243,102 @@ locc_status run_fused(locc_ctx* c, const locc_object* objs, int32_t n_objs, cons
   fa.claim = c->sched.claim;
   fa.dynamic = c->sched.dynamic;
   const int grid = fused_grid(c, n_pairs);
+  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
   if (c->sched.split) {
-    SplitWorkspace w{};
-    locc_status st = carve_split(c, n_pairs, &w);
-    if (st != LOCC_OK) return st;
-    CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, nullptr, w.rows, c->d_err};
-    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
-    fa.rows_bf16 = w.rows;
+    CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
+                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err};
+    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
+    fa.rows_bf16 = w.rows_bf16;
     fa.meta = w.meta;
     fa.counts = nullptr;        // written by the crop kernel
     fa.err_counter = nullptr;   // counted by the crop kernel
-    HIP_TRY(timed(c, "encoder_head_bf16", s, [&] {
-      return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, true, s);
-    }));
+    HIP_TRY(timed(c, "encoder_head_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, true, s); }));
     return LOCC_OK;
   }
-  HIP_TRY(timed(c, "fused_bf16", s, [&] {
-    return launch_fused_bf16(fa, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, grid, false, s);
-  }));
+  HIP_TRY(timed(c, "fused_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, false, s); }));
   return LOCC_OK;
 }
 
-locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
-                     int32_t n_pairs, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
-                     hipStream_t s) {
-  if (n_pairs == 0) return LOCC_OK;
-  Workspace w{};
-  if (c->cfg.precision == LOCC_FP32) {
-    locc_status st = carve(c, n_pairs, &w);
-    if (st != LOCC_OK) return st;
-  }
-  HIP_TRY(hipSetDevice(c->device));
-  if (c->cfg.precision == LOCC_BF16) return run_fused(c, objs, n_objs, pairs, n_pairs, out, counts, z_out, y_out, s);
-  CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
-              nullptr, counts, w.meta, w.rows, nullptr, c->d_err};
-  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
-  const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
-  NetArgs na{w.rows, w.meta, objs, n_pairs, c->cfg.K, z_out ? z_out : w.z, y_out, out};
-  HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
-  HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
+locc_status check_schedule(const locc_schedule* sc) {
+  if (sc->wg_per_cu < 1 || sc->wg_per_cu > kFusedWgPerCu)
+    return fail(LOCC_ERR_INVALID_ARG, "wg_per_cu=%d: must be 1..%d", sc->wg_per_cu, kFusedWgPerCu);
+  if (sc->claim < 1 || sc->claim > 64) return fail(LOCC_ERR_INVALID_ARG, "claim=%d: must be 1..64", sc->claim);
+  if (sc->dynamic != 0 && sc->dynamic != 1) return fail(LOCC_ERR_INVALID_ARG, "dynamic must be 0 or 1");
+  if (sc->split != 0 && sc->split != 1) return fail(LOCC_ERR_INVALID_ARG, "split must be 0 or 1");
+  if (sc->crop_unroll != 2 && sc->crop_unroll != 4 && sc->crop_unroll != 8)
+    return fail(LOCC_ERR_INVALID_ARG, "crop_unroll=%d: must be 2, 4 or 8", sc->crop_unroll);
+  if (sc->reserved[0] || sc->reserved[1] || sc->reserved[2])
+    return fail(LOCC_ERR_INVALID_ARG, "reserved fields must be 0");
   return LOCC_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+std::string tune_key(const locc_ctx* c, int n_pairs) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, c->device);
+  int bucket = 0;
+  while ((1 << (bucket + 1)) <= n_pairs) ++bucket;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/cu%d/K%d/h%d-%d-%d/p%d/pairs2^%d", prop.gcnArchName, c->n_cu, c->cfg.K,
+                c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, c->cfg.precision, bucket);
+  for (char* q = buf; *q; ++q)
+    if (*q == ' ') *q = '_';
+  return buf;
+}
+
+bool tune_cache_lookup(const char* path, const std::string& key, locc_schedule* sc, double* ms) {
+  if (!path) return false;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char k[256];
+  locc_schedule t{};
+  double m = 0;
+  bool hit = false;
+  while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &t.wg_per_cu, &t.claim, &t.dynamic, &t.split,
+                     &t.crop_unroll, &m) == 7) {
+    if (key == k && check_schedule(&t) == LOCC_OK) {
+      *sc = t;
+      *ms = m;
+      hit = true;
+    }
+  }
+  std::fclose(f);
+  return hit;
+}
+
+void tune_cache_store(const char* path, const std::string& key, const locc_schedule& sc, double ms) {
+  if (!path) return;
+  std::FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), sc.wg_per_cu, sc.claim, sc.dynamic, sc.split,
+               sc.crop_unroll, ms);
+  std::fclose(f);
+}
+
+std::vector<locc_schedule> tune_candidates(const locc_ctx* c) {
+  std::vector<locc_schedule> out;
+  if (c->cfg.precision == LOCC_FP32) {
+    for (int u : {2, 4, 8}) out.push_back(locc_schedule{kFusedWgPerCu, 4, 1, 0, u, {0, 0, 0}});
+    return out;
+  }
+  for (int split : {1, 0})
+    for (int wg : {2, 1})
+      for (int claim : {1, 4, 16})
+        for (int dyn : {1, 0})
+          for (int u : {4, 8}) {
+            if (!split && u != 8) continue;  // the fused kernel's scan unroll is fixed
+            out.push_back(locc_schedule{wg, claim, dyn, split, u, {0, 0, 0}});
+          }
+  return out;
 }
 
 }  // namespace
+
+struct locc_graph {
+  locc_ctx* ctx = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -317,6 +394,7 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_wfp32);
   (void)hipFree(c->d_wbf16);
   (void)hipFree(c->d_queue);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   (void)hipFree(c->d_ws);
   (void)hipFree(c->d_err);
   delete c;
@@ -412,7 +490,7 @@ locc_status locc_detect(locc_ctx* c, const locc_object* objs, int32_t n_objs, co
   locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
   if (st != LOCC_OK) return st;
   if (n_pairs > 0 && !out) return fail(LOCC_ERR_INVALID_ARG, "null output");
-  return run_path(c, objs, n_objs, pairs, n_pairs, out, counts, nullptr, nullptr,
+  return run_path(c, objs, n_objs, pairs, n_pairs, nullptr, out, counts, nullptr, nullptr,
                   static_cast<hipStream_t>(stream));
 }
 
@@ -422,7 +500,7 @@ locc_status locc_debug_forward(locc_ctx* c, const locc_object* objs, int32_t n_o
   locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
   if (st != LOCC_OK) return st;
   if (n_pairs > 0 && !out) return fail(LOCC_ERR_INVALID_ARG, "null output");
-  return run_path(c, objs, n_objs, pairs, n_pairs, out, counts, z, y, static_cast<hipStream_t>(stream));
+  return run_path(c, objs, n_objs, pairs, n_pairs, nullptr, out, counts, z, y, static_cast<hipStream_t>(stream));
 }
 
 locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
@@ -434,20 +512,17 @@ locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
   if (n_pairs == 0) return LOCC_OK;
   HIP_TRY(hipSetDevice(c->device));
-  CropArgs ca{objs, n_objs, pairs, n_pairs, c->lib(), c->cfg.K, c->cfg.pad_m,
+  CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), c->cfg.K, c->cfg.pad_m,
               idx, counts, nullptr, nullptr, nullptr, c->d_err};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s); }));
+  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));
   return LOCC_OK;
 }
 
 locc_status locc_set_schedule(locc_ctx* c, const locc_schedule* sc) {
   if (!c || !sc) return fail(LOCC_ERR_INVALID_ARG, "null context or schedule");
-  if (sc->wg_per_cu < 1 || sc->wg_per_cu > kFusedWgPerCu)
-    return fail(LOCC_ERR_INVALID_ARG, "wg_per_cu=%d: must be 1..%d", sc->wg_per_cu, kFusedWgPerCu);
-  if (sc->claim < 1 || sc->claim > 64) return fail(LOCC_ERR_INVALID_ARG, "claim=%d: must be 1..64", sc->claim);
-  if (sc->dynamic != 0 && sc->dynamic != 1) return fail(LOCC_ERR_INVALID_ARG, "dynamic must be 0 or 1");
-  if (sc->split != 0 && sc->split != 1) return fail(LOCC_ERR_INVALID_ARG, "split must be 0 or 1");
+  locc_status st = check_schedule(sc);
+  if (st != LOCC_OK) return st;
   c->sched = *sc;
   return LOCC_OK;
 }
@@ -484,6 +559,131 @@ locc_status locc_profile_read(locc_ctx* c, locc_kernel_time* out, int32_t capaci
     ++n;
   }
   *count = n;
+  return LOCC_OK;
+}
+
+locc_status locc_reserve(locc_ctx* c, int32_t max_pairs) {
+  if (!c || max_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "null context or negative size");
+  HIP_TRY(hipSetDevice(c->device));
+  // the largest workspace any schedule of this context could need
+  const locc_schedule keep = c->sched;
+  c->sched.split = 1;
+  const size_t bytes = workspace_bytes(c, max_pairs);
+  c->sched = keep;
+  return ensure_workspace(c, bytes);
+}
+
+locc_status locc_detect_device_count(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                                     const int32_t* n_dev, int32_t max_pairs, locc_contact* out, int32_t* counts,
+                                     void* stream) {
+  locc_status st = check_call(c, objs, n_objs, pairs, max_pairs);
+  if (st != LOCC_OK) return st;
+  if (!n_dev) return fail(LOCC_ERR_INVALID_ARG, "null device pair count");
+  if (max_pairs > 0 && !out) return fail(LOCC_ERR_INVALID_ARG, "null output");
+  if (workspace_bytes(c, max_pairs) > c->ws_bytes)
+    return fail(LOCC_ERR_RANGE, "workspace holds fewer than %d pairs: call locc_reserve first", max_pairs);
+  return run_path(c, objs, n_objs, pairs, max_pairs, n_dev, out, counts, nullptr, nullptr,
+                  static_cast<hipStream_t>(stream));
+}
+
+locc_status locc_graph_capture(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                               const int32_t* n_dev, int32_t max_pairs, locc_contact* out, int32_t* counts,
+                               locc_graph** graph) {
+  if (!graph) return fail(LOCC_ERR_INVALID_ARG, "null graph output");
+  *graph = nullptr;
+  locc_status st = check_call(c, objs, n_objs, pairs, max_pairs);
+  if (st != LOCC_OK) return st;
+  if (!n_dev || max_pairs <= 0 || !out) return fail(LOCC_ERR_INVALID_ARG, "null count or output, or no capacity");
+  st = locc_reserve(c, max_pairs);
+  if (st != LOCC_OK) return st;
+  if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+  HIP_TRY(hipDeviceSynchronize());
+  const bool prof = c->profiling;
+  c->profiling = false;  // no event nodes in the graph
+  c->capturing = true;
+  HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
+  st = run_path(c, objs, n_objs, pairs, max_pairs, n_dev, out, counts, nullptr, nullptr, c->capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
+  c->capturing = false;
+  c->profiling = prof;
+  if (st != LOCC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(LOCC_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  locc_graph* G = new locc_graph();
+  G->ctx = c;
+  G->graph = g;
+  const hipError_t e2 = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    locc_graph_destroy(G);
+    return fail(LOCC_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  }
+  *graph = G;
+  return LOCC_OK;
+}
+
+locc_status locc_graph_launch(locc_graph* G, void* stream) {
+  if (!G || !G->exec) return fail(LOCC_ERR_INVALID_ARG, "null graph");
+  HIP_TRY(hipSetDevice(G->ctx->device));
+  HIP_TRY(hipGraphLaunch(G->exec, static_cast<hipStream_t>(stream)));
+  return LOCC_OK;
+}
+
+void locc_graph_destroy(locc_graph* G) {
+  if (!G) return;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  delete G;
+}
+
+locc_status locc_autotune(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                          int32_t n_pairs, locc_contact* out, int32_t* counts, void* stream, const char* cache_path,
+                          locc_schedule* best, double* best_ms) {
+  locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
+  if (st != LOCC_OK) return st;
+  if (!best || (n_pairs > 0 && !out)) return fail(LOCC_ERR_INVALID_ARG, "null output or result");
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const std::string key = tune_key(c, n_pairs);
+  locc_schedule pick = c->sched;
+  double pick_ms = 0.0;
+  if (!tune_cache_lookup(cache_path, key, &pick, &pick_ms)) {
+    st = locc_reserve(c, n_pairs);
+    if (st != LOCC_OK) return st;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const bool prof = c->profiling;
+    c->profiling = false;
+    pick_ms = 1e30;
+    for (const locc_schedule& cand : tune_candidates(c)) {
+      c->sched = cand;
+      st = run_path(c, objs, n_objs, pairs, n_pairs, nullptr, out, counts, nullptr, nullptr, s);
+      if (st != LOCC_OK) break;
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < 3 && st == LOCC_OK; ++r)
+        st = run_path(c, objs, n_objs, pairs, n_pairs, nullptr, out, counts, nullptr, nullptr, s);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (st != LOCC_OK) break;
+      if (ms / 3.0 < pick_ms) {
+        pick_ms = ms / 3.0;
+        pick = cand;
+      }
+    }
+    c->profiling = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LOCC_OK) return st;
+    tune_cache_store(cache_path, key, pick, pick_ms);
+  }
+  c->sched = pick;
+  *best = pick;
+  if (best_ms) *best_ms = pick_ms;
   return LOCC_OK;
 }
 

@@ -15,6 +15,7 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int K = A.K;
+  if (p >= pair_count(A.n_pairs, A.n_pairs_dev)) return;  // uniform
 
   int a = -1, swapped = 0;
   locc_object oa, ob;

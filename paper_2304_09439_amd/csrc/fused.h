@@ -9,7 +9,8 @@ struct FusedArgs {
   const locc_object* objs;
   int32_t n_objs;
   const int32_t* pairs;
-  int32_t n_pairs;
+  int32_t n_pairs;              // capacity
+  const int32_t* n_pairs_dev;   // actual count in device memory, or null
   DeviceLibrary lib;
   int32_t K;
   double pad;

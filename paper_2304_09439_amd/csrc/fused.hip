@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
   const int g = lane >> 5;
   const int l32 = lane & 31;
   const int K = A.K;
-  const int P = A.n_pairs;
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
 
   // this wave's W2 slice, layer-1 weights and layer-2 bias stay in registers
   u16x8 w2f[CT][KS2];

@@ -52,11 +52,22 @@ struct DeviceLibrary {
   const float* nz;
 };
 
+// Pair count of a launch: n_pairs is the capacity (grid sizing); when
+// n_pairs_dev is set the kernels read the actual count from device memory
+// (clamped to the capacity), so one captured graph serves steps whose pair
+// counts differ.
+__device__ __forceinline__ int pair_count(int capacity, const int32_t* dev) {
+  if (!dev) return capacity;
+  const int n = *dev;
+  return n < 0 ? 0 : (n < capacity ? n : capacity);
+}
+
 struct CropArgs {
   const locc_object* objs;
   int32_t n_objs;
   const int32_t* pairs;
   int32_t n_pairs;
+  const int32_t* n_pairs_dev;  // or null
   DeviceLibrary lib;
   int32_t K;
   double pad;
@@ -91,6 +102,7 @@ struct NetArgs {
   const PairMeta* meta;   // [P]
   const locc_object* objs;
   int32_t n_pairs;
+  const int32_t* n_pairs_dev;  // or null
   int32_t K;
   float* z;               // [P][2 h2] workspace (always written)
   float* y_dbg;           // [P][8] or null

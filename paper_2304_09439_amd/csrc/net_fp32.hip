@@ -62,7 +62,8 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) bias2[ct] = W.b2[(wave * CT + ct) * 32 + (lane & 31)];
 
-  for (int p = blockIdx.x; p < A.n_pairs; p += gridDim.x) {
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
+  for (int p = blockIdx.x; p < P; p += gridDim.x) {
     const PairMeta mt = A.meta[p];
     float* zp = A.z + (size_t)p * 2 * H2;
     if (mt.a < 0) {
@@ -76,9 +77,11 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
     }
     for (int side = 0; side < 2; ++side) {
       const int m = side ? mt.m_b : mt.m_a;
+      // max-pool of the raw sums, bias and ReLU once per column afterwards
+      // (exact: rounding and ReLU are monotone; an empty set gives 0)
       float run[CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) run[ct] = 0.f;
+      for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
       const float* rbase = A.rows + ((size_t)p * 2 * K + side * K) * kRowFloats;
       for (int r0 = 0; r0 < m; r0 += 32) {
         const float4 xv = *reinterpret_cast<const float4*>(rbase + (r0 + (lane & 31)) * kRowFloats + 4 * g);
@@ -101,19 +104,25 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h, w2f[ct][ft * 16 + r], acc2[ct]);
           }
+        if (r0 + 32 <= m) {
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
+          for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
-            const float v = fmaxf(acc2[ct][r] + bias2[ct], 0.f);
-            if (row < m) run[ct] = fmaxf(run[ct], v);
-          }
+            for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+        } else {
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+              if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+            }
+        }
       }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        run[ct] = fmaxf(run[ct], __shfl_xor(run[ct], 32, 64));
-        if (lane < 32) zp[side * H2 + (wave * CT + ct) * 32 + lane] = run[ct];
+        const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) + bias2[ct], 0.f);
+        if (lane < 32) zp[side * H2 + (wave * CT + ct) * 32 + lane] = f;
       }
     }
   }
@@ -135,12 +144,14 @@ __global__ __launch_bounds__(256, 1) void head_fp32_kernel(Fp32Net W, NetArgs A)
   const int wave = tid >> 6;
   const int g = lane >> 5;
   const int p0 = blockIdx.x * kHeadPairs;
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
+  if (p0 >= P) return;  // uniform
 
   for (int e = tid; e < kHeadPairs * Z; e += 256) {
     const int i = e / Z, k = e - i * Z;
     const int p = p0 + i;
     float v = 0.f;
-    if (p < A.n_pairs) {
+    if (p < P) {
       v = A.z[(size_t)p * Z + k];
       if (v != v) v = 0.f;  // invalid pair: its outputs are NaN-ed in the epilogue
     }
@@ -197,7 +208,7 @@ __global__ __launch_bounds__(256, 1) void head_fp32_kernel(Fp32Net W, NetArgs A)
 
   if (tid < kHeadPairs) {
     const int p = p0 + tid;
-    if (p < A.n_pairs) {
+    if (p < P) {
       const PairMeta mt = A.meta[p];
       float out[8];
       const float* y = ys[tid];

@@ -401,3 +401,125 @@ def gaussian_weights(widths: Widths, seed: int = 0, bias_std: float = 0.0):
 
 def flatten_weights(layers) -> np.ndarray:
     return np.concatenate([np.asarray(a, np.float32).ravel() for a in layers])
+
+
+# ----------------------------------------------------------------------------
+# uneven environments (a batched simulation) and its host broad phase
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class EnvSteps:
+    """Objects of many independent environments over several simulation steps.
+
+    Every environment shares one world region (as vectorised simulations do);
+    objects only pair with objects of their own environment.
+      shape  int32 [n]            shape id per object
+      env    int32 [n]            environment of each object
+      pos    float32 [S, n, 3]    positions per step
+      quat   float32 [S, n, 4]    orientations per step (w, x, y, z)
+      pairs  list of int32 [P_s, 2]: broad-phase pairs of step s (i < j)
+    """
+    lib: ShapeLibrary
+    shape: np.ndarray
+    env: np.ndarray
+    pos: np.ndarray
+    quat: np.ndarray
+    pairs: list
+    side: float
+
+    @property
+    def n_steps(self) -> int:
+        return len(self.pairs)
+
+    def scene(self, step: int) -> Scene:
+        return Scene(self.lib, self.pos[step], self.quat[step], self.shape, self.pairs[step])
+
+
+def _local_boxes(lib: ShapeLibrary):
+    """Centre and half extent of each shape's point cloud (float64 [S, 3])."""
+    c = np.empty((lib.n_shapes, 3))
+    e = np.empty((lib.n_shapes, 3))
+    for s in range(lib.n_shapes):
+        p = lib.shape_points(s)[:, :3].astype(np.float64)
+        lo, hi = p.min(axis=0), p.max(axis=0)
+        c[s], e[s] = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    return c, e
+
+
+def broad_phase(lib_boxes, shape, env_slices, pos, quat) -> np.ndarray:
+    """All pairs (i < j) of one environment whose world bounding boxes overlap.
+
+    The world box of an object is the axis-aligned hull of its rotated local
+    box, computed with scipy's rotation matrices.  Returns int32 [P, 2].
+    """
+    c_loc, e_loc = lib_boxes
+    R = _scipy_rot(quat).as_matrix()
+    cw = np.einsum("nij,nj->ni", R, c_loc[shape]) + pos
+    ew = np.einsum("nij,nj->ni", np.abs(R), e_loc[shape])
+    lo, hi = cw - ew, cw + ew
+    out = []
+    for n, starts in env_slices:
+        iu, ju = np.triu_indices(n, 1)
+        if len(iu) == 0:
+            continue
+        I = starts[:, None] + iu[None, :]
+        J = starts[:, None] + ju[None, :]
+        ok = np.all((lo[I] <= hi[J]) & (lo[J] <= hi[I]), axis=-1)
+        out.append(np.stack([I[ok], J[ok]], axis=1))
+    return np.concatenate(out).astype(np.int32) if out else np.zeros((0, 2), np.int32)
+
+
+def env_workload(master: int = 3, n_envs: int = 4096, max_objects: int = 40, steps: int = 200,
+                 target_pairs: float = 2e5, lib: ShapeLibrary = None, jitter_m: float = 0.002,
+                 jitter_rad: float = 0.02) -> EnvSteps:
+    """Uneven environments: n_e ~ U{1..max_objects} objects per environment.
+
+    Shapes are drawn from the 32-shape library of the at-scale workload,
+    orientations are uniform, positions uniform in a cube whose side is set
+    (by bisection on the first step) so that the broad phase yields about
+    target_pairs pairs; each later step jitters every pose slightly.
+    """
+    g = streams(master)
+    if lib is None:
+        lib = scale_library()
+    rng = g[STREAM_ENVS]
+    sizes = rng.integers(1, max_objects + 1, n_envs)
+    n = int(sizes.sum())
+    env = np.repeat(np.arange(n_envs, dtype=np.int32), sizes)
+    starts_all = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    env_slices = [(int(k), starts_all[sizes == k]) for k in np.unique(sizes)]
+    shape = rng.integers(0, lib.n_shapes, n).astype(np.int32)
+    boxes = _local_boxes(lib)
+    q0 = uniform_quaternions(rng, n)
+    u0 = rng.random((n, 3)) - 0.5
+
+    def count(side):
+        return len(broad_phase(boxes, shape, env_slices, u0 * side, q0))
+
+    lo_s, hi_s = 0.05, 5.0
+    for _ in range(30):
+        mid = np.sqrt(lo_s * hi_s)
+        if count(mid) > target_pairs:
+            lo_s = mid
+        else:
+            hi_s = mid
+    side = float(np.sqrt(lo_s * hi_s))
+    pos = np.empty((steps, n, 3), np.float32)
+    quat = np.empty((steps, n, 4), np.float32)
+    t = u0 * side
+    q = q0.copy()
+    pairs = []
+    for s in range(steps):
+        if s:
+            t = t + rng.normal(0.0, jitter_m, t.shape)
+            axis = rng.normal(size=(n, 3))
+            axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+            ang = rng.normal(0.0, jitter_rad, n)
+            dq = np.concatenate([np.cos(ang / 2)[:, None], axis * np.sin(ang / 2)[:, None]], axis=1)
+            r = _scipy_rot(dq) * _scipy_rot(q)
+            xyzw = r.as_quat()
+            q = np.concatenate([xyzw[:, 3:], xyzw[:, :3]], axis=1)
+        pos[s] = t
+        quat[s] = q
+        pairs.append(broad_phase(boxes, shape, env_slices, pos[s].astype(np.float64), quat[s]))
+    return EnvSteps(lib, shape, env, pos, quat, pairs, side)

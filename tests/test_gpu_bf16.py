@@ -97,10 +97,14 @@ def test_bf16_fused_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene)
     _check(out[rows], counts[rows], z[rows], y[rows], ref, "scale sample")
 
 
-SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True), dict(wg_per_cu=1, claim=1, dynamic=True),
-             dict(wg_per_cu=2, claim=4, dynamic=True), dict(wg_per_cu=2, claim=3, dynamic=False),
-             dict(wg_per_cu=1, claim=64, dynamic=False), dict(wg_per_cu=2, claim=1, dynamic=True, split=True),
-             dict(wg_per_cu=2, claim=8, dynamic=False, split=True)]
+SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True, split=False),
+             dict(wg_per_cu=1, claim=1, dynamic=True, split=False),
+             dict(wg_per_cu=2, claim=4, dynamic=True, split=False),
+             dict(wg_per_cu=2, claim=3, dynamic=False, split=False),
+             dict(wg_per_cu=1, claim=64, dynamic=False, split=False),
+             dict(wg_per_cu=2, claim=1, dynamic=True, split=True, crop_unroll=2),
+             dict(wg_per_cu=2, claim=8, dynamic=False, split=True, crop_unroll=4),
+             dict(wg_per_cu=1, claim=4, dynamic=True, split=True, crop_unroll=8)]
 
 
 def test_bf16_results_do_not_depend_on_the_schedule(torch, small_scene):
