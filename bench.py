@@ -42,8 +42,17 @@ KERNEL_SOURCES = {
 }
 PATH_DESC = {
     "fp32": "per-step FP32: crop, encoder and head kernels on one stream",
-    "bf16": "batched BF16: one persistent fused crop+encoder+head launch per step",
+    "bf16": "batched BF16 (schedule chosen by the library's autotuner)",
 }
+
+
+def bf16_desc(schedule):
+    if not schedule:
+        return PATH_DESC["bf16"]
+    if schedule["split"]:
+        return ("batched BF16: crop kernel, then one persistent encoder+head launch over all pairs "
+                f"(autotuned: {schedule})")
+    return f"batched BF16: one persistent fused crop+encoder+head launch over all pairs (autotuned: {schedule})"
 
 
 def workload(name: str):
@@ -166,6 +175,9 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     out = torch.empty((P, 8), dtype=torch.float32, device="cuda")
     counts = torch.empty((P, 2), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    schedule = None
+    if precision != "fp32" and not args.no_autotune:
+        schedule, _ = ctx.autotune(objs, pairs)   # the library's own autotuner picks the schedule
     for _ in range(args.warmup):
         ctx.detect(objs, pairs, out, counts)
     torch.cuda.synchronize()
@@ -188,10 +200,85 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     ctx.close()
     ms = 1000.0 * wall / args.steps
     kernels = kernel_entries(kt, work, P, workload_name)
-    return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4),
+    return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
-                kernels=kernels, device_errors=int(n_bad), path=PATH_DESC[precision])
+                kernels=kernels, device_errors=int(n_bad),
+                path=PATH_DESC["fp32"] if precision == "fp32" else bf16_desc(schedule))
+
+
+def time_envs(args, envs, w, precision):
+    """One simulation step of the uneven-environment workload: H2D of every pose, the step's broad-phase
+    pairs and their count from pinned host buffers, then the detect (a replayed HIP graph for the
+    batched path, eager launches for the plain FP32 path).  Timed per step with events."""
+    import numpy as np
+    import torch
+    from paper_2304_09439_amd import binding as B
+    widths = envs_widths()
+    ctx = B.Context(128, widths, precision=precision)
+    ctx.upload_shapes(envs.lib.offsets, envs.lib.pts)
+    ctx.upload_weights(w)
+    S = envs.n_steps
+    n_obj = len(envs.shape)
+    cap = max(len(p) for p in envs.pairs)
+    objs_h = [torch.from_numpy(B.pack_objects(envs.pos[s], envs.quat[s], envs.shape)).pin_memory() for s in range(S)]
+    pairs_h = [torch.from_numpy(np.ascontiguousarray(p)).pin_memory() for p in envs.pairs]
+    n_h = [torch.tensor([len(p)], dtype=torch.int32).pin_memory() for p in envs.pairs]
+    objs = torch.empty((n_obj, 8), dtype=torch.float32, device="cuda")
+    pairs = torch.zeros((cap, 2), dtype=torch.int32, device="cuda")
+    n_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = torch.empty((cap, 8), dtype=torch.float32, device="cuda")
+    counts = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    ctx.reserve(cap)
+    graph, schedule = None, None
+    if precision != "fp32":
+        objs.copy_(objs_h[0])
+        pairs[:len(envs.pairs[0])].copy_(pairs_h[0])
+        if not args.no_autotune:
+            schedule, _ = ctx.autotune(objs, pairs[:len(envs.pairs[0])])
+        graph = ctx.capture_graph(objs, pairs, n_dev, out, counts)
+    stream = torch.cuda.current_stream()
+
+    def step(s):
+        P = len(envs.pairs[s])
+        objs.copy_(objs_h[s], non_blocking=True)
+        pairs[:P].copy_(pairs_h[s], non_blocking=True)
+        if graph is not None:
+            n_dev.copy_(n_h[s], non_blocking=True)
+            graph.launch()
+        else:
+            ctx.detect(objs, pairs[:P], out[:P], counts[:P])
+
+    for s in range(min(3, S)):
+        step(s)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(S)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(S):
+        ev[s][0].record(stream)
+        step(s)
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    total_pairs = sum(len(p) for p in envs.pairs)
+    n_bad = ctx.device_errors()
+    if graph is not None:
+        graph.close()
+    ctx.close()
+    return dict(value=round(total_pairs / wall, 1), unit=UNIT, steps=S, mean_pairs_per_step=round(total_pairs / S),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
+                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+                mean_step_ms=round(float(step_ms.mean()), 4), schedule=schedule, device_errors=int(n_bad),
+                path=("HIP graph per step (H2D of poses, pairs and count + replay), " + bf16_desc(schedule))
+                if graph is not None else "eager per step (H2D of poses and pairs + launches), " + PATH_DESC[precision])
+
+
+def envs_widths():
+    from paper_2304_09439_amd import inputs as I
+    wd = I.SCALE_WIDTHS
+    return (wd.h1, wd.h2, wd.hh)
 
 
 def run(args):
@@ -228,13 +315,21 @@ def run(args):
         ms_per_step=main_path["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32" if primary == "fp32" else primary, data="synthetic",
         config=dict(workload=W["desc"], pairs=scene.n_pairs, K=K, points_per_shape=W["n_points"],
-                    shapes=W["n_shapes"], precision=primary, geometry="f64", path=PATH_DESC[primary]),
+                    shapes=W["n_shapes"], precision=primary, geometry="f64", path=main_path["path"]),
         p50_step_ms=main_path["p50_step_ms"], p99_step_ms=main_path["p99_step_ms"],
         roofline=roofline, kernels=kernels, cpu_baseline=cpu, device_errors=main_path["device_errors"],
         paths={p: {k: v for k, v in r.items()} for p, r in paths.items()},
     )
     if "fp32" in paths and primary != "fp32":
         line["speedup_vs_fp32_plain"] = round(main_path["value"] / paths["fp32"]["value"], 3)
+    if args.env_steps > 0:
+        envs = I.env_workload(steps=args.env_steps)
+        print(f"[bench] uneven environments: {len(envs.shape)} objects, "
+              f"{sum(len(p) for p in envs.pairs) / envs.n_steps:.0f} pairs per step", file=sys.stderr, flush=True)
+        line["environments"] = dict(
+            workload=f"4096 environments, 1-40 objects each ({len(envs.shape)} objects) from the 32-shape library, "
+                     f"cube side {envs.side:.3f} m, {args.env_steps} jittered steps, host broad phase ahead of time",
+            **{p: time_envs(args, envs, w, p) for p in precisions})
     print(json.dumps(line), flush=True)
 
 
@@ -295,6 +390,9 @@ def main():
     ap.add_argument("--precision", default="fp32,bf16",
                     help="comma list of paths to time: fp32 (per-step) and/or bf16 (fused); bf16 is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
+    ap.add_argument("--env-steps", type=int, default=40,
+                    help="simulation steps of the uneven-environment workload to time (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
