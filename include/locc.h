@@ -237,6 +237,77 @@ LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs
 LOCC_API locc_status locc_graph_launch(locc_graph* graph, void* stream);
 LOCC_API void locc_graph_destroy(locc_graph* graph);
 
+/* Serving.  A server keeps an object table (poses) and the context's shape
+ * library and weights resident on the device, and runs a worker thread that
+ * batches collision-detection requests continuously: each request brings
+ * pose updates for some objects and a list of pairs; requests that arrive
+ * while earlier ones are on the GPU join the next batch as soon as a slot
+ * (device buffers sized from the memory budget) is free, and up to `slots`
+ * batches are in flight at once on separate streams.
+ *
+ * Batches are formed first in, first out: the first queued request that
+ * does not fit the slot, or that conflicts with a request in flight or in
+ * the same batch (it updates an object another one reads or updates, or
+ * reads one another updates), waits for the next batch.  A request's pairs
+ * therefore see the object table after its own updates and after every
+ * earlier request's, and its result is the same whether it runs alone or
+ * in a mix.  While a server runs, no other call may use its context.
+ *
+ *   max_objects        size of the resident object table
+ *   max_batch_pairs    pairs per batch; 0 = as many as the budget allows
+ *   max_batch_updates  pose updates per batch (>= the largest request's)
+ *   slots              batches in flight at once (1 .. 4)
+ *   batching           1: continuous batching; 0: one request per launch
+ *                      and one slot (the plain per-request path)
+ *   max_queued_pairs   host queue limit in pairs (0 = none); submit
+ *                      returns BUSY beyond it
+ *   hbm_budget_bytes   device memory the server may allocate (object
+ *                      table + every slot's buffers and scratch) */
+typedef struct {
+  int32_t max_objects;
+  int32_t max_batch_pairs;
+  int32_t max_batch_updates;
+  int32_t slots;
+  int32_t batching;
+  int32_t max_queued_pairs;
+  size_t hbm_budget_bytes;
+} locc_serve_config;
+
+typedef struct {
+  int64_t submitted, completed, batches, pairs_done;
+  int64_t max_batch_pairs; /* pairs per batch the budget allowed */
+  double busy_ms;          /* wall time with at least one batch in flight */
+} locc_serve_stats;
+
+typedef struct locc_server locc_server;
+
+/* Starts a server on ctx with the initial object table h_objects [n_objects]
+ * (host, copied).  Errors: INVALID_ARG, NOT_READY (no shapes / weights),
+ * OOM (budget too small for one slot of the given sizes), HIP. */
+LOCC_API locc_status locc_serve_start(locc_ctx* ctx, const locc_serve_config* cfg, const locc_object* h_objects,
+                                      int32_t n_objects, locc_server** out);
+
+/* Queues one request (host arrays, copied): n_upd pose updates
+ * (h_upd_ids[k] gets pose h_upd[k]) and n_pairs pairs of object indices.
+ * Returns its id.  Errors: INVALID_ARG (null, index out of the table),
+ * RANGE (larger than one batch), BUSY (queue full: retry later). */
+LOCC_API locc_status locc_serve_submit(locc_server* srv, const int32_t* h_upd_ids, const locc_object* h_upd,
+                                       int32_t n_upd, const int32_t* h_pairs, int32_t n_pairs, uint64_t* h_req_id);
+
+/* *h_done = 1 once the request has completed; then its contacts and counts
+ * are copied to h_out [n_pairs] / h_counts [n_pairs][2] (either may be NULL),
+ * *h_latency_ms (may be NULL) is completion minus submission on the host's
+ * steady clock, and the request is forgotten.  *h_done = 0 otherwise.
+ * Errors: INVALID_ARG (unknown id). */
+LOCC_API locc_status locc_serve_poll(locc_server* srv, uint64_t req_id, locc_contact* h_out, int32_t* h_counts,
+                                     int32_t* h_done, double* h_latency_ms);
+
+LOCC_API locc_status locc_serve_get_stats(locc_server* srv, locc_serve_stats* h_stats);
+
+/* Finishes every queued request, joins the worker and frees the server's
+ * device memory.  Unpolled results are dropped.  NULL is a no-op. */
+LOCC_API locc_status locc_serve_stop(locc_server* srv);
+
 /* Per-kernel timing.  While enabled, every kernel the context launches is
  * bracketed by two HIP events recorded on its launch stream; reading
  * synchronises on the recorded events and returns, per kernel name, the

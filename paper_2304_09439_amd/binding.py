@@ -25,7 +25,8 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
            "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
-           "locc_graph_destroy")
+           "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
+           "locc_serve_stop")
 
 
 class Config(ctypes.Structure):
@@ -41,6 +42,17 @@ class Schedule(ctypes.Structure):
     def as_dict(self):
         return dict(wg_per_cu=self.wg_per_cu, claim=self.claim, dynamic=bool(self.dynamic), split=bool(self.split),
                     crop_unroll=self.crop_unroll)
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_objects", ctypes.c_int32), ("max_batch_pairs", ctypes.c_int32),
+                ("max_batch_updates", ctypes.c_int32), ("slots", ctypes.c_int32), ("batching", ctypes.c_int32),
+                ("max_queued_pairs", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("pairs_done", ctypes.c_int64), ("max_batch_pairs", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
 
 
 class KernelTime(ctypes.Structure):
@@ -106,6 +118,17 @@ def load() -> ctypes.CDLL:
     L.locc_graph_launch.argtypes = [vp, vp]
     L.locc_graph_destroy.restype = None
     L.locc_graph_destroy.argtypes = [vp]
+    L.locc_serve_start.restype = ctypes.c_int
+    L.locc_serve_start.argtypes = [vp, ctypes.POINTER(ServeConfig), vp, i32, ctypes.POINTER(vp)]
+    L.locc_serve_submit.restype = ctypes.c_int
+    L.locc_serve_submit.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.locc_serve_poll.restype = ctypes.c_int
+    L.locc_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.locc_serve_get_stats.restype = ctypes.c_int
+    L.locc_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.locc_serve_stop.restype = ctypes.c_int
+    L.locc_serve_stop.argtypes = [vp]
     _lib = L
     return L
 
@@ -309,6 +332,65 @@ class Graph:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop on a context (locc_serve_* in locc.h).
+
+    Host numpy arrays in, host numpy arrays out; the context must not be used
+    by other calls until stop().
+    """
+
+    def __init__(self, ctx: Context, objects, max_objects=None, batching=True, slots=2, max_batch_pairs=0,
+                 max_batch_updates=4096, max_queued_pairs=0, hbm_budget_bytes=1 << 30):
+        objs = np.ascontiguousarray(objects, np.float32)
+        n = len(objs)
+        self.cfg = ServeConfig(max_objects or n, max_batch_pairs, max_batch_updates, slots, int(batching),
+                               max_queued_pairs, hbm_budget_bytes)
+        h = ctypes.c_void_p()
+        _check(load().locc_serve_start(ctx._h, ctypes.byref(self.cfg), objs.ctypes.data, n, ctypes.byref(h)))
+        self._h, self.ctx = h, ctx
+        self._n_pairs = {}
+
+    def submit(self, upd_ids, upd_objects, pairs) -> int:
+        ids = np.ascontiguousarray(upd_ids, np.int32)
+        upd = np.ascontiguousarray(upd_objects, np.float32)
+        pr = np.ascontiguousarray(pairs, np.int32)
+        rid = ctypes.c_uint64()
+        _check(load().locc_serve_submit(self._h, ids.ctypes.data, upd.ctypes.data, len(ids), pr.ctypes.data,
+                                        len(pr), ctypes.byref(rid)))
+        self._n_pairs[rid.value] = len(pr)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while running; (contacts [P, 8], counts [P, 2], latency_ms) once done."""
+        P = self._n_pairs[rid]
+        out = np.empty((P, 8), np.float32)
+        counts = np.empty((P, 2), np.int32)
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        _check(load().locc_serve_poll(self._h, rid, out.ctypes.data, counts.ctypes.data, ctypes.byref(done),
+                                      ctypes.byref(lat)))
+        if not done.value:
+            return None
+        del self._n_pairs[rid]
+        return out, counts, lat.value
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(load().locc_serve_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(load().locc_serve_stop(h))
+
+    def __del__(self):
+        try:
+            self.stop()
         except Exception:
             pass
 

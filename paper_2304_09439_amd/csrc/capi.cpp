@@ -10,12 +10,11 @@
 #include <string>
 #include <vector>
 
-#include "fused.h"
-#include "locc_internal.h"
+#include "context.h"
 
 using namespace locc;
 
-namespace {
+namespace locc {
 
 thread_local std::string g_last_error;
 
@@ -29,13 +28,9 @@ locc_status fail(locc_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                       \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(e_ == hipErrorOutOfMemory ? LOCC_ERR_OOM : LOCC_ERR_HIP, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
-  } while (0)
+}  // namespace locc
+
+namespace {
 
 bool widths_supported(int h1, int h2, int hh) {
   return (h1 == 64 && h2 == 128 && hh == 256) || (h1 == 128 && h2 == 256 && hh == 512);
@@ -48,44 +43,6 @@ size_t weight_floats(int h1, int h2, int hh) {
 
 }  // namespace
 
-struct locc_ctx {
-  locc_config cfg{};
-  int device = 0;
-  int n_cu = 0;
-  // shape library
-  int32_t n_shapes = 0;
-  int64_t n_points = 0;
-  ShapeDesc* d_shapes = nullptr;
-  float* d_points = nullptr;  // SoA: x, y, z, nx, ny, nz, each n_points floats
-  // weights
-  float* d_wfp32 = nullptr;
-  unsigned char* d_wbf16 = nullptr;
-  bool have_weights = false;
-  // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
-  locc_schedule sched{kFusedWgPerCu, 4, 1, 1, 8, {0, 0, 0}};  // split, claim 4: best on 16384 pairs
-  unsigned int* d_queue = nullptr;
-  hipStream_t capture_stream = nullptr;  // created on first graph capture
-  bool capturing = false;
-  // workspace
-  void* d_ws = nullptr;
-  size_t ws_bytes = 0;
-  unsigned long long* d_err = nullptr;
-  // event timing of each launch (locc_profile)
-  struct Pending {
-    std::string name;
-    hipEvent_t start, stop;
-  };
-  bool profiling = false;
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> event_pool;
-  std::map<std::string, std::pair<int64_t, double>> totals;
-
-  DeviceLibrary lib() const {
-    const float* b = d_points;
-    const size_t n = (size_t)n_points;
-    return DeviceLibrary{d_shapes, n_shapes, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n};
-  }
-};
 
 namespace {
 
@@ -158,7 +115,9 @@ struct Workspace {
   unsigned short* rows_bf16 = nullptr;
 };
 
-size_t workspace_bytes(const locc_ctx* c, int n_pairs) {
+}  // namespace
+
+size_t locc::workspace_bytes(const locc_ctx* c, int n_pairs) {
   const size_t P = (size_t)n_pairs;
   const size_t meta = align256(P * sizeof(PairMeta));
   if (c->cfg.precision == LOCC_FP32)
@@ -168,13 +127,21 @@ size_t workspace_bytes(const locc_ctx* c, int n_pairs) {
   return 0;
 }
 
-locc_status carve(locc_ctx* c, int n_pairs, Workspace* w) {
+namespace {
+
+locc_status carve(locc_ctx* c, int n_pairs, Workspace* w, const Scratch* own) {
   const size_t bytes = workspace_bytes(c, n_pairs);
   if (bytes == 0) return LOCC_OK;
-  locc_status st = ensure_workspace(c, bytes);
-  if (st != LOCC_OK) return st;
+  char* b = nullptr;
+  if (own) {
+    if (own->bytes < bytes) return fail(LOCC_ERR_RANGE, "scratch of %zu bytes, %zu needed", own->bytes, bytes);
+    b = static_cast<char*>(own->base);
+  } else {
+    locc_status st = ensure_workspace(c, bytes);
+    if (st != LOCC_OK) return st;
+    b = static_cast<char*>(c->d_ws);
+  }
   const size_t P = (size_t)n_pairs;
-  char* b = static_cast<char*>(c->d_ws);
   w->meta = reinterpret_cast<PairMeta*>(b);
   b += align256(P * sizeof(PairMeta));
   if (c->cfg.precision == LOCC_FP32) {
@@ -186,8 +153,10 @@ locc_status carve(locc_ctx* c, int n_pairs, Workspace* w) {
   return LOCC_OK;
 }
 
-locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
-                       int32_t n_pairs) {
+}  // namespace
+
+locc_status locc::check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                             int32_t n_pairs) {
   if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
   if (n_objs < 0 || n_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "negative count (n_objs=%d, n_pairs=%d)",
                                              n_objs, n_pairs);
@@ -197,6 +166,8 @@ locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, con
   return LOCC_OK;
 }
 
+namespace {
+
 int fused_grid(const locc_ctx* c, int n_pairs) {
   const int claim = c->sched.claim;
   const int tiles = (n_pairs + claim - 1) / claim;
@@ -204,13 +175,14 @@ int fused_grid(const locc_ctx* c, int n_pairs) {
   return tiles < grid ? tiles : grid;
 }
 
-// One step of the path for n_pairs pairs (the capacity when n_dev is set).
-locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
-                     const int32_t* n_dev, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
-                     hipStream_t s) {
+}  // namespace
+
+locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                           int32_t n_pairs, const int32_t* n_dev, locc_contact* out, int32_t* counts, float* z_out,
+                           float* y_out, hipStream_t s, const Scratch* own) {
   if (n_pairs == 0) return LOCC_OK;
   Workspace w{};
-  locc_status st = carve(c, n_pairs, &w);
+  locc_status st = carve(c, n_pairs, &w, own);
   if (st != LOCC_OK) return st;
   HIP_TRY(hipSetDevice(c->device));
   const int unroll = c->sched.crop_unroll;
@@ -239,7 +211,7 @@ locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const
   fa.z_dbg = z_out;
   fa.y_dbg = y_out;
   fa.err_counter = c->d_err;
-  fa.queue = c->d_queue;
+  fa.queue = own ? own->queue : c->d_queue;
   fa.claim = c->sched.claim;
   fa.dynamic = c->sched.dynamic;
   const int grid = fused_grid(c, n_pairs);
@@ -258,6 +230,8 @@ locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const
   HIP_TRY(timed(c, "fused_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, false, s); }));
   return LOCC_OK;
 }
+
+namespace {
 
 locc_status check_schedule(const locc_schedule* sc) {
   if (sc->wg_per_cu < 1 || sc->wg_per_cu > kFusedWgPerCu)

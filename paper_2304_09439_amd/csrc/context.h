@@ -1,0 +1,86 @@
+// Library-internal view of a context, shared by the C-ABI and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fused.h"
+#include "locc_internal.h"
+
+struct locc_ctx {
+  locc_config cfg{};
+  int device = 0;
+  int n_cu = 0;
+  // shape library
+  int32_t n_shapes = 0;
+  int64_t n_points = 0;
+  locc::ShapeDesc* d_shapes = nullptr;
+  float* d_points = nullptr;  // SoA: x, y, z, nx, ny, nz, each n_points floats
+  // weights
+  float* d_wfp32 = nullptr;
+  unsigned char* d_wbf16 = nullptr;
+  bool have_weights = false;
+  // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
+  locc_schedule sched{locc::kFusedWgPerCu, 4, 1, 1, 8, {0, 0, 0}};  // split, claim 4: best on 16384 pairs
+  unsigned int* d_queue = nullptr;
+  hipStream_t capture_stream = nullptr;  // created on first graph capture
+  bool capturing = false;
+  // workspace
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  unsigned long long* d_err = nullptr;
+  // event timing of each launch (locc_profile)
+  struct Pending {
+    std::string name;
+    hipEvent_t start, stop;
+  };
+  bool profiling = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  std::map<std::string, std::pair<int64_t, double>> totals;
+
+  locc::DeviceLibrary lib() const {
+    const float* b = d_points;
+    const size_t n = (size_t)n_points;
+    return locc::DeviceLibrary{d_shapes, n_shapes, b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, b + 5 * n};
+  }
+};
+
+
+namespace locc {
+
+// Records a formatted message for locc_last_error() and returns st.
+locc_status fail(locc_status st, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::locc::fail(e_ == hipErrorOutOfMemory ? LOCC_ERR_OOM : LOCC_ERR_HIP,          \
+                          "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+  } while (0)
+
+// Scratch a launch uses: the context's own (grown on demand), or a caller's
+// region of at least workspace_bytes() plus its own queue (serving slots).
+struct Scratch {
+  void* base = nullptr;
+  size_t bytes = 0;
+  unsigned int* queue = nullptr;
+};
+
+// Workspace bytes one launch of n_pairs needs under the current schedule.
+size_t workspace_bytes(const locc_ctx* c, int n_pairs);
+
+// Argument checks shared by the detect entry points.
+locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs);
+
+// One step of the path for n_pairs pairs (the capacity when n_dev is set),
+// enqueued on stream s.
+locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
+                     const int32_t* n_dev, locc_contact* out, int32_t* counts, float* z_out, float* y_out,
+                     hipStream_t s, const Scratch* own = nullptr);
+
+}  // namespace locc

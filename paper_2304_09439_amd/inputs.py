@@ -523,3 +523,73 @@ def env_workload(master: int = 3, n_envs: int = 4096, max_objects: int = 40, ste
         quat[s] = q
         pairs.append(broad_phase(boxes, shape, env_slices, pos[s].astype(np.float64), quat[s]))
     return EnvSteps(lib, shape, env, pos, quat, pairs, side)
+
+
+# ----------------------------------------------------------------------------
+# serving: a stream of simulation-step requests over resident environments
+# ----------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class RequestStream:
+    """Requests over a resident object table.
+
+    shape, pos0, quat0   the initial table (every object of every environment)
+    requests             list of (upd_ids int32 [u], pos float32 [u, 3],
+                         quat float32 [u, 4], pairs int32 [p, 2]); a request
+                         updates every object of the environments it covers,
+                         so its result depends only on its own data
+    """
+    lib: ShapeLibrary
+    shape: np.ndarray
+    pos0: np.ndarray
+    quat0: np.ndarray
+    requests: list
+
+    @property
+    def pairs_per_request(self) -> np.ndarray:
+        return np.array([len(r[3]) for r in self.requests])
+
+
+def serve_library(master: int = 4, n_shapes: int = 128, n_points: int = 4096) -> ShapeLibrary:
+    """128 shapes of 4096 points, drawn like the at-scale library (3-6 ellipsoids / boxes)."""
+    return shape_library(streams(master)[STREAM_SHAPES], n_shapes, n_points, (3, 6), 0.5)
+
+
+def request_stream(master: int = 4, n_requests: int = 10000, lib: ShapeLibrary = None, n_envs: int = 4096,
+                   versions: int = 4, min_pairs: int = 8, max_pairs: int = 2000) -> RequestStream:
+    """Simulation-step requests: pairs per request ~ log-uniform[min_pairs, max_pairs].
+
+    The environments (uneven, 1-40 objects) are stepped `versions` times;
+    each request takes distinct random environments of one random version
+    until it has enough broad-phase pairs, updates all their objects to that
+    version's poses and keeps the first n of their pairs.
+    """
+    g = streams(master)
+    if lib is None:
+        lib = serve_library(master)
+    env = env_workload(master, n_envs=n_envs, steps=versions, lib=lib, target_pairs=2e5 * n_envs / 4096)
+    rng = g[STREAM_REQUESTS]
+    members = np.split(np.arange(len(env.shape)), np.flatnonzero(np.diff(env.env)) + 1)
+    by_env = []
+    for v in range(versions):
+        pr = env.pairs[v]
+        owner = env.env[pr[:, 0]]
+        order = np.argsort(owner, kind="stable")
+        cuts = np.searchsorted(owner[order], np.arange(n_envs + 1))
+        by_env.append([pr[order[cuts[e]:cuts[e + 1]]] for e in range(n_envs)])
+    targets = np.exp(rng.uniform(np.log(min_pairs), np.log(max_pairs), n_requests)).astype(int)
+    reqs = []
+    for t in targets:
+        v = int(rng.integers(versions))
+        envs, have = [], 0
+        for e in rng.permutation(n_envs):
+            if len(by_env[v][e]) == 0:
+                continue
+            envs.append(e)
+            have += len(by_env[v][e])
+            if have >= t:
+                break
+        ids = np.concatenate([members[e] for e in envs]).astype(np.int32)
+        pairs = np.concatenate([by_env[v][e] for e in envs])[:t].astype(np.int32)
+        reqs.append((ids, env.pos[v][ids], env.quat[v][ids], pairs))
+    return RequestStream(lib, env.shape, env.pos[0], env.quat[0], reqs)
