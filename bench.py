@@ -7,7 +7,7 @@ per-step latency percentiles, the roofline of the dominant kernel (timed with
 HIP events on its launch stream inside the library) and the CPU FP64 oracle
 timed on this host on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32,bf16]
+  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32,bf16,fp8]
 
 Counter post-processing (turns rocprofv3 --pmc CSV output into a summary):
   python bench.py --summarize-counters FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME
@@ -38,11 +38,16 @@ KERNEL_SOURCES = {
     "crop": ["crop.hip", "geometry.h"],
     "encoder_fp32": ["net_fp32.hip"],
     "head_fp32": ["net_fp32.hip"],
-    "fused_bf16": ["fused.hip", "fused.h", "geometry.h"],
+    "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
+    "encoder_head_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
+    "encoder_head_fp8": ["fused_fp8.hip", "fused.h", "post.h"],
 }
 PATH_DESC = {
     "fp32": "per-step FP32: crop, encoder and head kernels on one stream",
     "bf16": "batched BF16 (schedule chosen by the library's autotuner)",
+    "fp8": "batched FP8: crop kernel, then one persistent encoder+head launch (encoder layer 2 and head "
+           "layers 1-2 e4m3 x e4m3, encoder layer 1 and head layer 3 bf16; activation scales calibrated "
+           "on the first 1,024 pairs)",
 }
 
 
@@ -147,12 +152,13 @@ def kernel_entries(kt, work, P, workload_name):
             entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
                          frac=round(achieved / PEAK_HBM_GBPS, 4))
         else:
-            if name.startswith("encoder"):
+            if name.startswith("encoder_head") or name.startswith("fused"):
+                flops = (work["enc_flops"] + work["head_flops"]) * P
+            elif name.startswith("encoder"):
                 flops = work["enc_flops"] * P
             elif name.startswith("head"):
                 flops = work["head_flops"] * P
-            else:  # fused: the whole network
-                flops = (work["enc_flops"] + work["head_flops"]) * P
+            if name.startswith("fused"):  # crop inside: its bytes too
                 gbps = (work["crop_bytes"] + work["contact_bytes"]) * P / (avg * 1e-3) / 1e9
                 entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
             prec = name.split("_")[-1]
@@ -176,7 +182,13 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     counts = torch.empty((P, 2), dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
     schedule = None
-    if precision != "fp32" and not args.no_autotune:
+    if precision == "fp8":
+        amax = ctx.calibrate(objs, pairs[:min(P, 1024)])
+        print(f"[bench] fp8: activation maxima {amax.tolist()}", file=sys.stderr, flush=True)
+    if precision != "fp32" and args.schedule.get(precision):
+        ctx.set_schedule(**args.schedule[precision])   # a schedule given on the command line
+        schedule = ctx.get_schedule()
+    elif precision != "fp32" and not args.no_autotune:
         schedule, _ = ctx.autotune(objs, pairs)   # the library's own autotuner picks the schedule
     for _ in range(args.warmup):
         ctx.detect(objs, pairs, out, counts)
@@ -204,7 +216,8 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
                 kernels=kernels, device_errors=int(n_bad),
-                path=PATH_DESC["fp32"] if precision == "fp32" else bf16_desc(schedule))
+                path={"fp32": PATH_DESC["fp32"], "fp8": PATH_DESC["fp8"] + f" (autotuned: {schedule})"}.get(
+                    precision, bf16_desc(schedule)))
 
 
 def time_envs(args, envs, w, precision):
@@ -275,6 +288,102 @@ def time_envs(args, envs, w, precision):
                 if graph is not None else "eager per step (H2D of poses and pairs + launches), " + PATH_DESC[precision])
 
 
+def serve_run(B, srv, reqs, arrivals):
+    """Submit requests at their arrival times (seconds from start; None = all at once) while polling
+    completions.  Returns (per-request latency ms = submit lag + library-measured latency, wall s)."""
+    import numpy as np
+    n = len(reqs)
+    lat = np.zeros(n)
+    pending = {}
+    t0 = time.perf_counter()
+    k = 0
+    while k < n or pending:
+        now = time.perf_counter() - t0
+        while k < n and (arrivals is None or arrivals[k] <= now):
+            ids, upd, pairs = reqs[k]
+            while True:
+                try:
+                    rid = srv.submit(ids, upd, pairs)
+                    break
+                except B.LoccError as e:   # queue full: poll and retry
+                    if e.status != B.ERR_BUSY:
+                        raise
+                    time.sleep(50e-6)
+            lag = (time.perf_counter() - t0) - (arrivals[k] if arrivals is not None else 0.0)
+            pending[rid] = (k, lag * 1e3)
+            k += 1
+            now = time.perf_counter() - t0
+        done = []
+        for rid, (j, lag) in pending.items():
+            r = srv.poll(rid)
+            if r is not None:
+                lat[j] = lag + r[2]
+                done.append(rid)
+        for rid in done:
+            del pending[rid]
+    return lat, time.perf_counter() - t0
+
+
+def serve_bench(args, w):
+    """Serving workload: Poisson stream of simulation-step requests over resident environments."""
+    import numpy as np
+    from paper_2304_09439_amd import binding as B
+    from paper_2304_09439_amd import inputs as I
+    rs = I.request_stream(n_requests=args.serve_requests)
+    table = B.pack_objects(rs.pos0, rs.quat0, rs.shape)
+    reqs = [(ids, B.pack_objects(pos, quat, rs.shape[ids]), np.ascontiguousarray(pairs))
+            for ids, pos, quat, pairs in rs.requests]
+    pp = rs.pairs_per_request
+    total = int(pp.sum())
+    print(f"[bench] serving: {len(reqs)} requests, mean {pp.mean():.1f} pairs, {len(rs.shape)} resident objects",
+          file=sys.stderr, flush=True)
+    wd = envs_widths()
+    max_upd = max(len(r[0]) for r in reqs)
+
+    def server(precision, batching):
+        ctx = B.Context(128, wd, precision=precision)
+        ctx.upload_shapes(rs.lib.offsets, rs.lib.pts)
+        ctx.upload_weights(w)
+        return ctx, B.Server(ctx, table, batching=batching, slots=3, max_batch_pairs=32768,
+                             max_batch_updates=max(max_upd, 65536), hbm_budget_bytes=8 << 30)
+
+    def summary(lat, wall):
+        return dict(p50_latency_ms=round(float(np.percentile(lat, 50)), 4),
+                    p99_latency_ms=round(float(np.percentile(lat, 99)), 4),
+                    throughput=round(total / wall, 1), unit=UNIT, wall_s=round(wall, 3))
+
+    out = dict(workload=f"{len(reqs)} requests, pairs per request log-uniform in [8, 2000] (mean {pp.mean():.1f}), "
+                        f"128 shapes x 4096 points, {len(rs.shape)} resident objects in 4096 environments")
+    # saturation of the plain FP32 per-request path sets the offered load
+    ctx, srv = server("fp32", False)
+    serve_run(B, srv, reqs[:200], None)                      # warm-up
+    lat, wall = serve_run(B, srv, reqs, None)
+    sat_fp32 = total / wall
+    srv.stop()
+    ctx.close()
+    rate = 0.7 * sat_fp32 / pp.mean()
+    arrivals = np.cumsum(np.random.default_rng(44).exponential(1.0 / rate, len(reqs)))
+    out["offered_load"] = dict(requests_per_s=round(rate, 1), fraction_of_fp32_saturation=0.7,
+                               fp32_per_request_saturated=round(sat_fp32, 1))
+    for name, precision, batching in (("fp32_per_request", "fp32", False), ("bf16_batched", "bf16", True)):
+        ctx, srv = server(precision, batching)
+        serve_run(B, srv, reqs[:200], None)
+        lat, wall = serve_run(B, srv, reqs, arrivals)
+        st = srv.stats()
+        srv.stop()
+        res = summary(lat, wall)
+        res["batches"] = int(st["batches"])
+        out[name] = res
+        ctx.close()
+    ctx, srv = server("bf16", True)
+    serve_run(B, srv, reqs[:200], None)
+    lat, wall = serve_run(B, srv, reqs, None)
+    srv.stop()
+    ctx.close()
+    out["bf16_batched_saturated"] = summary(lat, wall)
+    return out
+
+
 def envs_widths():
     from paper_2304_09439_amd import inputs as I
     wd = I.SCALE_WIDTHS
@@ -322,6 +431,8 @@ def run(args):
     )
     if "fp32" in paths and primary != "fp32":
         line["speedup_vs_fp32_plain"] = round(main_path["value"] / paths["fp32"]["value"], 3)
+    if args.serve_requests > 0:
+        line["serving"] = serve_bench(args, w)
     if args.env_steps > 0:
         envs = I.env_workload(steps=args.env_steps)
         print(f"[bench] uneven environments: {len(envs.shape)} objects, "
@@ -329,7 +440,7 @@ def run(args):
         line["environments"] = dict(
             workload=f"4096 environments, 1-40 objects each ({len(envs.shape)} objects) from the 32-shape library, "
                      f"cube side {envs.side:.3f} m, {args.env_steps} jittered steps, host broad phase ahead of time",
-            **{p: time_envs(args, envs, w, p) for p in precisions})
+            **{p: time_envs(args, envs, w, p) for p in precisions if p in ("fp32", "bf16")})
     print(json.dumps(line), flush=True)
 
 
@@ -387,10 +498,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale", choices=["scale", "small"])
-    ap.add_argument("--precision", default="fp32,bf16",
-                    help="comma list of paths to time: fp32 (per-step) and/or bf16 (fused); bf16 is the headline")
+    ap.add_argument("--schedule", action="append", default=[], metavar="PREC:WG,CLAIM,DYN,SPLIT,UNROLL",
+                    help="fix the schedule of a batched path instead of autotuning it, e.g. bf16:2,16,1,1,4 "
+                         "(repeatable; used to profile the schedule a previous run picked)")
+    ap.add_argument("--precision", default="fp32,bf16,fp8",
+                    help="comma list of paths to time: fp32 (per-step), bf16 (batched, the headline), fp8 (batched)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the serving workload (0 = skip)")
     ap.add_argument("--env-steps", type=int, default=40,
                     help="simulation steps of the uneven-environment workload to time (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
@@ -400,6 +516,12 @@ def main():
     ap.add_argument("--kernel-match", default="encoder_fp32_kernel")
     ap.add_argument("--copy-kernel", default="neg_kernel")
     args = ap.parse_args()
+    sched = {}
+    for item in args.schedule:
+        prec, vals = item.split(":")
+        wg, claim, dyn, split, unroll = (int(v) for v in vals.split(","))
+        sched[prec] = dict(wg_per_cu=wg, claim=claim, dynamic=bool(dyn), split=bool(split), crop_unroll=unroll)
+    args.schedule = sched
     if args.summarize_counters:
         return summarize_counters(args)
     if args.gpus != 1:

@@ -66,7 +66,13 @@ typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2 } locc_precision;
  *   precision  arithmetic of the encoder and head (locc_precision);
  *              the crop geometry is float64 in every precision.
  *              LOCC_FP32 runs the per-step path (crop, encoder, head
- *              kernels); LOCC_BF16 runs one fused persistent kernel
+ *              kernels); LOCC_BF16 runs one fused persistent kernel or
+ *              a crop kernel plus a persistent network kernel (see
+ *              locc_schedule); LOCC_FP8 runs the crop kernel plus a
+ *              persistent network kernel whose encoder layer 2 and head
+ *              layers 1-2 multiply OCP e4m3 operands (encoder layer 1 and
+ *              head layer 3 stay bf16) and needs activation maxima
+ *              (locc_calibrate or locc_set_activation_amax) first
  * Compiled width sets: (h1, h2, hh) = (64, 128, 256) and (128, 256, 512). */
 typedef struct {
   int32_t K;
@@ -128,6 +134,28 @@ LOCC_API void locc_destroy(locc_ctx* ctx);
  * Low precisions quantise from these values (per-layer scales for FP8).
  * Errors: INVALID_ARG (null, wrong n_floats, non-finite value), OOM, HIP. */
 LOCC_API locc_status locc_upload_weights(locc_ctx* ctx, const float* h_weights, size_t n_floats);
+
+/* FP8 contexts: activation scales of the quantised encoder and head layers
+ * (Sec. III and appendix "Architecture Details" define the layers; the
+ * quantisation is this library's).  Each e4m3 layer input x enters as
+ * e4m3(min(x / s, 448)) with s = amax / 448, a static per-layer scale; the
+ * weights carry their own per-layer scale (amax|W| / 448) set at upload.
+ * amax[0]: encoder layer-1 output (after ReLU), amax[1]: pooled encoder
+ * features [f_a, f_b], amax[2]: head layer-1 output (after ReLU).
+ *
+ * locc_calibrate measures them: it runs the crop step on the given workload
+ * (valid input for locc_detect, device buffers as there) and a float32
+ * forward pass of the uploaded (unquantised) weights over the valid pairs,
+ * takes the maxima, installs them and, if h_amax_out is not NULL, copies them
+ * to host memory.  It synchronises `stream` and may grow the workspace.
+ * locc_set_activation_amax installs given maxima (host memory, finite,
+ * >= 0; 0 means the activation is always 0).  locc_upload_weights clears
+ * them: calibrate again after new weights.
+ * Errors: INVALID_ARG (null, bad values), UNSUPPORTED (not an FP8 context),
+ * NOT_READY (no shapes or weights), RANGE (during graph capture), OOM, HIP. */
+LOCC_API locc_status locc_calibrate(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                           int32_t n_pairs, void* stream, float* h_amax_out);
+LOCC_API locc_status locc_set_activation_amax(locc_ctx* ctx, const float* h_amax);
 
 /* Shape library: n_shapes point clouds in their own frames, host memory,
  * copied synchronously; replaces any previous library.  Shape s owns rows

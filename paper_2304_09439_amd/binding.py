@@ -26,7 +26,7 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
            "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
-           "locc_serve_stop")
+           "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax")
 
 
 class Config(ctypes.Structure):
@@ -129,6 +129,10 @@ def load() -> ctypes.CDLL:
     L.locc_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.locc_serve_stop.restype = ctypes.c_int
     L.locc_serve_stop.argtypes = [vp]
+    L.locc_calibrate.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+    L.locc_calibrate.restype = ctypes.c_int
+    L.locc_set_activation_amax.argtypes = [vp, vp]
+    L.locc_set_activation_amax.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -278,6 +282,21 @@ class Context:
         _check(load().locc_autotune(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
                                     self._stream(stream), path, ctypes.byref(sc), ctypes.byref(ms)))
         return sc.as_dict(), ms.value
+
+    def calibrate(self, objs, pairs, stream=None):
+        """FP8: measure and install the activation maxima on this workload; returns them (3 floats)."""
+        n_objs, P = self._inputs(objs, pairs)
+        amax = np.zeros(3, np.float32)
+        _check(load().locc_calibrate(self._h, _ptr(objs), n_objs, _ptr(pairs), P, self._stream(stream),
+                                     amax.ctypes.data))
+        return amax
+
+    def set_activation_amax(self, amax):
+        """FP8: install activation maxima (layer-1 output, pooled features, head layer-1 output)."""
+        a = np.ascontiguousarray(amax, np.float32)
+        if a.shape != (3,):
+            raise ValueError("amax: expected 3 floats")
+        _check(load().locc_set_activation_amax(self._h, a.ctypes.data))
 
     def reserve(self, max_pairs: int):
         _check(load().locc_reserve(self._h, int(max_pairs)))

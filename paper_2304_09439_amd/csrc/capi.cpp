@@ -106,7 +106,7 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
 // Workspace of one launch, carved from the context's buffer:
 //   FP32 path: PairMeta [P], float rows [P][2K][8], pooled features z [P][2 h2]
-//   BF16 split: PairMeta [P], bf16 rows [P][2K][8]
+//   BF16 split and FP8: PairMeta [P], bf16 rows [P][2K][8]
 //   BF16 fused: nothing
 struct Workspace {
   PairMeta* meta = nullptr;
@@ -123,7 +123,8 @@ size_t locc::workspace_bytes(const locc_ctx* c, int n_pairs) {
   if (c->cfg.precision == LOCC_FP32)
     return meta + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)) +
            align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
-  if (c->sched.split) return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
+  if (c->sched.split || c->cfg.precision == LOCC_FP8)
+    return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
   return 0;
 }
 
@@ -163,10 +164,15 @@ locc_status locc::check_call(locc_ctx* c, const locc_object* objs, int32_t n_obj
   if (n_pairs > 0 && (!objs || !pairs)) return fail(LOCC_ERR_INVALID_ARG, "null objects or pairs");
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
   if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
+  if (c->cfg.precision == LOCC_FP8 && !c->have_act_scales)
+    return fail(LOCC_ERR_NOT_READY, "FP8: no activation scales (locc_calibrate or locc_set_activation_amax)");
   return LOCC_OK;
 }
 
 namespace {
+
+// Scale of an fp8 activation with maximum amax (448 is e4m3's largest finite value).
+float fp8_scale(float amax) { return amax > 0.f ? amax / 448.f : 1.f; }
 
 int fused_grid(const locc_ctx* c, int n_pairs) {
   const int claim = c->sched.claim;
@@ -196,6 +202,35 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
     HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
     return LOCC_OK;
   }
+  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
+  if (c->cfg.precision == LOCC_FP8) {
+    CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
+                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err};
+    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
+    Fp8Args fa{};
+    fa.objs = objs;
+    fa.n_pairs = n_pairs;
+    fa.n_pairs_dev = n_dev;
+    fa.K = c->cfg.K;
+    fp8_bind(fa, c->d_wfp8, h1, h2, hh);
+    fa.s_w2 = c->fp8_wscale[0];
+    fa.s_h1 = c->fp8_wscale[1];
+    fa.s_h2 = c->fp8_wscale[2];
+    fa.s_h1in = fp8_scale(c->fp8_amax[0]);
+    fa.s_z = fp8_scale(c->fp8_amax[1]);
+    fa.s_g1 = fp8_scale(c->fp8_amax[2]);
+    fa.rows_bf16 = w.rows_bf16;
+    fa.meta = w.meta;
+    fa.out = out;
+    fa.z_dbg = z_out;
+    fa.y_dbg = y_out;
+    fa.queue = own ? own->queue : c->d_queue;
+    fa.claim = c->sched.claim;
+    fa.dynamic = c->sched.dynamic;
+    const int grid = fused_grid(c, n_pairs);
+    HIP_TRY(timed(c, "encoder_head_fp8", s, [&] { return launch_encoder_head_fp8(fa, h1, h2, hh, grid, s); }));
+    return LOCC_OK;
+  }
   FusedArgs fa{};
   fa.objs = objs;
   fa.n_objs = n_objs;
@@ -215,7 +250,6 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   fa.claim = c->sched.claim;
   fa.dynamic = c->sched.dynamic;
   const int grid = fused_grid(c, n_pairs);
-  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
   if (c->sched.split) {
     CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
                 nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err};
@@ -301,6 +335,7 @@ std::vector<locc_schedule> tune_candidates(const locc_ctx* c) {
         for (int dyn : {1, 0})
           for (int u : {4, 8}) {
             if (!split && u != 8) continue;  // the fused kernel's scan unroll is fixed
+            if (!split && c->cfg.precision == LOCC_FP8) continue;  // FP8 runs split only
             out.push_back(locc_schedule{wg, claim, dyn, split, u, {0, 0, 0}});
           }
   return out;
@@ -333,7 +368,6 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (!widths_supported(cfg->enc_h1, cfg->enc_h2, cfg->head_h))
     return fail(LOCC_ERR_UNSUPPORTED, "widths (%d, %d, %d) not compiled in", cfg->enc_h1, cfg->enc_h2,
                 cfg->head_h);
-  if (cfg->precision == LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "precision %d not available", cfg->precision);
   if (device < 0) return fail(LOCC_ERR_INVALID_ARG, "device %d", device);
   int n_dev = 0;
   HIP_TRY(hipGetDeviceCount(&n_dev));
@@ -349,6 +383,7 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&c->d_queue, 2 * sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemset(c->d_queue, 0, 2 * sizeof(unsigned int));
+  if (e == hipSuccess && cfg->precision == LOCC_FP8) e = hipMalloc(&c->d_amax, 3 * sizeof(unsigned int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     locc_destroy(c);
@@ -367,6 +402,9 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_points);
   (void)hipFree(c->d_wfp32);
   (void)hipFree(c->d_wbf16);
+  (void)hipFree(c->d_wfp8);
+  (void)hipFree(c->d_wraw);
+  (void)hipFree(c->d_amax);
   (void)hipFree(c->d_queue);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   (void)hipFree(c->d_ws);
@@ -403,7 +441,67 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     if (!c->d_wbf16) HIP_TRY(hipMalloc(&c->d_wbf16, L.total));
     HIP_TRY(hipMemcpy(c->d_wbf16, bpack.data(), L.total, hipMemcpyHostToDevice));
   }
+  if (c->cfg.precision == LOCC_FP8) {
+    const Fp8Layout L = fp8_layout(h1, h2, hh);
+    std::vector<unsigned char> fpack(L.total);
+    float sc[3];
+    fp8_pack(W1, b1, W2, b2, H1, c1, H2, c2, H3, c3, h1, h2, hh, fpack.data(), sc);
+    if (!c->d_wfp8) HIP_TRY(hipMalloc(&c->d_wfp8, L.total));
+    HIP_TRY(hipMemcpy(c->d_wfp8, fpack.data(), L.total, hipMemcpyHostToDevice));
+    if (!c->d_wraw) HIP_TRY(hipMalloc(&c->d_wraw, n * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
+    for (int k = 0; k < 3; ++k) c->fp8_wscale[k] = sc[k];
+    c->have_act_scales = false;  // activation maxima belong to the previous weights
+  }
   c->have_weights = true;
+  return LOCC_OK;
+}
+
+locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
+  if (!c || !amax) return fail(LOCC_ERR_INVALID_ARG, "null context or maxima");
+  if (c->cfg.precision != LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "activation maxima: not an FP8 context");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(amax[k]) || amax[k] < 0.f)
+      return fail(LOCC_ERR_INVALID_ARG, "activation maximum %d = %g: must be finite and >= 0", k, amax[k]);
+  if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
+  for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
+  c->have_act_scales = true;
+  return LOCC_OK;
+}
+
+locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                           int32_t n_pairs, void* stream, float* amax_out) {
+  if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
+  if (c->cfg.precision != LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "calibration: not an FP8 context");
+  if (n_objs < 0 || n_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "negative count");
+  if (n_pairs > 0 && (!objs || !pairs)) return fail(LOCC_ERR_INVALID_ARG, "null objects or pairs");
+  if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
+  if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
+  if (c->capturing) return fail(LOCC_ERR_RANGE, "calibration during graph capture");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipSetDevice(c->device));
+  float amax[3] = {0.f, 0.f, 0.f};
+  if (n_pairs > 0) {
+    const size_t P = (size_t)n_pairs;
+    locc_status st = ensure_workspace(c, workspace_bytes(c, n_pairs));
+    if (st != LOCC_OK) return st;
+    PairMeta* meta = reinterpret_cast<PairMeta*>(c->d_ws);
+    unsigned short* rows = reinterpret_cast<unsigned short*>(static_cast<char*>(c->d_ws) + align256(P * sizeof(PairMeta)));
+    CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), c->cfg.K, c->cfg.pad_m,
+                nullptr, nullptr, meta, nullptr, rows, c->d_err};
+    HIP_TRY(launch_crop(ca, s, c->sched.crop_unroll));
+    HIP_TRY(hipMemsetAsync(c->d_amax, 0, 3 * sizeof(unsigned int), s));
+    CalibArgs ka{c->d_wraw, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, n_pairs, c->cfg.K, rows, meta, c->d_amax};
+    const int grid = n_pairs < 8 * c->n_cu ? n_pairs : 8 * c->n_cu;
+    HIP_TRY(launch_calibrate_fp8(ka, grid, s));
+    unsigned int bits[3];
+    HIP_TRY(hipMemcpyAsync(bits, c->d_amax, sizeof bits, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::memcpy(amax, bits, sizeof amax);
+  }
+  for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
+  c->have_act_scales = true;
+  if (amax_out) std::memcpy(amax_out, amax, sizeof amax);
   return LOCC_OK;
 }
 

@@ -22,6 +22,12 @@ struct locc_ctx {
   // weights
   float* d_wfp32 = nullptr;
   unsigned char* d_wbf16 = nullptr;
+  unsigned char* d_wfp8 = nullptr;
+  float* d_wraw = nullptr;         // FP8: the flat FP32 weights, for calibration
+  float fp8_wscale[3] = {1, 1, 1}; // FP8: s_w2, s_h1, s_h2
+  float fp8_amax[3] = {0, 0, 0};   // FP8: activation maxima (layer-1 output, pooled z, head layer 1)
+  bool have_act_scales = false;
+  unsigned int* d_amax = nullptr;  // FP8 calibration accumulator [3]
   bool have_weights = false;
   // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
   locc_schedule sched{locc::kFusedWgPerCu, 4, 1, 1, 8, {0, 0, 0}};  // split, claim 4: best on 16384 pairs

@@ -57,4 +57,68 @@ constexpr int kFusedTile = 32;
 // head only, reading rows_bf16 / meta written by the crop kernel.
 hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, bool precropped, hipStream_t s);
 
+// ---------------------------------------------------------------- FP8 path
+// Encoder + head on the rows the crop kernel wrote, with encoder layer 2 and
+// head layers 1-2 in OCP e4m3 (per-layer scales, FP32 accumulation).
+struct Fp8Args {
+  const locc_object* objs;
+  int32_t n_pairs;              // capacity
+  const int32_t* n_pairs_dev;   // actual count in device memory, or null
+  int32_t K;
+  // packed weights (see fp8_pack)
+  const unsigned short* w1p;    // bf16
+  const unsigned char* w2p;     // e4m3, W2 / s_w2
+  const float* b2;
+  const unsigned char* h1p;     // e4m3, H1 / s_h1
+  const float* c1;
+  const unsigned char* h2p;     // e4m3, H2 / s_h2
+  const float* c2;
+  const unsigned short* h3p;    // bf16
+  const float* c3;
+  // scales: weights (amax / 448) and activations entering an fp8 layer
+  float s_w2, s_h1, s_h2;
+  float s_h1in;  // encoder layer-1 output
+  float s_z;     // pooled encoder features
+  float s_g1;    // head layer-1 output
+  // rows and per-pair records from the crop kernel
+  const unsigned short* rows_bf16;  // [P][2K][8]
+  const PairMeta* meta;             // [P]
+  // outputs
+  locc_contact* out;
+  float* z_dbg;  // [P][2 h2] or null
+  float* y_dbg;  // [P][8] or null
+  // schedule
+  unsigned int* queue;
+  int32_t claim;
+  int32_t dynamic;
+};
+
+struct Fp8Layout {
+  size_t w1, w2, b2, h1, c1, h2, c2, h3, c3, total;
+};
+Fp8Layout fp8_layout(int h1, int h2, int hh);
+// weight_scales receives (s_w2, s_h1, s_h2).
+void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1, const float* c1,
+              const float* H2, const float* c2, const float* H3, const float* c3, int h1, int h2, int hh,
+              unsigned char* dst, float* weight_scales);
+void fp8_bind(Fp8Args& a, const unsigned char* dev_base, int h1, int h2, int hh);
+// OCP e4m3 (E4M3FN) of x, round to nearest even, saturating at 448.
+unsigned char host_e4m3(float x);
+hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, int grid, hipStream_t s);
+
+// Calibration: maxima over the valid pairs of the encoder layer-1 output, the
+// pooled encoder features and the head layer-1 output, computed in FP32 from
+// the crop kernel's rows and the unquantised weights; amax[3] (device, zeroed
+// by the caller) receives them as float bits via atomicMax.
+struct CalibArgs {
+  const float* w;                   // weights, flat (W1, b1, W2, b2, H1, c1, ...)
+  int32_t h1, h2, hh;
+  int32_t n_pairs;
+  int32_t K;
+  const unsigned short* rows_bf16;
+  const PairMeta* meta;
+  unsigned int* amax;
+};
+hipError_t launch_calibrate_fp8(const CalibArgs& a, int grid, hipStream_t s);
+
 }  // namespace locc

@@ -31,6 +31,7 @@
 // more resident workgroups than the encoder's register budget allows.
 #include "fused.h"
 #include "geometry.h"
+#include "post.h"
 
 #include <cstring>
 
@@ -154,37 +155,7 @@ __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& 
     S.y[0][i][j] = ((S.y[0][i][j] + S.y[1][i][j]) + S.y[2][i][j]) + S.y[3][i][j] + A.c3[j];
   }
   __syncthreads();
-  if (tid < n) {
-    const int p = S.pair[tid];
-    const int a = S.a[tid];
-    const float* y = S.y[0][tid];
-    float out[8];
-    if (a < 0) {
-      for (int k = 0; k < 8; ++k) out[k] = __builtin_nanf("");
-    } else {
-      const locc_object o = A.objs[a];
-      const double w = o.q[0], x = o.q[1], yq = o.q[2], zq = o.q[3];
-      const double R[9] = {1.0 - 2.0 * (yq * yq + zq * zq), 2.0 * (x * yq - w * zq), 2.0 * (x * zq + w * yq),
-                           2.0 * (x * yq + w * zq), 1.0 - 2.0 * (x * x + zq * zq), 2.0 * (yq * zq - w * x),
-                           2.0 * (x * zq - w * yq), 2.0 * (yq * zq + w * x), 1.0 - 2.0 * (x * x + yq * yq)};
-      const double sg = S.swapped[tid] ? -1.0 : 1.0;
-      out[0] = y[0];
-      for (int r = 0; r < 3; ++r) {
-        out[1 + r] = (float)(R[3 * r] * y[1] + R[3 * r + 1] * y[2] + R[3 * r + 2] * y[3] + (double)o.p[r]);
-        out[4 + r] = (float)(sg * (R[3 * r] * y[4] + R[3 * r + 1] * y[5] + R[3 * r + 2] * y[6]));
-      }
-      out[7] = y[7];
-    }
-    float4* dst = reinterpret_cast<float4*>(A.out + p);
-    dst[0] = make_float4(out[0], out[1], out[2], out[3]);
-    dst[1] = make_float4(out[4], out[5], out[6], out[7]);
-    if (A.y_dbg) {
-      float4* yd = reinterpret_cast<float4*>(A.y_dbg + (size_t)p * 8);
-      const float nan = __builtin_nanf("");
-      yd[0] = a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[0], y[1], y[2], y[3]);
-      yd[1] = a < 0 ? make_float4(nan, nan, nan, nan) : make_float4(y[4], y[5], y[6], y[7]);
-    }
-  }
+  if (tid < n) post_contact(A.objs, S.a[tid], S.swapped[tid], S.y[0][tid], A.out, A.y_dbg, S.pair[tid]);
   __syncthreads();
 }
 
@@ -230,10 +201,13 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
     if (base >= P) break;
     const int n_claim = P - base < A.claim ? P - base : A.claim;
 
-    // split schedule: each thread carries up to two 16-byte encoder rows of
-    // the next pair in registers, loaded while the current pair computes
+    // split schedule: each thread carries the next pair's record and up to two
+    // 16-byte encoder rows of it in registers, loaded while the current pair
+    // computes
     uint4 nxt[2];
+    PairMeta nmeta{};
     if constexpr (PRE) {
+      nmeta = A.meta[base];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         if (tid + 256 * i < 2 * K)
@@ -246,7 +220,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       int m_a = 0, m_b = 0;
       bool valid;
       if constexpr (PRE) {
-        const PairMeta mt = A.meta[p];
+        const PairMeta mt = nmeta;
         a = mt.a;
         swapped = mt.swapped;
         valid = a >= 0;
@@ -255,7 +229,8 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
 #pragma unroll
         for (int i = 0; i < 2; ++i)
           if (tid + 256 * i < 2 * K) reinterpret_cast<uint4*>(S.u.c.rows)[tid + 256 * i] = nxt[i];
-        if (c + 1 < n_claim) {
+        if (c + 1 < n_claim) {  // the next pair's record and rows load while this pair computes
+          nmeta = A.meta[p + 1];
 #pragma unroll
           for (int i = 0; i < 2; ++i)
             if (tid + 256 * i < 2 * K)

@@ -1,0 +1,505 @@
+// FP8 (OCP e4m3) encoder + head kernel of the split schedule.
+//
+// Same structure as the BF16 persistent kernel: workgroups claim pairs,
+// stage the bf16 encoder rows the crop kernel wrote, run the per-point
+// encoder with a per-object max-pool into an LDS tile, and run the head on
+// every 32-pair tile.  Precision by layer (per-layer scales):
+//   encoder layer 1  bf16 (inputs are coordinates and normals)  32x32x8 bf16
+//   encoder layer 2  fp8 x fp8, FP32 accumulation               32x32x64 f8f6f4
+//   head layers 1-2  fp8 x fp8, FP32 accumulation               32x32x64 f8f6f4
+//   head layer 3     bf16                                        32x32x16 bf16
+// A weight matrix is stored as W / s_W in e4m3 with s_W = amax|W| / 448; an
+// activation x enters a layer as e4m3(min(x / s_x, 448)) with a static
+// s_x = amax / 448 from a calibration batch.  The product of the two scales
+// is applied once per output in the epilogue (before the bias).  The
+// encoder's max-pool runs on the raw sums: with a positive scale,
+// fl(fl(max_r a_r s) + b) = max_r fl(fl(a_r s) + b) (rounding is monotone).
+// As in the BF16 kernel, layer 1's output registers feed layer 2's A
+// operand directly; each 64-wide k-step takes two 32-feature tiles, and W2
+// is packed so that lane group g, byte e of k-step s is feature
+// F(2 s + e / 16, g, e % 16), F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4.
+#include "fused.h"
+#include "geometry.h"
+#include "post.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace locc {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f32x16 mfma_k8(s16x4 a, s16x4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma_k16(u16x8 a, u16x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+// e4m3 x e4m3, unit block scales (E8M0 127 = 2^0)
+__device__ __forceinline__ f32x16 mfma_f8(i32x8 a, i32x8 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+}
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
+}
+// four floats -> four e4m3 bytes of min(ReLU(x) * inv, 448); inv > 0, so
+// ReLU(x) * inv = max(x * inv, 0) and one med3 does the ReLU and the clamp
+__device__ __forceinline__ float relu_clamp448(float x, float inv) {
+  return __builtin_amdgcn_fmed3f(x * inv, 0.f, 448.f);
+}
+__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d, float inv) {
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(a, inv), relu_clamp448(b, inv), 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(c, inv), relu_clamp448(d, inv), v, true);
+}
+
+template <int H1, int H2, int HH>
+struct Smem8 {
+  static constexpr int T = kFusedTile;
+  static constexpr int ZB = 2 * H2 + 16;  // bytes per row of the fp8 z tile
+  static constexpr int GB = HH + 16;      // bytes per row of the fp8 g1 tile
+  static constexpr int G2 = HH + 8;       // bf16 elements per row of the g2 tile
+  union alignas(16) {
+    unsigned short rows[2 * kMaxK * 8];   // encoder rows of the current pair (bf16)
+    unsigned short g2[T * G2];            // head layer-2 output (bf16)
+  } u;
+  alignas(16) unsigned char z[T * ZB];
+  alignas(16) unsigned char g1[T * GB];
+  float y[4][T][8];
+  int32_t pair[T];
+  int32_t a[T];
+  int32_t swapped[T];
+  int32_t claim;
+};
+
+// One fp8 head layer: dst = e4m3(min(ReLU(scale * src W^T + bias) * dst_inv, 448)) or, when
+// DST_BF16, bf16(ReLU(scale * src W^T + bias)).
+template <int KDIM, int SB, int DS, int CTH, bool DST_BF16>
+__device__ __forceinline__ void head_layer8(const unsigned char* __restrict__ pack, const float* __restrict__ bias,
+                                            float scale, float dst_inv, const unsigned char* src, void* dst) {
+  constexpr int KS = KDIM / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
+  const i32x8* bp = reinterpret_cast<const i32x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
+  const unsigned char* arow = src + l32 * SB + 32 * g;
+  f32x16 acc[CTH];
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) acc[c] = f32x16{};
+  i32x8 bcur[CTH];
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) bcur[c] = bp[(size_t)c * KS * 64];
+#pragma unroll 1
+  for (int s = 0; s < KS; ++s) {
+    i32x8 bnext[CTH];
+    const int sn = s + 1 < KS ? s + 1 : s;
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bnext[c] = bp[((size_t)c * KS + sn) * 64];
+    const uint4 a0 = *reinterpret_cast<const uint4*>(arow + 64 * s);
+    const uint4 a1 = *reinterpret_cast<const uint4*>(arow + 64 * s + 16);
+    const i32x8 av = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) acc[c] = mfma_f8(av, bcur[c], acc[c]);
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bcur[c] = bnext[c];
+  }
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) {
+    const int col = (wave * CTH + c) * 32 + l32;
+    const float bc = bias[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * g + (r & 3);
+      const float v = fmaxf(acc[c][r] * scale + bc, 0.f);
+      if constexpr (DST_BF16) {
+        static_cast<unsigned short*>(dst)[row * DS + col] = bf16_bits(v);
+      } else {
+        const int q = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(v * dst_inv, 448.f), 0.f, 0, false);
+        static_cast<unsigned char*>(dst)[row * DS + col] = (unsigned char)(q & 0xff);
+      }
+    }
+  }
+}
+
+template <int H1, int H2, int HH>
+__device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH>& S, int n) {
+  using S_t = Smem8<H1, H2, HH>;
+  constexpr int T = S_t::T, ZB = S_t::ZB, GB = S_t::GB, G2 = S_t::G2, CTH = HH / 128, KS3 = HH / 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  for (int e = tid; e < (T - n) * ZB; e += 256) S.z[n * ZB + e] = 0;
+  __syncthreads();
+  head_layer8<2 * H2, ZB, GB, CTH, false>(A.h1p, A.c1, A.s_z * A.s_h1, 1.f / A.s_g1, S.z, S.g1);
+  __syncthreads();
+  head_layer8<HH, GB, G2, CTH, true>(A.h2p, A.c2, A.s_g1 * A.s_h2, 0.f, S.g1, S.u.g2);
+  __syncthreads();
+  {
+    f32x16 acc = f32x16{};
+    const u16x8* bp = reinterpret_cast<const u16x8*>(A.h3p) + lane;
+    const unsigned short* arow = S.u.g2 + l32 * G2 + 8 * g;
+#pragma unroll
+    for (int s = wave * (KS3 / 4); s < (wave + 1) * (KS3 / 4); ++s)
+      acc = mfma_k16(*reinterpret_cast<const u16x8*>(arow + 16 * s), bp[(size_t)s * 64], acc);
+    if (l32 < 8)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S.y[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
+  }
+  __syncthreads();
+  for (int t = tid; t < T * 8; t += 256) {
+    const int i = t >> 3, j = t & 7;
+    S.y[0][i][j] = ((S.y[0][i][j] + S.y[1][i][j]) + S.y[2][i][j]) + S.y[3][i][j] + A.c3[j];
+  }
+  __syncthreads();
+  if (tid < n) post_contact(A.objs, S.a[tid], S.swapped[tid], S.y[0][tid], A.out, A.y_dbg, S.pair[tid]);
+  __syncthreads();
+}
+
+template <int H1, int H2, int HH>
+__global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp8Args A) {
+  using S_t = Smem8<H1, H2, HH>;
+  constexpr int T = S_t::T, ZB = S_t::ZB;
+  constexpr int FT = H1 / 32;    // layer-1 feature tiles
+  constexpr int KS2 = H1 / 64;   // layer-2 fp8 k-steps (two feature tiles each)
+  constexpr int CT = H2 / 128;   // encoder column tiles per wave
+  static_assert(H1 % 64 == 0 && H2 % 128 == 0 && HH % 128 == 0, "widths");
+  __shared__ S_t S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  const int K = A.K;
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
+  const float inv_h1 = 1.f / A.s_h1in, s_enc = A.s_h1in * A.s_w2, inv_z = 1.f / A.s_z;
+
+  i32x8 w2f[CT][KS2];
+  float bias2[CT];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+#pragma unroll
+    for (int s = 0; s < KS2; ++s)
+      w2f[ct][s] = reinterpret_cast<const i32x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
+    bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
+  }
+  s16x4 w1f[FT];
+#pragma unroll
+  for (int ft = 0; ft < FT; ++ft) w1f[ft] = reinterpret_cast<const s16x4*>(A.w1p)[(size_t)ft * 64 + lane];
+
+  int slot = 0;
+  for (int iter = 0;; ++iter) {
+    if (tid == 0)
+      S.claim = A.dynamic ? (int)atomicAdd(A.queue, (unsigned)A.claim) : (blockIdx.x + iter * gridDim.x) * A.claim;
+    __syncthreads();
+    const int base = S.claim;
+    __syncthreads();
+    if (base >= P) break;
+    const int n_claim = P - base < A.claim ? P - base : A.claim;
+    // the next pair's record and rows are carried in registers, loaded while the current pair computes
+    uint4 nxt[2];
+    PairMeta nmeta = A.meta[base];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (tid + 256 * i < 2 * K) nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)base * 2 * K + tid + 256 * i];
+    for (int c = 0; c < n_claim; ++c) {
+      const int p = base + c;
+      const PairMeta mt = nmeta;
+      const bool valid = mt.a >= 0;
+      const int m_a = valid ? mt.m_a : 0, m_b = valid ? mt.m_b : 0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (tid + 256 * i < 2 * K) reinterpret_cast<uint4*>(S.u.rows)[tid + 256 * i] = nxt[i];
+      if (c + 1 < n_claim) {
+        nmeta = A.meta[p + 1];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          if (tid + 256 * i < 2 * K)
+            nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)(p + 1) * 2 * K + tid + 256 * i];
+      }
+      if (tid == 0) {
+        S.pair[slot] = p;
+        S.a[slot] = valid ? mt.a : -1;
+        S.swapped[slot] = mt.swapped;
+      }
+      __syncthreads();
+      for (int side = 0; side < 2; ++side) {
+        const int m = side ? m_b : m_a;
+        float run[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
+        for (int r0 = 0; r0 < m; r0 += 32) {
+          const s16x4 xb = *reinterpret_cast<const s16x4*>(&S.u.rows[(side * K + r0 + l32) * 8 + 4 * g]);
+          f32x16 acc2[CT];
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
+#pragma unroll
+          for (int s = 0; s < KS2; ++s) {
+            const f32x16 lo = mfma_k8(w1f[2 * s], xb, f32x16{});
+            const f32x16 hi = mfma_k8(w1f[2 * s + 1], xb, f32x16{});
+            i32x8 av;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              av[q] = pack4_e4m3(lo[4 * q], lo[4 * q + 1], lo[4 * q + 2], lo[4 * q + 3], inv_h1);
+              av[4 + q] = pack4_e4m3(hi[4 * q], hi[4 * q + 1], hi[4 * q + 2], hi[4 * q + 3], inv_h1);
+            }
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_f8(av, w2f[ct][s], acc2[ct]);
+          }
+          if (r0 + 32 <= m) {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+          } else {
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+                if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+              }
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) * s_enc + bias2[ct], 0.f);
+          if (lane < 32) {
+            const int col = side * H2 + (wave * CT + ct) * 32 + lane;
+            const int q = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(f * inv_z, 448.f), 0.f, 0, false);
+            S.z[slot * ZB + col] = (unsigned char)(q & 0xff);
+            if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? f : __builtin_nanf("");
+          }
+        }
+      }
+      ++slot;
+      __syncthreads();
+      if (slot == T) {
+        head_tile8<H1, H2, HH>(A, S, T);
+        slot = 0;
+      }
+    }
+  }
+  if (slot > 0) head_tile8<H1, H2, HH>(A, S, slot);
+  if (A.dynamic && tid == 0) {
+    __threadfence();
+    if (atomicAdd(A.queue + 1, 1u) == gridDim.x - 1) {
+      atomicExch(A.queue, 0u);
+      atomicExch(A.queue + 1, 0u);
+    }
+  }
+}
+
+// One workgroup per pair (grid-stride); plain FP32 dot products, one output
+// feature per thread.  Rows are the crop kernel's bf16 rows, as the FP8
+// kernel consumes them.
+constexpr int kCalibH1 = 128, kCalibH2 = 256, kCalibHH = 512;
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(256) void calibrate_fp8_kernel(CalibArgs A) {
+  __shared__ float x[8];
+  __shared__ float h[kCalibH1];
+  __shared__ float z[2 * kCalibH2];
+  const int tid = threadIdx.x, h1 = A.h1, h2 = A.h2, hh = A.hh, K = A.K;
+  const float* W1 = A.w;
+  const float* b1 = W1 + 6 * h1;
+  const float* W2 = b1 + h1;
+  const float* b2 = W2 + (size_t)h2 * h1;
+  const float* H1 = b2 + h2;
+  const float* c1 = H1 + (size_t)hh * 2 * h2;
+  float m_h = 0.f, m_z = 0.f, m_g = 0.f;
+  for (int p = blockIdx.x; p < A.n_pairs; p += gridDim.x) {
+    const PairMeta mt = A.meta[p];
+    if (mt.a < 0) continue;  // the same for the whole workgroup
+    for (int side = 0; side < 2; ++side) {
+      const int m = side ? mt.m_b : mt.m_a;
+      float zr = 0.f;
+      for (int r = 0; r < m; ++r) {
+        if (tid < 6) {
+          const unsigned short bits = A.rows_bf16[((size_t)p * 2 * K + side * K + r) * 8 + tid];
+          x[tid] = (float)__builtin_bit_cast(__bf16, bits);
+        }
+        __syncthreads();
+        if (tid < h1) {
+          float v = b1[tid];
+          for (int c = 0; c < 6; ++c) v += W1[tid * 6 + c] * x[c];
+          v = fmaxf(v, 0.f);
+          h[tid] = v;
+          m_h = fmaxf(m_h, v);
+        }
+        __syncthreads();
+        if (tid < h2) {
+          float v = b2[tid];
+          for (int k = 0; k < h1; ++k) v += W2[(size_t)tid * h1 + k] * h[k];
+          zr = fmaxf(zr, v);
+        }
+        __syncthreads();
+      }
+      if (tid < h2) {
+        z[side * h2 + tid] = zr;
+        m_z = fmaxf(m_z, zr);
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < hh; o += 256) {
+      float v = c1[o];
+      for (int k = 0; k < 2 * h2; ++k) v += H1[(size_t)o * 2 * h2 + k] * z[k];
+      m_g = fmaxf(m_g, v);
+    }
+    __syncthreads();
+  }
+  m_h = wave_max(m_h);
+  m_z = wave_max(m_z);
+  m_g = wave_max(m_g);
+  if ((tid & 63) == 0) {  // non-negative floats order as their bit patterns
+    atomicMax(A.amax + 0, __float_as_uint(m_h));
+    atomicMax(A.amax + 1, __float_as_uint(m_z));
+    atomicMax(A.amax + 2, __float_as_uint(m_g));
+  }
+}
+
+// ------------------------------------------------------------- host packing
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) + 4 * g + r % 4; }
+
+unsigned short host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+float amax_of(const float* w, size_t n) {
+  float m = 0.f;
+  for (size_t k = 0; k < n; ++k) m = std::fmax(m, std::fabs(w[k]));
+  return m;
+}
+
+}  // namespace
+
+// OCP e4m3 (E4M3FN) of x with round to nearest even; magnitudes beyond 448
+// saturate to 448.
+unsigned char host_e4m3(float x) {
+  const unsigned char s = std::signbit(x) ? 0x80 : 0;
+  const double a = std::fabs((double)x);
+  if (!(a == a)) return 0x7F;
+  if (a >= 464.0) return s | 0x7E;
+  if (a < std::ldexp(1.0, -6)) return s | (unsigned char)std::nearbyint(a / std::ldexp(1.0, -9));
+  int e;
+  std::frexp(a, &e);
+  e -= 1;
+  double q = std::nearbyint((a / std::ldexp(1.0, e) - 1.0) * 8.0);
+  if (q == 8.0) {
+    q = 0.0;
+    e += 1;
+  }
+  int code = ((e + 7) << 3) | (int)q;
+  if (code > 0x7E) code = 0x7E;
+  return s | (unsigned char)code;
+}
+
+Fp8Layout fp8_layout(int h1, int h2, int hh) {
+  Fp8Layout L{};
+  size_t o = 0;
+  L.w1 = o; o = align256(o + (size_t)h1 * 8 * 2);
+  L.w2 = o; o = align256(o + (size_t)h2 * h1);
+  L.b2 = o; o = align256(o + (size_t)h2 * 4);
+  L.h1 = o; o = align256(o + (size_t)hh * 2 * h2);
+  L.c1 = o; o = align256(o + (size_t)hh * 4);
+  L.h2 = o; o = align256(o + (size_t)hh * hh);
+  L.c2 = o; o = align256(o + (size_t)hh * 4);
+  L.h3 = o; o = align256(o + (size_t)32 * hh * 2);
+  L.c3 = o; o = align256(o + 8 * 4);
+  L.total = o;
+  return L;
+}
+
+void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1, const float* c1,
+              const float* H2, const float* c2, const float* H3, const float* c3, int h1, int h2, int hh,
+              unsigned char* dst, float* weight_scales) {
+  const Fp8Layout L = fp8_layout(h1, h2, hh);
+  std::memset(dst, 0, L.total);
+  auto u16 = [&](size_t off) { return reinterpret_cast<unsigned short*>(dst + off); };
+  auto f32 = [&](size_t off) { return reinterpret_cast<float*>(dst + off); };
+  // encoder layer 1 (bf16, A operand of 32x32x8)
+  for (int ft = 0; ft < h1 / 32; ++ft)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 4; ++e) {
+        const int f = 32 * ft + l % 32, c = 4 * (l / 32) + e;
+        u16(L.w1)[((size_t)ft * 64 + l) * 4 + e] = host_bf16(c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f));
+      }
+  const float s_w2 = std::fmax(amax_of(W2, (size_t)h2 * h1), 1e-30f) / 448.f;
+  const float s_h1 = std::fmax(amax_of(H1, (size_t)hh * 2 * h2), 1e-30f) / 448.f;
+  const float s_h2 = std::fmax(amax_of(H2, (size_t)hh * hh), 1e-30f) / 448.f;
+  weight_scales[0] = s_w2;
+  weight_scales[1] = s_h1;
+  weight_scales[2] = s_h2;
+  // encoder layer 2 (e4m3, B operand of 32x32x64), reduction index permuted to layer 1's output
+  const int CT = h2 / 128, KS2 = h1 / 64;
+  for (int w = 0; w < 4; ++w)
+    for (int ct = 0; ct < CT; ++ct)
+      for (int s = 0; s < KS2; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 32; ++e) {
+            const int col = (w * CT + ct) * 32 + l % 32;
+            const int f = perm_feature(2 * s + e / 16, l / 32, e % 16);
+            dst[L.w2 + (((size_t)(w * CT + ct) * KS2 + s) * 64 + l) * 32 + e] = host_e4m3(W2[(size_t)col * h1 + f] / s_w2);
+          }
+  std::memcpy(f32(L.b2), b2, sizeof(float) * h2);
+  // head layers 1-2 (e4m3, B operand): lane l holds H[32 ct + l % 32][64 s + 32 (l / 32) + e]
+  auto pack8 = [&](const float* H, int in, int out, float sc, size_t at) {
+    const int ks = in / 64;
+    for (int ct = 0; ct < out / 32; ++ct)
+      for (int s = 0; s < ks; ++s)
+        for (int l = 0; l < 64; ++l)
+          for (int e = 0; e < 32; ++e)
+            dst[at + (((size_t)ct * ks + s) * 64 + l) * 32 + e] =
+                host_e4m3(H[(size_t)(32 * ct + l % 32) * in + 64 * s + 32 * (l / 32) + e] / sc);
+  };
+  pack8(H1, 2 * h2, hh, s_h1, L.h1);
+  std::memcpy(f32(L.c1), c1, sizeof(float) * hh);
+  pack8(H2, hh, hh, s_h2, L.h2);
+  std::memcpy(f32(L.c2), c2, sizeof(float) * hh);
+  // head layer 3 (bf16, 8 outputs padded to 32 columns)
+  for (int s = 0; s < hh / 16; ++s)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 8; ++e) {
+        const int row = l % 32;
+        u16(L.h3)[(((size_t)s) * 64 + l) * 8 + e] = row < 8 ? host_bf16(H3[(size_t)row * hh + 16 * s + 8 * (l / 32) + e]) : 0;
+      }
+  std::memcpy(f32(L.c3), c3, sizeof(float) * 8);
+}
+
+void fp8_bind(Fp8Args& a, const unsigned char* base, int h1, int h2, int hh) {
+  const Fp8Layout L = fp8_layout(h1, h2, hh);
+  a.w1p = reinterpret_cast<const unsigned short*>(base + L.w1);
+  a.w2p = base + L.w2;
+  a.b2 = reinterpret_cast<const float*>(base + L.b2);
+  a.h1p = base + L.h1;
+  a.c1 = reinterpret_cast<const float*>(base + L.c1);
+  a.h2p = base + L.h2;
+  a.c2 = reinterpret_cast<const float*>(base + L.c2);
+  a.h3p = reinterpret_cast<const unsigned short*>(base + L.h3);
+  a.c3 = reinterpret_cast<const float*>(base + L.c3);
+}
+
+hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, int grid, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (h1 == 64 && h2 == 128 && hh == 256)
+    hipLaunchKernelGGL((encoder_head_fp8_kernel<64, 128, 256>), dim3(grid), dim3(256), 0, s, a);
+  else if (h1 == 128 && h2 == 256 && hh == 512)
+    hipLaunchKernelGGL((encoder_head_fp8_kernel<128, 256, 512>), dim3(grid), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_calibrate_fp8(const CalibArgs& a, int grid, hipStream_t s) {
+  if (a.h1 > kCalibH1 || a.h2 > kCalibH2 || a.hh > kCalibHH || a.h1 > 256 || a.h2 > 256)
+    return hipErrorInvalidValue;
+  if (a.n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(calibrate_fp8_kernel, dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace locc
