@@ -44,13 +44,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 
-// ReLU of 8 packed bf16 values: as int16 every negative bf16 (sign bit set)
-// is below 0 and the positive ones keep their order, so max(v, 0) in int16
-// is ReLU in bf16 (two values per v_pk_max_i16).
-__device__ __forceinline__ u16x8 bf16x8_relu(u16x8 v) {
-  const s16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
-  return __builtin_bit_cast(u16x8, __builtin_elementwise_max(__builtin_bit_cast(s16x8, v), z));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// ReLU(bf16(a)), ReLU(bf16(b)) packed in one word: one v_cvt_pk_bf16_f32
+// (round to nearest even) and one v_pk_max_i16 for two values.
+__device__ __forceinline__ unsigned bf16x2_relu(float a, float b) {
+  const bf16x2 h = __builtin_convertvector((f32x2){a, b}, bf16x2);
+  return __builtin_bit_cast(unsigned, __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0}));
 }
+
+// IEEE maximum (NaN-propagating, -0 < +0).  The matrix-core results feeding
+// the max-pool are not known to be canonical floats, so fmaxf would
+// canonicalise each operand first; maximum needs no canonicalisation and
+// chains into v_maximum3_f32.
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
 
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   const __bf16 h = (__bf16)f;  // round to nearest even
@@ -306,10 +316,10 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
             if (ft + 1 < FT) acc1n = mfma_k8(w1f[ft + 1 < FT ? ft + 1 : ft], xb, f32x16{});
 #pragma unroll
             for (int hf = 0; hf < 2; ++hf) {
-              u16x8 av;
+              u32x4 w;
 #pragma unroll
-              for (int e = 0; e < 8; ++e) av[e] = bf16_bits(acc1[8 * hf + e]);
-              av = bf16x8_relu(av);
+              for (int e = 0; e < 4; ++e) w[e] = bf16x2_relu(acc1[8 * hf + 2 * e], acc1[8 * hf + 2 * e + 1]);
+              const u16x8 av = __builtin_bit_cast(u16x8, w);
 #pragma unroll
               for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av, w2f[ct][2 * ft + hf], acc2[ct]);
             }
@@ -319,14 +329,14 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-              for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+              for (int r = 0; r < 16; r += 2) run[ct] = vmax(vmax(run[ct], acc2[ct][r]), acc2[ct][r + 1]);
           } else {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
               for (int r = 0; r < 16; ++r) {
                 const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
-                if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+                if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
               }
           }
         }

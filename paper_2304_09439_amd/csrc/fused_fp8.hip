@@ -45,6 +45,8 @@ __device__ __forceinline__ f32x16 mfma_k16(u16x8 a, u16x8 b, f32x16 c) {
 __device__ __forceinline__ f32x16 mfma_f8(i32x8 a, i32x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
 }
+// IEEE maximum: no canonicalisation of matrix-core results (see fused.hip)
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
@@ -246,14 +248,14 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-              for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+              for (int r = 0; r < 16; r += 2) run[ct] = vmax(vmax(run[ct], acc2[ct][r]), acc2[ct][r + 1]);
           } else {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
               for (int r = 0; r < 16; ++r) {
                 const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
-                if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+                if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
               }
           }
         }

@@ -30,6 +30,11 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// IEEE maximum (NaN-propagating, -0 < +0).  Matrix-core results are not
+// known to be canonical floats, so fmaxf would canonicalise each operand
+// first; maximum needs no canonicalisation and chains into v_maximum3_f32.
+__device__ __forceinline__ float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+
 __device__ __forceinline__ f32x16 mfma32x32x2(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
         for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
-            const float h = fmaxf(acc1[ft][r], 0.f);
+            const float h = vmax(acc1[ft][r], 0.f);
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h, w2f[ct][ft * 16 + r], acc2[ct]);
           }
@@ -108,14 +113,14 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) run[ct] = fmaxf(run[ct], fmaxf(acc2[ct][r], acc2[ct][r + 1]));
+            for (int r = 0; r < 16; r += 2) run[ct] = vmax(vmax(run[ct], acc2[ct][r]), acc2[ct][r + 1]);
         } else {
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
               const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
-              if (row < m) run[ct] = fmaxf(run[ct], acc2[ct][r]);
+              if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
             }
         }
       }
