@@ -108,11 +108,14 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 //   FP32 path: PairMeta [P], float rows [P][2K][8], pooled features z [P][2 h2]
 //   BF16 split and FP8: PairMeta [P], bf16 rows [P][2K][8]
 //   BF16 fused: nothing
+// followed, for every path that runs the crop kernel, by the pair set-up
+// records [P].
 struct Workspace {
   PairMeta* meta = nullptr;
   float* rows = nullptr;
   float* z = nullptr;
   unsigned short* rows_bf16 = nullptr;
+  void* setup = nullptr;  // pair set-up records of the crop kernel
 };
 
 }  // namespace
@@ -120,11 +123,12 @@ struct Workspace {
 size_t locc::workspace_bytes(const locc_ctx* c, int n_pairs) {
   const size_t P = (size_t)n_pairs;
   const size_t meta = align256(P * sizeof(PairMeta));
+  const size_t setup = align256(P * kPairSetupBytes);
   if (c->cfg.precision == LOCC_FP32)
     return meta + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)) +
-           align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
+           align256(P * 2 * c->cfg.enc_h2 * sizeof(float)) + setup;
   if (c->sched.split || c->cfg.precision == LOCC_FP8)
-    return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
+    return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short)) + setup;
   return 0;
 }
 
@@ -147,10 +151,14 @@ locc_status carve(locc_ctx* c, int n_pairs, Workspace* w, const Scratch* own) {
   b += align256(P * sizeof(PairMeta));
   if (c->cfg.precision == LOCC_FP32) {
     w->rows = reinterpret_cast<float*>(b);
-    w->z = reinterpret_cast<float*>(b + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)));
+    b += align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float));
+    w->z = reinterpret_cast<float*>(b);
+    b += align256(P * 2 * c->cfg.enc_h2 * sizeof(float));
   } else {
     w->rows_bf16 = reinterpret_cast<unsigned short*>(b);
+    b += align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short));
   }
+  w->setup = b;
   return LOCC_OK;
 }
 
@@ -194,7 +202,7 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   const int unroll = c->sched.crop_unroll;
   if (c->cfg.precision == LOCC_FP32) {
     CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, w.rows, nullptr, c->d_err};
+                nullptr, counts, w.meta, w.rows, nullptr, c->d_err, w.setup};
     HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
     const Fp32Net net = fp32_view(c->d_wfp32, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
     NetArgs na{w.rows, w.meta, objs, n_pairs, n_dev, c->cfg.K, z_out ? z_out : w.z, y_out, out};
@@ -205,7 +213,7 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
   if (c->cfg.precision == LOCC_FP8) {
     CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err};
+                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err, w.setup};
     HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
     Fp8Args fa{};
     fa.objs = objs;
@@ -252,7 +260,7 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   const int grid = fused_grid(c, n_pairs);
   if (c->sched.split) {
     CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err};
+                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err, w.setup};
     HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
     fa.rows_bf16 = w.rows_bf16;
     fa.meta = w.meta;
@@ -482,13 +490,13 @@ locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   HIP_TRY(hipSetDevice(c->device));
   float amax[3] = {0.f, 0.f, 0.f};
   if (n_pairs > 0) {
-    const size_t P = (size_t)n_pairs;
-    locc_status st = ensure_workspace(c, workspace_bytes(c, n_pairs));
+    Workspace w{};
+    locc_status st = carve(c, n_pairs, &w, nullptr);
     if (st != LOCC_OK) return st;
-    PairMeta* meta = reinterpret_cast<PairMeta*>(c->d_ws);
-    unsigned short* rows = reinterpret_cast<unsigned short*>(static_cast<char*>(c->d_ws) + align256(P * sizeof(PairMeta)));
+    PairMeta* meta = w.meta;
+    unsigned short* rows = w.rows_bf16;
     CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, nullptr, meta, nullptr, rows, c->d_err};
+                nullptr, nullptr, meta, nullptr, rows, c->d_err, w.setup};
     HIP_TRY(launch_crop(ca, s, c->sched.crop_unroll));
     HIP_TRY(hipMemsetAsync(c->d_amax, 0, 3 * sizeof(unsigned int), s));
     CalibArgs ka{c->d_wraw, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h, n_pairs, c->cfg.K, rows, meta, c->d_amax};
@@ -584,8 +592,10 @@ locc_status locc_debug_crop(locc_ctx* c, const locc_object* objs, int32_t n_objs
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
   if (n_pairs == 0) return LOCC_OK;
   HIP_TRY(hipSetDevice(c->device));
+  locc_status st = ensure_workspace(c, align256((size_t)n_pairs * kPairSetupBytes));
+  if (st != LOCC_OK) return st;
   CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), c->cfg.K, c->cfg.pad_m,
-              idx, counts, nullptr, nullptr, nullptr, c->d_err};
+              idx, counts, nullptr, nullptr, nullptr, c->d_err, c->d_ws};
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));
   return LOCC_OK;

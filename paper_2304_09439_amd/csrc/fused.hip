@@ -253,7 +253,9 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       if (valid) {  // uniform over the workgroup
         PairGeom gm;
         geo_pair(oa, ob, da, db, A.pad, gm);
-        geo_scan_select<4>(gm, da, db, A.lib, K, S.u.c.crop);
+        PairScreen sc;
+        geo_screen(gm, db, sc);
+        geo_scan_select<4>(&gm, sc, da.off, da.n, db.off, db.n, A.lib, K, A.counts != nullptr, S.u.c.crop);
         const int n_a = S.u.c.crop.count[0], n_b = S.u.c.crop.count[1];
         m_a = n_a < K ? n_a : K;
         m_b = n_b < K ? n_b : K;

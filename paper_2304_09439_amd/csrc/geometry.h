@@ -166,7 +166,7 @@ __device__ __forceinline__ float geo_uniform(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-__device__ __forceinline__ void geo_screen(const PairGeom& g, const ShapeDesc& db, PairScreen& sc) {
+__device__ __forceinline__ void geo_screen_values(const PairGeom& g, const ShapeDesc& db, PairScreen& sc) {
 #pragma clang fp contract(off)
   double P[3];
 #pragma unroll
@@ -185,7 +185,12 @@ __device__ __forceinline__ void geo_screen(const PairGeom& g, const ShapeDesc& d
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) sc.R[k] = (float)g.R[k];
-  // every thread of the workgroup holds the same values: scalar registers
+}
+
+// Screening constants when every thread of the workgroup computed the same
+// geometry: kept in scalar registers.
+__device__ __forceinline__ void geo_screen(const PairGeom& g, const ShapeDesc& db, PairScreen& sc) {
+  geo_screen_values(g, db, sc);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     sc.alo[i] = geo_uniform(sc.alo[i]);
@@ -205,7 +210,10 @@ __device__ __forceinline__ bool geo_member_a(const PairScreen& sc, float x, floa
          (z <= sc.ahi[2]);
 }
 
-__device__ __forceinline__ bool geo_member_b(const PairGeom& g, const PairScreen& sc, float x, float y, float z) {
+// gp: the pair's float64 geometry, read only for the points the screen cannot
+// decide (a pointer, so that a caller holding it in memory keeps it there)
+__device__ __forceinline__ bool geo_member_b(const PairGeom* __restrict__ gp, const PairScreen& sc, float x, float y,
+                                             float z) {
   const float q0 = __builtin_fmaf(sc.R[2], z, __builtin_fmaf(sc.R[1], y, __builtin_fmaf(sc.R[0], x, sc.t[0])));
   const float q1 = __builtin_fmaf(sc.R[5], z, __builtin_fmaf(sc.R[4], y, __builtin_fmaf(sc.R[3], x, sc.t[1])));
   const float q2 = __builtin_fmaf(sc.R[8], z, __builtin_fmaf(sc.R[7], y, __builtin_fmaf(sc.R[6], x, sc.t[2])));
@@ -215,73 +223,113 @@ __device__ __forceinline__ bool geo_member_b(const PairGeom& g, const PairScreen
                    (q2 < sc.out_lo[2]) | (q2 > sc.out_hi[2]);
   if (in | out) return in;
   double q[3];
-  geo_xform(g, x, y, z, q);
-  return geo_inside(g, q[0], q[1], q[2]);
+  geo_xform(*gp, x, y, z, q);
+  return geo_inside(*gp, q[0], q[1], q[2]);
 }
 
 // Membership scan and ordered first-K selection for one pair, by a
-// workgroup of 256 threads (4 wave64).  Waves 0-1 scan object a, waves 2-3
-// object b, one 64-bit ballot per 64 consecutive points kept in LDS (each
-// wave issues the loads of kScanUnroll blocks before testing them); after
-// one barrier one wave per object turns the ballots into ordered positions
-// (prefix of popcounts + rank inside the ballot) and stores the first K
-// indices.  Ends with a barrier; S.sel / S.count are then valid.
+// workgroup of 256 threads (4 wave64) over blocks of 64 stored points.  A
+// round lists the next blocks, in stored order, of each object still being
+// scanned, a-blocks first; wave w tests the round's blocks w, w + 4, ...,
+// kScanUnroll blocks' loads in flight at a time (so the cheap a-side and the
+// transforming b-side tests spread evenly over the waves), and one 64-bit
+// ballot per block goes to LDS.  With full == true one round covers every
+// block and the counts are exact.  Otherwise a round holds at most
+// 4 kScanUnroll blocks (half each while both objects are scanned); after its
+// barrier every thread adds its popcounts to the per-object counts, and an
+// object's scan ends as soon as it has K members: its first K members in
+// stored order are then known, and its count is a lower bound >= K.
+// Finally wave 0 (object a) and wave 2 (object b) turn the ballots into
+// ordered positions (prefix of popcounts over blocks, then each lane walks
+// its block's set bits) and store the first K indices.  Ends with a
+// barrier; S.sel / S.count are then valid.
 template <int kScanUnroll>
-__device__ __forceinline__ void geo_scan_select(const PairGeom& g, const ShapeDesc& da, const ShapeDesc& db,
-                                                const DeviceLibrary& lib, int K, CropShared& S) {
+__device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp, const PairScreen& sc, int off_a, int n_a,
+                                                int off_b, int n_b, const DeviceLibrary& lib, int K, bool full,
+                                                CropShared& S) {
+  constexpr int R = 4 * kScanUnroll;  // blocks per round
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int side = wave >> 1;
-  const ShapeDesc ds = side ? db : da;
-  const int nblk = (ds.n + 63) >> 6;
-  PairScreen sc;
-  geo_screen(g, db, sc);
-  for (int blk0 = wave & 1; blk0 < nblk; blk0 += 2 * kScanUnroll) {
-    float x[kScanUnroll], y[kScanUnroll], z[kScanUnroll];
+  const int nblk_a = (n_a + 63) >> 6, nblk_b = (n_b + 63) >> 6;
+  int cur_a = 0, cur_b = 0, cnt_a = 0, cnt_b = 0;  // uniform
+  for (;;) {
+    const bool act_a = cur_a < nblk_a && (full || cnt_a < K);
+    const bool act_b = cur_b < nblk_b && (full || cnt_b < K);
+    if (!act_a && !act_b) break;
+    // a round: all remaining blocks when every count is wanted (one barrier
+    // in total), else at most R blocks, shared between the two objects
+    int q_a = 0, q_b = 0;
+    if (full) {
+      q_a = nblk_a - cur_a;
+      q_b = nblk_b - cur_b;
+    } else {
+      if (act_a) q_a = nblk_a - cur_a < (act_b ? R / 2 : R) ? nblk_a - cur_a : (act_b ? R / 2 : R);
+      if (act_b) q_b = nblk_b - cur_b < R - q_a ? nblk_b - cur_b : R - q_a;
+    }
+    const int q = q_a + q_b;
+    for (int i0 = wave; i0 < q; i0 += 4 * kScanUnroll) {
+      float x[kScanUnroll], y[kScanUnroll], z[kScanUnroll];
 #pragma unroll
-    for (int u = 0; u < kScanUnroll; ++u) {
-      const int k = ((blk0 + 2 * u) << 6) + lane;
-      x[u] = y[u] = z[u] = 0.f;
-      if (k < ds.n) {
-        const int gi = ds.off + k;
-        x[u] = lib.px[gi];
-        y[u] = lib.py[gi];
-        z[u] = lib.pz[gi];
+      for (int u = 0; u < kScanUnroll; ++u) {
+        const int i = i0 + 4 * u;
+        const int side = i >= q_a;
+        const int k = ((side ? cur_b + i - q_a : cur_a + i) << 6) + lane;
+        x[u] = y[u] = z[u] = 0.f;
+        if (i < q && k < (side ? n_b : n_a)) {
+          const int gi = (side ? off_b : off_a) + k;
+          x[u] = lib.px[gi];
+          y[u] = lib.py[gi];
+          z[u] = lib.pz[gi];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kScanUnroll; ++u) {
+        const int i = i0 + 4 * u;
+        if (i < q) {  // uniform
+          const int side = i >= q_a;
+          const int lb = side ? cur_b + i - q_a : cur_a + i;
+          const int k = (lb << 6) + lane;
+          bool in = false;
+          if (k < (side ? n_b : n_a))
+            in = side ? geo_member_b(gp, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
+          const unsigned long long m = __ballot(in);
+          if (lane == 0) S.mask[side][lb] = m;
+        }
       }
     }
+    __syncthreads();
+    cur_a += q_a;
+    cur_b += q_b;
+    if (full) continue;  // every block is scanned in the one round
+    // the round's popcounts, one block per lane, summed over the wave (every
+    // wave computes the same totals)
+    int ca = 0, cb = 0;
+    for (int i = lane; i < q_a; i += 64) ca += __popcll(S.mask[0][cur_a - q_a + i]);
+    for (int i = lane; i < q_b; i += 64) cb += __popcll(S.mask[1][cur_b - q_b + i]);
 #pragma unroll
-    for (int u = 0; u < kScanUnroll; ++u) {
-      const int blk = blk0 + 2 * u;
-      const int k = (blk << 6) + lane;
-      bool in = false;
-      if (k < ds.n) in = side ? geo_member_b(g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
-      const unsigned long long m = __ballot(in);
-      if (lane == 0 && blk < nblk) S.mask[side][blk] = m;
+    for (int o = 32; o > 0; o >>= 1) {
+      ca += __shfl_xor(ca, o, 64);
+      cb += __shfl_xor(cb, o, 64);
     }
+    cnt_a += ca;
+    cnt_b += cb;
   }
-  __syncthreads();
   if ((wave & 1) == 0) {
-    // prefix of popcounts over blocks (lane = block within a chunk of 64),
-    // then the blocks that still have room below K are written one at a time
-    // by the whole wave: member bit l of block b goes to start(b) + rank of
-    // bit l among the block's set bits.
+    const int side = wave >> 1;
+    const int nblk = side ? cur_b : cur_a;  // blocks scanned
+    // one block per lane (chunks of 64 blocks): exclusive prefix of the
+    // popcounts gives the block's first position; the lane then writes its
+    // block's members, lowest point first, while the position is below K.
     int carry = 0;
     for (int base = 0; base < nblk; base += 64) {
       const int blk = base + lane;
-      const unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
+      unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
       const int c = __popcll(m);
       const int incl = geo_wave_inclusive_scan(c, lane);
-      const int excl = carry + incl - c;
-      const int nb = nblk - base < 64 ? nblk - base : 64;
-      for (int j = 0; j < nb; ++j) {
-        const int start = __shfl(excl, j, 64);
-        if (start >= K) break;
-        const unsigned long long mj = S.mask[side][base + j];
-        if ((mj >> lane) & 1ull) {
-          const int pos = start + __popcll(mj & ((1ull << lane) - 1ull));
-          if (pos < K) S.sel[side][pos] = ((base + j) << 6) + lane;
-        }
+      for (int pos = carry + incl - c; m != 0ull && pos < K; ++pos) {
+        S.sel[side][pos] = (blk << 6) + __builtin_ctzll(m);
+        m &= m - 1ull;
       }
       carry += __shfl(incl, 63, 64);
     }
@@ -289,6 +337,16 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom& g, const ShapeDe
   }
   __syncthreads();
 }
+
+// Per-pair record of the pair set-up kernel.
+struct PairSetup {
+  PairGeom g;
+  PairScreen sc;
+  int32_t valid;          // 0: invalid pair (index out of range, i == j, shape id out of range)
+  int32_t a, swapped;     // canonical first object, caller order flag
+  int32_t off_a, n_a, off_b, n_b;  // stored points of the two shapes
+};
+static_assert(sizeof(PairSetup) <= kPairSetupBytes, "pair set-up record");
 
 // Encoder input row (x, y, z, nx, ny, nz) in a's frame of stored point gi of
 // object `side` (0 = a as stored, 1 = b transformed in float64, then rounded).

@@ -78,8 +78,14 @@ struct CropArgs {
   unsigned short* rows_bf16;  // [P][2K][8] bf16 (x, y, z, nx, ny, nz, 1, 0), rows up to the next
                               // multiple of 32 of each object's count written, may be null
   unsigned long long* err_counter;
+  void* setup;           // [P] records of kPairSetupBytes (library workspace), required
 };
 
+// Bytes of the per-pair record (pose, box, screening constants, canonical
+// order) the pair set-up kernel writes for the crop kernel.
+constexpr size_t kPairSetupBytes = 320;
+
+// Pair set-up (one thread per pair), then the crop (one workgroup per pair).
 // unroll: blocks of 64 points whose loads a wave issues together (2, 4 or 8)
 hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll = 8);
 

@@ -169,3 +169,30 @@ def test_bf16_invalid_pairs_and_ragged_batches(torch, small_scene):
         if n:
             assert torch.equal(o, ref_out[:n]) and torch.equal(c, ref_counts[:n])
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_contacts_are_the_same_with_and_without_counts(torch, scale_scene, precision):
+    """Without counts the scan of an object stops once it has K members: the
+    first K members in stored order, and so the contacts, must not change."""
+    sc = scale_scene
+    w = _weights(LW)
+    say(f"{precision}: contacts with and without member counts")
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision=precision)
+    if precision == "bf16":
+        ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=True)
+    objs, pairs = B.scene_tensors(sc)
+    with_counts, counts = ctx.detect(objs, pairs)
+    without, none = ctx.detect(objs, pairs, want_counts=False)
+    torch.cuda.synchronize()
+    assert none is None
+    assert torch.equal(with_counts, without)
+    c = counts.cpu().numpy()
+    say(f"  objects with more than K members: {np.mean(c >= 128):.3f}")
+    if precision == "bf16":   # the fused schedule stops early too
+        ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=False)
+        fused, _ = ctx.detect(objs, pairs, want_counts=False)
+        fused_c, _ = ctx.detect(objs, pairs)
+        torch.cuda.synchronize()
+        assert torch.equal(fused, fused_c)
+    ctx.close()
