@@ -142,24 +142,27 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
 
 # ------------------------------------------------------------------ GPU run
 
-def kernel_entries(kt, work, P, workload_name):
+def kernel_entries(kt, work, P, workload_name, steps):
+    """Per kernel: average launch duration and the algorithmic rate of one launch (a step of P pairs may
+    run a kernel several times, once per chunk of pairs)."""
     kernels = {}
     for name, (launches, total_ms) in sorted(kt.items()):
         avg = total_ms / max(launches, 1)
-        entry = dict(avg_ms=round(avg, 4), launches=int(launches))
+        P_launch = P * steps / max(launches, 1)
+        entry = dict(avg_ms=round(avg, 4), launches=int(launches), pairs_per_launch=round(P_launch, 1))
         if name == "crop":
-            achieved = work["crop_bytes"] * P / (avg * 1e-3) / 1e9
+            achieved = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
             entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
                          frac=round(achieved / PEAK_HBM_GBPS, 4))
         else:
             if name.startswith("encoder_head") or name.startswith("fused"):
-                flops = (work["enc_flops"] + work["head_flops"]) * P
+                flops = (work["enc_flops"] + work["head_flops"]) * P_launch
             elif name.startswith("encoder"):
-                flops = work["enc_flops"] * P
+                flops = work["enc_flops"] * P_launch
             elif name.startswith("head"):
-                flops = work["head_flops"] * P
+                flops = work["head_flops"] * P_launch
             if name.startswith("fused"):  # crop inside: its bytes too
-                gbps = (work["crop_bytes"] + work["contact_bytes"]) * P / (avg * 1e-3) / 1e9
+                gbps = (work["crop_bytes"] + work["contact_bytes"]) * P_launch / (avg * 1e-3) / 1e9
                 entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
             prec = name.split("_")[-1]
             achieved = flops / (avg * 1e-3) / 1e12
@@ -211,7 +214,7 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     n_bad = ctx.device_errors()
     ctx.close()
     ms = 1000.0 * wall / args.steps
-    kernels = kernel_entries(kt, work, P, workload_name)
+    kernels = kernel_entries(kt, work, P, workload_name, args.steps)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
@@ -498,8 +501,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale", choices=["scale", "small"])
-    ap.add_argument("--schedule", action="append", default=[], metavar="PREC:WG,CLAIM,DYN,SPLIT,UNROLL",
-                    help="fix the schedule of a batched path instead of autotuning it, e.g. bf16:2,16,1,1,4 "
+    ap.add_argument("--schedule", action="append", default=[], metavar="PREC:WG,CLAIM,DYN,SPLIT,UNROLL,CHUNKS",
+                    help="fix the schedule of a batched path instead of autotuning it, e.g. bf16:2,16,1,1,4,2 "
                          "(repeatable; used to profile the schedule a previous run picked)")
     ap.add_argument("--precision", default="fp32,bf16,fp8",
                     help="comma list of paths to time: fp32 (per-step), bf16 (batched, the headline), fp8 (batched)")
@@ -519,8 +522,9 @@ def main():
     sched = {}
     for item in args.schedule:
         prec, vals = item.split(":")
-        wg, claim, dyn, split, unroll = (int(v) for v in vals.split(","))
-        sched[prec] = dict(wg_per_cu=wg, claim=claim, dynamic=bool(dyn), split=bool(split), crop_unroll=unroll)
+        wg, claim, dyn, split, unroll, chunks = (int(v) for v in vals.split(","))
+        sched[prec] = dict(wg_per_cu=wg, claim=claim, dynamic=bool(dyn), split=bool(split), crop_unroll=unroll,
+                           chunks=chunks)
     args.schedule = sched
     if args.summarize_counters:
         return summarize_counters(args)

@@ -208,6 +208,11 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
  *              1: a crop kernel writes bf16 encoder rows to a library
  *              workspace, then the persistent kernel runs encoder and head
  *   crop_unroll  also used by the FP32 path's crop kernel
+ *   chunks     split schedule and FP8 (1, 2, 4 or 8): the step is cut into
+ *              that many runs of pairs; the crop of run k + 1 runs on a
+ *              second stream of the context while the network of run k runs
+ *              on the caller's stream (halved while a run would hold fewer
+ *              than 256 pairs; always 1 for serving slots)
  * Results do not depend on the schedule: every pair is computed on its own.
  * Errors: INVALID_ARG (null, out of range). */
 typedef struct {
@@ -216,7 +221,8 @@ typedef struct {
   int32_t dynamic;
   int32_t split;
   int32_t crop_unroll; /* 2, 4 or 8: 64-point blocks whose loads a crop wave issues together */
-  int32_t reserved[3]; /* must be 0 */
+  int32_t chunks;
+  int32_t reserved[2]; /* must be 0 */
 } locc_schedule;
 
 LOCC_API locc_status locc_set_schedule(locc_ctx* ctx, const locc_schedule* sched);

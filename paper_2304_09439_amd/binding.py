@@ -37,11 +37,12 @@ class Config(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("wg_per_cu", ctypes.c_int32), ("claim", ctypes.c_int32), ("dynamic", ctypes.c_int32),
-                ("split", ctypes.c_int32), ("crop_unroll", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("split", ctypes.c_int32), ("crop_unroll", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
     def as_dict(self):
         return dict(wg_per_cu=self.wg_per_cu, claim=self.claim, dynamic=bool(self.dynamic), split=bool(self.split),
-                    crop_unroll=self.crop_unroll)
+                    crop_unroll=self.crop_unroll, chunks=self.chunks)
 
 
 class ServeConfig(ctypes.Structure):
@@ -261,8 +262,8 @@ class Context:
         return out, counts, z, y
 
     def set_schedule(self, wg_per_cu: int = 2, claim: int = 4, dynamic: bool = True, split: bool = True,
-                     crop_unroll: int = 8):
-        sc = Schedule(wg_per_cu, claim, int(dynamic), int(split), crop_unroll)
+                     crop_unroll: int = 8, chunks: int = 1):
+        sc = Schedule(wg_per_cu, claim, int(dynamic), int(split), crop_unroll, chunks)
         _check(load().locc_set_schedule(self._h, ctypes.byref(sc)))
 
     def get_schedule(self) -> dict:

@@ -211,32 +211,79 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
     return LOCC_OK;
   }
   const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
-  if (c->cfg.precision == LOCC_FP8) {
-    CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err, w.setup};
-    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
-    Fp8Args fa{};
-    fa.objs = objs;
-    fa.n_pairs = n_pairs;
-    fa.n_pairs_dev = n_dev;
-    fa.K = c->cfg.K;
-    fp8_bind(fa, c->d_wfp8, h1, h2, hh);
-    fa.s_w2 = c->fp8_wscale[0];
-    fa.s_h1 = c->fp8_wscale[1];
-    fa.s_h2 = c->fp8_wscale[2];
-    fa.s_h1in = fp8_scale(c->fp8_amax[0]);
-    fa.s_z = fp8_scale(c->fp8_amax[1]);
-    fa.s_g1 = fp8_scale(c->fp8_amax[2]);
-    fa.rows_bf16 = w.rows_bf16;
-    fa.meta = w.meta;
-    fa.out = out;
-    fa.z_dbg = z_out;
-    fa.y_dbg = y_out;
-    fa.queue = own ? own->queue : c->d_queue;
-    fa.claim = c->sched.claim;
-    fa.dynamic = c->sched.dynamic;
-    const int grid = fused_grid(c, n_pairs);
-    HIP_TRY(timed(c, "encoder_head_fp8", s, [&] { return launch_encoder_head_fp8(fa, h1, h2, hh, grid, s); }));
+  const int K = c->cfg.K;
+  if (c->cfg.precision == LOCC_FP8 || c->sched.split) {
+    // Crop kernel, then the persistent encoder + head kernel.  With chunks > 1
+    // the step is cut into that many runs of pairs: the crop of run k + 1 (on
+    // the context's second stream) overlaps the network of run k (on s).
+    int C = own ? 1 : c->sched.chunks;
+    while (C > 1 && n_pairs / C < 256) C >>= 1;
+    const int L = (n_pairs + C - 1) / C;
+    hipStream_t cs = C > 1 ? c->crop_stream : s;
+    if (C > 1) {
+      HIP_TRY(hipEventRecord(c->chunk_ev[0], s));
+      HIP_TRY(hipStreamWaitEvent(cs, c->chunk_ev[0], 0));
+    }
+    for (int k = 0; k < C; ++k) {
+      const int s0 = k * L;
+      const int len = n_pairs - s0 < L ? n_pairs - s0 : L;
+      if (len <= 0) break;
+      PairMeta* meta = w.meta + s0;
+      unsigned short* rows = w.rows_bf16 + (size_t)s0 * 2 * K * 8;
+      CropArgs ca{objs, n_objs, pairs + 2 * (size_t)s0, len, n_dev, c->lib(), K, c->cfg.pad_m,
+                  nullptr, counts ? counts + 2 * (size_t)s0 : nullptr, meta, nullptr, rows, c->d_err,
+                  static_cast<char*>(w.setup) + (size_t)s0 * kPairSetupBytes, s0};
+      HIP_TRY(timed(c, "crop", cs, [&] { return launch_crop(ca, cs, unroll); }));
+      if (C > 1) {
+        HIP_TRY(hipEventRecord(c->chunk_ev[k + 1], cs));
+        HIP_TRY(hipStreamWaitEvent(s, c->chunk_ev[k + 1], 0));
+      }
+      const int grid = fused_grid(c, len);
+      if (c->cfg.precision == LOCC_FP8) {
+        Fp8Args fa{};
+        fa.objs = objs;
+        fa.n_pairs = len;
+        fa.n_pairs_dev = n_dev;
+        fa.dev_base = s0;
+        fa.K = K;
+        fp8_bind(fa, c->d_wfp8, h1, h2, hh);
+        fa.s_w2 = c->fp8_wscale[0];
+        fa.s_h1 = c->fp8_wscale[1];
+        fa.s_h2 = c->fp8_wscale[2];
+        fa.s_h1in = fp8_scale(c->fp8_amax[0]);
+        fa.s_z = fp8_scale(c->fp8_amax[1]);
+        fa.s_g1 = fp8_scale(c->fp8_amax[2]);
+        fa.rows_bf16 = rows;
+        fa.meta = meta;
+        fa.out = out + s0;
+        fa.z_dbg = z_out ? z_out + (size_t)s0 * 2 * h2 : nullptr;
+        fa.y_dbg = y_out ? y_out + (size_t)s0 * 8 : nullptr;
+        fa.queue = own ? own->queue : c->d_queue;
+        fa.claim = c->sched.claim;
+        fa.dynamic = c->sched.dynamic;
+        HIP_TRY(timed(c, "encoder_head_fp8", s, [&] { return launch_encoder_head_fp8(fa, h1, h2, hh, grid, s); }));
+      } else {
+        FusedArgs fa{};
+        fa.objs = objs;
+        fa.n_objs = n_objs;
+        fa.n_pairs = len;
+        fa.n_pairs_dev = n_dev;
+        fa.dev_base = s0;
+        fa.lib = c->lib();
+        fa.K = K;
+        fa.pad = c->cfg.pad_m;
+        bf16_bind(fa, c->d_wbf16, h1, h2, hh);
+        fa.out = out + s0;
+        fa.z_dbg = z_out ? z_out + (size_t)s0 * 2 * h2 : nullptr;
+        fa.y_dbg = y_out ? y_out + (size_t)s0 * 8 : nullptr;
+        fa.rows_bf16 = rows;
+        fa.meta = meta;
+        fa.queue = own ? own->queue : c->d_queue;
+        fa.claim = c->sched.claim;
+        fa.dynamic = c->sched.dynamic;
+        HIP_TRY(timed(c, "encoder_head_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, true, s); }));
+      }
+    }
     return LOCC_OK;
   }
   FusedArgs fa{};
@@ -246,9 +293,9 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   fa.n_pairs = n_pairs;
   fa.n_pairs_dev = n_dev;
   fa.lib = c->lib();
-  fa.K = c->cfg.K;
+  fa.K = K;
   fa.pad = c->cfg.pad_m;
-  bf16_bind(fa, c->d_wbf16, c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
+  bf16_bind(fa, c->d_wbf16, h1, h2, hh);
   fa.out = out;
   fa.counts = counts;
   fa.z_dbg = z_out;
@@ -258,17 +305,6 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   fa.claim = c->sched.claim;
   fa.dynamic = c->sched.dynamic;
   const int grid = fused_grid(c, n_pairs);
-  if (c->sched.split) {
-    CropArgs ca{objs, n_objs, pairs, n_pairs, n_dev, c->lib(), c->cfg.K, c->cfg.pad_m,
-                nullptr, counts, w.meta, nullptr, w.rows_bf16, c->d_err, w.setup};
-    HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, unroll); }));
-    fa.rows_bf16 = w.rows_bf16;
-    fa.meta = w.meta;
-    fa.counts = nullptr;        // written by the crop kernel
-    fa.err_counter = nullptr;   // counted by the crop kernel
-    HIP_TRY(timed(c, "encoder_head_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, true, s); }));
-    return LOCC_OK;
-  }
   HIP_TRY(timed(c, "fused_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, false, s); }));
   return LOCC_OK;
 }
@@ -283,7 +319,9 @@ locc_status check_schedule(const locc_schedule* sc) {
   if (sc->split != 0 && sc->split != 1) return fail(LOCC_ERR_INVALID_ARG, "split must be 0 or 1");
   if (sc->crop_unroll != 2 && sc->crop_unroll != 4 && sc->crop_unroll != 8)
     return fail(LOCC_ERR_INVALID_ARG, "crop_unroll=%d: must be 2, 4 or 8", sc->crop_unroll);
-  if (sc->reserved[0] || sc->reserved[1] || sc->reserved[2])
+  if (sc->chunks != 1 && sc->chunks != 2 && sc->chunks != 4 && sc->chunks != 8)
+    return fail(LOCC_ERR_INVALID_ARG, "chunks=%d: must be 1, 2, 4 or 8", sc->chunks);
+  if (sc->reserved[0] || sc->reserved[1])
     return fail(LOCC_ERR_INVALID_ARG, "reserved fields must be 0");
   return LOCC_OK;
 }
@@ -310,8 +348,8 @@ bool tune_cache_lookup(const char* path, const std::string& key, locc_schedule* 
   locc_schedule t{};
   double m = 0;
   bool hit = false;
-  while (std::fscanf(f, "%255s %d %d %d %d %d %lf", k, &t.wg_per_cu, &t.claim, &t.dynamic, &t.split,
-                     &t.crop_unroll, &m) == 7) {
+  while (std::fscanf(f, "%255s %d %d %d %d %d %d %lf", k, &t.wg_per_cu, &t.claim, &t.dynamic, &t.split,
+                     &t.crop_unroll, &t.chunks, &m) == 8) {
     if (key == k && check_schedule(&t) == LOCC_OK) {
       *sc = t;
       *ms = m;
@@ -326,26 +364,27 @@ void tune_cache_store(const char* path, const std::string& key, const locc_sched
   if (!path) return;
   std::FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d %.6f\n", key.c_str(), sc.wg_per_cu, sc.claim, sc.dynamic, sc.split,
-               sc.crop_unroll, ms);
+  std::fprintf(f, "%s %d %d %d %d %d %d %.6f\n", key.c_str(), sc.wg_per_cu, sc.claim, sc.dynamic, sc.split,
+               sc.crop_unroll, sc.chunks, ms);
   std::fclose(f);
 }
 
 std::vector<locc_schedule> tune_candidates(const locc_ctx* c) {
   std::vector<locc_schedule> out;
   if (c->cfg.precision == LOCC_FP32) {
-    for (int u : {2, 4, 8}) out.push_back(locc_schedule{kFusedWgPerCu, 4, 1, 0, u, {0, 0, 0}});
+    for (int u : {2, 4, 8}) out.push_back(locc_schedule{kFusedWgPerCu, 4, 1, 0, u, 1, {0, 0}});
     return out;
   }
   for (int split : {1, 0})
     for (int wg : {2, 1})
-      for (int claim : {1, 4, 16})
+      for (int claim : {4, 16})
         for (int dyn : {1, 0})
-          for (int u : {4, 8}) {
-            if (!split && u != 8) continue;  // the fused kernel's scan unroll is fixed
-            if (!split && c->cfg.precision == LOCC_FP8) continue;  // FP8 runs split only
-            out.push_back(locc_schedule{wg, claim, dyn, split, u, {0, 0, 0}});
-          }
+          for (int u : {4, 8})
+            for (int chunks : {1, 2, 4}) {
+              if (!split && (u != 8 || chunks != 1)) continue;  // the fused kernel: fixed scan unroll, no chunks
+              if (!split && c->cfg.precision == LOCC_FP8) continue;  // FP8 runs split only
+              out.push_back(locc_schedule{wg, claim, dyn, split, u, chunks, {0, 0}});
+            }
   return out;
 }
 
@@ -392,6 +431,11 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (e == hipSuccess) e = hipMalloc(&c->d_queue, 2 * sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemset(c->d_queue, 0, 2 * sizeof(unsigned int));
   if (e == hipSuccess && cfg->precision == LOCC_FP8) e = hipMalloc(&c->d_amax, 3 * sizeof(unsigned int));
+  if (e == hipSuccess && cfg->precision != LOCC_FP32) {
+    e = hipStreamCreateWithFlags(&c->crop_stream, hipStreamNonBlocking);
+    for (int k = 0; e == hipSuccess && k <= locc_ctx::kMaxChunks; ++k)
+      e = hipEventCreateWithFlags(&c->chunk_ev[k], hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     locc_destroy(c);
@@ -415,6 +459,9 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_amax);
   (void)hipFree(c->d_queue);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  if (c->crop_stream) (void)hipStreamDestroy(c->crop_stream);
+  for (hipEvent_t e : c->chunk_ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipFree(c->d_ws);
   (void)hipFree(c->d_err);
   delete c;

@@ -30,8 +30,12 @@ struct locc_ctx {
   unsigned int* d_amax = nullptr;  // FP8 calibration accumulator [3]
   bool have_weights = false;
   // fused-kernel schedule and its self-resetting queue (two uint32, zero between launches)
-  locc_schedule sched{locc::kFusedWgPerCu, 4, 1, 1, 8, {0, 0, 0}};  // split, claim 4: best on 16384 pairs
+  locc_schedule sched{locc::kFusedWgPerCu, 4, 1, 1, 8, 1, {0, 0}};  // split, claim 4
   unsigned int* d_queue = nullptr;
+  // chunked schedules: the crop's stream and the fork / per-run events
+  static constexpr int kMaxChunks = 8;
+  hipStream_t crop_stream = nullptr;
+  hipEvent_t chunk_ev[kMaxChunks + 1] = {};
   hipStream_t capture_stream = nullptr;  // created on first graph capture
   bool capturing = false;
   // workspace

@@ -14,7 +14,7 @@ constexpr int kThreads = 256;
 
 __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
-  if (p >= pair_count(A.n_pairs, A.n_pairs_dev)) return;
+  if (p >= pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base)) return;
   PairSetup r{};
   locc_object oa, ob;
   ShapeDesc da, db;
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int K = A.K;
-  if (p >= pair_count(A.n_pairs, A.n_pairs_dev)) return;  // uniform
+  if (p >= pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base)) return;  // uniform
 
   // the pair's record: the same address for the whole workgroup
   const PairSetup* __restrict__ rec =

@@ -37,6 +37,7 @@ struct FusedArgs {
   unsigned int* queue;  // [2]: next unclaimed pair, finished workgroups (both 0 between launches)
   int32_t claim;        // pairs claimed at once
   int32_t dynamic;      // 1: atomic queue, 0: static round robin
+  int32_t dev_base;     // first pair of this launch within the step (device count mode)
 };
 
 // Byte offsets of the packed BF16 weights inside one device buffer.
@@ -91,6 +92,7 @@ struct Fp8Args {
   unsigned int* queue;
   int32_t claim;
   int32_t dynamic;
+  int32_t dev_base;  // first pair of this launch within the step (device count mode)
 };
 
 struct Fp8Layout {

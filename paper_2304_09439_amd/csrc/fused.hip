@@ -102,7 +102,7 @@ template <int KDIM, int SS, int DS, int CTH>
 __device__ __forceinline__ void head_layer(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
                                            const unsigned short* src, unsigned short* dst) {
   constexpr int KS = KDIM / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
+  const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
   const unsigned short* arow = src + l32 * SS + 8 * g;
   f32x16 acc[CTH];
@@ -140,7 +140,7 @@ template <int H1, int H2, int HH>
 __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& S, int n) {
   using S_t = Smem<H1, H2, HH>;
   constexpr int T = S_t::T, ZS = S_t::ZS, GS = S_t::GS, CTH = HH / 128, KS3 = HH / 16;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   for (int e = tid; e < (T - n) * ZS; e += 256) S.z[n * ZS + e] = 0;
   __syncthreads();
   head_layer<2 * H2, ZS, GS, CTH>(A.h1p, A.c1, S.z, S.u.g);
@@ -181,11 +181,11 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = wave_index();
   const int g = lane >> 5;
   const int l32 = lane & 31;
   const int K = A.K;
-  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base);
 
   // this wave's W2 slice, layer-1 weights and layer-2 bias stay in registers
   u16x8 w2f[CT][KS2];

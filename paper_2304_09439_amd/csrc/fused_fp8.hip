@@ -85,7 +85,7 @@ template <int KDIM, int SB, int DS, int CTH, bool DST_BF16>
 __device__ __forceinline__ void head_layer8(const unsigned char* __restrict__ pack, const float* __restrict__ bias,
                                             float scale, float dst_inv, const unsigned char* src, void* dst) {
   constexpr int KS = KDIM / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
+  const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const i32x8* bp = reinterpret_cast<const i32x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
   const unsigned char* arow = src + l32 * SB + 32 * g;
   f32x16 acc[CTH];
@@ -130,7 +130,7 @@ template <int H1, int H2, int HH>
 __device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH>& S, int n) {
   using S_t = Smem8<H1, H2, HH>;
   constexpr int T = S_t::T, ZB = S_t::ZB, GB = S_t::GB, G2 = S_t::G2, CTH = HH / 128, KS3 = HH / 16;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   for (int e = tid; e < (T - n) * ZB; e += 256) S.z[n * ZB + e] = 0;
   __syncthreads();
   head_layer8<2 * H2, ZB, GB, CTH, false>(A.h1p, A.c1, A.s_z * A.s_h1, 1.f / A.s_g1, S.z, S.g1);
@@ -167,9 +167,9 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
   constexpr int CT = H2 / 128;   // encoder column tiles per wave
   static_assert(H1 % 64 == 0 && H2 % 128 == 0 && HH % 128 == 0, "widths");
   __shared__ S_t S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 5, l32 = lane & 31;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const int K = A.K;
-  const int P = pair_count(A.n_pairs, A.n_pairs_dev);
+  const int P = pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base);
   const float inv_h1 = 1.f / A.s_h1in, s_enc = A.s_h1in * A.s_w2, inv_z = 1.f / A.s_z;
 
   i32x8 w2f[CT][KS2];

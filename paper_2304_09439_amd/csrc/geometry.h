@@ -115,6 +115,10 @@ __device__ __forceinline__ bool geo_inside(const PairGeom& g, double q0, double 
          (q2 <= g.hi[2]);
 }
 
+// Index of the calling wave in its workgroup, as a wave-uniform (scalar)
+// value, so that everything derived from it stays in scalar registers.
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
 __device__ __forceinline__ int geo_wave_inclusive_scan(int v, int lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -250,7 +254,7 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp,
   constexpr int R = 4 * kScanUnroll;  // blocks per round
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = wave_index();
   const int nblk_a = (n_a + 63) >> 6, nblk_b = (n_b + 63) >> 6;
   int cur_a = 0, cur_b = 0, cnt_a = 0, cnt_b = 0;  // uniform
   for (;;) {
@@ -272,15 +276,17 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp,
       float x[kScanUnroll], y[kScanUnroll], z[kScanUnroll];
 #pragma unroll
       for (int u = 0; u < kScanUnroll; ++u) {
+        // block, object and base pointers are wave-uniform; only the lane
+        // offset lives in a vector register
         const int i = i0 + 4 * u;
         const int side = i >= q_a;
-        const int k = ((side ? cur_b + i - q_a : cur_a + i) << 6) + lane;
+        const int off = side ? off_b : off_a;
+        const unsigned k = ((unsigned)(side ? cur_b + i - q_a : cur_a + i) << 6) + (unsigned)lane;
         x[u] = y[u] = z[u] = 0.f;
-        if (i < q && k < (side ? n_b : n_a)) {
-          const int gi = (side ? off_b : off_a) + k;
-          x[u] = lib.px[gi];
-          y[u] = lib.py[gi];
-          z[u] = lib.pz[gi];
+        if (i < q && k < (unsigned)(side ? n_b : n_a)) {
+          x[u] = (lib.px + off)[k];
+          y[u] = (lib.py + off)[k];
+          z[u] = (lib.pz + off)[k];
         }
       }
 #pragma unroll
@@ -312,8 +318,8 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp,
       ca += __shfl_xor(ca, o, 64);
       cb += __shfl_xor(cb, o, 64);
     }
-    cnt_a += ca;
-    cnt_b += cb;
+    cnt_a += __builtin_amdgcn_readfirstlane(ca);  // the same in every lane: keep the counts scalar
+    cnt_b += __builtin_amdgcn_readfirstlane(cb);
   }
   if ((wave & 1) == 0) {
     const int side = wave >> 1;

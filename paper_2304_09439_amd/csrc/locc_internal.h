@@ -55,10 +55,11 @@ struct DeviceLibrary {
 // Pair count of a launch: n_pairs is the capacity (grid sizing); when
 // n_pairs_dev is set the kernels read the actual count from device memory
 // (clamped to the capacity), so one captured graph serves steps whose pair
-// counts differ.
-__device__ __forceinline__ int pair_count(int capacity, const int32_t* dev) {
+// counts differ.  A launch over a chunk that starts at pair `base` of the
+// step sees *dev - base pairs, clamped to [0, capacity].
+__device__ __forceinline__ int pair_count(int capacity, const int32_t* dev, int base = 0) {
   if (!dev) return capacity;
-  const int n = *dev;
+  const int n = *dev - base;
   return n < 0 ? 0 : (n < capacity ? n : capacity);
 }
 
@@ -79,6 +80,7 @@ struct CropArgs {
                               // multiple of 32 of each object's count written, may be null
   unsigned long long* err_counter;
   void* setup;           // [P] records of kPairSetupBytes (library workspace), required
+  int32_t dev_base;      // first pair of this launch within the step (device count mode)
 };
 
 // Bytes of the per-pair record (pose, box, screening constants, canonical

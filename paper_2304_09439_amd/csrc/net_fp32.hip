@@ -35,6 +35,9 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // first; maximum needs no canonicalisation and chains into v_maximum3_f32.
 __device__ __forceinline__ float vmax(float a, float b) { return __builtin_elementwise_maximum(a, b); }
 
+// Index of the calling wave in its workgroup, wave-uniform (scalar register).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
 __device__ __forceinline__ f32x16 mfma32x32x2(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
@@ -49,7 +52,7 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
   constexpr int CT = H2 / 128;  // 32-column tiles per wave
   static_assert(H1 % 32 == 0 && H2 % 128 == 0, "widths");
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_index();
   const int g = lane >> 5;
   const int K = A.K;
 
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(256, 1) void head_fp32_kernel(Fp32Net W, NetArgs A)
   float* gt = smem + kHeadPairs * (LZ > LG ? LZ : LG);  // [32][LG]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = wave_index();
   const int g = lane >> 5;
   const int p0 = blockIdx.x * kHeadPairs;
   const int P = pair_count(A.n_pairs, A.n_pairs_dev);

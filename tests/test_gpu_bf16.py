@@ -104,7 +104,9 @@ SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True, split=False),
              dict(wg_per_cu=1, claim=64, dynamic=False, split=False),
              dict(wg_per_cu=2, claim=1, dynamic=True, split=True, crop_unroll=2),
              dict(wg_per_cu=2, claim=8, dynamic=False, split=True, crop_unroll=4),
-             dict(wg_per_cu=1, claim=4, dynamic=True, split=True, crop_unroll=8)]
+             dict(wg_per_cu=1, claim=4, dynamic=True, split=True, crop_unroll=8),
+             dict(wg_per_cu=2, claim=4, dynamic=True, split=True, crop_unroll=4, chunks=2),
+             dict(wg_per_cu=1, claim=16, dynamic=False, split=True, crop_unroll=8, chunks=8)]
 
 
 def test_bf16_results_do_not_depend_on_the_schedule(torch, small_scene):

@@ -48,10 +48,12 @@ def _ctx(envs, precision):
     return ctx
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp32"])
-def test_graph_replays_match_eager_launches(torch, envs, precision):
-    say(f"graph replay vs eager, {precision}, {envs.n_steps} steps of uneven environments")
+@pytest.mark.parametrize("precision,chunks", [("bf16", 1), ("bf16", 4), ("fp32", 1)])
+def test_graph_replays_match_eager_launches(torch, envs, precision, chunks):
+    say(f"graph replay vs eager, {precision}, chunks {chunks}, {envs.n_steps} steps of uneven environments")
     ctx = _ctx(envs, precision)
+    if chunks > 1:   # runs of pairs whose crop overlaps the previous run's network, on a second stream
+        ctx.set_schedule(wg_per_cu=1, claim=4, dynamic=True, split=True, crop_unroll=4, chunks=chunks)
     cap = max(len(p) for p in envs.pairs) + 17
     n_obj = len(envs.shape)
     objs = torch.zeros((n_obj, 8), dtype=torch.float32, device="cuda")
@@ -81,17 +83,19 @@ def test_graph_replays_match_eager_launches(torch, envs, precision):
 
 def test_device_count_is_clamped_to_the_capacity(torch, envs):
     ctx = _ctx(envs, "bf16")
-    sc = envs.scene(0).subset(np.arange(500))
+    sc = envs.scene(0).subset(np.arange(1100))
     objs, pairs = B.scene_tensors(sc)
-    ctx.reserve(500)
+    ctx.reserve(1100)
     ref, _ = ctx.detect(objs, pairs)
-    for n, expect in ((10**6, 500), (-5, 0), (0, 0), (123, 123)):
-        out = torch.full((500, 8), 7.0, dtype=torch.float32, device="cuda")
-        n_dev = torch.tensor([n], dtype=torch.int32, device="cuda")
-        ctx.detect_device_count(objs, pairs, n_dev, out)
-        torch.cuda.synchronize()
-        assert torch.equal(out[:expect], ref[:expect])
-        assert torch.all(out[expect:] == 7.0)
+    for chunks in (1, 2):   # two runs of 550 pairs: counts that end in either run
+        ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=True, crop_unroll=4, chunks=chunks)
+        for n, expect in ((10**6, 1100), (-5, 0), (0, 0), (123, 123), (600, 600)):
+            out = torch.full((1100, 8), 7.0, dtype=torch.float32, device="cuda")
+            n_dev = torch.tensor([n], dtype=torch.int32, device="cuda")
+            ctx.detect_device_count(objs, pairs, n_dev, out)
+            torch.cuda.synchronize()
+            assert torch.equal(out[:expect], ref[:expect]), (chunks, n)
+            assert torch.all(out[expect:] == 7.0), (chunks, n)
     ctx.close()
 
 
