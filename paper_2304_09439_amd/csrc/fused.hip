@@ -97,31 +97,37 @@ struct Smem {
 
 // One head layer on the tile: dst = ReLU(src W^T + bias), bf16 in / out.
 // Wave w computes output column tiles [w CTH, (w+1) CTH); B fragments stream
-// from global memory (L2) one k-step ahead.
-template <int KDIM, int SS, int DS, int CTH>
+// from global memory (L2) D k-steps ahead, in a ring of registers, so that
+// several L2 round trips are in flight behind the matrix cores.
+template <int KDIM, int SS, int DS, int CTH, int D>
 __device__ __forceinline__ void head_layer(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
                                            const unsigned short* src, unsigned short* dst) {
   constexpr int KS = KDIM / 16;
+  static_assert(KS % D == 0, "k-steps per head layer");
   const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
   const unsigned short* arow = src + l32 * SS + 8 * g;
   f32x16 acc[CTH];
 #pragma unroll
   for (int c = 0; c < CTH; ++c) acc[c] = f32x16{};
-  u16x8 bcur[CTH];
+  u16x8 bq[D][CTH];
 #pragma unroll
-  for (int c = 0; c < CTH; ++c) bcur[c] = bp[(size_t)c * KS * 64];
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + d) * 64];
 #pragma unroll 1
-  for (int s = 0; s < KS; ++s) {
-    u16x8 bnext[CTH];
-    const int sn = s + 1 < KS ? s + 1 : s;
+  for (int s0 = 0; s0 < KS; s0 += D) {
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) bnext[c] = bp[((size_t)c * KS + sn) * 64];
-    const u16x8 av = *reinterpret_cast<const u16x8*>(arow + 16 * s);
+    for (int d = 0; d < D; ++d) {
+      const int s = s0 + d;
+      const u16x8 av = *reinterpret_cast<const u16x8*>(arow + 16 * s);
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) acc[c] = mfma_k16(av, bcur[c], acc[c]);
+      for (int c = 0; c < CTH; ++c) acc[c] = mfma_k16(av, bq[d][c], acc[c]);
+      if (s + D < KS) {
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) bcur[c] = bnext[c];
+        for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + s + D) * 64];
+      }
+    }
   }
 #pragma unroll
   for (int c = 0; c < CTH; ++c) {
@@ -136,16 +142,17 @@ __device__ __forceinline__ void head_layer(const unsigned short* __restrict__ pa
 }
 
 // Head on the first n rows of the z tile, then the world-frame epilogue.
-template <int H1, int H2, int HH>
+// D: k-steps of weight fragments in flight (registers permitting)
+template <int H1, int H2, int HH, int D>
 __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& S, int n) {
   using S_t = Smem<H1, H2, HH>;
   constexpr int T = S_t::T, ZS = S_t::ZS, GS = S_t::GS, CTH = HH / 128, KS3 = HH / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   for (int e = tid; e < (T - n) * ZS; e += 256) S.z[n * ZS + e] = 0;
   __syncthreads();
-  head_layer<2 * H2, ZS, GS, CTH>(A.h1p, A.c1, S.z, S.u.g);
+  head_layer<2 * H2, ZS, GS, CTH, D>(A.h1p, A.c1, S.z, S.u.g);
   __syncthreads();
-  head_layer<HH, GS, ZS, CTH>(A.h2p, A.c2, S.u.g, S.z);
+  head_layer<HH, GS, ZS, CTH, D>(A.h2p, A.c2, S.u.g, S.z);
   __syncthreads();
   // layer 3 (8 outputs, padded to 32 columns), reduction split over the 4 waves
   {
@@ -355,12 +362,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       ++slot;
       __syncthreads();  // rows and crop scratch are reused by the next pair
       if (slot == T) {
-        head_tile<H1, H2, HH>(A, S, T);
+        head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, T);
         slot = 0;
       }
     }
   }
-  if (slot > 0) head_tile<H1, H2, HH>(A, S, slot);
+  if (slot > 0) head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, slot);
 
   if (A.dynamic && tid == 0) {
     __threadfence();

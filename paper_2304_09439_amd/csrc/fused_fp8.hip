@@ -84,29 +84,34 @@ struct Smem8 {
 template <int KDIM, int SB, int DS, int CTH, bool DST_BF16>
 __device__ __forceinline__ void head_layer8(const unsigned char* __restrict__ pack, const float* __restrict__ bias,
                                             float scale, float dst_inv, const unsigned char* src, void* dst) {
-  constexpr int KS = KDIM / 64;
+  constexpr int KS = KDIM / 64, D = 2;  // weight fragments D k-steps ahead, in a ring of registers
+  static_assert(KS % D == 0, "k-steps per head layer");
   const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const i32x8* bp = reinterpret_cast<const i32x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
   const unsigned char* arow = src + l32 * SB + 32 * g;
   f32x16 acc[CTH];
 #pragma unroll
   for (int c = 0; c < CTH; ++c) acc[c] = f32x16{};
-  i32x8 bcur[CTH];
+  i32x8 bq[D][CTH];
 #pragma unroll
-  for (int c = 0; c < CTH; ++c) bcur[c] = bp[(size_t)c * KS * 64];
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + d) * 64];
 #pragma unroll 1
-  for (int s = 0; s < KS; ++s) {
-    i32x8 bnext[CTH];
-    const int sn = s + 1 < KS ? s + 1 : s;
+  for (int s0 = 0; s0 < KS; s0 += D) {
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) bnext[c] = bp[((size_t)c * KS + sn) * 64];
-    const uint4 a0 = *reinterpret_cast<const uint4*>(arow + 64 * s);
-    const uint4 a1 = *reinterpret_cast<const uint4*>(arow + 64 * s + 16);
-    const i32x8 av = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+    for (int d = 0; d < D; ++d) {
+      const int s = s0 + d;
+      const uint4 a0 = *reinterpret_cast<const uint4*>(arow + 64 * s);
+      const uint4 a1 = *reinterpret_cast<const uint4*>(arow + 64 * s + 16);
+      const i32x8 av = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) acc[c] = mfma_f8(av, bcur[c], acc[c]);
+      for (int c = 0; c < CTH; ++c) acc[c] = mfma_f8(av, bq[d][c], acc[c]);
+      if (s + D < KS) {
 #pragma unroll
-    for (int c = 0; c < CTH; ++c) bcur[c] = bnext[c];
+        for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + s + D) * 64];
+      }
+    }
   }
 #pragma unroll
   for (int c = 0; c < CTH; ++c) {
