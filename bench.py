@@ -35,7 +35,9 @@ PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 
 CSRC = os.path.join(ROOT, "paper_2304_09439_amd", "csrc")
 KERNEL_SOURCES = {
-    "crop": ["crop.hip", "geometry.h"],
+    "crop_fp32": ["crop.hip", "geometry.h"],   # the crop kernel writing float32 rows
+    "crop_bf16": ["crop.hip", "geometry.h"],   # ... bf16 rows (BF16 split schedule)
+    "crop_fp8": ["crop.hip", "geometry.h"],    # ... bf16 rows (FP8 path)
     "encoder_fp32": ["net_fp32.hip"],
     "head_fp32": ["net_fp32.hip"],
     "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
@@ -142,7 +144,7 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
 
 # ------------------------------------------------------------------ GPU run
 
-def kernel_entries(kt, work, P, workload_name, steps):
+def kernel_entries(kt, work, P, workload_name, steps, precision):
     """Per kernel: average launch duration and the algorithmic rate of one launch (a step of P pairs may
     run a kernel several times, once per chunk of pairs)."""
     kernels = {}
@@ -168,7 +170,7 @@ def kernel_entries(kt, work, P, workload_name, steps):
             achieved = flops / (avg * 1e-3) / 1e12
             entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
                          frac=round(achieved / PEAK_TFLOPS[prec], 4))
-        entry["traffic"] = counter_traffic(name, workload_name)
+        entry["traffic"] = counter_traffic(f"crop_{precision}" if name == "crop" else name, workload_name)
         kernels[name] = entry
     return kernels
 
@@ -214,7 +216,7 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     n_bad = ctx.device_errors()
     ctx.close()
     ms = 1000.0 * wall / args.steps
-    kernels = kernel_entries(kt, work, P, workload_name, args.steps)
+    kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
