@@ -101,12 +101,13 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
     }
   }
   if (A.rows_bf16) {
-    // bf16 rows (x, y, z, nx, ny, nz, 1, 0), zero-padded to a multiple of 32 per object
-    const int ra = (m_a + 31) & ~31, rb = (m_b + 31) & ~31;
-    for (int e = tid; e < ra + rb; e += kThreads) {
-      const int s = e >= ra;
-      const int r = s ? e - ra : e;
-      const int m = s ? m_b : m_a;
+    // bf16 rows (x, y, z, nx, ny, nz, 1, 0), zero-padded to a multiple of 32
+    // per object; waves 0-1 write object a's rows, waves 2-3 object b's (the
+    // float64 transform of b's rows then never diverges inside a wave)
+    const int s = wave_index() >> 1;
+    const int rm = s ? (m_b + 31) & ~31 : (m_a + 31) & ~31;
+    const int m = s ? m_b : m_a;
+    for (int r = tid & 127; r < rm; r += 128) {
       unsigned short row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (r < m) {
         float v[6];

@@ -244,8 +244,8 @@ __device__ __forceinline__ bool geo_member_b(const PairGeom* __restrict__ gp, co
 // object's scan ends as soon as it has K members: its first K members in
 // stored order are then known, and its count is a lower bound >= K.
 // Finally wave 0 (object a) and wave 2 (object b) turn the ballots into
-// ordered positions (prefix of popcounts over blocks, then each lane walks
-// its block's set bits) and store the first K indices.  Ends with a
+// ordered positions (prefix of popcounts over blocks, then rank of each
+// member inside its block's ballot) and store the first K indices.  Ends with a
 // barrier; S.sel / S.count are then valid.
 template <int kScanUnroll>
 __device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp, const PairScreen& sc, int off_a, int n_a,
@@ -324,18 +324,27 @@ __device__ __forceinline__ void geo_scan_select(const PairGeom* __restrict__ gp,
   if ((wave & 1) == 0) {
     const int side = wave >> 1;
     const int nblk = side ? cur_b : cur_a;  // blocks scanned
-    // one block per lane (chunks of 64 blocks): exclusive prefix of the
-    // popcounts gives the block's first position; the lane then writes its
-    // block's members, lowest point first, while the position is below K.
+    // block per lane (chunks of 64 blocks): the exclusive prefix of the
+    // popcounts is each block's first position.  Then, block after block in
+    // stored order while positions stay below K, the block's ballot and
+    // start are read from its lane into scalar registers and every lane
+    // places its own point at start + (members below it in the block).
     int carry = 0;
     for (int base = 0; base < nblk; base += 64) {
       const int blk = base + lane;
-      unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
+      const unsigned long long m = blk < nblk ? S.mask[side][blk] : 0ull;
       const int c = __popcll(m);
       const int incl = geo_wave_inclusive_scan(c, lane);
-      for (int pos = carry + incl - c; m != 0ull && pos < K; ++pos) {
-        S.sel[side][pos] = (blk << 6) + __builtin_ctzll(m);
-        m &= m - 1ull;
+      const int start = carry + incl - c;
+      const int nb = nblk - base < 64 ? nblk - base : 64;
+      const unsigned m_lo = (unsigned)m, m_hi = (unsigned)(m >> 32);
+      for (int j = 0; j < nb; ++j) {
+        const int sj = __builtin_amdgcn_readlane(start, j);
+        if (sj >= K) break;
+        const unsigned lo = __builtin_amdgcn_readlane(m_lo, j), hi = __builtin_amdgcn_readlane(m_hi, j);
+        const unsigned mine = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+        const int pos = sj + (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+        if (mine && pos < K) S.sel[side][pos] = ((base + j) << 6) + lane;
       }
       carry += __shfl(incl, 63, 64);
     }
