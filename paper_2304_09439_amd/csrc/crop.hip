@@ -1,7 +1,7 @@
 // Crop step: a set-up kernel with one thread per pair validates the pair,
 // puts it in canonical order and computes its float64 relative pose, crop box
 // and float32 screening constants (geometry.h), so that this work is done
-// once per pair instead of once per wave; then one workgroup (4 wave64) per
+// once per pair instead of once per wave; then one wave per object of every
 // pair runs the membership scan and the ordered first-K selection, and
 // writes counts, the optional index sets, the per-pair records and the
 // encoder input rows (float32 for the FP32 path, bf16 for BF16 / FP8).
@@ -33,85 +33,150 @@ __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
   *reinterpret_cast<PairSetup*>(static_cast<char*>(A.setup) + (size_t)p * kPairSetupBytes) = r;
 }
 
+// One wave per object of a pair: workgroup 2p + side scans, selects and
+// gathers object `side` of pair p on its own (no barrier; the two objects of
+// a pair never wait for each other), so many more pairs are in flight per
+// compute unit than with a workgroup per pair.
+struct ObjectShared {
+  unsigned long long mask[kMaxBlocks];  // one ballot per 64 stored points
+  int32_t sel[kMaxK];
+};
+
 template <int U>
-__global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
-  __shared__ CropShared S;
-  const int p = blockIdx.x;
-  const int tid = threadIdx.x;
+__global__ __launch_bounds__(64) void crop_kernel(CropArgs A) {
+  __shared__ ObjectShared S;
+  const int p = blockIdx.x >> 1;
+  const int side = blockIdx.x & 1;
+  const int lane = threadIdx.x;
   const int K = A.K;
   if (p >= pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base)) return;  // uniform
 
-  // the pair's record: the same address for the whole workgroup
+  // the pair's record: the same address for the whole wave (scalar loads)
   const PairSetup* __restrict__ rec =
       reinterpret_cast<const PairSetup*>(static_cast<const char*>(A.setup) + (size_t)p * kPairSetupBytes);
-  const int a = rec->a, swapped = rec->swapped;
-  if (!rec->valid) {  // uniform
-    if (A.idx_out)
-      for (int e = tid; e < 2 * K; e += kThreads) A.idx_out[(size_t)p * 2 * K + e] = -1;
-    if (tid == 0) {
-      if (A.counts_out) {
-        A.counts_out[2 * p] = -1;
-        A.counts_out[2 * p + 1] = -1;
+  if (!rec->valid) {  // uniform; object 0's wave reports the pair
+    if (side == 0) {
+      if (A.idx_out)
+        for (int e = lane; e < 2 * K; e += 64) A.idx_out[(size_t)p * 2 * K + e] = -1;
+      if (lane == 0) {
+        if (A.counts_out) {
+          A.counts_out[2 * p] = -1;
+          A.counts_out[2 * p + 1] = -1;
+        }
+        if (A.meta) A.meta[p] = PairMeta{-1, 0, 0, 0};
+        atomicAdd(A.err_counter, 1ull);
       }
-      if (A.meta) A.meta[p] = PairMeta{-1, 0, 0, 0};
-      atomicAdd(A.err_counter, 1ull);
     }
     return;
   }
+  const int swapped = rec->swapped;
+  const int n = side ? rec->n_b : rec->n_a;
+  const int off = side ? rec->off_b : rec->off_a;
   const PairScreen sc = rec->sc;
-  const int off_a = rec->off_a, off_b = rec->off_b;
-  geo_scan_select<U>(&rec->g, sc, off_a, rec->n_a, off_b, rec->n_b, A.lib, K, A.counts_out != nullptr, S);
-  const PairGeom g = rec->g;
+  const bool full = A.counts_out != nullptr;  // else stop once K members are known
+  const float* __restrict__ px = A.lib.px + off;
+  const float* __restrict__ py = A.lib.py + off;
+  const float* __restrict__ pz = A.lib.pz + off;
 
-  const int n_a = S.count[0], n_b = S.count[1];
-  const int m_a = n_a < K ? n_a : K;
-  const int m_b = n_b < K ? n_b : K;
-  if (tid == 0) {
-    if (A.counts_out) {
-      A.counts_out[2 * p + swapped] = n_a;
-      A.counts_out[2 * p + 1 - swapped] = n_b;
+  // membership scan: U blocks of 64 points per round, loads in flight together
+  const int nblk = (n + 63) >> 6;
+  int scanned = 0, found = 0;  // wave-uniform
+  while (scanned < nblk && (full || found < K)) {
+    float x[U], y[U], z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned k = ((unsigned)(scanned + u) << 6) + (unsigned)lane;
+      x[u] = y[u] = z[u] = 0.f;
+      if (k < (unsigned)n) {
+        x[u] = px[k];
+        y[u] = py[k];
+        z[u] = pz[k];
+      }
     }
-    if (A.meta) A.meta[p] = PairMeta{a, swapped, m_a, m_b};
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int blk = scanned + u;
+      if (blk < nblk) {  // uniform
+        const unsigned k = ((unsigned)blk << 6) + (unsigned)lane;
+        bool in = false;
+        if (k < (unsigned)n) in = side ? geo_member_b(&rec->g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
+        const unsigned long long m = __ballot(in);
+        if (lane == 0) S.mask[blk] = m;
+        found += __popcll(m);
+      }
+    }
+    scanned = scanned + U < nblk ? scanned + U : nblk;
   }
-  if (A.idx_out) {
-    for (int e = tid; e < 2 * K; e += kThreads) {
-      const int s = e >= K;
-      const int r = e - s * K;
-      const int m = s ? m_b : m_a;
-      A.idx_out[((size_t)p * 2 + (s ^ swapped)) * K + r] = r < m ? S.sel[s][r] : -1;
+  // found: every member when full, else at least min(K, members)
+  __syncthreads();  // the ballots (written by lane 0) are read by every lane
+
+  // ordered first-K selection: block per lane (chunks of 64 blocks), the
+  // exclusive prefix of the popcounts is each block's first position; block
+  // after block while positions stay below K, the block's ballot and start
+  // go to scalar registers and every lane places its own point at start +
+  // (members below it in the block).
+  int carry = 0;
+  for (int base = 0; base < scanned && carry < K; base += 64) {
+    const int blk = base + lane;
+    const unsigned long long m = blk < scanned ? S.mask[blk] : 0ull;
+    const int c = __popcll(m);
+    const int incl = geo_wave_inclusive_scan(c, lane);
+    const int start = carry + incl - c;
+    const int nb = scanned - base < 64 ? scanned - base : 64;
+    const unsigned m_lo = (unsigned)m, m_hi = (unsigned)(m >> 32);
+    for (int j = 0; j < nb; ++j) {
+      const int sj = __builtin_amdgcn_readlane(start, j);
+      if (sj >= K) break;
+      const unsigned lo = __builtin_amdgcn_readlane(m_lo, j), hi = __builtin_amdgcn_readlane(m_hi, j);
+      const unsigned mine = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+      const int pos = sj + (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+      if (mine && pos < K) S.sel[pos] = ((base + j) << 6) + lane;
+    }
+    carry += __shfl(incl, 63, 64);
+  }
+  __syncthreads();  // the selected indices are read by other lanes
+  const int m = found < K ? found : K;
+  const int caller = side ^ swapped;  // position of this object in the caller's pair
+  if (lane == 0) {
+    if (A.counts_out) A.counts_out[2 * p + caller] = found;
+    if (A.meta) {
+      if (side == 0) {
+        A.meta[p].a = rec->a;
+        A.meta[p].swapped = swapped;
+        A.meta[p].m_a = m;
+      } else {
+        A.meta[p].m_b = m;
+      }
     }
   }
+  if (A.idx_out)
+    for (int r = lane; r < K; r += 64) A.idx_out[((size_t)p * 2 + caller) * K + r] = r < m ? S.sel[r] : -1;
   if (A.rows) {
     // rows (x, y, z, nx, ny, nz, 1, 0) stored permuted as (e0, e2, e4, e6, e1, e3, e5, e7);
     // zero rows past the valid count
-    for (int e = tid; e < 2 * K; e += kThreads) {
-      const int s = e >= K;
-      const int r = e - s * K;
-      const int m = s ? m_b : m_a;
+    const PairGeom g = rec->g;
+    for (int r = lane; r < K; r += 64) {
       float4 lo4 = make_float4(0.f, 0.f, 0.f, 0.f), hi4 = lo4;
       if (r < m) {
         float v[6];
-        geo_row(g, A.lib, (s ? off_b : off_a) + S.sel[s][r], s, v);
+        geo_row(g, A.lib, off + S.sel[r], side, v);
         lo4 = make_float4(v[0], v[2], v[4], 1.0f);
         hi4 = make_float4(v[1], v[3], v[5], 0.0f);
       }
-      float4* dst = reinterpret_cast<float4*>(A.rows + ((size_t)p * 2 * K + e) * kRowFloats);
+      float4* dst = reinterpret_cast<float4*>(A.rows + ((size_t)p * 2 * K + side * K + r) * kRowFloats);
       dst[0] = lo4;
       dst[1] = hi4;
     }
   }
   if (A.rows_bf16) {
     // bf16 rows (x, y, z, nx, ny, nz, 1, 0), zero-padded to a multiple of 32
-    // per object; waves 0-1 write object a's rows, waves 2-3 object b's (the
-    // float64 transform of b's rows then never diverges inside a wave)
-    const int s = wave_index() >> 1;
-    const int rm = s ? (m_b + 31) & ~31 : (m_a + 31) & ~31;
-    const int m = s ? m_b : m_a;
-    for (int r = tid & 127; r < rm; r += 128) {
+    const PairGeom g = rec->g;
+    const int rm = (m + 31) & ~31;
+    for (int r = lane; r < rm; r += 64) {
       unsigned short row[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       if (r < m) {
         float v[6];
-        geo_row(g, A.lib, (s ? off_b : off_a) + S.sel[s][r], s, v);
+        geo_row(g, A.lib, off + S.sel[r], side, v);
 #pragma unroll
         for (int k = 0; k < 6; ++k) row[k] = __builtin_bit_cast(unsigned short, (__bf16)v[k]);
         row[6] = 0x3f80;  // 1.0
@@ -121,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void crop_kernel(CropArgs A) {
       packed.y = row[2] | ((unsigned)row[3] << 16);
       packed.z = row[4] | ((unsigned)row[5] << 16);
       packed.w = row[6] | ((unsigned)row[7] << 16);
-      *reinterpret_cast<uint4*>(A.rows_bf16 + ((size_t)p * 2 * K + s * K + r) * 8) = packed;
+      *reinterpret_cast<uint4*>(A.rows_bf16 + ((size_t)p * 2 * K + side * K + r) * 8) = packed;
     }
   }
 }
@@ -133,9 +198,9 @@ hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll) {
   if (!a.setup || (unroll != 2 && unroll != 4 && unroll != 8)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pair_setup_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
   switch (unroll) {
-    case 2: hipLaunchKernelGGL(crop_kernel<2>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(crop_kernel<4>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(crop_kernel<8>, dim3(a.n_pairs), dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(crop_kernel<2>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(crop_kernel<4>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(crop_kernel<8>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
