@@ -184,7 +184,9 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     objs, pairs = B.scene_tensors(scene)
     P = scene.n_pairs
     out = torch.empty((P, 8), dtype=torch.float32, device="cuda")
-    counts = torch.empty((P, 2), dtype=torch.int32, device="cuda")
+    # the query's outputs are the contacts; the per-object member counts are an optional diagnostic, and
+    # without them each object's scan stops once its first K members are known (same contacts)
+    counts = torch.empty((P, 2), dtype=torch.int32, device="cuda") if args.member_counts else None
     stream = torch.cuda.current_stream()
     schedule = None
     if precision == "fp8":
@@ -194,9 +196,9 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
         ctx.set_schedule(**args.schedule[precision])   # a schedule given on the command line
         schedule = ctx.get_schedule()
     elif precision != "fp32" and not args.no_autotune:
-        schedule, _ = ctx.autotune(objs, pairs)   # the library's own autotuner picks the schedule
+        schedule, _ = ctx.autotune(objs, pairs, want_counts=counts is not None)   # the library's own autotuner
     for _ in range(args.warmup):
-        ctx.detect(objs, pairs, out, counts)
+        ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
     torch.cuda.synchronize()
     print(f"[bench] {precision}: warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs",
           file=sys.stderr, flush=True)
@@ -206,13 +208,23 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     t0 = time.perf_counter()
     for k in range(args.steps):
         ev[k][0].record(stream)
-        ctx.detect(objs, pairs, out, counts)
+        ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.profile(False)
     kt = ctx.profile_read()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    extra = {}
+    if counts is None:   # the same schedule with member counts requested (every point of both objects tested)
+        full = torch.empty((P, 2), dtype=torch.int32, device="cuda")
+        ctx.detect(objs, pairs, out, full)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.detect(objs, pairs, out, full)
+        torch.cuda.synchronize()
+        extra["ms_per_step_with_member_counts"] = round(1000.0 * (time.perf_counter() - t1) / args.steps, 4)
     n_bad = ctx.device_errors()
     ctx.close()
     ms = 1000.0 * wall / args.steps
@@ -220,7 +232,7 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
-                kernels=kernels, device_errors=int(n_bad),
+                kernels=kernels, device_errors=int(n_bad), member_counts=bool(args.member_counts), **extra,
                 path={"fp32": PATH_DESC["fp32"], "fp8": PATH_DESC["fp8"] + f" (autotuned: {schedule})"}.get(
                     precision, bf16_desc(schedule)))
 
@@ -246,14 +258,14 @@ def time_envs(args, envs, w, precision):
     pairs = torch.zeros((cap, 2), dtype=torch.int32, device="cuda")
     n_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
     out = torch.empty((cap, 8), dtype=torch.float32, device="cuda")
-    counts = torch.empty((cap, 2), dtype=torch.int32, device="cuda")
+    counts = torch.empty((cap, 2), dtype=torch.int32, device="cuda") if args.member_counts else None
     ctx.reserve(cap)
     graph, schedule = None, None
     if precision != "fp32":
         objs.copy_(objs_h[0])
         pairs[:len(envs.pairs[0])].copy_(pairs_h[0])
         if not args.no_autotune:
-            schedule, _ = ctx.autotune(objs, pairs[:len(envs.pairs[0])])
+            schedule, _ = ctx.autotune(objs, pairs[:len(envs.pairs[0])], want_counts=counts is not None)
         graph = ctx.capture_graph(objs, pairs, n_dev, out, counts)
     stream = torch.cuda.current_stream()
 
@@ -265,7 +277,7 @@ def time_envs(args, envs, w, precision):
             n_dev.copy_(n_h[s], non_blocking=True)
             graph.launch()
         else:
-            ctx.detect(objs, pairs[:P], out[:P], counts[:P])
+            ctx.detect(objs, pairs[:P], out[:P], None if counts is None else counts[:P], want_counts=counts is not None)
 
     for s in range(min(3, S)):
         step(s)
@@ -429,6 +441,8 @@ def run(args):
         ms_per_step=main_path["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype="f32" if primary == "fp32" else primary, data="synthetic",
         config=dict(workload=W["desc"], pairs=scene.n_pairs, K=K, points_per_shape=W["n_points"],
+                    outputs="contacts (logit, point, normal, depth)" + (" and member counts" if args.member_counts
+                                                                        else "; member counts not requested"),
                     shapes=W["n_shapes"], precision=primary, geometry="f64", path=main_path["path"]),
         p50_step_ms=main_path["p50_step_ms"], p99_step_ms=main_path["p99_step_ms"],
         roofline=roofline, kernels=kernels, cpu_baseline=cpu, device_errors=main_path["device_errors"],
@@ -508,6 +522,8 @@ def main():
                          "(repeatable; used to profile the schedule a previous run picked)")
     ap.add_argument("--precision", default="fp32,bf16,fp8",
                     help="comma list of paths to time: fp32 (per-step), bf16 (batched, the headline), fp8 (batched)")
+    ap.add_argument("--member-counts", action="store_true",
+                    help="request the per-object member counts in the timed steps (full scans of both objects)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
     ap.add_argument("--serve-requests", type=int, default=10000,

@@ -173,7 +173,9 @@ LOCC_API locc_status locc_upload_shapes(locc_ctx* ctx, int32_t n_shapes, const i
  *   d_pairs   [n_pairs][2] int32 object indices (i, j), device
  *   d_out     [n_pairs] locc_contact, device, written
  *   d_counts  [n_pairs][2] int32, device, or NULL: members of object i and of
- *             object j inside the crop box before the cap at K (-1 if invalid)
+ *             object j inside the crop box before the cap at K (-1 if invalid).
+ *             Without it each object's scan stops once its first K members
+ *             in stored order are known; the contacts are the same.
  * Device buffers belong to the caller and must stay valid until the stream
  * has run the work.  n_pairs == 0 is a no-op.  The library's own workspace
  * grows on demand (this may allocate; the call then synchronises the
@@ -236,7 +238,9 @@ LOCC_API locc_status locc_get_schedule(const locc_ctx* ctx, locc_schedule* sched
  * text file of earlier results keyed by device, configuration and the
  * power-of-two bucket of n_pairs is read first (a hit skips the timing) and
  * appended to after a miss.  d_out / d_counts receive the outputs of the
- * timed runs.  Synchronises `stream`.  *h_best_ms may be NULL.
+ * timed runs; d_counts may be NULL (the candidates are then timed as
+ * locc_detect runs without counts, whose scans stop once K members are
+ * known).  Synchronises `stream`.  *h_best_ms may be NULL.
  * Errors: as locc_detect, plus HIP. */
 LOCC_API locc_status locc_autotune(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
                                    int32_t n_pairs, locc_contact* d_out, int32_t* d_counts, void* stream,

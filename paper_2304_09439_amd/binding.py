@@ -271,12 +271,13 @@ class Context:
         _check(load().locc_get_schedule(self._h, ctypes.byref(sc)))
         return sc.as_dict()
 
-    def autotune(self, objs, pairs, cache_path=None, stream=None):
-        """Time every schedule on this workload, install and return the fastest: (schedule dict, ms)."""
+    def autotune(self, objs, pairs, cache_path=None, stream=None, want_counts=True):
+        """Time every schedule on this workload (with or without member counts), install and return the
+        fastest: (schedule dict, ms)."""
         import torch
         n_objs, P = self._inputs(objs, pairs)
         out = torch.empty((P, 8), dtype=torch.float32, device=objs.device)
-        counts = torch.empty((P, 2), dtype=torch.int32, device=objs.device)
+        counts = torch.empty((P, 2), dtype=torch.int32, device=objs.device) if want_counts else None
         sc = Schedule()
         ms = ctypes.c_double()
         path = None if cache_path is None else str(cache_path).encode()
