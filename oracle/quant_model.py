@@ -18,11 +18,14 @@ with a model written from the number formats, not from the kernel.
       with the static s_x = amax_x / 448 (amax over a calibration batch, or
       1 when that maximum is 0).  Scales are float32; the two scales of a
       layer are multiplied once, after the sum.
-  Q4  layer precisions: encoder layer 1 bf16 x bf16 (rows rounded float64 ->
-      float32 -> bf16, bias in bf16), encoder layer 2 e4m3 x e4m3, the
-      max-pool on the unscaled sums, then scale, bias and ReLU; head layers
-      1 and 2 e4m3 x e4m3; head layer 2's output rounded to bf16; head layer
-      3 bf16 x bf16.  Every sum is float32 in the kernel; here sums are
+  Q4  layer precisions: encoder layer 1 bf16 x bf16 in units of the scale
+      s_x of its output (weights and bias stored as bf16(W1 * (1 / s_x)),
+      bf16(b1 * (1 / s_x)), products in float32; rows rounded float64 ->
+      float32 -> bf16), its output entering encoder layer 2 as
+      e4m3(min(ReLU(h), 448)); encoder layer 2 e4m3 x e4m3, the max-pool on
+      the unscaled sums, then scale s_x s_W2, bias and ReLU; head layers 1 and
+      2 e4m3 x e4m3; head layer 2's output rounded to bf16; head layer 3 bf16
+      x bf16.  Every sum is float32 in the kernel; here sums are
       float64 and the result is rounded to float32 where a quantisation
       decision follows, so both sides take each decision in float32.
 """
@@ -113,7 +116,9 @@ def fp8_forward(geoms, weights_flat, widths, amax, quantise=True):
     q8 = e4m3 if quantise else f32
     s_w2, s_h1, s_h2 = weight_scale(W2), weight_scale(H1), weight_scale(H2)
     s_x, s_z, s_g = (act_scale(a) for a in amax)
-    W1q, b1q, H3q = [qb(w).astype(np.float64) for w in (W1, b1, H3)]
+    inv_x = np.float32(1.0) / s_x
+    W1q, b1q = [qb(f32(w) * inv_x).astype(np.float64) for w in (W1, b1)]   # layer 1 in units of s_x
+    H3q = qb(H3).astype(np.float64)
     W2q = q8(W2 / s_w2).astype(np.float64)
     H1q = q8(H1 / s_h1).astype(np.float64)
     H2q = q8(H2 / s_h2).astype(np.float64)
@@ -127,8 +132,8 @@ def fp8_forward(geoms, weights_flat, widths, amax, quantise=True):
         feats = []
         for rows in (g.rows_a, g.rows_b):
             r = qb(f32(rows)).astype(np.float64)
-            h = np.maximum(f32(r @ W1q.T + b1q), 0)
-            acc = qa(h, s_x).astype(np.float64) @ W2q.T
+            h = np.maximum(f32(r @ W1q.T + b1q), 0)                 # already divided by s_x
+            acc = q8(np.minimum(h, np.float32(E4M3_MAX))).astype(np.float64) @ W2q.T
             raw = acc.max(axis=0) if len(acc) else np.full(h2w, -np.inf)
             feats.append(np.maximum(f32(raw * np.float64(s_enc) + b2), 0))   # one rounding, as a fused multiply-add
         z[p] = np.concatenate(feats)

@@ -506,11 +506,32 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     if (!c->d_wraw) HIP_TRY(hipMalloc(&c->d_wraw, n * sizeof(float)));
     HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
     for (int k = 0; k < 3; ++k) c->fp8_wscale[k] = sc[k];
+    c->h_w1b1.assign(W1, W1 + (size_t)h1 * 6);
+    c->h_w1b1.insert(c->h_w1b1.end(), b1, b1 + h1);
     c->have_act_scales = false;  // activation maxima belong to the previous weights
   }
   c->have_weights = true;
   return LOCC_OK;
 }
+
+namespace {
+
+// Installs FP8 activation maxima and repacks encoder layer 1 in units of the
+// scale of its output (so the kernel converts without a multiply).
+locc_status fp8_install_amax(locc_ctx* c, const float* amax) {
+  const int h1 = c->cfg.enc_h1;
+  const float inv = 1.f / fp8_scale(amax[0]);
+  std::vector<unsigned short> w1((size_t)h1 * 8);
+  fp8_pack_w1(c->h_w1b1.data(), c->h_w1b1.data() + (size_t)h1 * 6, h1, inv, w1.data());
+  const Fp8Layout L = fp8_layout(h1, c->cfg.enc_h2, c->cfg.head_h);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipMemcpy(c->d_wfp8 + L.w1, w1.data(), w1.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
+  for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
+  c->have_act_scales = true;
+  return LOCC_OK;
+}
+
+}  // namespace
 
 locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
   if (!c || !amax) return fail(LOCC_ERR_INVALID_ARG, "null context or maxima");
@@ -519,9 +540,8 @@ locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
     if (!std::isfinite(amax[k]) || amax[k] < 0.f)
       return fail(LOCC_ERR_INVALID_ARG, "activation maximum %d = %g: must be finite and >= 0", k, amax[k]);
   if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
-  for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
-  c->have_act_scales = true;
-  return LOCC_OK;
+  if (c->capturing) return fail(LOCC_ERR_RANGE, "activation maxima during graph capture");
+  return fp8_install_amax(c, amax);
 }
 
 locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
@@ -554,8 +574,8 @@ locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs,
     HIP_TRY(hipStreamSynchronize(s));
     std::memcpy(amax, bits, sizeof amax);
   }
-  for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
-  c->have_act_scales = true;
+  const locc_status ist = fp8_install_amax(c, amax);
+  if (ist != LOCC_OK) return ist;
   if (amax_out) std::memcpy(amax_out, amax, sizeof amax);
   return LOCC_OK;
 }

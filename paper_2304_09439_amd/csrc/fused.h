@@ -78,7 +78,7 @@ struct Fp8Args {
   const float* c3;
   // scales: weights (amax / 448) and activations entering an fp8 layer
   float s_w2, s_h1, s_h2;
-  float s_h1in;  // encoder layer-1 output
+  float s_h1in;  // encoder layer-1 output (layer 1's weights are packed divided by it)
   float s_z;     // pooled encoder features
   float s_g1;    // head layer-1 output
   // rows and per-pair records from the crop kernel
@@ -106,6 +106,8 @@ void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2
 void fp8_bind(Fp8Args& a, const unsigned char* dev_base, int h1, int h2, int hh);
 // OCP e4m3 (E4M3FN) of x, round to nearest even, saturating at 448.
 unsigned char host_e4m3(float x);
+// Encoder layer-1 pack of the FP8 path, scaled by inv = 1 / s_x (h1 * 8 bf16 values).
+void fp8_pack_w1(const float* W1, const float* b1, int h1, float inv, unsigned short* dst);
 hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, int grid, hipStream_t s);
 
 // Calibration: maxima over the valid pairs of the encoder layer-1 output, the

@@ -50,14 +50,12 @@ __device__ __forceinline__ float vmax(float a, float b) { return __builtin_eleme
 __device__ __forceinline__ unsigned short bf16_bits(float f) {
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
-// four floats -> four e4m3 bytes of min(ReLU(x) * inv, 448); inv > 0, so
-// ReLU(x) * inv = max(x * inv, 0) and one med3 does the ReLU and the clamp
-__device__ __forceinline__ float relu_clamp448(float x, float inv) {
-  return __builtin_amdgcn_fmed3f(x * inv, 0.f, 448.f);
-}
-__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d, float inv) {
-  int v = __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(a, inv), relu_clamp448(b, inv), 0, false);
-  return __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(c, inv), relu_clamp448(d, inv), v, true);
+// four floats -> four e4m3 bytes of min(ReLU(x), 448): one med3 does the
+// ReLU and the clamp (layer 1 already works in units of the activation scale)
+__device__ __forceinline__ float relu_clamp448(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 448.f); }
+__device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d) {
+  int v = __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(a), relu_clamp448(b), 0, false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(c), relu_clamp448(d), v, true);
 }
 
 template <int H1, int H2, int HH>
@@ -175,7 +173,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const int K = A.K;
   const int P = pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base);
-  const float inv_h1 = 1.f / A.s_h1in, s_enc = A.s_h1in * A.s_w2, inv_z = 1.f / A.s_z;
+  const float s_enc = A.s_h1in * A.s_w2, inv_z = 1.f / A.s_z;
 
   i32x8 w2f[CT][KS2];
   float bias2[CT];
@@ -243,8 +241,8 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
             i32x8 av;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              av[q] = pack4_e4m3(lo[4 * q], lo[4 * q + 1], lo[4 * q + 2], lo[4 * q + 3], inv_h1);
-              av[4 + q] = pack4_e4m3(hi[4 * q], hi[4 * q + 1], hi[4 * q + 2], hi[4 * q + 3], inv_h1);
+              av[q] = pack4_e4m3(lo[4 * q], lo[4 * q + 1], lo[4 * q + 2], lo[4 * q + 3]);
+              av[4 + q] = pack4_e4m3(hi[4 * q], hi[4 * q + 1], hi[4 * q + 2], hi[4 * q + 3]);
             }
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_f8(av, w2f[ct][s], acc2[ct]);
@@ -405,6 +403,18 @@ unsigned char host_e4m3(float x) {
   return s | (unsigned char)code;
 }
 
+// Encoder layer 1 in units of the activation scale of layer 2's input:
+// bf16(W1 * inv), bf16(b1 * inv) (products in float32), A operand of 32x32x8.
+void fp8_pack_w1(const float* W1, const float* b1, int h1, float inv, unsigned short* dst) {
+  for (int ft = 0; ft < h1 / 32; ++ft)
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 4; ++e) {
+        const int f = 32 * ft + l % 32, c = 4 * (l / 32) + e;
+        const float v = c < 6 ? W1[f * 6 + c] * inv : (c == 6 ? b1[f] * inv : 0.f);
+        dst[((size_t)ft * 64 + l) * 4 + e] = host_bf16(v);
+      }
+}
+
 Fp8Layout fp8_layout(int h1, int h2, int hh) {
   Fp8Layout L{};
   size_t o = 0;
@@ -428,13 +438,8 @@ void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2
   std::memset(dst, 0, L.total);
   auto u16 = [&](size_t off) { return reinterpret_cast<unsigned short*>(dst + off); };
   auto f32 = [&](size_t off) { return reinterpret_cast<float*>(dst + off); };
-  // encoder layer 1 (bf16, A operand of 32x32x8)
-  for (int ft = 0; ft < h1 / 32; ++ft)
-    for (int l = 0; l < 64; ++l)
-      for (int e = 0; e < 4; ++e) {
-        const int f = 32 * ft + l % 32, c = 4 * (l / 32) + e;
-        u16(L.w1)[((size_t)ft * 64 + l) * 4 + e] = host_bf16(c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f));
-      }
+  // encoder layer 1 (bf16): unscaled until the activation scale is known
+  fp8_pack_w1(W1, b1, h1, 1.f, u16(L.w1));
   const float s_w2 = std::fmax(amax_of(W2, (size_t)h2 * h1), 1e-30f) / 448.f;
   const float s_h1 = std::fmax(amax_of(H1, (size_t)hh * 2 * h2), 1e-30f) / 448.f;
   const float s_h2 = std::fmax(amax_of(H2, (size_t)hh * hh), 1e-30f) / 448.f;
