@@ -431,6 +431,12 @@ class EnvSteps:
     def n_steps(self) -> int:
         return len(self.pairs)
 
+    @property
+    def env_offsets(self) -> np.ndarray:
+        """int32 [E + 1]: objects of environment e are env_offsets[e] .. env_offsets[e+1] - 1."""
+        n_env = int(self.env.max()) + 1 if len(self.env) else 0
+        return np.concatenate([[0], np.cumsum(np.bincount(self.env, minlength=n_env))]).astype(np.int32)
+
     def scene(self, step: int) -> Scene:
         return Scene(self.lib, self.pos[step], self.quat[step], self.shape, self.pairs[step])
 
