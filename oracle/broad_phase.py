@@ -22,6 +22,11 @@ computes, per simulation step:
       every pair i < j whose world boxes overlap on all three axes (closed
       intervals: lo_i <= hi_j and lo_j <= hi_i);
   B3  the pairs listed by environment, then i, then j, ascending.
+
+Readings for input the paper does not consider: an object whose shape id is
+out of range has a NaN box, and NaN compares false, so it is in no pair (as
+is an object whose pose holds a NaN); each environment bound is clamped to
+[0, n], and an empty or reversed range holds no object.
 """
 
 from __future__ import annotations
@@ -50,6 +55,9 @@ def world_boxes(lib_pts, lib_offsets, pos, quat, shape):
     lo = np.empty((n, 3))
     hi = np.empty((n, 3))
     for k in range(n):
+        if not 0 <= shape[k] < len(c_loc):
+            lo[k] = hi[k] = np.nan
+            continue
         R = O.rotation(quat[k])
         c, e = c_loc[shape[k]], e_loc[shape[k]]
         p = np.asarray(pos[k], np.float64)
@@ -64,8 +72,9 @@ def world_boxes(lib_pts, lib_offsets, pos, quat, shape):
 def broad_phase(lo, hi, env_offsets):
     """B2-B3: int32 [P, 2] pairs (i < j) of overlapping world boxes, per environment."""
     out = []
+    n = len(lo)
     for e in range(len(env_offsets) - 1):
-        a, b = int(env_offsets[e]), int(env_offsets[e + 1])
+        a, b = (min(max(int(v), 0), n) for v in env_offsets[e:e + 2])
         for i in range(a, b):
             j = np.arange(i + 1, b)
             if len(j) == 0:

@@ -81,3 +81,27 @@ def test_empty_and_single_object_environments():
     np.testing.assert_array_equal(pairs, [[0, 1]])
     lo2 = np.array([[0.0, 0, 0], [1.0, 0, 0]])
     np.testing.assert_array_equal(BP.broad_phase(lo2, lo2 + 1.0, np.array([0, 2])), [[0, 1]])   # closed intervals
+
+
+def test_invalid_shapes_and_clamped_environments(envs):
+    """Readings for input outside the paper's setting: an out-of-range shape id
+    gives a NaN box (in no pair); environment bounds are clamped to [0, n]."""
+    shape = envs.shape.copy()
+    shape[[3, 10]] = [-1, envs.lib.n_shapes]
+    lo, hi = BP.world_boxes(envs.lib.pts, envs.lib.offsets, envs.pos[0], envs.quat[0], shape)
+    assert np.isnan(lo[[3, 10]]).all() and np.isfinite(np.delete(lo, [3, 10], axis=0)).all()
+    pairs = BP.broad_phase(lo, hi, envs.env_offsets)
+    assert not np.isin(pairs, [3, 10]).any()
+    lo0, hi0 = _boxes(envs, 0)
+    full = BP.broad_phase(lo0, hi0, envs.env_offsets)
+    keep = ~np.isin(full, [3, 10]).any(axis=1)
+    np.testing.assert_array_equal(pairs, full[keep])
+    # bounds past either end clamp; a reversed range is empty
+    n = len(lo0)
+    got = np.concatenate([BP.broad_phase(lo0, hi0, np.array([-5, 4, 2, 60])),
+                          BP.broad_phase(lo0, hi0, np.array([n - 30, n + 7]))])
+    ref = np.concatenate([BP.broad_phase(lo0[:4], hi0[:4], np.array([0, 4])),
+                          BP.broad_phase(lo0, hi0, np.array([2, 60])),
+                          BP.broad_phase(lo0, hi0, np.array([n - 30, n]))])
+    assert len(ref) > 0
+    np.testing.assert_array_equal(got, ref)
