@@ -275,6 +275,59 @@ LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs
 LOCC_API locc_status locc_graph_launch(locc_graph* graph, void* stream);
 LOCC_API void locc_graph_destroy(locc_graph* graph);
 
+/* Broad phase over environments (Sec. II, footnote on the broad phase:
+ * pairs that are far apart are ruled out before the narrow phase; the
+ * paper's simulations step many environments at once, and an object pairs
+ * only with objects of its own environment).
+ *
+ *   d_objs         [n_objs] locc_object, device
+ *   d_env_offsets  int32 [n_envs + 1], device: environment e holds objects
+ *                  d_env_offsets[e] .. d_env_offsets[e + 1] - 1, both
+ *                  bounds clamped to [0, n_objs]; an empty or reversed range
+ *                  holds none
+ *   d_pairs        int32 [capacity][2], device, out: pairs (i, j), i < j,
+ *                  listed by environment, then i, then j; may be NULL when
+ *                  capacity is 0
+ *   d_count        int32 [2], device, out: [0] pairs written =
+ *                  min(total, capacity), [1] total (saturated at INT32_MAX)
+ *
+ * The world box of an object is the axis-aligned hull of its shape's box
+ * (component-wise min and max of the stored xyz) after its rotation and
+ * translation, computed in float64 as
+ *   c_w[i] = ((R[i][0] c0 + R[i][1] c1) + R[i][2] c2) + p_i,
+ *   e_w[i] = (|R[i][0]| e0 + |R[i][1]| e1) + |R[i][2]| e2,
+ *   lo = c_w - e_w, hi = c_w + e_w
+ * with c, e the centre and half extent of the shape box and R the rotation
+ * of the quaternion as given; two boxes overlap when their closed intervals
+ * meet on all three axes.  An object whose shape id is out of range (or
+ * whose pose holds a NaN) is in no pair.  Each environment is tested pair by
+ * pair (n (n - 1) / 2 tests for n objects).
+ *
+ * Asynchronous on `stream`.  The scratch (48 bytes per object, 16 per
+ * environment) grows synchronously on first use; under graph capture it
+ * must already be large enough (locc_reserve_broad_phase), else RANGE.
+ * Errors: INVALID_ARG (negative sizes, null pointers), NOT_READY (no shape
+ * library), RANGE, OOM, HIP. */
+LOCC_API locc_status locc_broad_phase(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                      const int32_t* d_env_offsets, int32_t n_envs, int32_t* d_pairs,
+                                      int32_t capacity, int32_t* d_count, void* stream);
+
+/* Grows the broad-phase scratch for n_objs objects and n_envs environments
+ * (synchronous; may allocate).  Errors: INVALID_ARG, OOM, HIP. */
+LOCC_API locc_status locc_reserve_broad_phase(locc_ctx* ctx, int32_t n_objs, int32_t n_envs);
+
+/* One whole simulation step captured as a HIP graph: locc_broad_phase into
+ * d_pairs / d_count, then locc_detect_device_count on those pairs with the
+ * device count d_count[0] (results in d_out[0 .. d_count[0]), counts in
+ * d_counts, which may be NULL).  The caller updates the objects in place
+ * between launches.  Reserves the workspace and the scratch first; records
+ * no memset node.  Errors: as locc_broad_phase and locc_graph_capture
+ * (capacity must be positive, d_out non-NULL). */
+LOCC_API locc_status locc_step_graph_capture(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                             const int32_t* d_env_offsets, int32_t n_envs, int32_t* d_pairs,
+                                             int32_t capacity, int32_t* d_count, locc_contact* d_out,
+                                             int32_t* d_counts, locc_graph** out);
+
 /* Serving.  A server keeps an object table (poses) and the context's shape
  * library and weights resident on the device, and runs a worker thread that
  * batches collision-detection requests continuously: each request brings

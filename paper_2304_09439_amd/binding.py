@@ -26,7 +26,8 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
            "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
-           "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax")
+           "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax", "locc_broad_phase",
+           "locc_reserve_broad_phase", "locc_step_graph_capture")
 
 
 class Config(ctypes.Structure):
@@ -134,6 +135,12 @@ def load() -> ctypes.CDLL:
     L.locc_calibrate.restype = ctypes.c_int
     L.locc_set_activation_amax.argtypes = [vp, vp]
     L.locc_set_activation_amax.restype = ctypes.c_int
+    L.locc_broad_phase.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, vp]
+    L.locc_broad_phase.restype = ctypes.c_int
+    L.locc_reserve_broad_phase.argtypes = [vp, i32, i32]
+    L.locc_reserve_broad_phase.restype = ctypes.c_int
+    L.locc_step_graph_capture.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, ctypes.POINTER(vp)]
+    L.locc_step_graph_capture.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -317,6 +324,39 @@ class Context:
         _check(load().locc_graph_capture(self._h, _ptr(objs), n_objs, _ptr(pairs), _ptr(n_dev), cap, _ptr(out),
                                          _ptr(counts), ctypes.byref(g)))
         return Graph(self, g, (objs, pairs, n_dev, out, counts))
+
+    def broad_phase(self, objs, env_offsets, pairs, count, stream=None):
+        """Overlapping pairs per environment into pairs (int32 [capacity, 2], device) and
+        count (int32 [2], device: written, total).  env_offsets: int32 [E + 1], device."""
+        import torch
+        self._check_dev("objs", objs, torch.float32, (8,))
+        self._check_dev("pairs", pairs, torch.int32, (2,))
+        self._check_dev("env_offsets", env_offsets, torch.int32, ())
+        self._check_dev("count", count, torch.int32, ())
+        if count.numel() < 2 or env_offsets.numel() < 1:
+            raise ValueError("count needs 2 entries, env_offsets at least 1")
+        _check(load().locc_broad_phase(self._h, _ptr(objs), objs.shape[0], _ptr(env_offsets),
+                                       env_offsets.numel() - 1, _ptr(pairs), pairs.shape[0], _ptr(count),
+                                       self._stream(stream)))
+        return pairs, count
+
+    def reserve_broad_phase(self, n_objs: int, n_envs: int):
+        _check(load().locc_reserve_broad_phase(self._h, int(n_objs), int(n_envs)))
+
+    def capture_step_graph(self, objs, env_offsets, pairs, count, out, counts=None) -> "Graph":
+        """Capture broad phase + detect (device count) as one HIP graph over these buffers."""
+        import torch
+        self._check_dev("objs", objs, torch.float32, (8,))
+        self._check_dev("pairs", pairs, torch.int32, (2,))
+        self._check_dev("env_offsets", env_offsets, torch.int32, ())
+        self._check_dev("count", count, torch.int32, ())
+        if count.numel() < 2 or env_offsets.numel() < 1:
+            raise ValueError("count needs 2 entries, env_offsets at least 1")
+        g = ctypes.c_void_p()
+        _check(load().locc_step_graph_capture(self._h, _ptr(objs), objs.shape[0], _ptr(env_offsets),
+                                              env_offsets.numel() - 1, _ptr(pairs), pairs.shape[0], _ptr(count),
+                                              _ptr(out), _ptr(counts), ctypes.byref(g)))
+        return Graph(self, g, (objs, env_offsets, pairs, count, out, counts))
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop per-kernel event timing."""

@@ -463,6 +463,7 @@ void locc_destroy(locc_ctx* c) {
   for (hipEvent_t e : c->chunk_ev)
     if (e) (void)hipEventDestroy(e);
   (void)hipFree(c->d_ws);
+  (void)hipFree(c->d_bp);
   (void)hipFree(c->d_err);
   delete c;
 }
@@ -735,23 +736,20 @@ locc_status locc_detect_device_count(locc_ctx* c, const locc_object* objs, int32
                   static_cast<hipStream_t>(stream));
 }
 
-locc_status locc_graph_capture(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
-                               const int32_t* n_dev, int32_t max_pairs, locc_contact* out, int32_t* counts,
-                               locc_graph** graph) {
-  if (!graph) return fail(LOCC_ERR_INVALID_ARG, "null graph output");
-  *graph = nullptr;
-  locc_status st = check_call(c, objs, n_objs, pairs, max_pairs);
-  if (st != LOCC_OK) return st;
-  if (!n_dev || max_pairs <= 0 || !out) return fail(LOCC_ERR_INVALID_ARG, "null count or output, or no capacity");
-  st = locc_reserve(c, max_pairs);
-  if (st != LOCC_OK) return st;
+}  // extern "C"
+
+namespace {
+
+// Captures body(stream) on the context's capture stream as a HIP graph.
+template <class F>
+locc_status capture_graph(locc_ctx* c, locc_graph** graph, F&& body) {
   if (!c->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
   HIP_TRY(hipDeviceSynchronize());
   const bool prof = c->profiling;
   c->profiling = false;  // no event nodes in the graph
   c->capturing = true;
   HIP_TRY(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed));
-  st = run_path(c, objs, n_objs, pairs, max_pairs, n_dev, out, counts, nullptr, nullptr, c->capture_stream);
+  locc_status st = body(c->capture_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->capture_stream, &g);
   c->capturing = false;
@@ -771,6 +769,106 @@ locc_status locc_graph_capture(locc_ctx* c, const locc_object* objs, int32_t n_o
   }
   *graph = G;
   return LOCC_OK;
+}
+
+locc_status ensure_broad_scratch(locc_ctx* c, int n_objs, int n_envs) {
+  const size_t bytes = broad_phase_scratch_bytes(n_objs, n_envs);
+  if (bytes <= c->bp_bytes) return LOCC_OK;
+  if (c->capturing)
+    return fail(LOCC_ERR_RANGE, "broad-phase scratch of %zu bytes too small for %zu during graph capture",
+                c->bp_bytes, bytes);
+  if (c->d_bp) HIP_TRY(hipFree(c->d_bp));
+  c->d_bp = nullptr;
+  c->bp_bytes = 0;
+  HIP_TRY(hipMalloc(&c->d_bp, bytes));
+  c->bp_bytes = bytes;
+  return LOCC_OK;
+}
+
+locc_status check_broad(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* env_offsets,
+                        int32_t n_envs, const int32_t* pairs, int32_t capacity, const int32_t* count) {
+  if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
+  if (n_objs < 0 || n_envs < 0 || capacity < 0)
+    return fail(LOCC_ERR_INVALID_ARG, "negative size (n_objs=%d, n_envs=%d, capacity=%d)", n_objs, n_envs,
+                capacity);
+  if (!count) return fail(LOCC_ERR_INVALID_ARG, "null pair count");
+  if (n_objs > 0 && !objs) return fail(LOCC_ERR_INVALID_ARG, "null objects");
+  if (n_envs > 0 && !env_offsets) return fail(LOCC_ERR_INVALID_ARG, "null environment offsets");
+  if (capacity > 0 && !pairs) return fail(LOCC_ERR_INVALID_ARG, "null pair output");
+  if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
+  return LOCC_OK;
+}
+
+locc_status run_broad(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* env_offsets,
+                      int32_t n_envs, int32_t* pairs, int32_t capacity, int32_t* count, hipStream_t s) {
+  locc_status st = ensure_broad_scratch(c, n_objs, n_envs);
+  if (st != LOCC_OK) return st;
+  BroadArgs a{};
+  a.objs = objs;
+  a.n_objs = n_objs;
+  a.env_offsets = env_offsets;
+  a.n_envs = n_envs;
+  a.lib = c->lib();
+  broad_phase_carve(c->d_bp, n_objs, n_envs, a);
+  a.pairs = pairs;
+  a.capacity = capacity;
+  a.count = count;
+  HIP_TRY(timed(c, "broad_phase", s, [&] { return launch_broad_phase(a, s); }));
+  return LOCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+locc_status locc_graph_capture(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                               const int32_t* n_dev, int32_t max_pairs, locc_contact* out, int32_t* counts,
+                               locc_graph** graph) {
+  if (!graph) return fail(LOCC_ERR_INVALID_ARG, "null graph output");
+  *graph = nullptr;
+  locc_status st = check_call(c, objs, n_objs, pairs, max_pairs);
+  if (st != LOCC_OK) return st;
+  if (!n_dev || max_pairs <= 0 || !out) return fail(LOCC_ERR_INVALID_ARG, "null count or output, or no capacity");
+  st = locc_reserve(c, max_pairs);
+  if (st != LOCC_OK) return st;
+  return capture_graph(c, graph, [&](hipStream_t s) {
+    return run_path(c, objs, n_objs, pairs, max_pairs, n_dev, out, counts, nullptr, nullptr, s);
+  });
+}
+
+locc_status locc_broad_phase(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* env_offsets,
+                             int32_t n_envs, int32_t* pairs, int32_t capacity, int32_t* count, void* stream) {
+  locc_status st = check_broad(c, objs, n_objs, env_offsets, n_envs, pairs, capacity, count);
+  if (st != LOCC_OK) return st;
+  HIP_TRY(hipSetDevice(c->device));
+  return run_broad(c, objs, n_objs, env_offsets, n_envs, pairs, capacity, count, static_cast<hipStream_t>(stream));
+}
+
+locc_status locc_reserve_broad_phase(locc_ctx* c, int32_t n_objs, int32_t n_envs) {
+  if (!c || n_objs < 0 || n_envs < 0) return fail(LOCC_ERR_INVALID_ARG, "null context or negative size");
+  HIP_TRY(hipSetDevice(c->device));
+  return ensure_broad_scratch(c, n_objs, n_envs);
+}
+
+locc_status locc_step_graph_capture(locc_ctx* c, const locc_object* objs, int32_t n_objs,
+                                    const int32_t* env_offsets, int32_t n_envs, int32_t* pairs, int32_t capacity,
+                                    int32_t* count, locc_contact* out, int32_t* counts, locc_graph** graph) {
+  if (!graph) return fail(LOCC_ERR_INVALID_ARG, "null graph output");
+  *graph = nullptr;
+  locc_status st = check_broad(c, objs, n_objs, env_offsets, n_envs, pairs, capacity, count);
+  if (st != LOCC_OK) return st;
+  st = check_call(c, objs, n_objs, pairs, capacity);
+  if (st != LOCC_OK) return st;
+  if (capacity <= 0 || !out) return fail(LOCC_ERR_INVALID_ARG, "null output or no capacity");
+  HIP_TRY(hipSetDevice(c->device));
+  st = locc_reserve(c, capacity);
+  if (st == LOCC_OK) st = ensure_broad_scratch(c, n_objs, n_envs);
+  if (st != LOCC_OK) return st;
+  return capture_graph(c, graph, [&](hipStream_t s) {
+    locc_status r = run_broad(c, objs, n_objs, env_offsets, n_envs, pairs, capacity, count, s);
+    if (r != LOCC_OK) return r;
+    return run_path(c, objs, n_objs, pairs, capacity, count, out, counts, nullptr, nullptr, s);
+  });
 }
 
 locc_status locc_graph_launch(locc_graph* G, void* stream) {

@@ -43,6 +43,9 @@ struct locc_ctx {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   unsigned long long* d_err = nullptr;
+  // broad-phase scratch (world boxes, per-environment counts and starts)
+  void* d_bp = nullptr;
+  size_t bp_bytes = 0;
   // event timing of each launch (locc_profile)
   struct Pending {
     std::string name;

@@ -91,6 +91,30 @@ constexpr size_t kPairSetupBytes = 320;
 // unroll: blocks of 64 points whose loads a wave issues together (2, 4 or 8)
 hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll = 8);
 
+// Broad phase over environments: world boxes, then every overlapping pair
+// i < j of objects of the same environment (see broad_phase.hip).
+struct BroadArgs {
+  const locc_object* objs;
+  int32_t n_objs;
+  const int32_t* env_offsets;  // [n_envs + 1]
+  int32_t n_envs;
+  DeviceLibrary lib;
+  double* boxes;               // [n_objs][6] lo xyz, hi xyz (scratch)
+  long long* env_count;        // [n_envs] overlapping pairs per environment (scratch)
+  long long* env_start;        // [n_envs] first output position per environment (scratch)
+  int32_t* pairs;              // [capacity][2], may be null when capacity is 0
+  int32_t capacity;
+  int32_t* count;              // [2]: pairs written, total (saturated)
+};
+
+// Scratch bytes of a broad phase over n_objs objects and n_envs environments.
+size_t broad_phase_scratch_bytes(int n_objs, int n_envs);
+// Carves the scratch at `base` into a.boxes / env_count / env_start.
+void broad_phase_carve(void* base, int n_objs, int n_envs, BroadArgs& a);
+// Four launches on s: world boxes, per-environment counts, the scan (which
+// writes count), the ordered write of the pairs.
+hipError_t launch_broad_phase(const BroadArgs& a, hipStream_t s);
+
 // FP32 network weights packed in MFMA fragment order (see net_fp32.hip).
 struct Fp32Net {
   int h1, h2, hh;
