@@ -237,10 +237,12 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
                     precision, bf16_desc(schedule)))
 
 
-def time_envs(args, envs, w, precision):
+def time_envs(args, envs, w, precision, gpu_broad=False):
     """One simulation step of the uneven-environment workload: H2D of every pose, the step's broad-phase
     pairs and their count from pinned host buffers, then the detect (a replayed HIP graph for the
-    batched path, eager launches for the plain FP32 path).  Timed per step with events."""
+    batched path, eager launches for the plain FP32 path).  With gpu_broad, H2D of the poses only and
+    one replayed graph holding the library's broad phase and the detect on its device count.  Timed
+    per step with events."""
     import numpy as np
     import torch
     from paper_2304_09439_amd import binding as B
@@ -261,17 +263,25 @@ def time_envs(args, envs, w, precision):
     counts = torch.empty((cap, 2), dtype=torch.int32, device="cuda") if args.member_counts else None
     ctx.reserve(cap)
     graph, schedule = None, None
+    env_off = torch.from_numpy(envs.env_offsets).cuda()
+    count = torch.zeros(2, dtype=torch.int32, device="cuda")
     if precision != "fp32":
         objs.copy_(objs_h[0])
         pairs[:len(envs.pairs[0])].copy_(pairs_h[0])
         if not args.no_autotune:
             schedule, _ = ctx.autotune(objs, pairs[:len(envs.pairs[0])], want_counts=counts is not None)
-        graph = ctx.capture_graph(objs, pairs, n_dev, out, counts)
+        if gpu_broad:
+            graph = ctx.capture_step_graph(objs, env_off, pairs, count, out, counts)
+        else:
+            graph = ctx.capture_graph(objs, pairs, n_dev, out, counts)
     stream = torch.cuda.current_stream()
 
     def step(s):
         P = len(envs.pairs[s])
         objs.copy_(objs_h[s], non_blocking=True)
+        if gpu_broad:
+            graph.launch()
+            return
         pairs[:P].copy_(pairs_h[s], non_blocking=True)
         if graph is not None:
             n_dev.copy_(n_h[s], non_blocking=True)
@@ -293,16 +303,33 @@ def time_envs(args, envs, w, precision):
     wall = time.perf_counter() - t0
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     total_pairs = sum(len(p) for p in envs.pairs)
+    extra = {}
+    if gpu_broad:
+        # the last step's count against the host list, then the broad phase alone (event-timed launches)
+        extra["last_step_count_matches_host"] = count.cpu().tolist() == [len(envs.pairs[-1])] * 2
+        ctx.profile(True)
+        for s in range(S):
+            objs.copy_(objs_h[s], non_blocking=True)
+            ctx.broad_phase(objs, env_off, pairs, count)
+        torch.cuda.synchronize()
+        n_l, tot = ctx.profile_read()["broad_phase"]
+        ctx.profile(False)
+        extra["broad_phase_ms"] = round(tot / n_l, 5)
     n_bad = ctx.device_errors()
     if graph is not None:
         graph.close()
     ctx.close()
+    if gpu_broad:
+        path = "HIP graph per step (H2D of poses + replay of broad phase and detect), " + bf16_desc(schedule)
+    elif graph is not None:
+        path = "HIP graph per step (H2D of poses, pairs and count + replay), " + bf16_desc(schedule)
+    else:
+        path = "eager per step (H2D of poses and pairs + launches), " + PATH_DESC[precision]
     return dict(value=round(total_pairs / wall, 1), unit=UNIT, steps=S, mean_pairs_per_step=round(total_pairs / S),
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
                 mean_step_ms=round(float(step_ms.mean()), 4), schedule=schedule, device_errors=int(n_bad),
-                path=("HIP graph per step (H2D of poses, pairs and count + replay), " + bf16_desc(schedule))
-                if graph is not None else "eager per step (H2D of poses and pairs + launches), " + PATH_DESC[precision])
+                path=path, **extra)
 
 
 def serve_run(B, srv, reqs, arrivals):
@@ -458,8 +485,11 @@ def run(args):
               f"{sum(len(p) for p in envs.pairs) / envs.n_steps:.0f} pairs per step", file=sys.stderr, flush=True)
         line["environments"] = dict(
             workload=f"4096 environments, 1-40 objects each ({len(envs.shape)} objects) from the 32-shape library, "
-                     f"cube side {envs.side:.3f} m, {args.env_steps} jittered steps, host broad phase ahead of time",
+                     f"cube side {envs.side:.3f} m, {args.env_steps} jittered steps; pairs from a host broad "
+                     f"phase ahead of time, or from the library's broad phase inside the step",
             **{p: time_envs(args, envs, w, p) for p in precisions if p in ("fp32", "bf16")})
+        if "bf16" in precisions:
+            line["environments"]["bf16_gpu_broad_phase"] = time_envs(args, envs, w, "bf16", gpu_broad=True)
     print(json.dumps(line), flush=True)
 
 
@@ -504,7 +534,8 @@ def summarize_counters(args):
     write_b = kw * 1024.0 * w_scale
     print(f"kernel {args.kernel} ({kk})")
     print(f"source_sha256 {source_hash(args.kernel)}")
-    print(f"copy_kernel {ck} copy_bytes {copy_bytes}")
+    short = ck.split("(")[0].split("<")[0].replace("void ", "")
+    print(f"copy_kernel torch.neg ({short}) copy_bytes {copy_bytes}")
     print(f"fetch_scale {f_scale:.4f} write_scale {w_scale:.4f}")
     print(f"fetch_kib_per_dispatch {kf:.1f} write_kib_per_dispatch {kw:.1f}")
     print(f"hbm_bytes_per_launch {fetch_b + write_b:.0f}")
