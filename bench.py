@@ -144,7 +144,7 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
 
 # ------------------------------------------------------------------ GPU run
 
-def kernel_entries(kt, work, P, workload_name, steps, precision):
+def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True):
     """Per kernel: average launch duration and the algorithmic rate of one launch (a step of P pairs may
     run a kernel several times, once per chunk of pairs)."""
     kernels = {}
@@ -155,7 +155,10 @@ def kernel_entries(kt, work, P, workload_name, steps, precision):
         if name == "crop":
             achieved = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
             entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
-                         frac=round(achieved / PEAK_HBM_GBPS, 4))
+                         frac=round(achieved / PEAK_HBM_GBPS, 4),
+                         bytes_basis="full scans of both objects (2N x 12 B per pair) + 2K gathered rows" + (
+                             "" if full_scan else "; member counts not requested, so each scan stops at K "
+                                                  "members and this overstates the bytes the algorithm reads"))
         else:
             if name.startswith("encoder_head") or name.startswith("fused"):
                 flops = (work["enc_flops"] + work["head_flops"]) * P_launch
@@ -228,7 +231,7 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     n_bad = ctx.device_errors()
     ctx.close()
     ms = 1000.0 * wall / args.steps
-    kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision)
+    kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision, full_scan=counts is not None)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
