@@ -399,6 +399,32 @@ def gaussian_weights(widths: Widths, seed: int = 0, bias_std: float = 0.0):
     return out
 
 
+# Weight layout of the voxel-embedding variant (shape encoder: point MLP 3-256-256-256, 3D U-Net of 128
+# channels with 3x3x3 kernels, linear 384 -> 16; predictor: 28-128-128-128 per object, 128-128-128-128,
+# 128 -> 1), each entry (W shape, bias length) with W [out][in...].
+VOXEL_LAYERS = (
+    [((256, 3), 256), ((256, 256), 256), ((256, 256), 256)]
+    + [((128, 256, 3, 3, 3), 128)] + [((128, 128, 3, 3, 3), 128)] * 3
+    + [((128, 128, 3, 3, 3), 128)] + [((128, 256, 3, 3, 3), 128)] * 3
+    + [((16, 384), 16)]
+    + [((128, 28), 128), ((128, 128), 128), ((128, 128), 128)]
+    + [((128, 128), 128)] * 3 + [((1, 128), 1)]
+)
+
+
+def voxel_weights(seed: int = 0, bias_std: float = 0.0):
+    """He-initialised weights of the voxel-embedding variant, W ~ N(0, 2 / fan_in) (fan_in = the product
+    of W's input dimensions), float32, drawn from ``default_rng(seed)`` layer by layer (W, then bias)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for wshape, nb in VOXEL_LAYERS:
+        fan_in = int(np.prod(wshape[1:]))
+        out.append((rng.standard_normal(wshape) * math.sqrt(2.0 / fan_in)).astype(np.float32))
+        b = rng.standard_normal(nb) * bias_std if bias_std > 0 else np.zeros(nb)
+        out.append(b.astype(np.float32))
+    return out
+
+
 def flatten_weights(layers) -> np.ndarray:
     return np.concatenate([np.asarray(a, np.float32).ravel() for a in layers])
 
