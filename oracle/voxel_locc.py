@@ -153,8 +153,8 @@ def conv3d(x, W, b, pad):
     for u0 in range(3):
         for u1 in range(3):
             for u2 in range(3):
-                y += np.einsum("oc,cxyz->oxyz", W[:, :, u0, u1, u2],
-                               xp[:, u0:u0 + Do, u1:u1 + Do, u2:u2 + Do])
+                tap = xp[:, u0:u0 + Do, u1:u1 + Do, u2:u2 + Do].reshape(C, -1)
+                y += (W[:, :, u0, u1, u2] @ tap).reshape(y.shape)
     return y
 
 
@@ -169,8 +169,8 @@ def conv3d_transpose(x, W, b, pad):
     for u0 in range(3):
         for u1 in range(3):
             for u2 in range(3):
-                y += np.einsum("oc,cxyz->oxyz", W[:, :, u0, u1, u2],
-                               xp[:, 2 - u0:2 - u0 + Do, 2 - u1:2 - u1 + Do, 2 - u2:2 - u2 + Do])
+                tap = xp[:, 2 - u0:2 - u0 + Do, 2 - u1:2 - u1 + Do, 2 - u2:2 - u2 + Do].reshape(C, -1)
+                y += (W[:, :, u0, u1, u2] @ tap).reshape(y.shape)
     return y
 
 

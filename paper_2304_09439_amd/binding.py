@@ -27,7 +27,9 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
            "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
            "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax", "locc_broad_phase",
-           "locc_reserve_broad_phase", "locc_step_graph_capture")
+           "locc_reserve_broad_phase", "locc_step_graph_capture", "locc_voxel_weight_count", "locc_voxel_create",
+           "locc_voxel_destroy", "locc_voxel_upload_weights", "locc_voxel_upload_shapes", "locc_voxel_embeddings",
+           "locc_voxel_detect", "locc_voxel_device_errors")
 
 
 class Config(ctypes.Structure):
@@ -141,6 +143,22 @@ def load() -> ctypes.CDLL:
     L.locc_reserve_broad_phase.restype = ctypes.c_int
     L.locc_step_graph_capture.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, ctypes.POINTER(vp)]
     L.locc_step_graph_capture.restype = ctypes.c_int
+    L.locc_voxel_weight_count.argtypes = []
+    L.locc_voxel_weight_count.restype = ctypes.c_size_t
+    L.locc_voxel_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.locc_voxel_create.restype = ctypes.c_int
+    L.locc_voxel_destroy.argtypes = [vp]
+    L.locc_voxel_destroy.restype = None
+    L.locc_voxel_upload_weights.argtypes = [vp, vp, ctypes.c_size_t]
+    L.locc_voxel_upload_weights.restype = ctypes.c_int
+    L.locc_voxel_upload_shapes.argtypes = [vp, i32, vp, vp]
+    L.locc_voxel_upload_shapes.restype = ctypes.c_int
+    L.locc_voxel_embeddings.argtypes = [vp, vp, vp]
+    L.locc_voxel_embeddings.restype = ctypes.c_int
+    L.locc_voxel_detect.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp]
+    L.locc_voxel_detect.restype = ctypes.c_int
+    L.locc_voxel_device_errors.argtypes = [vp, vp, i64p, ctypes.c_int]
+    L.locc_voxel_device_errors.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -395,6 +413,75 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class VoxelContext:
+    """The voxel-embedding variant (include/locc_voxel.h): shape embeddings computed on the device at
+    upload, then per pair cell selection, mean embeddings and the predictor MLPs."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(load().locc_voxel_create(device, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().locc_voxel_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload_weights(self, flat):
+        w = np.ascontiguousarray(flat, np.float32)
+        _check(load().locc_voxel_upload_weights(self._h, w.ctypes.data, w.size))
+
+    def upload_shapes(self, offsets, points):
+        off = np.ascontiguousarray(offsets, np.int64)
+        pts = np.ascontiguousarray(points, np.float32)
+        _check(load().locc_voxel_upload_shapes(self._h, len(off) - 1, off.ctypes.data, pts.ctypes.data))
+        self.n_shapes = len(off) - 1
+
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(int(s.cuda_stream))
+
+    def embeddings(self, stream=None):
+        """float32 [S, 216, 16] (torch, on the device)."""
+        import torch
+        out = torch.empty((self.n_shapes, 216, 16), dtype=torch.float32, device=f"cuda:{self.device}")
+        _check(load().locc_voxel_embeddings(self._h, _ptr(out), self._stream(stream)))
+        return out
+
+    def detect(self, objs, pairs, out=None, counts=None, pooled=None, stream=None, want_counts=True,
+               want_pooled=False):
+        """(logit, probability) float32 [P, 2], counts int32 [P, 2] and pooled float32 [P, 2, 16]."""
+        import torch
+        for name, t, dt, tail in (("objs", objs, torch.float32, (8,)), ("pairs", pairs, torch.int32, (2,))):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous() \
+                    or tuple(t.shape[1:]) != tail:
+                raise ValueError(f"{name}: expected a contiguous {dt} [n, {tail[0]}] tensor on the GPU")
+        P = pairs.shape[0]
+        dev = objs.device
+        if out is None:
+            out = torch.empty((P, 2), dtype=torch.float32, device=dev)
+        if counts is None and want_counts:
+            counts = torch.empty((P, 2), dtype=torch.int32, device=dev)
+        if pooled is None and want_pooled:
+            pooled = torch.empty((P, 2, 16), dtype=torch.float32, device=dev)
+        _check(load().locc_voxel_detect(self._h, _ptr(objs), objs.shape[0], _ptr(pairs), P, _ptr(out), _ptr(counts),
+                                        _ptr(pooled), self._stream(stream)))
+        return out, counts, pooled
+
+    def device_errors(self, reset: bool = False, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(load().locc_voxel_device_errors(self._h, self._stream(stream), ctypes.byref(n), int(reset)))
+        return n.value
 
 
 class Server:

@@ -1,0 +1,597 @@
+// Voxel-embedding LOCC variant (Sec. III, appendix "Architecture Details").
+//
+// Shape encoder (once per shape, at upload; float32 arithmetic, float64 grid
+// assignment): point_mlp_kernel runs the per-point MLP over chunks of 32
+// points and keeps the channel-wise max per grid cell (atomic max on the bit
+// patterns, which order like the values for the non-negative ReLU outputs);
+// conv_kernel runs every convolution and transposed convolution of the
+// U-Net (one thread per output value, the skip concatenation read from two
+// inputs); global_kernel takes max and mean over the bottleneck cells;
+// embed_kernel maps [last layer, global feature] to the 16-float embedding;
+// cells_kernel writes the float64 cell centres and the margin of each shape.
+//
+// Predictor (per pair, pair_kernel): 32 pairs per workgroup of four waves.
+// One thread per pair validates it, puts it in canonical order and computes
+// the float64 relative pose; then each wave takes object sides in turn: 216
+// cell tests (float64, fixed order, contraction off) as four 64-lane
+// ballots, and the mean of the selected cells' embeddings (lane = feature x
+// cell residue mod 4, reduced across the residues); the per-object MLP runs
+// on the 64 side rows, the pair max folds them to 32 rows, the pair MLP and
+// the output layer follow.  Activations stay in LDS; every thread owns one
+// output column of a layer for its half of the rows, reading the weights
+// [in][out] from L2 (coalesced) and the rows from LDS as broadcasts.
+#include "geometry.h"
+#include "voxel.h"
+
+namespace locc {
+namespace vox {
+namespace {
+
+__device__ __forceinline__ float relu(float x) { return x > 0.f ? x : 0.f; }
+
+// Grid cell of a stored point (float64, the order of the reading).
+__device__ __forceinline__ int cell_of(float x, float y, float z, const Shape& sh) {
+#pragma clang fp contract(off)
+  const float p[3] = {x, y, z};
+  int idx = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double lo = sh.lo[k], hi = sh.hi[k];
+    const double ext = hi - lo;
+    int i = 0;
+    if (ext > 0.0) {
+      const double t = (((double)p[k] - lo) * (double)kM) / ext;
+      i = (int)__builtin_floor(t);
+      i = i < 0 ? 0 : (i > kM - 1 ? kM - 1 : i);
+    }
+    idx = idx * kM + i;
+  }
+  return idx;
+}
+
+constexpr int kPts = 32;  // points per workgroup of the point MLP
+
+__global__ __launch_bounds__(256) void point_mlp_kernel(PackedNet w, const Shape* shapes, const float* xyz,
+                                                         int64_t n_points, float* grid) {
+  __shared__ float X[kPts][4];
+  __shared__ int cell[kPts];
+  __shared__ __align__(16) float H[kPts][kH];
+  const int s = blockIdx.y;
+  const Shape sh = shapes[s];
+  const int base = blockIdx.x * kPts;
+  if (base >= sh.n) return;  // uniform
+  const int np = sh.n - base < kPts ? sh.n - base : kPts;
+  const int t = threadIdx.x;
+  if (t < kPts) {
+    float x = 0.f, y = 0.f, z = 0.f;
+    int c = -1;
+    if (t < np) {
+      const int64_t r = (int64_t)sh.off + base + t;
+      x = xyz[r];
+      y = xyz[n_points + r];
+      z = xyz[2 * n_points + r];
+      c = cell_of(x, y, z, sh);
+    }
+    X[t][0] = x;
+    X[t][1] = y;
+    X[t][2] = z;
+    cell[t] = c;
+  }
+  __syncthreads();
+  const int o = t;  // output channel
+  {
+    const float w0 = w.P1[3 * o], w1 = w.P1[3 * o + 1], w2 = w.P1[3 * o + 2], b = w.p1[o];
+#pragma unroll 4
+    for (int p = 0; p < kPts; ++p) H[p][o] = relu(((w0 * X[p][0] + w1 * X[p][1]) + w2 * X[p][2]) + b);
+  }
+  __syncthreads();
+  float acc[kPts];
+  for (int layer = 0; layer < 2; ++layer) {
+    const float* Wt = layer ? w.P3t : w.P2t;
+    const float b = (layer ? w.p3 : w.p2)[o];
+#pragma unroll
+    for (int p = 0; p < kPts; ++p) acc[p] = b;
+    for (int c = 0; c < kH; c += 4) {
+      const float w0 = Wt[(c + 0) * kH + o], w1 = Wt[(c + 1) * kH + o];
+      const float w2 = Wt[(c + 2) * kH + o], w3 = Wt[(c + 3) * kH + o];
+#pragma unroll
+      for (int p = 0; p < kPts; ++p) {
+        const float4 h = *reinterpret_cast<const float4*>(&H[p][c]);
+        acc[p] = fmaf(h.x, w0, acc[p]);
+        acc[p] = fmaf(h.y, w1, acc[p]);
+        acc[p] = fmaf(h.z, w2, acc[p]);
+        acc[p] = fmaf(h.w, w3, acc[p]);
+      }
+    }
+    __syncthreads();  // every thread has read H
+    if (layer == 0) {
+#pragma unroll
+      for (int p = 0; p < kPts; ++p) H[p][o] = relu(acc[p]);
+      __syncthreads();
+    }
+  }
+  unsigned int* g = reinterpret_cast<unsigned int*>(grid) + ((size_t)s * kH + o) * kCells;
+  for (int p = 0; p < np; ++p) atomicMax(g + cell[p], __float_as_uint(relu(acc[p])));
+}
+
+// One thread per output value.  conv: in[x + u - pad]; transposed: in[x - u + pad].
+struct ConvArgs {
+  const float* in1;  // [S][c1][D^3]
+  int c1;
+  const float* in2;  // [S][c2][D^3] (the concatenated skip), or null with c2 = 0
+  int c2;
+  const float* W;    // [O][c1 + c2][27]
+  const float* b;    // [O]
+  float* out;        // [S][O][Do^3]
+  int O, D, Do, pad, transposed, n_shapes;
+};
+
+__global__ __launch_bounds__(256) void conv_kernel(ConvArgs A) {
+  const int D3 = A.D * A.D * A.D, Do3 = A.Do * A.Do * A.Do;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= (long long)A.n_shapes * A.O * Do3) return;
+  const int x = (int)(id % Do3);
+  const int o = (int)((id / Do3) % A.O);
+  const int s = (int)(id / ((long long)Do3 * A.O));
+  const int x0 = x / (A.Do * A.Do), x1 = (x / A.Do) % A.Do, x2 = x % A.Do;
+  const int C = A.c1 + A.c2;
+  float acc = A.b[o];
+  for (int c = 0; c < C; ++c) {
+    const float* src = c < A.c1 ? A.in1 + ((size_t)s * A.c1 + c) * D3 : A.in2 + ((size_t)s * A.c2 + (c - A.c1)) * D3;
+    const float* wk = A.W + ((size_t)o * C + c) * 27;
+#pragma unroll
+    for (int u0 = 0; u0 < 3; ++u0) {
+      const int j0 = A.transposed ? x0 - u0 + A.pad : x0 + u0 - A.pad;
+      if (j0 < 0 || j0 >= A.D) continue;
+#pragma unroll
+      for (int u1 = 0; u1 < 3; ++u1) {
+        const int j1 = A.transposed ? x1 - u1 + A.pad : x1 + u1 - A.pad;
+        if (j1 < 0 || j1 >= A.D) continue;
+#pragma unroll
+        for (int u2 = 0; u2 < 3; ++u2) {
+          const int j2 = A.transposed ? x2 - u2 + A.pad : x2 + u2 - A.pad;
+          if (j2 < 0 || j2 >= A.D) continue;
+          acc = fmaf(wk[(u0 * 3 + u1) * 3 + u2], src[(j0 * A.D + j1) * A.D + j2], acc);
+        }
+      }
+    }
+  }
+  A.out[id] = relu(acc);
+}
+
+// Global feature: [max, mean] over the bottleneck cells of each channel.
+__global__ __launch_bounds__(kC) void global_kernel(const float* c4, float* glob) {
+  const int s = blockIdx.x, c = threadIdx.x;
+  const float* src = c4 + ((size_t)s * kC + c) * kB;
+  float m = src[0], sum = 0.f;
+  for (int x = 0; x < kB; ++x) {
+    m = src[x] > m ? src[x] : m;
+    sum += src[x];
+  }
+  glob[(size_t)s * 2 * kC + c] = m;
+  glob[(size_t)s * 2 * kC + kC + c] = sum / (float)kB;
+}
+
+// E[s][cell][f] = l[f] + L[f] . [d4[s][:][cell], glob[s]]
+__global__ __launch_bounds__(256) void embed_kernel(PackedNet w, const float* d4, const float* glob, float* emb,
+                                                    int n_shapes) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= n_shapes * kCells * kF) return;
+  const int f = id % kF, cell = (id / kF) % kCells, s = id / (kF * kCells);
+  const float* Lf = w.L + (size_t)f * 3 * kC;
+  float acc = w.l[f];
+  for (int k = 0; k < kC; ++k) acc = fmaf(Lf[k], d4[((size_t)s * kC + k) * kCells + cell], acc);
+  for (int k = 0; k < 2 * kC; ++k) acc = fmaf(Lf[kC + k], glob[(size_t)s * 2 * kC + k], acc);
+  emb[id] = acc;
+}
+
+// Cell centres lo + (i + 1/2) s and the margin sqrt((s0^2 + s1^2) + s2^2) / 2, float64.
+__global__ __launch_bounds__(256) void cells_kernel(const Shape* shapes, double* centres, double* eps) {
+#pragma clang fp contract(off)
+  const int s = blockIdx.x, k = threadIdx.x;
+  const Shape sh = shapes[s];
+  double step[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) step[a] = ((double)sh.hi[a] - (double)sh.lo[a]) / (double)kM;
+  if (k < kCells) {
+    const int i[3] = {k / (kM * kM), (k / kM) % kM, k % kM};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) centres[((size_t)s * kCells + k) * 3 + a] = (double)sh.lo[a] + ((double)i[a] + 0.5) * step[a];
+  }
+  if (k == 0) eps[s] = __builtin_sqrt((step[0] * step[0] + step[1] * step[1]) + step[2] * step[2]) * 0.5;
+}
+
+// ------------------------------------------------------------------ pairs --
+
+constexpr int kTP = 32;  // pairs per workgroup
+
+struct PairShared {
+  double R[kTP][9];
+  double t[kTP][3];
+  int shape[kTP][2];
+  int valid[kTP];
+  int swapped[kTP];
+  alignas(16) float Z[2 * kTP][kIn];
+  alignas(16) float H0[2 * kTP][kHP];
+  alignas(16) float H1[2 * kTP][kHP];
+};
+
+// Out[row][o] = ReLU(bias[o] + sum_k In[row][k] Wt[k][o]) for ROWS rows from row0.
+template <int ROWS, int K, int STRIDE>
+__device__ __forceinline__ void dense(const float* In, float* Out, const float* __restrict__ Wt,
+                                      const float* __restrict__ bias, int o, int row0) {
+  float acc[ROWS];
+  const float b = bias[o];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) acc[r] = b;
+#pragma unroll 2
+  for (int k = 0; k < K; k += 4) {
+    const float w0 = Wt[(k + 0) * kHP + o], w1 = Wt[(k + 1) * kHP + o];
+    const float w2 = Wt[(k + 2) * kHP + o], w3 = Wt[(k + 3) * kHP + o];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      const float4 v = *reinterpret_cast<const float4*>(In + (row0 + r) * STRIDE + k);
+      acc[r] = fmaf(v.x, w0, acc[r]);
+      acc[r] = fmaf(v.y, w1, acc[r]);
+      acc[r] = fmaf(v.z, w2, acc[r]);
+      acc[r] = fmaf(v.w, w3, acc[r]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) Out[(row0 + r) * kHP + o] = relu(acc[r]);
+}
+
+__global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  PairShared& S = *reinterpret_cast<PairShared*>(smem_raw);
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int q0 = blockIdx.x * kTP;
+
+  // pair set-up: validation, canonical order, float64 relative pose
+  if (t < kTP) {
+    const int q = q0 + t;
+    int valid = 0, swp = 0, sa = 0, sb = 0;
+    if (q < A.n_pairs) {
+      const int i = A.pairs[2 * q], j = A.pairs[2 * q + 1];
+      if (i >= 0 && i < A.n_objs && j >= 0 && j < A.n_objs && i != j) {
+        swp = i > j;
+        const locc_object oa = A.objs[swp ? j : i], ob = A.objs[swp ? i : j];
+        sa = oa.shape;
+        sb = ob.shape;
+        if (sa >= 0 && sa < A.n_shapes && sb >= 0 && sb < A.n_shapes) {
+#pragma clang fp contract(off)
+          valid = 1;
+          double Ra[9], Rb[9];
+          geo_quat_to_rot(oa.q, Ra);
+          geo_quat_to_rot(ob.q, Rb);
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.R[t][3 * r + c] = (Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c]) + Ra[6 + r] * Rb[6 + c];
+          const double d0 = (double)ob.p[0] - (double)oa.p[0];
+          const double d1 = (double)ob.p[1] - (double)oa.p[1];
+          const double d2 = (double)ob.p[2] - (double)oa.p[2];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) S.t[t][r] = (Ra[r] * d0 + Ra[3 + r] * d1) + Ra[6 + r] * d2;
+        }
+      }
+      if (!valid) {
+        const float nan = __builtin_nanf("");
+        A.out[2 * q] = nan;
+        A.out[2 * q + 1] = nan;
+        if (A.counts) {
+          A.counts[2 * q] = -1;
+          A.counts[2 * q + 1] = -1;
+        }
+        if (A.pooled)
+          for (int f = 0; f < 2 * kF; ++f) A.pooled[(size_t)q * 2 * kF + f] = nan;
+        atomicAdd(A.err, 1ull);
+      }
+    }
+    S.valid[t] = valid;
+    S.swapped[t] = swp;
+    S.shape[t][0] = sa;
+    S.shape[t][1] = sb;
+  }
+  __syncthreads();
+
+  // cell selection and mean embedding, one object side per wave at a time
+  for (int j = wave; j < 2 * kTP; j += 4) {
+    const int q = j >> 1, side = j & 1;  // uniform
+    if (!S.valid[q]) {
+      if (lane < kIn) S.Z[j][lane] = 0.f;
+      continue;
+    }
+    const int sh = S.shape[q][side], so = S.shape[q][side ^ 1];
+    const Shape other = A.shapes[so];
+    const double e = A.eps[sh];
+    double lo_w[3], hi_w[3], R[9], tt[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo_w[k] = (double)other.lo[k] - e;
+      hi_w[k] = (double)other.hi[k] + e;
+      tt[k] = S.t[q][k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = S.R[q][k];
+    unsigned long long m[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 64 * r + lane;
+      bool in = false;
+      if (k < kCells) {
+#pragma clang fp contract(off)
+        const double* c = A.centres + ((size_t)sh * kCells + k) * 3;
+        const double c0 = c[0], c1 = c[1], c2 = c[2];
+        double x[3];
+        if (side == 0) {  // a's cell into b's frame: R^T (c - t)
+          const double e0 = c0 - tt[0], e1 = c1 - tt[1], e2 = c2 - tt[2];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) x[i] = (R[i] * e0 + R[3 + i] * e1) + R[6 + i] * e2;
+        } else {          // b's cell into a's frame: R c + t
+#pragma unroll
+          for (int i = 0; i < 3; ++i) x[i] = ((R[3 * i] * c0 + R[3 * i + 1] * c1) + R[3 * i + 2] * c2) + tt[i];
+        }
+        in = (x[0] >= lo_w[0]) & (x[0] <= hi_w[0]) & (x[1] >= lo_w[1]) & (x[1] <= hi_w[1]) & (x[2] >= lo_w[2]) &
+             (x[2] <= hi_w[2]);
+      }
+      m[r] = __ballot(in);
+    }
+    const int count = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
+    // lane = feature f (16) x residue g (4): sum over the selected cells k = g mod 4
+    const int f = lane & (kF - 1), g = lane >> 4;
+    const float* E = A.emb + (size_t)sh * kCells * kF + f;
+    float acc = 0.f;
+    for (int k = g; k < kCells; k += 4) {
+      const unsigned long long mk = k < 64 ? m[0] : (k < 128 ? m[1] : (k < 192 ? m[2] : m[3]));
+      if ((mk >> (k & 63)) & 1ull) acc += E[k * kF];
+    }
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    const float mean = count > 0 ? acc / (float)count : 0.f;
+    const int cpos = side ^ S.swapped[q];  // the object's position in the caller's pair
+    if (lane < kF) {
+      S.Z[j][lane] = mean;
+      if (A.pooled) A.pooled[((size_t)(q0 + q) * 2 + cpos) * kF + lane] = mean;
+    } else if (lane < kIn) {
+      const int jj = lane - kF;
+      double v;
+      if (side == 0) {  // a in b's frame: (-R^T t, R^T)
+        if (jj < 3) {
+#pragma clang fp contract(off)
+          v = -((R[jj] * tt[0] + R[3 + jj] * tt[1]) + R[6 + jj] * tt[2]);
+        } else {
+          const int m9 = jj - 3;
+          v = R[3 * (m9 % 3) + m9 / 3];
+        }
+      } else {          // b in a's frame: (t, R)
+        v = jj < 3 ? tt[jj] : R[jj - 3];
+      }
+      S.Z[j][lane] = (float)v;
+    }
+    if (lane == 0 && A.counts) A.counts[(size_t)(q0 + q) * 2 + cpos] = count;
+  }
+  __syncthreads();
+
+  // per-object MLP on the 64 side rows
+  const int o = t & (kHP - 1), half = t >> 7;
+  dense<kTP, kIn, kIn>(&S.Z[0][0], &S.H0[0][0], A.w.At[0], A.w.a[0], o, half * kTP);
+  __syncthreads();
+  dense<kTP, kHP, kHP>(&S.H0[0][0], &S.H1[0][0], A.w.At[1], A.w.a[1], o, half * kTP);
+  __syncthreads();
+  dense<kTP, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.At[2], A.w.a[2], o, half * kTP);
+  __syncthreads();
+  // max over the two objects of each pair
+  for (int id = t; id < kTP * kHP; id += 256) {
+    const int q = id / kHP, c = id % kHP;
+    const float u = S.H0[2 * q][c], v = S.H0[2 * q + 1][c];
+    S.H1[q][c] = u > v ? u : v;
+  }
+  __syncthreads();
+  // pair MLP on the 32 pair rows
+  constexpr int kHalf = kTP / 2;
+  dense<kHalf, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.Bt[0], A.w.b[0], o, half * kHalf);
+  __syncthreads();
+  dense<kHalf, kHP, kHP>(&S.H0[0][0], &S.H1[0][0], A.w.Bt[1], A.w.b[1], o, half * kHalf);
+  __syncthreads();
+  dense<kHalf, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.Bt[2], A.w.b[2], o, half * kHalf);
+  __syncthreads();
+  // output layer and sigmoid: a wave per 8 pairs
+  const float w_lo = A.w.B4[lane], w_hi = A.w.B4[lane + 64], b4 = A.w.b[3][0];
+  for (int k = 0; k < kTP / 4; ++k) {
+    const int q = wave * (kTP / 4) + k;
+    float v = fmaf(w_lo, S.H0[q][lane], w_hi * S.H0[q][lane + 64]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0 && S.valid[q]) {
+      const float logit = v + b4;
+      A.out[2 * (q0 + q)] = logit;
+      A.out[2 * (q0 + q) + 1] = 1.f / (1.f + expf(-logit));
+    }
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- host --
+
+namespace {
+
+// Floats of each array of the flat weight vector, in order (W, bias per layer).
+constexpr size_t kSizes[] = {
+    kH * 3, kH, kH * kH, kH, kH * kH, kH,                                  // point MLP
+    (size_t)kC * kH * 27, kC, (size_t)kC * kC * 27, kC, (size_t)kC * kC * 27, kC, (size_t)kC * kC * 27, kC,
+    (size_t)kC * kC * 27, kC, (size_t)kC * 2 * kC * 27, kC, (size_t)kC * 2 * kC * 27, kC,
+    (size_t)kC * 2 * kC * 27, kC,                                          // U-Net
+    (size_t)kF * 3 * kC, kF,                                               // embedding map
+    (size_t)kHP * kIn, kHP, (size_t)kHP * kHP, kHP, (size_t)kHP * kHP, kHP,  // per-object MLP
+    (size_t)kHP * kHP, kHP, (size_t)kHP * kHP, kHP, (size_t)kHP * kHP, kHP, kHP, 1,  // pair MLP, output
+};
+constexpr int kArrays = sizeof(kSizes) / sizeof(kSizes[0]);
+
+constexpr size_t total_weights() {
+  size_t n = 0;
+  for (size_t v : kSizes) n += v;
+  return n;
+}
+static_assert(total_weights() == kWeightCount, "weight count");
+
+void offsets(size_t* off) {
+  size_t o = 0;
+  for (int i = 0; i < kArrays; ++i) {
+    off[i] = o;
+    o += kSizes[i];
+  }
+}
+
+// [rows][cols] -> [cols][rows]
+void transpose(const float* src, int rows, int cols, float* dst) {
+  for (int r = 0; r < rows; ++r)
+    for (int c = 0; c < cols; ++c) dst[(size_t)c * rows + r] = src[(size_t)r * cols + c];
+}
+
+// Packed buffer: P2t, P3t, A1t, A2t, A3t, B1t, B2t, B3t.
+constexpr size_t kPackSizes[] = {kH * kH, kH * kH, (size_t)kIn * kHP, kHP * kHP, kHP * kHP,
+                                 kHP * kHP, kHP * kHP, kHP * kHP};
+
+}  // namespace
+
+size_t packed_floats() {
+  size_t n = 0;
+  for (size_t v : kPackSizes) n += v;
+  return n;
+}
+
+void pack_transposed(const float* flat, float* dst) {
+  size_t off[kArrays];
+  offsets(off);
+  float* d = dst;
+  transpose(flat + off[2], kH, kH, d);                 // P2
+  d += kH * kH;
+  transpose(flat + off[4], kH, kH, d);                 // P3
+  d += kH * kH;
+  transpose(flat + off[24], kHP, kIn, d);              // A1 [128][28]
+  d += (size_t)kIn * kHP;
+  for (int i : {26, 28, 30, 32, 34}) {                 // A2, A3, B1, B2, B3
+    transpose(flat + off[i], kHP, kHP, d);
+    d += kHP * kHP;
+  }
+}
+
+PackedNet packed_view(const float* raw, const float* packed) {
+  size_t off[kArrays];
+  offsets(off);
+  PackedNet w{};
+  w.P1 = raw + off[0];
+  w.p1 = raw + off[1];
+  w.p2 = raw + off[3];
+  w.p3 = raw + off[5];
+  for (int i = 0; i < 4; ++i) {
+    w.C[i] = raw + off[6 + 2 * i];
+    w.k[i] = raw + off[7 + 2 * i];
+    w.D[i] = raw + off[14 + 2 * i];
+    w.e[i] = raw + off[15 + 2 * i];
+  }
+  w.L = raw + off[22];
+  w.l = raw + off[23];
+  for (int i = 0; i < 3; ++i) {
+    w.a[i] = raw + off[25 + 2 * i];
+    w.b[i] = raw + off[31 + 2 * i];
+  }
+  w.B4 = raw + off[36];
+  w.b[3] = raw + off[37];
+  const float* d = packed;
+  w.P2t = d;
+  d += kH * kH;
+  w.P3t = d;
+  d += kH * kH;
+  w.At[0] = d;
+  d += (size_t)kIn * kHP;
+  w.At[1] = d;
+  d += kHP * kHP;
+  w.At[2] = d;
+  d += kHP * kHP;
+  for (int i = 0; i < 3; ++i) {
+    w.Bt[i] = d;
+    d += kHP * kHP;
+  }
+  return w;
+}
+
+size_t encoder_scratch_floats(int n_shapes) {
+  const size_t S = (size_t)n_shapes;
+  return S * kH * kCells + 7 * S * kC * kB + S * kC * kCells + S * 2 * kC;
+}
+
+EncoderBuffers encoder_carve(float* base, int n_shapes) {
+  const size_t S = (size_t)n_shapes;
+  EncoderBuffers b{};
+  float* p = base;
+  b.grid = p;
+  p += S * kH * kCells;
+  for (int i = 0; i < 4; ++i) {
+    b.c[i] = p;
+    p += S * kC * kB;
+  }
+  for (int i = 0; i < 3; ++i) {
+    b.d[i] = p;
+    p += S * kC * kB;
+  }
+  b.d4 = p;
+  p += S * kC * kCells;
+  b.glob = p;
+  return b;
+}
+
+namespace {
+
+hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float* W, const float* bias, float* out,
+                int D, int Do, int pad, int transposed, int n_shapes, hipStream_t s) {
+  ConvArgs a{in1, c1, in2, c2, W, bias, out, kC, D, Do, pad, transposed, n_shapes};
+  const long long n = (long long)n_shapes * kC * Do * Do * Do;
+  hipLaunchKernelGGL(conv_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,
+                          int64_t n_points, const EncoderBuffers& b, float* emb, double* centres, double* eps,
+                          hipStream_t s) {
+  if (n_shapes <= 0 || max_points <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(point_mlp_kernel, dim3((max_points + kPts - 1) / kPts, n_shapes), dim3(256), 0, s, w, shapes,
+                     xyz, n_points, b.grid);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = conv(b.grid, kH, nullptr, 0, w.C[0], w.k[0], b.c[0], kM, 4, 0, 0, n_shapes, s);
+  for (int i = 1; i < 4 && e == hipSuccess; ++i)
+    e = conv(b.c[i - 1], kC, nullptr, 0, w.C[i], w.k[i], b.c[i], 4, 4, 1, 0, n_shapes, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(global_kernel, dim3(n_shapes), dim3(kC), 0, s, b.c[3], b.glob);
+    e = hipGetLastError();
+  }
+  // transposed convs: on the bottleneck, then on [previous, matching conv output]
+  if (e == hipSuccess) e = conv(b.c[3], kC, nullptr, 0, w.D[0], w.e[0], b.d[0], 4, 4, 1, 1, n_shapes, s);
+  if (e == hipSuccess) e = conv(b.d[0], kC, b.c[2], kC, w.D[1], w.e[1], b.d[1], 4, 4, 1, 1, n_shapes, s);
+  if (e == hipSuccess) e = conv(b.d[1], kC, b.c[1], kC, w.D[2], w.e[2], b.d[2], 4, 4, 1, 1, n_shapes, s);
+  if (e == hipSuccess) e = conv(b.d[2], kC, b.c[0], kC, w.D[3], w.e[3], b.d4, 4, kM, 0, 1, n_shapes, s);
+  if (e == hipSuccess) {
+    const int n = n_shapes * kCells * kF;
+    hipLaunchKernelGGL(embed_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, b.d4, b.glob, emb, n_shapes);
+    hipLaunchKernelGGL(cells_kernel, dim3(n_shapes), dim3(256), 0, s, shapes, centres, eps);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_pairs(const PairArgs& a, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  const size_t smem = sizeof(PairShared);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pair_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(256), smem, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vox
+}  // namespace locc

@@ -13,8 +13,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    with open(os.path.join(ROOT, "include", "locc.h")) as f:
-        text = f.read()
+    text = ""
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            with open(os.path.join(ROOT, "include", name)) as f:
+                text += f.read()
     return sorted(set(re.findall(r"LOCC_API[^;(]*?\b(locc_\w+)\s*\(", text)))
 
 
@@ -79,3 +82,14 @@ def test_object_and_contact_layouts_are_32_bytes():
     objs = B.pack_objects(np.zeros((3, 3)), np.tile([1, 0, 0, 0], (3, 1)), [0, 5, -1])
     assert objs.dtype == np.float32 and objs.shape == (3, 8) and objs.nbytes == 96
     assert list(objs[:, 3].view(np.int32)) == [0, 5, -1]
+
+
+def test_voxel_weight_count_and_host_argument_checks():
+    L = B.load()
+    from oracle import voxel_locc as V
+    assert L.locc_voxel_weight_count() == V.n_weights()
+    out = ctypes.c_void_p()
+    assert L.locc_voxel_create(0, None) == B.ERR_INVALID_ARG
+    assert L.locc_voxel_upload_weights(None, None, 0) == B.ERR_INVALID_ARG
+    assert L.locc_voxel_detect(None, None, 0, None, 0, None, None, None, None) == B.ERR_INVALID_ARG
+    del out
