@@ -431,6 +431,60 @@ def serve_bench(args, w):
     return out
 
 
+def voxel_pair_flops():
+    """Algorithmic FLOPs per pair of the voxel variant's predictor: the per-object MLP 28-128-128-128 on
+    both objects and the pair MLP 128-128-128-128 plus the 128 -> 1 output (cell tests and means are
+    float64 compares and float32 adds, not counted)."""
+    per_object = 2 * (28 * 128 + 128 * 128 + 128 * 128)
+    return 2 * per_object + 2 * (3 * 128 * 128 + 128)
+
+
+def time_voxel(args, scene):
+    """The voxel-embedding variant on the same pairs: shape embeddings computed at upload, then the
+    per-pair kernel (logit and probability; counts not requested), timed with events on its stream."""
+    import numpy as np
+    import torch
+    from paper_2304_09439_amd import binding as B
+    from paper_2304_09439_amd import inputs as I
+    ctx = B.VoxelContext()
+    ctx.upload_weights(I.flatten_weights(I.voxel_weights(seed=0)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.upload_shapes(scene.lib.offsets, scene.lib.pts)   # synchronous: host copy + encoder kernels
+    encode_ms = 1000.0 * (time.perf_counter() - t0)
+    objs, pairs = B.scene_tensors(scene)
+    P = scene.n_pairs
+    out = torch.empty((P, 2), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        ctx.detect(objs, pairs, out, want_counts=False)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.detect(objs, pairs, out, want_counts=False)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    n_bad = ctx.device_errors()
+    ctx.close()
+    avg = float(step_ms.mean())
+    achieved = voxel_pair_flops() * P / (avg * 1e-3) / 1e12
+    ms = 1000.0 * wall / args.steps
+    return dict(value=round(P / (ms * 1e-3), 1), unit=UNIT, ms_per_step=round(ms, 4),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
+                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+                kernel=dict(name="voxel_pair_kernel", avg_ms=round(avg, 4), bound="alu",
+                            achieved=round(achieved, 2), peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                            frac=round(achieved / PEAK_TFLOPS["fp32"], 4), flops_per_pair=voxel_pair_flops()),
+                shape_encoder_ms=round(encode_ms, 2), device_errors=int(n_bad),
+                path="voxel-embedding variant: per-shape embeddings at upload (point MLP, 6^3 cell max, 3D U-Net, "
+                     "F=16), per pair one kernel (float64 cell tests, mean embeddings, float32 MLPs, pair max, "
+                     "sigmoid), 32 pairs per workgroup")
+
+
 def envs_widths():
     from paper_2304_09439_amd import inputs as I
     wd = I.SCALE_WIDTHS
@@ -480,6 +534,8 @@ def run(args):
     )
     if "fp32" in paths and primary != "fp32":
         line["speedup_vs_fp32_plain"] = round(main_path["value"] / paths["fp32"]["value"], 3)
+    if not args.no_voxel:
+        line["voxel_variant"] = time_voxel(args, scene)
     if args.serve_requests > 0:
         line["serving"] = serve_bench(args, w)
     if args.env_steps > 0:
@@ -565,6 +621,7 @@ def main():
     ap.add_argument("--env-steps", type=int, default=40,
                     help="simulation steps of the uneven-environment workload to time (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
+    ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-embedding variant's leg")
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default="encoder_fp32")

@@ -59,7 +59,7 @@ EncoderBuffers encoder_carve(float* base, int n_shapes);
 
 // Shape encoder over every shape; grid must be zero (the cell max starts at 0).
 hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,
-                          int64_t n_points, const EncoderBuffers& b, float* emb, double* centres, double* eps,
+                          int64_t n_points, const EncoderBuffers& b, float* emb, double* consts,
                           hipStream_t s);
 
 struct PairArgs {
@@ -69,8 +69,7 @@ struct PairArgs {
   int32_t n_pairs;
   const Shape* shapes;
   int32_t n_shapes;
-  const double* centres;  // [S][216][3]
-  const double* eps;      // [S]
+  const double* consts;   // [S][4]: cell size s_0, s_1, s_2 and the margin eps (float64)
   const float* emb;       // [S][216][16]
   PackedNet w;
   float* out;             // [P][2]

@@ -8,18 +8,20 @@
 // U-Net (one thread per output value, the skip concatenation read from two
 // inputs); global_kernel takes max and mean over the bottleneck cells;
 // embed_kernel maps [last layer, global feature] to the 16-float embedding;
-// cells_kernel writes the float64 cell centres and the margin of each shape.
+// consts_kernel writes the float64 cell size and margin of each shape.
 //
-// Predictor (per pair, pair_kernel): 32 pairs per workgroup of four waves.
+// Predictor (per pair, pair_kernel): 32 pairs per workgroup of eight waves.
 // One thread per pair validates it, puts it in canonical order and computes
 // the float64 relative pose; then each wave takes object sides in turn: 216
-// cell tests (float64, fixed order, contraction off) as four 64-lane
-// ballots, and the mean of the selected cells' embeddings (lane = feature x
-// cell residue mod 4, reduced across the residues); the per-object MLP runs
-// on the 64 side rows, the pair max folds them to 32 rows, the pair MLP and
-// the output layer follow.  Activations stay in LDS; every thread owns one
-// output column of a layer for its half of the rows, reading the weights
-// [in][out] from L2 (coalesced) and the rows from LDS as broadcasts.
+// cell tests (centres formed in registers; float64, fixed order, contraction
+// off) as four 64-lane ballots, and the mean of the selected cells'
+// embeddings (lane = 4 features x cell residue mod 16, float4 loads issued
+// together, summed across the residues by shuffles); the per-object MLP
+// runs on the 64 side rows, the pair max folds them to 32 rows, the pair
+// MLP and the output layer follow.  Activations stay in one LDS buffer that
+// each layer overwrites after all its reads; every thread owns one output
+// column of a layer for a quarter of the rows, reading the weights [in][out]
+// from L2 (coalesced) and the rows from LDS as broadcasts.
 #include "geometry.h"
 #include "voxel.h"
 
@@ -185,25 +187,30 @@ __global__ __launch_bounds__(256) void embed_kernel(PackedNet w, const float* d4
   emb[id] = acc;
 }
 
-// Cell centres lo + (i + 1/2) s and the margin sqrt((s0^2 + s1^2) + s2^2) / 2, float64.
-__global__ __launch_bounds__(256) void cells_kernel(const Shape* shapes, double* centres, double* eps) {
+// Per shape: the cell size s = (hi - lo) / 6 per axis and the margin
+// sqrt((s0^2 + s1^2) + s2^2) / 2, float64 (cell centres lo + (i + 1/2) s are
+// formed from these where they are used).
+__global__ __launch_bounds__(64) void consts_kernel(const Shape* shapes, int n_shapes, double* consts) {
 #pragma clang fp contract(off)
-  const int s = blockIdx.x, k = threadIdx.x;
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= n_shapes) return;
   const Shape sh = shapes[s];
   double step[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) step[a] = ((double)sh.hi[a] - (double)sh.lo[a]) / (double)kM;
-  if (k < kCells) {
-    const int i[3] = {k / (kM * kM), (k / kM) % kM, k % kM};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) centres[((size_t)s * kCells + k) * 3 + a] = (double)sh.lo[a] + ((double)i[a] + 0.5) * step[a];
-  }
-  if (k == 0) eps[s] = __builtin_sqrt((step[0] * step[0] + step[1] * step[1]) + step[2] * step[2]) * 0.5;
+  double* c = consts + (size_t)s * 4;
+  c[0] = step[0];
+  c[1] = step[1];
+  c[2] = step[2];
+  c[3] = __builtin_sqrt((step[0] * step[0] + step[1] * step[1]) + step[2] * step[2]) * 0.5;
 }
 
 // ------------------------------------------------------------------ pairs --
 
-constexpr int kTP = 32;  // pairs per workgroup
+constexpr int kTP = 32;       // pairs per workgroup
+constexpr int kWaves = 8;     // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kGroups = kThreads / kHP;  // row groups of a layer (one output column per thread)
 
 struct PairShared {
   double R[kTP][9];
@@ -212,19 +219,17 @@ struct PairShared {
   int valid[kTP];
   int swapped[kTP];
   alignas(16) float Z[2 * kTP][kIn];
-  alignas(16) float H0[2 * kTP][kHP];
-  alignas(16) float H1[2 * kTP][kHP];
+  alignas(16) float H[2 * kTP][kHP];  // activations, overwritten layer by layer
 };
 
-// Out[row][o] = ReLU(bias[o] + sum_k In[row][k] Wt[k][o]) for ROWS rows from row0.
+// acc[r] = bias[o] + sum_k In[row0 + r][k] Wt[k][o]
 template <int ROWS, int K, int STRIDE>
-__device__ __forceinline__ void dense(const float* In, float* Out, const float* __restrict__ Wt,
-                                      const float* __restrict__ bias, int o, int row0) {
-  float acc[ROWS];
+__device__ __forceinline__ void dense(const float* In, const float* __restrict__ Wt, const float* __restrict__ bias,
+                                      int o, int row0, float* acc) {
   const float b = bias[o];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) acc[r] = b;
-#pragma unroll 2
+#pragma unroll 4
   for (int k = 0; k < K; k += 4) {
     const float w0 = Wt[(k + 0) * kHP + o], w1 = Wt[(k + 1) * kHP + o];
     const float w2 = Wt[(k + 2) * kHP + o], w3 = Wt[(k + 3) * kHP + o];
@@ -237,13 +242,21 @@ __device__ __forceinline__ void dense(const float* In, float* Out, const float* 
       acc[r] = fmaf(v.w, w3, acc[r]);
     }
   }
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) Out[(row0 + r) * kHP + o] = relu(acc[r]);
 }
 
-__global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  PairShared& S = *reinterpret_cast<PairShared*>(smem_raw);
+// One layer over ROWS rows per row group, in place in H (reads finish before the writes).
+template <int ROWS, int K, int STRIDE>
+__device__ __forceinline__ void layer(const float* In, float* H, const float* Wt, const float* bias, int o, int grp) {
+  float acc[ROWS];
+  dense<ROWS, K, STRIDE>(In, Wt, bias, o, grp * ROWS, acc);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) H[(grp * ROWS + r) * kHP + o] = relu(acc[r]);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel(PairArgs A) {
+  __shared__ PairShared S;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int q0 = blockIdx.x * kTP;
 
@@ -296,15 +309,16 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
   __syncthreads();
 
   // cell selection and mean embedding, one object side per wave at a time
-  for (int j = wave; j < 2 * kTP; j += 4) {
+  for (int j = wave; j < 2 * kTP; j += kWaves) {
     const int q = j >> 1, side = j & 1;  // uniform
     if (!S.valid[q]) {
       if (lane < kIn) S.Z[j][lane] = 0.f;
       continue;
     }
     const int sh = S.shape[q][side], so = S.shape[q][side ^ 1];
-    const Shape other = A.shapes[so];
-    const double e = A.eps[sh];
+    const Shape own = A.shapes[sh], other = A.shapes[so];
+    const double* kc = A.consts + (size_t)sh * 4;
+    const double step[3] = {kc[0], kc[1], kc[2]}, e = kc[3];
     double lo_w[3], hi_w[3], R[9], tt[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -321,16 +335,17 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
       bool in = false;
       if (k < kCells) {
 #pragma clang fp contract(off)
-        const double* c = A.centres + ((size_t)sh * kCells + k) * 3;
-        const double c0 = c[0], c1 = c[1], c2 = c[2];
-        double x[3];
+        const int ci[3] = {k / (kM * kM), (k / kM) % kM, k % kM};
+        double c[3], x[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] = (double)own.lo[a] + ((double)ci[a] + 0.5) * step[a];
         if (side == 0) {  // a's cell into b's frame: R^T (c - t)
-          const double e0 = c0 - tt[0], e1 = c1 - tt[1], e2 = c2 - tt[2];
+          const double e0 = c[0] - tt[0], e1 = c[1] - tt[1], e2 = c[2] - tt[2];
 #pragma unroll
           for (int i = 0; i < 3; ++i) x[i] = (R[i] * e0 + R[3 + i] * e1) + R[6 + i] * e2;
         } else {          // b's cell into a's frame: R c + t
 #pragma unroll
-          for (int i = 0; i < 3; ++i) x[i] = ((R[3 * i] * c0 + R[3 * i + 1] * c1) + R[3 * i + 2] * c2) + tt[i];
+          for (int i = 0; i < 3; ++i) x[i] = ((R[3 * i] * c[0] + R[3 * i + 1] * c[1]) + R[3 * i + 2] * c[2]) + tt[i];
         }
         in = (x[0] >= lo_w[0]) & (x[0] <= hi_w[0]) & (x[1] >= lo_w[1]) & (x[1] <= hi_w[1]) & (x[2] >= lo_w[2]) &
              (x[2] <= hi_w[2]);
@@ -338,34 +353,58 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
       m[r] = __ballot(in);
     }
     const int count = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
-    // lane = feature f (16) x residue g (4): sum over the selected cells k = g mod 4
-    const int f = lane & (kF - 1), g = lane >> 4;
-    const float* E = A.emb + (size_t)sh * kCells * kF + f;
-    float acc = 0.f;
-    for (int k = g; k < kCells; k += 4) {
+    // lane = 4 features (f4) x cell residue g mod 16: float4 loads of the selected cells, all issued
+    // together, then a sum over the 16 residues
+    const int f4 = lane & 3, g = lane >> 2;
+    const float4* E = reinterpret_cast<const float4*>(A.emb + (size_t)sh * kCells * kF) + f4;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 7
+    for (int it = 0; it < (kCells + 15) / 16; ++it) {
+      const int k = 16 * it + g;
       const unsigned long long mk = k < 64 ? m[0] : (k < 128 ? m[1] : (k < 192 ? m[2] : m[3]));
-      if ((mk >> (k & 63)) & 1ull) acc += E[k * kF];
+      if (k < kCells && ((mk >> (k & 63)) & 1ull)) {
+        const float4 v = E[k * (kF / 4)];
+        acc.x += v.x;
+        acc.y += v.y;
+        acc.z += v.z;
+        acc.w += v.w;
+      }
     }
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    const float mean = count > 0 ? acc / (float)count : 0.f;
+#pragma unroll
+    for (int d = 4; d < 64; d <<= 1) {
+      acc.x += __shfl_xor(acc.x, d, 64);
+      acc.y += __shfl_xor(acc.y, d, 64);
+      acc.z += __shfl_xor(acc.z, d, 64);
+      acc.w += __shfl_xor(acc.w, d, 64);
+    }
+    const float inv = count > 0 ? 1.f / (float)count : 0.f;
     const int cpos = side ^ S.swapped[q];  // the object's position in the caller's pair
-    if (lane < kF) {
-      S.Z[j][lane] = mean;
-      if (A.pooled) A.pooled[((size_t)(q0 + q) * 2 + cpos) * kF + lane] = mean;
-    } else if (lane < kIn) {
+    if (lane < 4) {
+      const float4 mean = make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv);
+      *reinterpret_cast<float4*>(&S.Z[j][4 * lane]) = mean;
+      if (A.pooled) {
+        float* dst = A.pooled + ((size_t)(q0 + q) * 2 + cpos) * kF + 4 * lane;
+        dst[0] = mean.x;
+        dst[1] = mean.y;
+        dst[2] = mean.z;
+        dst[3] = mean.w;
+      }
+    } else if (lane >= kF && lane < kIn) {
+      // lane-indexed values come from LDS (a register array indexed by lane would go to scratch)
       const int jj = lane - kF;
+      const double* Rq = S.R[q];
+      const double* tq = S.t[q];
       double v;
       if (side == 0) {  // a in b's frame: (-R^T t, R^T)
         if (jj < 3) {
 #pragma clang fp contract(off)
-          v = -((R[jj] * tt[0] + R[3 + jj] * tt[1]) + R[6 + jj] * tt[2]);
+          v = -((Rq[jj] * tq[0] + Rq[3 + jj] * tq[1]) + Rq[6 + jj] * tq[2]);
         } else {
           const int m9 = jj - 3;
-          v = R[3 * (m9 % 3) + m9 / 3];
+          v = Rq[3 * (m9 % 3) + m9 / 3];
         }
       } else {          // b in a's frame: (t, R)
-        v = jj < 3 ? tt[jj] : R[jj - 3];
+        v = jj < 3 ? tq[jj] : Rq[jj - 3];
       }
       S.Z[j][lane] = (float)v;
     }
@@ -373,34 +412,35 @@ __global__ __launch_bounds__(256) void pair_kernel(PairArgs A) {
   }
   __syncthreads();
 
-  // per-object MLP on the 64 side rows
-  const int o = t & (kHP - 1), half = t >> 7;
-  dense<kTP, kIn, kIn>(&S.Z[0][0], &S.H0[0][0], A.w.At[0], A.w.a[0], o, half * kTP);
-  __syncthreads();
-  dense<kTP, kHP, kHP>(&S.H0[0][0], &S.H1[0][0], A.w.At[1], A.w.a[1], o, half * kTP);
-  __syncthreads();
-  dense<kTP, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.At[2], A.w.a[2], o, half * kTP);
-  __syncthreads();
-  // max over the two objects of each pair
-  for (int id = t; id < kTP * kHP; id += 256) {
-    const int q = id / kHP, c = id % kHP;
-    const float u = S.H0[2 * q][c], v = S.H0[2 * q + 1][c];
-    S.H1[q][c] = u > v ? u : v;
+  // per-object MLP on the 64 side rows, then the max over the two objects of each pair
+  const int o = t & (kHP - 1), grp = t / kHP;
+  constexpr int kR1 = 2 * kTP / kGroups, kR2 = kTP / kGroups;
+  layer<kR1, kIn, kIn>(&S.Z[0][0], &S.H[0][0], A.w.At[0], A.w.a[0], o, grp);
+  layer<kR1, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.At[1], A.w.a[1], o, grp);
+  layer<kR1, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.At[2], A.w.a[2], o, grp);
+  {
+    float mx[kR2];
+#pragma unroll
+    for (int r = 0; r < kR2; ++r) {
+      const int q = grp * kR2 + r;
+      const float u = S.H[2 * q][o], v = S.H[2 * q + 1][o];
+      mx[r] = u > v ? u : v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kR2; ++r) S.H[grp * kR2 + r][o] = mx[r];
+    __syncthreads();
   }
-  __syncthreads();
   // pair MLP on the 32 pair rows
-  constexpr int kHalf = kTP / 2;
-  dense<kHalf, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.Bt[0], A.w.b[0], o, half * kHalf);
-  __syncthreads();
-  dense<kHalf, kHP, kHP>(&S.H0[0][0], &S.H1[0][0], A.w.Bt[1], A.w.b[1], o, half * kHalf);
-  __syncthreads();
-  dense<kHalf, kHP, kHP>(&S.H1[0][0], &S.H0[0][0], A.w.Bt[2], A.w.b[2], o, half * kHalf);
-  __syncthreads();
-  // output layer and sigmoid: a wave per 8 pairs
+  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[0], A.w.b[0], o, grp);
+  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[1], A.w.b[1], o, grp);
+  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[2], A.w.b[2], o, grp);
+  // output layer and sigmoid: a wave per kTP / kWaves pairs
   const float w_lo = A.w.B4[lane], w_hi = A.w.B4[lane + 64], b4 = A.w.b[3][0];
-  for (int k = 0; k < kTP / 4; ++k) {
-    const int q = wave * (kTP / 4) + k;
-    float v = fmaf(w_lo, S.H0[q][lane], w_hi * S.H0[q][lane + 64]);
+#pragma unroll
+  for (int k = 0; k < kTP / kWaves; ++k) {
+    const int q = wave * (kTP / kWaves) + k;
+    float v = fmaf(w_lo, S.H[q][lane], w_hi * S.H[q][lane + 64]);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     if (lane == 0 && S.valid[q]) {
@@ -556,8 +596,7 @@ hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float*
 }  // namespace
 
 hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,
-                          int64_t n_points, const EncoderBuffers& b, float* emb, double* centres, double* eps,
-                          hipStream_t s) {
+                          int64_t n_points, const EncoderBuffers& b, float* emb, double* consts, hipStream_t s) {
   if (n_shapes <= 0 || max_points <= 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(point_mlp_kernel, dim3((max_points + kPts - 1) / kPts, n_shapes), dim3(256), 0, s, w, shapes,
                      xyz, n_points, b.grid);
@@ -577,7 +616,7 @@ hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes,
   if (e == hipSuccess) {
     const int n = n_shapes * kCells * kF;
     hipLaunchKernelGGL(embed_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, b.d4, b.glob, emb, n_shapes);
-    hipLaunchKernelGGL(cells_kernel, dim3(n_shapes), dim3(256), 0, s, shapes, centres, eps);
+    hipLaunchKernelGGL(consts_kernel, dim3((n_shapes + 63) / 64), dim3(64), 0, s, shapes, n_shapes, consts);
     e = hipGetLastError();
   }
   return e;
@@ -585,11 +624,7 @@ hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes,
 
 hipError_t launch_pairs(const PairArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  const size_t smem = sizeof(PairShared);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pair_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(256), smem, s, a);
+  hipLaunchKernelGGL(pair_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

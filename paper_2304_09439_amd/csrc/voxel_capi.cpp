@@ -26,8 +26,7 @@ struct locc_voxel_ctx {
   float* d_packed = nullptr;
   // per-shape results of the encoder
   float* d_emb = nullptr;       // [S][216][16]
-  double* d_centres = nullptr;  // [S][216][3]
-  double* d_eps = nullptr;      // [S]
+  double* d_consts = nullptr;   // [S][4] cell size and margin
   bool have_embeddings = false;
   unsigned long long* d_err = nullptr;
 };
@@ -38,13 +37,11 @@ void free_shapes(locc_voxel_ctx* c) {
   (void)hipFree(c->d_shapes);
   (void)hipFree(c->d_xyz);
   (void)hipFree(c->d_emb);
-  (void)hipFree(c->d_centres);
-  (void)hipFree(c->d_eps);
+  (void)hipFree(c->d_consts);
   c->d_shapes = nullptr;
   c->d_xyz = nullptr;
   c->d_emb = nullptr;
-  c->d_centres = nullptr;
-  c->d_eps = nullptr;
+  c->d_consts = nullptr;
   c->have_embeddings = false;
 }
 
@@ -60,7 +57,7 @@ locc_status encode(locc_voxel_ctx* c) {
   hipError_t e = hipMemset(b.grid, 0, (size_t)S * kH * kCells * sizeof(float));
   if (e == hipSuccess)
     e = launch_encoder(packed_view(c->d_raw, c->d_packed), c->d_shapes, S, c->max_points, c->d_xyz, c->n_points, b,
-                       c->d_emb, c->d_centres, c->d_eps, nullptr);
+                       c->d_emb, c->d_consts, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   (void)hipFree(scratch);
   if (e != hipSuccess) return fail(LOCC_ERR_HIP, "shape encoder: %s", hipGetErrorString(e));
@@ -161,8 +158,7 @@ locc_status locc_voxel_upload_shapes(locc_voxel_ctx* c, int32_t n_shapes, const 
   HIP_TRY(hipMalloc(&c->d_shapes, sizeof(Shape) * n_shapes));
   HIP_TRY(hipMalloc(&c->d_xyz, sizeof(float) * xyz.size()));
   HIP_TRY(hipMalloc(&c->d_emb, sizeof(float) * (size_t)n_shapes * kCells * kF));
-  HIP_TRY(hipMalloc(&c->d_centres, sizeof(double) * (size_t)n_shapes * kCells * 3));
-  HIP_TRY(hipMalloc(&c->d_eps, sizeof(double) * (size_t)n_shapes));
+  HIP_TRY(hipMalloc(&c->d_consts, sizeof(double) * (size_t)n_shapes * 4));
   HIP_TRY(hipMemcpy(c->d_shapes, shapes.data(), sizeof(Shape) * n_shapes, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_xyz, xyz.data(), sizeof(float) * xyz.size(), hipMemcpyHostToDevice));
   c->n_shapes = n_shapes;
@@ -196,8 +192,7 @@ locc_status locc_voxel_detect(locc_voxel_ctx* c, const locc_object* objs, int32_
   a.n_pairs = n_pairs;
   a.shapes = c->d_shapes;
   a.n_shapes = c->n_shapes;
-  a.centres = c->d_centres;
-  a.eps = c->d_eps;
+  a.consts = c->d_consts;
   a.emb = c->d_emb;
   a.w = packed_view(c->d_raw, c->d_packed);
   a.out = out;
