@@ -476,13 +476,13 @@ def time_voxel(args, scene):
     return dict(value=round(P / (ms * 1e-3), 1), unit=UNIT, ms_per_step=round(ms, 4),
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
-                kernel=dict(name="voxel_pair_kernel", avg_ms=round(avg, 4), bound="alu",
+                kernel=dict(name="voxel select + mlp kernels (one step)", avg_ms=round(avg, 4), bound="alu",
                             achieved=round(achieved, 2), peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
                             frac=round(achieved / PEAK_TFLOPS["fp32"], 4), flops_per_pair=voxel_pair_flops()),
                 shape_encoder_ms=round(encode_ms, 2), device_errors=int(n_bad),
                 path="voxel-embedding variant: per-shape embeddings at upload (point MLP, 6^3 cell max, 3D U-Net, "
-                     "F=16), per pair one kernel (float64 cell tests, mean embeddings, float32 MLPs, pair max, "
-                     "sigmoid), 32 pairs per workgroup")
+                     "F=16); per pair a selection kernel (one wave per pair: float64 cell tests, mean embeddings) "
+                     "and an MLP kernel (float32 MFMA, 32 pairs per workgroup, pair max, sigmoid)")
 
 
 def envs_widths():

@@ -32,15 +32,14 @@ struct Shape {
 static_assert(sizeof(Shape) == 32, "Shape layout");
 
 // Device pointers to every weight array: the flat vector as uploaded, except
-// the point MLP's layers 2-3 and the predictor's matrices, which are used
-// transposed to [in][out] (a coalesced row of outputs per input) from a
-// second, packed buffer.
+// the point MLP's layers 2-3, which are used transposed to [in][out] (a
+// coalesced row of outputs per input) from a second, packed buffer.
 struct PackedNet {
   const float *P1, *p1, *P2t, *p2, *P3t, *p3;  // point MLP
   const float *C[4], *k[4], *D[4], *e[4];      // U-Net convs, transposed convs
   const float *L, *l;                          // embedding map [16][384]
-  const float *At[3], *a[3];                   // per-object MLP: [28][128], [128][128] x 2
-  const float *Bt[3], *b[4], *B4;              // pair MLP [128][128] x 3, output row [128], b[3] = its bias
+  const float *A[3], *a[3];                    // per-object MLP [128][28], [128][128] x 2 (row-major)
+  const float *Bw[3], *b[4], *B4;              // pair MLP [128][128] x 3, output row [128], b[3] = its bias
 };
 size_t packed_floats();
 // Host-side transposition of the flat weights into dst (packed_floats() floats).
@@ -76,7 +75,15 @@ struct PairArgs {
   int32_t* counts;        // [P][2] or null
   float* pooled;          // [P][2][16] or null
   unsigned long long* err;
+  float* z;               // workspace [P][2][28]: per-object predictor inputs (canonical order)
+  int32_t* valid;         // workspace [P]
 };
+// Workspace bytes of a launch over n_pairs pairs.
+size_t pair_workspace_bytes(int n_pairs);
+// Carves the workspace at base into a.z / a.valid.
+void pair_workspace_carve(void* base, int n_pairs, PairArgs& a);
+// Two launches: cell selection and mean embeddings (one wave per pair), then
+// the predictor MLPs (32 pairs per workgroup).
 hipError_t launch_pairs(const PairArgs& a, hipStream_t s);
 
 }  // namespace vox

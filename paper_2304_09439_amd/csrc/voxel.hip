@@ -10,18 +10,20 @@
 // embed_kernel maps [last layer, global feature] to the 16-float embedding;
 // consts_kernel writes the float64 cell size and margin of each shape.
 //
-// Predictor (per pair, pair_kernel): 32 pairs per workgroup of eight waves.
-// One thread per pair validates it, puts it in canonical order and computes
-// the float64 relative pose; then each wave takes object sides in turn: 216
-// cell tests (centres formed in registers; float64, fixed order, contraction
-// off) as four 64-lane ballots, and the mean of the selected cells'
-// embeddings (lane = 4 features x cell residue mod 16, float4 loads issued
-// together, summed across the residues by shuffles); the per-object MLP
-// runs on the 64 side rows, the pair max folds them to 32 rows, the pair
-// MLP and the output layer follow.  Activations stay in one LDS buffer that
-// each layer overwrites after all its reads; every thread owns one output
-// column of a layer for a quarter of the rows, reading the weights [in][out]
-// from L2 (coalesced) and the rows from LDS as broadcasts.
+// Predictor, two launches.  select_kernel: one wave per pair validates it,
+// puts it in canonical order, computes the float64 relative pose
+// (wave-uniform), runs each object's 216 cell tests (centres formed in
+// registers; float64, fixed order, contraction off) as four 64-lane ballots
+// and the means of the selected cells' embeddings (lane = 4 features x cell
+// residue mod 16, the float4 loads of both objects issued together, summed
+// across the residues by shuffles), and writes both objects' predictor input
+// rows to the workspace; with small register use many waves are in flight
+// to hide the load latency.  mlp_kernel: 32 pairs per workgroup of eight waves run the
+// per-object MLP on the 64 rows, the pair max, the pair MLP and the output
+// layer in float32, activations in one LDS buffer that each layer
+// overwrites after all its reads; every thread owns one output column of a
+// layer for a quarter of the rows, reading the weights [in][out] from L2
+// (coalesced) and the rows from LDS as broadcasts.
 #include "geometry.h"
 #include "voxel.h"
 
@@ -207,128 +209,70 @@ __global__ __launch_bounds__(64) void consts_kernel(const Shape* shapes, int n_s
 
 // ------------------------------------------------------------------ pairs --
 
-constexpr int kTP = 32;       // pairs per workgroup
-constexpr int kWaves = 8;     // waves per workgroup
-constexpr int kThreads = 64 * kWaves;
-constexpr int kGroups = kThreads / kHP;  // row groups of a layer (one output column per thread)
-
-struct PairShared {
-  double R[kTP][9];
-  double t[kTP][3];
-  int shape[kTP][2];
-  int valid[kTP];
-  int swapped[kTP];
-  alignas(16) float Z[2 * kTP][kIn];
-  alignas(16) float H[2 * kTP][kHP];  // activations, overwritten layer by layer
-};
-
-// acc[r] = bias[o] + sum_k In[row0 + r][k] Wt[k][o]
-template <int ROWS, int K, int STRIDE>
-__device__ __forceinline__ void dense(const float* In, const float* __restrict__ Wt, const float* __restrict__ bias,
-                                      int o, int row0, float* acc) {
-  const float b = bias[o];
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) acc[r] = b;
-#pragma unroll 4
-  for (int k = 0; k < K; k += 4) {
-    const float w0 = Wt[(k + 0) * kHP + o], w1 = Wt[(k + 1) * kHP + o];
-    const float w2 = Wt[(k + 2) * kHP + o], w3 = Wt[(k + 3) * kHP + o];
-#pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-      const float4 v = *reinterpret_cast<const float4*>(In + (row0 + r) * STRIDE + k);
-      acc[r] = fmaf(v.x, w0, acc[r]);
-      acc[r] = fmaf(v.y, w1, acc[r]);
-      acc[r] = fmaf(v.z, w2, acc[r]);
-      acc[r] = fmaf(v.w, w3, acc[r]);
-    }
+// Cell selection and mean embeddings: one wave per pair (grid P).  The
+// pair's validation, canonical order and float64 relative pose are
+// wave-uniform; both objects' cell tests and embedding loads are then issued
+// together, and each object's predictor input row [mean (16), pose in the
+// other object's frame (12)] goes to the workspace.
+__global__ __launch_bounds__(64) void select_kernel(PairArgs A) {
+  const int q = blockIdx.x, lane = threadIdx.x;
+  if (q >= A.n_pairs) return;
+  float* zrow = A.z + (size_t)q * 2 * kIn;
+  const int i = A.pairs[2 * q], j = A.pairs[2 * q + 1];
+  bool valid = i >= 0 && i < A.n_objs && j >= 0 && j < A.n_objs && i != j;
+  const int swp = i > j;
+  locc_object oa{}, ob{};
+  if (valid) {
+    oa = A.objs[swp ? j : i];
+    ob = A.objs[swp ? i : j];
+    valid = oa.shape >= 0 && oa.shape < A.n_shapes && ob.shape >= 0 && ob.shape < A.n_shapes;
   }
-}
-
-// One layer over ROWS rows per row group, in place in H (reads finish before the writes).
-template <int ROWS, int K, int STRIDE>
-__device__ __forceinline__ void layer(const float* In, float* H, const float* Wt, const float* bias, int o, int grp) {
-  float acc[ROWS];
-  dense<ROWS, K, STRIDE>(In, Wt, bias, o, grp * ROWS, acc);
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < ROWS; ++r) H[(grp * ROWS + r) * kHP + o] = relu(acc[r]);
-  __syncthreads();
-}
-
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel(PairArgs A) {
-  __shared__ PairShared S;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int q0 = blockIdx.x * kTP;
-
-  // pair set-up: validation, canonical order, float64 relative pose
-  if (t < kTP) {
-    const int q = q0 + t;
-    int valid = 0, swp = 0, sa = 0, sb = 0;
-    if (q < A.n_pairs) {
-      const int i = A.pairs[2 * q], j = A.pairs[2 * q + 1];
-      if (i >= 0 && i < A.n_objs && j >= 0 && j < A.n_objs && i != j) {
-        swp = i > j;
-        const locc_object oa = A.objs[swp ? j : i], ob = A.objs[swp ? i : j];
-        sa = oa.shape;
-        sb = ob.shape;
-        if (sa >= 0 && sa < A.n_shapes && sb >= 0 && sb < A.n_shapes) {
+  if (!valid) {  // uniform
+    const float nan = __builtin_nanf("");
+    if (lane < 2 * kIn / 4) reinterpret_cast<float4*>(zrow)[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (A.pooled && lane < 2 * kF) A.pooled[(size_t)q * 2 * kF + lane] = nan;
+    if (lane == 0) {
+      A.out[2 * q] = nan;
+      A.out[2 * q + 1] = nan;
+      if (A.counts) {
+        A.counts[2 * q] = -1;
+        A.counts[2 * q + 1] = -1;
+      }
+      A.valid[q] = 0;
+      atomicAdd(A.err, 1ull);
+    }
+    return;
+  }
+  // float64 relative pose of b in a's frame (the same in every lane)
+  double R[9], tt[3];
+  {
 #pragma clang fp contract(off)
-          valid = 1;
-          double Ra[9], Rb[9];
-          geo_quat_to_rot(oa.q, Ra);
-          geo_quat_to_rot(ob.q, Rb);
+    double Ra[9], Rb[9];
+    geo_quat_to_rot(oa.q, Ra);
+    geo_quat_to_rot(ob.q, Rb);
 #pragma unroll
-          for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) S.R[t][3 * r + c] = (Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c]) + Ra[6 + r] * Rb[6 + c];
-          const double d0 = (double)ob.p[0] - (double)oa.p[0];
-          const double d1 = (double)ob.p[1] - (double)oa.p[1];
-          const double d2 = (double)ob.p[2] - (double)oa.p[2];
+      for (int c = 0; c < 3; ++c) R[3 * r + c] = (Ra[r] * Rb[c] + Ra[3 + r] * Rb[3 + c]) + Ra[6 + r] * Rb[6 + c];
+    const double d0 = (double)ob.p[0] - (double)oa.p[0];
+    const double d1 = (double)ob.p[1] - (double)oa.p[1];
+    const double d2 = (double)ob.p[2] - (double)oa.p[2];
 #pragma unroll
-          for (int r = 0; r < 3; ++r) S.t[t][r] = (Ra[r] * d0 + Ra[3 + r] * d1) + Ra[6 + r] * d2;
-        }
-      }
-      if (!valid) {
-        const float nan = __builtin_nanf("");
-        A.out[2 * q] = nan;
-        A.out[2 * q + 1] = nan;
-        if (A.counts) {
-          A.counts[2 * q] = -1;
-          A.counts[2 * q + 1] = -1;
-        }
-        if (A.pooled)
-          for (int f = 0; f < 2 * kF; ++f) A.pooled[(size_t)q * 2 * kF + f] = nan;
-        atomicAdd(A.err, 1ull);
-      }
-    }
-    S.valid[t] = valid;
-    S.swapped[t] = swp;
-    S.shape[t][0] = sa;
-    S.shape[t][1] = sb;
+    for (int r = 0; r < 3; ++r) tt[r] = (Ra[r] * d0 + Ra[3 + r] * d1) + Ra[6 + r] * d2;
   }
-  __syncthreads();
-
-  // cell selection and mean embedding, one object side per wave at a time
-  for (int j = wave; j < 2 * kTP; j += kWaves) {
-    const int q = j >> 1, side = j & 1;  // uniform
-    if (!S.valid[q]) {
-      if (lane < kIn) S.Z[j][lane] = 0.f;
-      continue;
-    }
-    const int sh = S.shape[q][side], so = S.shape[q][side ^ 1];
-    const Shape own = A.shapes[sh], other = A.shapes[so];
-    const double* kc = A.consts + (size_t)sh * 4;
+  const Shape box_a = A.shapes[oa.shape], box_b = A.shapes[ob.shape];
+  unsigned long long m[2][4];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double* kc = A.consts + (size_t)(side ? ob.shape : oa.shape) * 4;
     const double step[3] = {kc[0], kc[1], kc[2]}, e = kc[3];
-    double lo_w[3], hi_w[3], R[9], tt[3];
+    double own_lo[3], lo_w[3], hi_w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      lo_w[k] = (double)other.lo[k] - e;
-      hi_w[k] = (double)other.hi[k] + e;
-      tt[k] = S.t[q][k];
+      own_lo[k] = side ? box_b.lo[k] : box_a.lo[k];
+      lo_w[k] = (double)(side ? box_a.lo[k] : box_b.lo[k]) - e;
+      hi_w[k] = (double)(side ? box_a.hi[k] : box_b.hi[k]) + e;
     }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) R[k] = S.R[q][k];
-    unsigned long long m[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = 64 * r + lane;
@@ -338,103 +282,184 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const int ci[3] = {k / (kM * kM), (k / kM) % kM, k % kM};
         double c[3], x[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) c[a] = (double)own.lo[a] + ((double)ci[a] + 0.5) * step[a];
+        for (int a = 0; a < 3; ++a) c[a] = own_lo[a] + ((double)ci[a] + 0.5) * step[a];
         if (side == 0) {  // a's cell into b's frame: R^T (c - t)
           const double e0 = c[0] - tt[0], e1 = c[1] - tt[1], e2 = c[2] - tt[2];
 #pragma unroll
-          for (int i = 0; i < 3; ++i) x[i] = (R[i] * e0 + R[3 + i] * e1) + R[6 + i] * e2;
+          for (int a = 0; a < 3; ++a) x[a] = (R[a] * e0 + R[3 + a] * e1) + R[6 + a] * e2;
         } else {          // b's cell into a's frame: R c + t
 #pragma unroll
-          for (int i = 0; i < 3; ++i) x[i] = ((R[3 * i] * c[0] + R[3 * i + 1] * c[1]) + R[3 * i + 2] * c[2]) + tt[i];
+          for (int a = 0; a < 3; ++a) x[a] = ((R[3 * a] * c[0] + R[3 * a + 1] * c[1]) + R[3 * a + 2] * c[2]) + tt[a];
         }
         in = (x[0] >= lo_w[0]) & (x[0] <= hi_w[0]) & (x[1] >= lo_w[1]) & (x[1] <= hi_w[1]) & (x[2] >= lo_w[2]) &
              (x[2] <= hi_w[2]);
       }
-      m[r] = __ballot(in);
+      m[side][r] = __ballot(in);
     }
-    const int count = __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
-    // lane = 4 features (f4) x cell residue g mod 16: float4 loads of the selected cells, all issued
-    // together, then a sum over the 16 residues
-    const int f4 = lane & 3, g = lane >> 2;
-    const float4* E = reinterpret_cast<const float4*>(A.emb + (size_t)sh * kCells * kF) + f4;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 7
+  }
+  // lane = 4 features (f4) x cell residue g mod 16: float4 loads of the selected cells of both
+  // objects, issued together, then sums over the 16 residues by shuffles
+  const int f4 = lane & 3, g = lane >> 2;
+  float4 acc[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const float4* E = reinterpret_cast<const float4*>(A.emb + (size_t)(side ? ob.shape : oa.shape) * kCells * kF) + f4;
+    acc[side] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
     for (int it = 0; it < (kCells + 15) / 16; ++it) {
-      const int k = 16 * it + g;
-      const unsigned long long mk = k < 64 ? m[0] : (k < 128 ? m[1] : (k < 192 ? m[2] : m[3]));
-      if (k < kCells && ((mk >> (k & 63)) & 1ull)) {
+      const int k = 16 * it + g;  // 16 consecutive cells per step: one ballot word, m[side][it / 4]
+      if (k < kCells && ((m[side][it >> 2] >> (k & 63)) & 1ull)) {
         const float4 v = E[k * (kF / 4)];
-        acc.x += v.x;
-        acc.y += v.y;
-        acc.z += v.z;
-        acc.w += v.w;
+        acc[side].x += v.x;
+        acc[side].y += v.y;
+        acc[side].z += v.z;
+        acc[side].w += v.w;
       }
     }
+  }
+#pragma unroll
+  for (int side = 0; side < 2; ++side)
 #pragma unroll
     for (int d = 4; d < 64; d <<= 1) {
-      acc.x += __shfl_xor(acc.x, d, 64);
-      acc.y += __shfl_xor(acc.y, d, 64);
-      acc.z += __shfl_xor(acc.z, d, 64);
-      acc.w += __shfl_xor(acc.w, d, 64);
+      acc[side].x += __shfl_xor(acc[side].x, d, 64);
+      acc[side].y += __shfl_xor(acc[side].y, d, 64);
+      acc[side].z += __shfl_xor(acc[side].z, d, 64);
+      acc[side].w += __shfl_xor(acc[side].w, d, 64);
     }
-    const float inv = count > 0 ? 1.f / (float)count : 0.f;
-    const int cpos = side ^ S.swapped[q];  // the object's position in the caller's pair
-    if (lane < 4) {
-      const float4 mean = make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w * inv);
-      *reinterpret_cast<float4*>(&S.Z[j][4 * lane]) = mean;
-      if (A.pooled) {
-        float* dst = A.pooled + ((size_t)(q0 + q) * 2 + cpos) * kF + 4 * lane;
-        dst[0] = mean.x;
-        dst[1] = mean.y;
-        dst[2] = mean.z;
-        dst[3] = mean.w;
-      }
-    } else if (lane >= kF && lane < kIn) {
-      // lane-indexed values come from LDS (a register array indexed by lane would go to scratch)
-      const int jj = lane - kF;
-      const double* Rq = S.R[q];
-      const double* tq = S.t[q];
-      double v;
-      if (side == 0) {  // a in b's frame: (-R^T t, R^T)
-        if (jj < 3) {
+  const int count_a = (int)(__popcll(m[0][0]) + __popcll(m[0][1]) + __popcll(m[0][2]) + __popcll(m[0][3]));
+  const int count_b = (int)(__popcll(m[1][0]) + __popcll(m[1][1]) + __popcll(m[1][2]) + __popcll(m[1][3]));
+  // lanes 0..3 / 4..7: the means of a / b (4 features each)
+  const int side = (lane >> 2) & 1;
+  if (lane < 8) {
+    const float4 sum = side ? acc[1] : acc[0];
+    const int cnt = side ? count_b : count_a;
+    const float inv = cnt > 0 ? 1.f / (float)cnt : 0.f;
+    const float mean[4] = {sum.x * inv, sum.y * inv, sum.z * inv, sum.w * inv};
+    const int f0 = 4 * (lane & 3), cpos = side ^ swp;  // the object's position in the caller's pair
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      zrow[side * kIn + f0 + f] = mean[f];
+      if (A.pooled) A.pooled[((size_t)q * 2 + cpos) * kF + f0 + f] = mean[f];
+    }
+  }
+  // the poses, written by one lane each with fixed indices: a in b's frame (-R^T t, R^T), b in
+  // a's frame (t, R)
+  if (lane == 8) {
 #pragma clang fp contract(off)
-          v = -((Rq[jj] * tq[0] + Rq[3 + jj] * tq[1]) + Rq[6 + jj] * tq[2]);
-        } else {
-          const int m9 = jj - 3;
-          v = Rq[3 * (m9 % 3) + m9 / 3];
-        }
-      } else {          // b in a's frame: (t, R)
-        v = jj < 3 ? tq[jj] : Rq[jj - 3];
-      }
-      S.Z[j][lane] = (float)v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zrow[kF + a] = (float)(-((R[a] * tt[0] + R[3 + a] * tt[1]) + R[6 + a] * tt[2]));
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) zrow[kF + 3 + 3 * r + c] = (float)R[3 * c + r];
+  } else if (lane == 9) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) zrow[kIn + kF + a] = (float)tt[a];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) zrow[kIn + kF + 3 + a] = (float)R[a];
+  }
+  if (lane == 0) {
+    if (A.counts) {
+      A.counts[(size_t)q * 2 + swp] = count_a;
+      A.counts[(size_t)q * 2 + (swp ^ 1)] = count_b;
     }
-    if (lane == 0 && A.counts) A.counts[(size_t)(q0 + q) * 2 + cpos] = count;
+    A.valid[q] = 1;
+  }
+}
+
+constexpr int kTP = 32;                  // pairs per workgroup of the predictor
+constexpr int kWaves = 8;                // waves per workgroup, one 16-column stripe each
+constexpr int kThreads = 64 * kWaves;
+constexpr int kZS = 36;                  // LDS row strides (floats): the inputs padded to 32 columns,
+constexpr int kHS = kHP + 4;             // +4 so that 8 consecutive rows start in different banks
+
+struct MlpShared {
+  int valid[kTP];
+  alignas(16) float Z[2 * kTP][kZS];
+  alignas(16) float H[2 * kTP][kHS];     // activations, overwritten layer by layer
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One layer, Out = ReLU(In W^T + b), over RT row tiles of 16 rows, for this
+// wave's 16 output columns c0.. (v_mfma_f32_16x16x4f32).  The reduction index
+// is permuted so that each lane reads four consecutive inputs at once: at
+// k-step 4u + v, lane group g = lane / 16 holds k = 16u + 4g + v, in A (the
+// rows, from LDS) and in B (the weight row W[c0 + lane % 16][...], from L2)
+// alike.  K16 = K / 16 rounded up; inputs past K are zero in both.
+template <int RT, int K, int K16, int IS>
+__device__ __forceinline__ void mfma_layer(const float* In, float* Out, const float* __restrict__ W,
+                                           const float* __restrict__ bias, int c0, int lane) {
+  const int j = lane & 15, g = lane >> 4;
+  float4 b[K16];
+#pragma unroll
+  for (int u = 0; u < K16; ++u) {
+    const int k = 16 * u + 4 * g;
+    b[u] = k < K ? *reinterpret_cast<const float4*>(W + (size_t)(c0 + j) * K + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const float bj = bias[c0 + j];
+  f32x4 acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = f32x4{bj, bj, bj, bj};
+#pragma unroll
+  for (int u = 0; u < K16; ++u) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float4 a = *reinterpret_cast<const float4*>(In + (rt * 16 + j) * IS + 16 * u + 4 * g);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[u].x, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[u].y, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[u].z, acc[rt], 0, 0, 0);
+      acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[u].w, acc[rt], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave has read In (Out may be the same buffer)
+  // D[i][j]: row 4 g + r of the tile, column j
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Out[(rt * 16 + 4 * g + r) * kHS + c0 + j] = relu(acc[rt][r]);
+  __syncthreads();
+}
+
+// Predictor MLPs: 32 pairs per workgroup; the 64 object rows come from the workspace.
+__global__ __launch_bounds__(kThreads) void mlp_kernel(PairArgs A) {
+  __shared__ MlpShared S;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int q0 = blockIdx.x * kTP;
+  const int n = A.n_pairs - q0 < kTP ? A.n_pairs - q0 : kTP;  // pairs of this workgroup
+  if (t < kTP) S.valid[t] = t < n ? A.valid[q0 + t] : 0;
+  for (int id = t; id < 2 * kTP * 8; id += kThreads) {  // 64 rows x 8 float4 (28 inputs, zero to 32)
+    const int row = id >> 3, c4 = id & 7;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < 2 * n && c4 < kIn / 4) v = *reinterpret_cast<const float4*>(A.z + ((size_t)q0 * 2 + row) * kIn + 4 * c4);
+    *reinterpret_cast<float4*>(&S.Z[row][4 * c4]) = v;
   }
   __syncthreads();
-
-  // per-object MLP on the 64 side rows, then the max over the two objects of each pair
-  const int o = t & (kHP - 1), grp = t / kHP;
-  constexpr int kR1 = 2 * kTP / kGroups, kR2 = kTP / kGroups;
-  layer<kR1, kIn, kIn>(&S.Z[0][0], &S.H[0][0], A.w.At[0], A.w.a[0], o, grp);
-  layer<kR1, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.At[1], A.w.a[1], o, grp);
-  layer<kR1, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.At[2], A.w.a[2], o, grp);
-  {
-    float mx[kR2];
+  const int c0 = 16 * wave;
+  const float* H = &S.H[0][0];
+  float* Hw = &S.H[0][0];
+  mfma_layer<4, kIn, 2, kZS>(&S.Z[0][0], Hw, A.w.A[0], A.w.a[0], c0, lane);
+  mfma_layer<4, kHP, kHP / 16, kHS>(H, Hw, A.w.A[1], A.w.a[1], c0, lane);
+  mfma_layer<4, kHP, kHP / 16, kHS>(H, Hw, A.w.A[2], A.w.a[2], c0, lane);
+  {  // max over the two objects of each pair: rows 2q, 2q + 1 -> row q
+    float mx[kTP * kHP / kThreads];
 #pragma unroll
-    for (int r = 0; r < kR2; ++r) {
-      const int q = grp * kR2 + r;
-      const float u = S.H[2 * q][o], v = S.H[2 * q + 1][o];
+    for (int r = 0; r < kTP * kHP / kThreads; ++r) {
+      const int id = t + r * kThreads, q = id / kHP, c = id % kHP;
+      const float u = S.H[2 * q][c], v = S.H[2 * q + 1][c];
       mx[r] = u > v ? u : v;
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kR2; ++r) S.H[grp * kR2 + r][o] = mx[r];
+    for (int r = 0; r < kTP * kHP / kThreads; ++r) {
+      const int id = t + r * kThreads;
+      S.H[id / kHP][id % kHP] = mx[r];
+    }
     __syncthreads();
   }
-  // pair MLP on the 32 pair rows
-  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[0], A.w.b[0], o, grp);
-  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[1], A.w.b[1], o, grp);
-  layer<kR2, kHP, kHP>(&S.H[0][0], &S.H[0][0], A.w.Bt[2], A.w.b[2], o, grp);
+  mfma_layer<2, kHP, kHP / 16, kHS>(H, Hw, A.w.Bw[0], A.w.b[0], c0, lane);
+  mfma_layer<2, kHP, kHP / 16, kHS>(H, Hw, A.w.Bw[1], A.w.b[1], c0, lane);
+  mfma_layer<2, kHP, kHP / 16, kHS>(H, Hw, A.w.Bw[2], A.w.b[2], c0, lane);
   // output layer and sigmoid: a wave per kTP / kWaves pairs
   const float w_lo = A.w.B4[lane], w_hi = A.w.B4[lane + 64], b4 = A.w.b[3][0];
 #pragma unroll
@@ -490,9 +515,8 @@ void transpose(const float* src, int rows, int cols, float* dst) {
     for (int c = 0; c < cols; ++c) dst[(size_t)c * rows + r] = src[(size_t)r * cols + c];
 }
 
-// Packed buffer: P2t, P3t, A1t, A2t, A3t, B1t, B2t, B3t.
-constexpr size_t kPackSizes[] = {kH * kH, kH * kH, (size_t)kIn * kHP, kHP * kHP, kHP * kHP,
-                                 kHP * kHP, kHP * kHP, kHP * kHP};
+// Packed buffer: P2t, P3t.
+constexpr size_t kPackSizes[] = {kH * kH, kH * kH};
 
 }  // namespace
 
@@ -509,13 +533,6 @@ void pack_transposed(const float* flat, float* dst) {
   transpose(flat + off[2], kH, kH, d);                 // P2
   d += kH * kH;
   transpose(flat + off[4], kH, kH, d);                 // P3
-  d += kH * kH;
-  transpose(flat + off[24], kHP, kIn, d);              // A1 [128][28]
-  d += (size_t)kIn * kHP;
-  for (int i : {26, 28, 30, 32, 34}) {                 // A2, A3, B1, B2, B3
-    transpose(flat + off[i], kHP, kHP, d);
-    d += kHP * kHP;
-  }
 }
 
 PackedNet packed_view(const float* raw, const float* packed) {
@@ -544,16 +561,9 @@ PackedNet packed_view(const float* raw, const float* packed) {
   w.P2t = d;
   d += kH * kH;
   w.P3t = d;
-  d += kH * kH;
-  w.At[0] = d;
-  d += (size_t)kIn * kHP;
-  w.At[1] = d;
-  d += kHP * kHP;
-  w.At[2] = d;
-  d += kHP * kHP;
   for (int i = 0; i < 3; ++i) {
-    w.Bt[i] = d;
-    d += kHP * kHP;
+    w.A[i] = raw + off[24 + 2 * i];
+    w.Bw[i] = raw + off[30 + 2 * i];
   }
   return w;
 }
@@ -622,9 +632,22 @@ hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes,
   return e;
 }
 
+size_t pair_workspace_bytes(int n_pairs) {
+  const size_t P = (size_t)n_pairs;
+  return ((P * 2 * kIn * sizeof(float) + 255) & ~size_t(255)) + P * sizeof(int32_t);
+}
+
+void pair_workspace_carve(void* base, int n_pairs, PairArgs& a) {
+  const size_t P = (size_t)n_pairs;
+  a.z = static_cast<float*>(base);
+  a.valid = reinterpret_cast<int32_t*>(static_cast<char*>(base) + ((P * 2 * kIn * sizeof(float) + 255) & ~size_t(255)));
+}
+
 hipError_t launch_pairs(const PairArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(pair_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(kThreads), 0, s, a);
+  if (!a.z || !a.valid) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(select_kernel, dim3(a.n_pairs), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(mlp_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

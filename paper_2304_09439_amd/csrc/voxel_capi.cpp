@@ -29,6 +29,9 @@ struct locc_voxel_ctx {
   double* d_consts = nullptr;   // [S][4] cell size and margin
   bool have_embeddings = false;
   unsigned long long* d_err = nullptr;
+  // predictor workspace (grown on demand)
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
 };
 
 namespace {
@@ -97,6 +100,7 @@ void locc_voxel_destroy(locc_voxel_ctx* c) {
   (void)hipFree(c->d_raw);
   (void)hipFree(c->d_packed);
   (void)hipFree(c->d_err);
+  (void)hipFree(c->d_ws);
   delete c;
 }
 
@@ -199,6 +203,15 @@ locc_status locc_voxel_detect(locc_voxel_ctx* c, const locc_object* objs, int32_
   a.counts = counts;
   a.pooled = pooled;
   a.err = c->d_err;
+  const size_t need = pair_workspace_bytes(n_pairs);
+  if (need > c->ws_bytes) {  // synchronous growth
+    if (c->d_ws) HIP_TRY(hipFree(c->d_ws));
+    c->d_ws = nullptr;
+    c->ws_bytes = 0;
+    HIP_TRY(hipMalloc(&c->d_ws, need + need / 4));
+    c->ws_bytes = need + need / 4;
+  }
+  pair_workspace_carve(c->d_ws, n_pairs, a);
   HIP_TRY(launch_pairs(a, static_cast<hipStream_t>(stream)));
   return LOCC_OK;
 }
