@@ -34,7 +34,9 @@ differentiation in this order:
 
 The crop selection is piecewise constant in the poses and contributes
 nothing; away from selection boundaries and argmax ties the result is the
-derivative of the logit.
+derivative of the logit.  At a tie every row attaining the maximum gives a
+valid one-sided derivative, so the argmax rows of the second object may be
+given (argmax_b) instead of taken as the first maximum.
 """
 
 from __future__ import annotations
@@ -68,12 +70,15 @@ def encoder_argmax(rows, W1, b1, W2):
     return s[r, np.arange(s.shape[1])], r
 
 
-def pair_gradient(g, pts_b, qa, pa, qb, pb, weights):
-    """G1-G6 for one canonical pair: (logit, dp_a, dq_a, dp_b, dq_b, r*_b)."""
+def pair_gradient(g, pts_b, qa, pa, qb, pb, weights, argmax_b=None):
+    """G1-G6 for one canonical pair: (logit, dp_a, dq_a, dp_b, dq_b, r*_b), r*_b the first maxima.
+    argmax_b: the second object's argmax rows to use instead (each must attain its channel's maximum
+    up to the caller's tolerance)."""
     W1, b1, W2, b2, H1, c1, H2, c2, H3, c3 = weights
     h2 = W2.shape[0]
     m_a, _ = encoder_argmax(g.rows_a, W1, b1, W2)
-    m_b, r_b = encoder_argmax(g.rows_b, W1, b1, W2)
+    m_b, first_b = encoder_argmax(g.rows_b, W1, b1, W2)
+    r_b = first_b if argmax_b is None or len(g.rows_b) == 0 else np.asarray(argmax_b, np.int64)
     f = np.concatenate([O.relu(m_a + b2), O.relu(m_b + b2)])       # -inf + b2 -> 0 for an empty crop
     u1 = f @ H1.T + c1
     u2 = O.relu(u1) @ H2.T + c2
@@ -101,27 +106,30 @@ def pair_gradient(g, pts_b, qa, pa, qb, pb, weights):
     dRa = Rb @ GR.T + np.outer(d, gt)
     dRb = Ra @ GR
     dp_b = Ra @ gt
-    return logit, -dp_b, rotation_grad(qa, dRa), dp_b, rotation_grad(qb, dRb), r_b
+    return logit, -dp_b, rotation_grad(qa, dRa), dp_b, rotation_grad(qb, dRb), first_b
 
 
-def pose_gradients(lib_pts, lib_offsets, pos, quat, shape, pairs, weights_flat, widths, K, pad=O.PAD_M):
-    """G1-G7 for every pair: dict(logit [P], grad [P, 14], argmax_b [P, h2] (canonical b))."""
+def pose_gradients(lib_pts, lib_offsets, pos, quat, shape, pairs, weights_flat, widths, K, pad=O.PAD_M,
+                   argmax_b=None):
+    """G1-G7 for every pair: dict(logit [P], grad [P, 14], first_argmax_b [P, h2] (the first maxima of the
+    canonical second object)).  argmax_b [P, h2], optional: that object's argmax rows to use per pair."""
     h1, h2, hh = widths
     weights = O.unpack_weights(weights_flat, h1, h2, hh)
     geoms, _, _ = O.crop(lib_pts, lib_offsets, pos, quat, shape, pairs, K, pad)
     P = len(pairs)
     logit = np.full(P, np.nan)
     grad = np.full((P, 14), np.nan)
-    argmax_b = np.full((P, h2), -1, np.int64)
+    first_argmax_b = np.full((P, h2), -1, np.int64)
     for p, g in enumerate(geoms):
         if g is None:
             continue
         sb = int(shape[g.b])
         pts_b = lib_pts[lib_offsets[sb]:lib_offsets[sb + 1]]
-        lg, dpa, dqa, dpb, dqb, rb = pair_gradient(g, pts_b, quat[g.a], pos[g.a], quat[g.b], pos[g.b], weights)
+        lg, dpa, dqa, dpb, dqb, rb = pair_gradient(g, pts_b, quat[g.a], pos[g.a], quat[g.b], pos[g.b], weights,
+                                                   None if argmax_b is None else argmax_b[p])
         logit[p] = lg
-        argmax_b[p] = rb
+        first_argmax_b[p] = rb
         first = np.concatenate([dpa, dqa])
         second = np.concatenate([dpb, dqb])
         grad[p] = np.concatenate([first, second]) if g.sgn > 0 else np.concatenate([second, first])
-    return dict(logit=logit, grad=grad, argmax_b=argmax_b, geoms=geoms)
+    return dict(logit=logit, grad=grad, first_argmax_b=first_argmax_b, geoms=geoms)
