@@ -275,6 +275,31 @@ LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs
 LOCC_API locc_status locc_graph_launch(locc_graph* graph, void* stream);
 LOCC_API void locc_graph_destroy(locc_graph* graph);
 
+/* Pose gradients of the collision logit (Sec. II, collision resolution with
+ * an object collision network: contact force and torque directions come from
+ * the gradient of the network's output with respect to the poses).  FP32
+ * contexts only.  Runs the crop and the FP32 encoder (recording per object
+ * and channel the row of the largest raw second-layer sum, the first on
+ * ties), the head backward and the encoder backward at those rows of the
+ * second object (the first object's rows are its own stored points and do
+ * not depend on the poses), then the chain rule through R_ab = R_a^T R_b,
+ * t_ab = R_a^T (p_b - p_a) and the rotation polynomial of the quaternion as
+ * given (not renormalised).  The crop selection is piecewise constant in
+ * the poses and contributes nothing.
+ *   d_grad  float32 [n_pairs][14], device, out: d logit / d (p (3), q (4)) of
+ *           the caller's first object, then of its second; NaN for an
+ *           invalid pair
+ *   d_out   [n_pairs] locc_contact (as locc_detect), or NULL
+ *   d_argmax_b  uint8 [n_pairs][enc_h2], or NULL: the argmax row (index in
+ *           the object's crop) of each channel of the canonical second
+ *           object (b = max(i, j)), 255 where it has no rows or the pair
+ *           is invalid; a parity hook for ties
+ * Asynchronous on `stream`; the workspace grows on demand (synchronous).
+ * Errors: INVALID_ARG, NOT_READY, UNSUPPORTED (not FP32), OOM, HIP. */
+LOCC_API locc_status locc_pose_gradients(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                         const int32_t* d_pairs, int32_t n_pairs, float* d_grad,
+                                         locc_contact* d_out, uint8_t* d_argmax_b, void* stream);
+
 /* Broad phase over environments (Sec. II, footnote on the broad phase:
  * pairs that are far apart are ruled out before the narrow phase; the
  * paper's simulations step many environments at once, and an object pairs

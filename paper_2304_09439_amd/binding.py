@@ -29,7 +29,7 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax", "locc_broad_phase",
            "locc_reserve_broad_phase", "locc_step_graph_capture", "locc_voxel_weight_count", "locc_voxel_create",
            "locc_voxel_destroy", "locc_voxel_upload_weights", "locc_voxel_upload_shapes", "locc_voxel_embeddings",
-           "locc_voxel_detect", "locc_voxel_device_errors")
+           "locc_voxel_detect", "locc_voxel_device_errors", "locc_pose_gradients")
 
 
 class Config(ctypes.Structure):
@@ -143,6 +143,8 @@ def load() -> ctypes.CDLL:
     L.locc_reserve_broad_phase.restype = ctypes.c_int
     L.locc_step_graph_capture.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, ctypes.POINTER(vp)]
     L.locc_step_graph_capture.restype = ctypes.c_int
+    L.locc_pose_gradients.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp]
+    L.locc_pose_gradients.restype = ctypes.c_int
     L.locc_voxel_weight_count.argtypes = []
     L.locc_voxel_weight_count.restype = ctypes.c_size_t
     L.locc_voxel_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
@@ -342,6 +344,21 @@ class Context:
         _check(load().locc_graph_capture(self._h, _ptr(objs), n_objs, _ptr(pairs), _ptr(n_dev), cap, _ptr(out),
                                          _ptr(counts), ctypes.byref(g)))
         return Graph(self, g, (objs, pairs, n_dev, out, counts))
+
+    def pose_gradients(self, objs, pairs, grad=None, out=None, stream=None, want_contacts=False,
+                       want_argmax=False):
+        """d logit / d (p, q) of both objects, float32 [P, 14] (caller order); optionally the contacts and
+        the second object's argmax rows uint8 [P, enc_h2]."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        if grad is None:
+            grad = torch.empty((P, 14), dtype=torch.float32, device=objs.device)
+        if out is None and want_contacts:
+            out = torch.empty((P, 8), dtype=torch.float32, device=objs.device)
+        amax = torch.empty((P, self.cfg.enc_h2), dtype=torch.uint8, device=objs.device) if want_argmax else None
+        _check(load().locc_pose_gradients(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(grad), _ptr(out),
+                                          _ptr(amax), self._stream(stream)))
+        return (grad, out, amax) if want_argmax else (grad, out)
 
     def broad_phase(self, objs, env_offsets, pairs, count, stream=None):
         """Overlapping pairs per environment into pairs (int32 [capacity, 2], device) and

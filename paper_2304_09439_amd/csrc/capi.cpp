@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "context.h"
+#include "grad.h"
 
 using namespace locc;
 
@@ -456,6 +457,7 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_wbf16);
   (void)hipFree(c->d_wfp8);
   (void)hipFree(c->d_wraw);
+  (void)hipFree(c->d_wgrad);
   (void)hipFree(c->d_amax);
   (void)hipFree(c->d_queue);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -490,6 +492,19 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   HIP_TRY(hipSetDevice(c->device));
   if (!c->d_wfp32) HIP_TRY(hipMalloc(&c->d_wfp32, pack.size() * sizeof(float)));
   HIP_TRY(hipMemcpy(c->d_wfp32, pack.data(), pack.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (c->cfg.precision == LOCC_FP32) {
+    // the pose gradients read the plain weights and the two head matrices transposed
+    std::vector<float> t((size_t)2 * h2 * hh + (size_t)hh * hh);
+    for (int o = 0; o < hh; ++o)
+      for (int k = 0; k < 2 * h2; ++k) t[(size_t)k * hh + o] = H1[(size_t)o * 2 * h2 + k];
+    float* t2 = t.data() + (size_t)2 * h2 * hh;
+    for (int o = 0; o < hh; ++o)
+      for (int k = 0; k < hh; ++k) t2[(size_t)k * hh + o] = H2[(size_t)o * hh + k];
+    if (!c->d_wraw) HIP_TRY(hipMalloc(&c->d_wraw, n * sizeof(float)));
+    if (!c->d_wgrad) HIP_TRY(hipMalloc(&c->d_wgrad, t.size() * sizeof(float)));
+    HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_wgrad, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
   if (c->cfg.precision == LOCC_BF16) {
     const Bf16Layout L = bf16_layout(h1, h2, hh);
     std::vector<unsigned char> bpack(L.total);
@@ -931,6 +946,77 @@ locc_status locc_autotune(locc_ctx* c, const locc_object* objs, int32_t n_objs, 
   c->sched = pick;
   *best = pick;
   if (best_ms) *best_ms = pick_ms;
+  return LOCC_OK;
+}
+
+locc_status locc_pose_gradients(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                                int32_t n_pairs, float* grad, locc_contact* out, uint8_t* argmax_b, void* stream) {
+  locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
+  if (st != LOCC_OK) return st;
+  if (c->cfg.precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "pose gradients need an FP32 context");
+  if (n_pairs > 0 && !grad) return fail(LOCC_ERR_INVALID_ARG, "null gradient output");
+  if (n_pairs == 0) return LOCC_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h, K = c->cfg.K;
+  const size_t P = (size_t)n_pairs;
+  const size_t base = workspace_bytes(c, n_pairs);
+  const size_t b_idx = align256(P * 2 * K * sizeof(int32_t)), b_amax = align256(P * 2 * h2);
+  st = ensure_workspace(c, base + b_idx + b_amax + align256(P * h2 * sizeof(float)));
+  if (st != LOCC_OK) return st;
+  Workspace w{};
+  st = carve(c, n_pairs, &w, nullptr);
+  if (st != LOCC_OK) return st;
+  char* extra = static_cast<char*>(c->d_ws) + base;
+  int32_t* idx = reinterpret_cast<int32_t*>(extra);
+  uint8_t* amax = reinterpret_cast<uint8_t*>(extra + b_idx);
+  float* dm = reinterpret_cast<float*>(extra + b_idx + b_amax);
+  CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), K, c->cfg.pad_m,
+              idx, nullptr, w.meta, w.rows, nullptr, c->d_err, w.setup};
+  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));
+  const Fp32Net net = fp32_view(c->d_wfp32, h1, h2, hh);
+  NetArgs na{w.rows, w.meta, objs, n_pairs, nullptr, K, w.z, nullptr, out, amax};
+  HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+  if (out) HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
+  GradArgs ga{};
+  ga.objs = objs;
+  ga.n_objs = n_objs;
+  ga.pairs = pairs;
+  ga.n_pairs = n_pairs;
+  ga.meta = w.meta;
+  ga.rows = w.rows;
+  ga.idx = idx;
+  ga.z = w.z;
+  ga.amax = amax;
+  ga.dm = dm;
+  ga.grad = grad;
+  ga.K = K;
+  ga.lib = c->lib();
+  ga.raw = c->d_wraw;
+  size_t o = 0;
+  ga.off.W1 = o;
+  o += (size_t)h1 * 6;
+  ga.off.b1 = o;
+  o += h1;
+  ga.off.W2 = o;
+  o += (size_t)h2 * h1;
+  ga.off.b2 = o;
+  o += h2;
+  ga.off.H1 = o;
+  o += (size_t)hh * 2 * h2;
+  ga.off.c1 = o;
+  o += hh;
+  ga.off.H2 = o;
+  o += (size_t)hh * hh;
+  ga.off.c2 = o;
+  o += hh;
+  ga.off.H3 = o;
+  o += (size_t)8 * hh;
+  ga.off.c3 = o;
+  ga.H1t = c->d_wgrad;
+  ga.H2t = c->d_wgrad + (size_t)2 * h2 * hh;
+  ga.argmax_b = argmax_b;
+  HIP_TRY(timed(c, "pose_grad", s, [&] { return launch_pose_gradients(ga, h1, h2, hh, s); }));
   return LOCC_OK;
 }
 

@@ -1,0 +1,38 @@
+// Internal declarations of the pose-gradient path (grad.hip).
+#pragma once
+
+#include "locc_internal.h"
+
+namespace locc {
+
+// Offsets (floats) of the arrays in the flat FP32 weight vector W1, b1, W2, b2, H1, c1, H2, c2, H3, c3.
+struct GradOffsets {
+  size_t W1, b1, W2, b2, H1, c1, H2, c2, H3, c3;
+};
+
+struct GradArgs {
+  const locc_object* objs;
+  int32_t n_objs;
+  const int32_t* pairs;
+  int32_t n_pairs;
+  const PairMeta* meta;   // [P] from the crop
+  const float* rows;      // [P][2K][8] FP32 encoder rows
+  const int32_t* idx;     // [P][2][K] stored point indices, caller order
+  const float* z;         // [P][2 h2] pooled features
+  const uint8_t* amax;    // [P][2][h2] argmax rows
+  float* dm;              // [P][h2] workspace: d logit / d (second object's raw maxima)
+  float* grad;            // [P][14] out
+  int32_t K;
+  DeviceLibrary lib;
+  const float* raw;       // flat FP32 weights (device)
+  GradOffsets off;
+  const float* H1t;       // [2 h2][hh]
+  const float* H2t;       // [hh][hh]
+  uint8_t* argmax_b;      // [P][h2] copy of the second object's argmax rows, or null
+};
+
+// Head backward (32 pairs per workgroup), then one workgroup per pair for the
+// encoder backward at the argmax rows and the chain to the poses.
+hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipStream_t s);
+
+}  // namespace locc

@@ -139,6 +139,7 @@ struct NetArgs {
   float* z;               // [P][2 h2] workspace (always written)
   float* y_dbg;           // [P][8] or null
   locc_contact* out;      // [P]
+  uint8_t* amax;          // [P][2][h2] row of the largest raw layer-2 sum per channel (first on ties), or null
 };
 
 hipError_t launch_encoder_fp32(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s);

@@ -45,7 +45,9 @@ __device__ __forceinline__ f32x16 mfma32x32x2(float a, float b, f32x16 c) {
 __host__ __device__ constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) + 4 * g + r % 4; }
 
 // -------------------------------------------------------------------- encoder
-template <int H1, int H2>
+// ARGMAX: also record, per object and channel, the row of the largest raw
+// sum (the first such row on ties), for the pose-gradient path.
+template <int H1, int H2, bool ARGMAX>
 __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs A) {
   constexpr int FT = H1 / 32;   // 32-feature tiles of layer 1
   constexpr int KS = H1 / 2;    // layer-2 k-steps
@@ -88,8 +90,12 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
       // max-pool of the raw sums, bias and ReLU once per column afterwards
       // (exact: rounding and ReLU are monotone; an empty set gives 0)
       float run[CT];
+      int arg[CT];
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
+      for (int ct = 0; ct < CT; ++ct) {
+        run[ct] = -__builtin_inff();
+        arg[ct] = 255;
+      }
       const float* rbase = A.rows + ((size_t)p * 2 * K + side * K) * kRowFloats;
       for (int r0 = 0; r0 < m; r0 += 32) {
         const float4 xv = *reinterpret_cast<const float4*>(rbase + (r0 + (lane & 31)) * kRowFloats + 4 * g);
@@ -112,7 +118,19 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h, w2f[ct][ft * 16 + r], acc2[ct]);
           }
-        if (r0 + 32 <= m) {
+        if (ARGMAX) {
+          // a lane's rows ascend with r, and blocks ascend with r0: strict > keeps the first maximum
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+              if (row < m && acc2[ct][r] > run[ct]) {
+                run[ct] = acc2[ct][r];
+                arg[ct] = row;
+              }
+            }
+        } else if (r0 + 32 <= m) {
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
@@ -129,8 +147,16 @@ __global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs
       }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
-        const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) + bias2[ct], 0.f);
+        const float other = __shfl_xor(run[ct], 32, 64);
+        const float f = fmaxf(fmaxf(run[ct], other) + bias2[ct], 0.f);
         if (lane < 32) zp[side * H2 + (wave * CT + ct) * 32 + lane] = f;
+        if (ARGMAX) {
+          // the two half-waves hold rows 4g + ... of every block: the larger value wins, the lower row on ties
+          const int other_arg = __shfl_xor(arg[ct], 32, 64);
+          const bool take = other > run[ct] || (other == run[ct] && other_arg < arg[ct]);
+          if (lane < 32)
+            A.amax[((size_t)p * 2 + side) * H2 + (wave * CT + ct) * 32 + lane] = (uint8_t)(take ? other_arg : arg[ct]);
+        }
       }
     }
   }
@@ -258,7 +284,10 @@ size_t head_smem_bytes() {
 template <int H1, int H2>
 hipError_t run_encoder(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s) {
   int grid = a.n_pairs < n_cu ? a.n_pairs : n_cu;
-  hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2>), dim3(grid), dim3(256), 0, s, w, a);
+  if (a.amax)
+    hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2, true>), dim3(grid), dim3(256), 0, s, w, a);
+  else
+    hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2, false>), dim3(grid), dim3(256), 0, s, w, a);
   return hipGetLastError();
 }
 
