@@ -485,6 +485,59 @@ def time_voxel(args, scene):
                      "and an MLP kernel (float32 MFMA, 32 pairs per workgroup, pair max, sigmoid)")
 
 
+def pose_grad_flops(widths):
+    """FLOPs per pair of the gradient kernels: the head forward recomputed and its backward to the second
+    object's pooled features (2 (2 h2 hh + hh^2 + hh^2 + hh h2)), and the encoder backward at the argmax
+    rows (2 h2 channels x h1 units x 12: layer-1 pre-activation and the W1^T product)."""
+    h1, h2, hh = widths.h1, widths.h2, widths.hh
+    return 2 * (2 * h2 * hh + hh * hh + hh * hh + hh * h2) + 2 * h2 * h1 * 12
+
+
+def time_pose_grad(args, scene, K, widths, w):
+    """d logit / d (p, q) of both objects of every pair (FP32 context): crop, FP32 encoder with argmax
+    rows, head backward, encoder backward at the argmax rows and the float64 chain to the poses."""
+    import numpy as np
+    import torch
+    from paper_2304_09439_amd import binding as B
+    wd = (widths.h1, widths.h2, widths.hh)
+    ctx = B.context_for_scene(scene, K, wd, w, precision="fp32")
+    objs, pairs = B.scene_tensors(scene)
+    P = scene.n_pairs
+    grad = torch.empty((P, 14), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        ctx.pose_gradients(objs, pairs, grad)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.pose_gradients(objs, pairs, grad)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    kt = ctx.profile_read()
+    n_bad = ctx.device_errors()
+    ctx.close()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    kernels = {name: dict(avg_ms=round(tot / max(n, 1), 4), launches=int(n)) for name, (n, tot) in sorted(kt.items())}
+    g = kernels.get("pose_grad")
+    if g:
+        achieved = pose_grad_flops(widths) * P / (g["avg_ms"] * 1e-3) / 1e12
+        g.update(bound="alu", achieved=round(achieved, 2), peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                 frac=round(achieved / PEAK_TFLOPS["fp32"], 4), flops_per_pair=pose_grad_flops(widths))
+    ms = 1000.0 * wall / args.steps
+    return dict(value=round(P / (ms * 1e-3), 1), unit="pair-gradients/s", ms_per_step=round(ms, 4),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
+                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4), kernels=kernels,
+                device_errors=int(n_bad),
+                path="FP32: crop (with index sets), encoder recording argmax rows, head backward (32 pairs per "
+                     "workgroup), encoder backward at the argmax rows and float64 chain to the poses")
+
+
 def envs_widths():
     from paper_2304_09439_amd import inputs as I
     wd = I.SCALE_WIDTHS
@@ -536,6 +589,8 @@ def run(args):
         line["speedup_vs_fp32_plain"] = round(main_path["value"] / paths["fp32"]["value"], 3)
     if not args.no_voxel:
         line["voxel_variant"] = time_voxel(args, scene)
+    if not args.no_pose_grad:
+        line["pose_gradients"] = time_pose_grad(args, scene, K, widths, w)
     if args.serve_requests > 0:
         line["serving"] = serve_bench(args, w)
     if args.env_steps > 0:
@@ -622,6 +677,7 @@ def main():
                     help="simulation steps of the uneven-environment workload to time (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-embedding variant's leg")
+    ap.add_argument("--no-pose-grad", action="store_true", help="skip the pose-gradient leg")
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default="encoder_fp32")

@@ -493,13 +493,16 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   if (!c->d_wfp32) HIP_TRY(hipMalloc(&c->d_wfp32, pack.size() * sizeof(float)));
   HIP_TRY(hipMemcpy(c->d_wfp32, pack.data(), pack.size() * sizeof(float), hipMemcpyHostToDevice));
   if (c->cfg.precision == LOCC_FP32) {
-    // the pose gradients read the plain weights and the two head matrices transposed
-    std::vector<float> t((size_t)2 * h2 * hh + (size_t)hh * hh);
+    // the pose gradients read the plain weights, the two head matrices transposed and W2 transposed
+    std::vector<float> t((size_t)2 * h2 * hh + (size_t)hh * hh + (size_t)h1 * h2);
     for (int o = 0; o < hh; ++o)
       for (int k = 0; k < 2 * h2; ++k) t[(size_t)k * hh + o] = H1[(size_t)o * 2 * h2 + k];
     float* t2 = t.data() + (size_t)2 * h2 * hh;
     for (int o = 0; o < hh; ++o)
       for (int k = 0; k < hh; ++k) t2[(size_t)k * hh + o] = H2[(size_t)o * hh + k];
+    float* t3 = t2 + (size_t)hh * hh;
+    for (int c = 0; c < h2; ++c)
+      for (int k = 0; k < h1; ++k) t3[(size_t)k * h2 + c] = W2[(size_t)c * h1 + k];
     if (!c->d_wraw) HIP_TRY(hipMalloc(&c->d_wraw, n * sizeof(float)));
     if (!c->d_wgrad) HIP_TRY(hipMalloc(&c->d_wgrad, t.size() * sizeof(float)));
     HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
@@ -1015,6 +1018,7 @@ locc_status locc_pose_gradients(locc_ctx* c, const locc_object* objs, int32_t n_
   ga.off.c3 = o;
   ga.H1t = c->d_wgrad;
   ga.H2t = c->d_wgrad + (size_t)2 * h2 * hh;
+  ga.W2t = ga.H2t + (size_t)hh * hh;
   ga.argmax_b = argmax_b;
   HIP_TRY(timed(c, "pose_grad", s, [&] { return launch_pose_gradients(ga, h1, h2, hh, s); }));
   return LOCC_OK;

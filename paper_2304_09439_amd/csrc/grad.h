@@ -28,6 +28,7 @@ struct GradArgs {
   GradOffsets off;
   const float* H1t;       // [2 h2][hh]
   const float* H2t;       // [hh][hh]
+  const float* W2t;       // [h1][h2]
   uint8_t* argmax_b;      // [P][h2] copy of the second object's argmax rows, or null
 };
 

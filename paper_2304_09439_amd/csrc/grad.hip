@@ -8,12 +8,14 @@
 //
 //   head_backward_kernel  32 pairs per workgroup: u1 = H1 f + c1, u2 = H2
 //     ReLU(u1) + c2, then du2 = H3[0] (u2 > 0), du1 = (H2^T du2) (u1 > 0), and
-//     for the second object's channels dm = (H1^T du1)[h2 + c] (f > 0); the
-//     pairs' activations stay in LDS, each thread owns output columns and
-//     reads the weights [in][out] (coalesced) with the rows as LDS broadcasts.
+//     for the second object's channels dm = (H1^T du1)[h2 + c] (f > 0): four
+//     products on 16x16x4 FP32 matrix cores, the pairs' activations in LDS,
+//     each wave owning a quarter of the output columns, the weight rows
+//     (row-major [out][in]: H1, H2, H2^T, H1^T) read from L2 as float4.
 //   pose_kernel  one workgroup per pair, one thread per channel c of the
 //     second object: at its argmax row r the layer-1 pre-activation is
-//     recomputed, dr = W1^T ((W2[c] dm[c]) (W1 r + b1 > 0)) gives the point
+//     recomputed (W1 in LDS), dr = W1^T ((W2[c] dm[c]) (W1 r + b1 > 0)) (W2
+//     read transposed, coalesced over c) gives the point
 //     and normal derivatives, and with the stored point p and normal n of
 //     that row dR_ab += dx p^T + dn n^T, dt_ab += dx; a block reduction, then
 //     one thread applies the chain rule through R_ab = R_a^T R_b, t_ab =
@@ -27,29 +29,35 @@ namespace {
 
 constexpr int kGT = 32;  // pairs per head-backward workgroup
 
-// acc[j][r] = sum_k In[r][k] Wt[k * N + col0 + 256 j + t] over K inputs (K a multiple of 4).
-template <int J, int K, int IS>
-__device__ __forceinline__ void rows_times(const float* In, const float* __restrict__ Wt, int N, int col0, int t,
-                                           float (&acc)[J][kGT]) {
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// acc[rt][ct] = In[32 rows][K] . W^T for this wave's columns c0 + 16 ct + (0..15), W row-major [out][K]
+// (ldw floats per row), with v_mfma_f32_16x16x4f32: A[i][k], B[k][j] with i, j = lane % 16 and the
+// reduction index permuted so that at k-step 4u + v lane group g = lane / 16 holds k = 16u + 4g + v,
+// which lets A (LDS rows) and B (weight rows) be read as float4.  D[i][j]: row 4g + r, column j.
+template <int CT, int K>
+__device__ __forceinline__ void mfma_rows32(const float* In, int IS, const float* __restrict__ W, int ldw, int c0,
+                                            int lane, f32x4 (&acc)[2][CT]) {
+  const int j = lane & 15, g = lane >> 4;
 #pragma unroll
-  for (int j = 0; j < J; ++j)
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int r = 0; r < kGT; ++r) acc[j][r] = 0.f;
-  for (int k = 0; k < K; k += 4) {
-    float w[J][4];
+    for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+  for (int u = 0; u < K / 16; ++u) {
+    float4 b[CT];
 #pragma unroll
-    for (int j = 0; j < J; ++j)
+    for (int ct = 0; ct < CT; ++ct)
+      b[ct] = *reinterpret_cast<const float4*>(W + (size_t)(c0 + 16 * ct + j) * ldw + 16 * u + 4 * g);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) w[j][q] = Wt[(size_t)(k + q) * N + col0 + 256 * j + t];
+    for (int rt = 0; rt < 2; ++rt) {
+      const float4 a = *reinterpret_cast<const float4*>(In + (16 * rt + j) * IS + 16 * u + 4 * g);
 #pragma unroll
-    for (int r = 0; r < kGT; ++r) {
-      const float4 v = *reinterpret_cast<const float4*>(In + r * IS + k);
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        acc[j][r] = fmaf(v.x, w[j][0], acc[j][r]);
-        acc[j][r] = fmaf(v.y, w[j][1], acc[j][r]);
-        acc[j][r] = fmaf(v.z, w[j][2], acc[j][r]);
-        acc[j][r] = fmaf(v.w, w[j][3], acc[j][r]);
+      for (int ct = 0; ct < CT; ++ct) {
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b[ct].x, acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b[ct].y, acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b[ct].z, acc[rt][ct], 0, 0, 0);
+        acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b[ct].w, acc[rt][ct], 0, 0, 0);
       }
     }
   }
@@ -58,13 +66,15 @@ __device__ __forceinline__ void rows_times(const float* In, const float* __restr
 template <int Z, int HH>
 __global__ __launch_bounds__(256) void head_backward_kernel(GradArgs A) {
   constexpr int H2 = Z / 2;
-  constexpr int J = HH / 256;  // output columns per thread for the HH-wide layers
-  constexpr int LA = (Z > HH ? Z : HH) + 4;
+  constexpr int CT = HH / 64;   // 16-column tiles per wave for the HH-wide products (4 waves)
+  constexpr int CT2 = H2 / 64;  // ... for the H2-wide one
+  constexpr int LA = (Z > HH ? Z : HH) + 4;  // +4: rows 16 B apart in the LDS banks
   constexpr int LB = HH + 4;
   extern __shared__ __align__(16) float smem[];
   float* As = smem;             // [32][LA]: f, later du2
   float* Bs = smem + kGT * LA;  // [32][LB]: ReLU(u1), later du1
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int j = lane & 15, g = lane >> 4;
   const int p0 = blockIdx.x * kGT;
   const int n = A.n_pairs - p0 < kGT ? A.n_pairs - p0 : kGT;
   for (int e = t; e < kGT * Z; e += 256) {
@@ -74,52 +84,72 @@ __global__ __launch_bounds__(256) void head_backward_kernel(GradArgs A) {
   }
   __syncthreads();
   const float* raw = A.raw;
-  const float* H1 = raw + A.off.H1;
+  const float* H1 = raw + A.off.H1;  // [hh][2 h2]
   const float* c1 = raw + A.off.c1;
-  const float* H2m = raw + A.off.H2;
+  const float* H2m = raw + A.off.H2;  // [hh][hh]
   const float* c2 = raw + A.off.c2;
   const float* h3 = raw + A.off.H3;  // row 0: the logit
-  float acc[J][kGT];
-  // u1 = f H1^T + c1 -> ReLU into B
-  rows_times<J, Z, LA>(As, A.H1t, HH, 0, t, acc);
+  const int c0 = wave * (HH / 4);
+  f32x4 acc[2][CT];
+  // u1 = f H1^T + c1 -> ReLU(u1) into B
+  mfma_rows32<CT, Z>(As, LA, H1, Z, c0, lane, acc);
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int o = 256 * j + t;
-    const float b = c1[o];
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
+    const float b = c1[col];
 #pragma unroll
-    for (int r = 0; r < kGT; ++r) {
-      const float u = acc[j][r] + b;
-      Bs[r * LB + o] = u > 0.f ? u : 0.f;
-    }
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float u = acc[rt][ct][r] + b;
+        Bs[(16 * rt + 4 * g + r) * LB + col] = u > 0.f ? u : 0.f;
+      }
   }
   __syncthreads();
   // u2 = ReLU(u1) H2^T + c2 -> du2 = H3[0] (u2 > 0) into A
-  rows_times<J, HH, LB>(Bs, A.H2t, HH, 0, t, acc);
+  mfma_rows32<CT, HH>(Bs, LB, H2m, HH, c0, lane, acc);
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int o = 256 * j + t;
-    const float b = c2[o], w3 = h3[o];
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
+    const float b = c2[col], w3 = h3[col];
 #pragma unroll
-    for (int r = 0; r < kGT; ++r) As[r * LA + o] = acc[j][r] + b > 0.f ? w3 : 0.f;
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) As[(16 * rt + 4 * g + r) * LA + col] = acc[rt][ct][r] + b > 0.f ? w3 : 0.f;
   }
   __syncthreads();
-  // du1 = (du2 H2) (u1 > 0) into B (each thread reads and writes only its own columns)
-  rows_times<J, HH, LA>(As, H2m, HH, 0, t, acc);
+  // du1 = (du2 H2) (u1 > 0) into B: the weight rows are H2's columns (H2^T row-major); each lane reads
+  // and rewrites only its own entries of B
+  mfma_rows32<CT, HH>(As, LA, A.H2t, HH, c0, lane, acc);
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int o = 256 * j + t;
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
 #pragma unroll
-    for (int r = 0; r < kGT; ++r) Bs[r * LB + o] = Bs[r * LB + o] > 0.f ? acc[j][r] : 0.f;
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float* e = Bs + (16 * rt + 4 * g + r) * LB + col;
+        *e = *e > 0.f ? acc[rt][ct][r] : 0.f;
+      }
   }
   __syncthreads();
-  // dm[c] = (du1 H1)[h2 + c] (f[h2 + c] > 0), second object's channels
-  if (t < H2) {
-    float a1[1][kGT];
-    rows_times<1, HH, LB>(Bs, H1, Z, H2, t, a1);
-    for (int r = 0; r < n; ++r) {
-      const float f = A.z[(size_t)(p0 + r) * Z + H2 + t];
-      A.dm[(size_t)(p0 + r) * H2 + t] = f > 0.f ? a1[0][r] : 0.f;
-    }
+  // dm[c] = (du1 H1)[h2 + c] (f[h2 + c] > 0): the weight rows are H1's columns h2 + c (H1^T rows)
+  f32x4 acc2[2][CT2];
+  const int d0 = wave * (H2 / 4);
+  mfma_rows32<CT2, HH>(Bs, LB, A.H1t + (size_t)H2 * HH, HH, d0, lane, acc2);
+#pragma unroll
+  for (int ct = 0; ct < CT2; ++ct) {
+    const int col = d0 + 16 * ct + j;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * g + r;
+        if (row < n) {
+          const float f = A.z[(size_t)(p0 + row) * Z + H2 + col];
+          A.dm[(size_t)(p0 + row) * H2 + col] = f > 0.f ? acc2[rt][ct][r] : 0.f;
+        }
+      }
   }
 }
 
@@ -151,8 +181,14 @@ __device__ __forceinline__ void rotation_grad(const float* qf, const double* G, 
 template <int H1, int H2>
 __global__ __launch_bounds__(256) void pose_kernel(GradArgs A) {
   __shared__ float red[4][12];
+  __shared__ float w1s[H1][8];  // W1 row and bias per hidden unit
   const int p = blockIdx.x, t = threadIdx.x;
   const PairMeta mt = A.meta[p];
+  for (int e = t; e < H1 * 7; e += 256) {
+    const int k = e / 7, q = e % 7;
+    w1s[k][q] = q < 6 ? A.raw[A.off.W1 + 6 * k + q] : A.raw[A.off.b1 + k];
+  }
+  __syncthreads();
   float v[12];
 #pragma unroll
   for (int q = 0; q < 12; ++q) v[q] = 0.f;
@@ -167,19 +203,15 @@ __global__ __launch_bounds__(256) void pose_kernel(GradArgs A) {
       const float* row = A.rows + ((size_t)p * 2 * A.K + A.K + r) * kRowFloats;
       const float4 lo = *reinterpret_cast<const float4*>(row), hi = *reinterpret_cast<const float4*>(row + 4);
       const float x[6] = {lo.x, hi.x, lo.y, hi.y, lo.z, hi.z};
-      const float* W1 = A.raw + A.off.W1;
-      const float* b1 = A.raw + A.off.b1;
-      const float* w2 = A.raw + A.off.W2 + (size_t)t * H1;
       float dr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
       for (int k = 0; k < H1; ++k) {
-        const float* wk = W1 + 6 * k;
+        const float* wk = w1s[k];
         const float pre = ((((wk[0] * x[0] + wk[1] * x[1]) + wk[2] * x[2]) + wk[3] * x[3]) + wk[4] * x[4]) +
-                          wk[5] * x[5] + b1[k];
-        if (pre > 0.f) {
-          const float d = w2[k] * dm;
+                          wk[5] * x[5] + wk[6];
+        const float d = pre > 0.f ? A.W2t[(size_t)k * H2 + t] * dm : 0.f;  // W2[c][k], coalesced over c
 #pragma unroll
-          for (int q = 0; q < 6; ++q) dr[q] = fmaf(wk[q], d, dr[q]);
-        }
+        for (int q = 0; q < 6; ++q) dr[q] = fmaf(wk[q], d, dr[q]);
       }
       // the stored point and normal of that row (b's own frame)
       const int cpos = 1 ^ mt.swapped;
