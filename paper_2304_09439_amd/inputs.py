@@ -317,6 +317,23 @@ def sphere_labels(scene: Scene, rows=None) -> dict:
 # workloads
 # ----------------------------------------------------------------------------
 
+def sphere_training_set(master: int = 5, n_shapes: int = 32, n_points: int = 1024, n_pairs: int = 4096,
+                        gap_std: float = 0.020):
+    """Labelled sphere pairs for fitting the network: shapes drawn with replacement from a library of
+    spheres (radii U[0.02, 0.08] m), centre distance r_a + r_b + g with g ~ N(0, gap_std) (the paper's
+    distance manipulation, Sec. III-A), uniform orientations, about half the pairs reversed.
+    Returns (Scene, labels float32 [n_pairs]: 1 where the spheres overlap, from the closed form)."""
+    g = streams(master)
+    lib = sphere_library(g[STREAM_SHAPES], n_shapes, n_points)
+    rng = g[STREAM_POSES]
+    sa = rng.integers(0, n_shapes, n_pairs).astype(np.int32)
+    sb = rng.integers(0, n_shapes, n_pairs).astype(np.int32)
+    ta, qa, tb, qb = sphere_pair_poses(rng, lib.radius[sa], lib.radius[sb], gap_std)
+    scene = _pack_pair_scene(lib, ta, qa, tb, qb, sa, sb, _interleave_pairs(rng, n_pairs))
+    return scene, sphere_labels(scene)["flag"].astype(np.float32)
+
+
+
 def small_workload(master: int = 0, n_points: int = 1024, n_nonconvex_pairs: int = 64, n_sphere_pairs: int = 16):
     """Plain, CPU-checkable case: 64 pairs of 3-ellipsoid unions + 16 sphere pairs.
 
