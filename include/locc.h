@@ -300,6 +300,38 @@ LOCC_API locc_status locc_pose_gradients(locc_ctx* ctx, const locc_object* d_obj
                                          const int32_t* d_pairs, int32_t n_pairs, float* d_grad,
                                          locc_contact* d_out, uint8_t* d_argmax_b, void* stream);
 
+/* One training step of an FP32 context on a labelled batch (Sec. III-A: the
+ * network is fitted to collision labels of pairs placed by distance
+ * manipulation, with binary cross-entropy plus alpha times the squared norm
+ * of the shape features, and Adam; the appendix gives alpha = 0.5, lr 1e-3,
+ * beta1 0.9, beta2 0.999, eps 1e-8).  Here the shape features are the two
+ * pooled crop features of a pair and only the logit output is trained:
+ *   loss = (1/B) sum_p [BCE(logit_p, y_p) + alpha ||[f_a, f_b]||^2],
+ * B = n_pairs (an invalid pair contributes nothing), then one Adam step on
+ * every weight (t counts the steps since the last locc_upload_weights).
+ * Runs the crop and the FP32 encoder (argmax rows), the head forward and
+ * backward, the weight gradients (every reduction in a fixed order: a step
+ * is reproducible bit for bit), Adam, and the repacking of the updated
+ * weights; later detect calls use them.
+ *   d_labels  float32 [n_pairs], device: 1 for a collision, 0 otherwise
+ *   d_loss    float32 [2], device, out: mean cross-entropy, alpha x mean
+ *             squared feature norm (of the weights before the step)
+ *   d_argmax  uint8 [n_pairs][2][enc_h2], device, or NULL: the argmax rows
+ *             used (canonical order; undefined for invalid pairs), a parity
+ *             hook for ties
+ * Asynchronous on `stream`; workspace and optimiser state grow on demand.
+ * Errors: INVALID_ARG (empty batch, null pointers, alpha < 0, lr <= 0, beta
+ * outside [0, 1), eps <= 0), NOT_READY, UNSUPPORTED (not FP32), OOM, HIP. */
+LOCC_API locc_status locc_train_step(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
+                                     const float* d_labels, int32_t n_pairs, float alpha, float lr, float beta1,
+                                     float beta2, float eps, float* d_loss, uint8_t* d_argmax, void* stream);
+
+/* Copies the FP32 context's flat weights (which = 0, in the locc_upload_weights
+ * order), the last step's gradient (1) or the Adam moments (2: first, 3:
+ * second) to host memory (n floats, synchronous).  Errors: INVALID_ARG,
+ * NOT_READY, UNSUPPORTED, HIP. */
+LOCC_API locc_status locc_get_weights(locc_ctx* ctx, int which, float* h_out, size_t n);
+
 /* Broad phase over environments (Sec. II, footnote on the broad phase:
  * pairs that are far apart are ruled out before the narrow phase; the
  * paper's simulations step many environments at once, and an object pairs

@@ -29,7 +29,8 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax", "locc_broad_phase",
            "locc_reserve_broad_phase", "locc_step_graph_capture", "locc_voxel_weight_count", "locc_voxel_create",
            "locc_voxel_destroy", "locc_voxel_upload_weights", "locc_voxel_upload_shapes", "locc_voxel_embeddings",
-           "locc_voxel_detect", "locc_voxel_device_errors", "locc_pose_gradients")
+           "locc_voxel_detect", "locc_voxel_device_errors", "locc_pose_gradients", "locc_train_step",
+           "locc_get_weights")
 
 
 class Config(ctypes.Structure):
@@ -143,6 +144,11 @@ def load() -> ctypes.CDLL:
     L.locc_reserve_broad_phase.restype = ctypes.c_int
     L.locc_step_graph_capture.argtypes = [vp, vp, i32, vp, i32, vp, i32, vp, vp, vp, ctypes.POINTER(vp)]
     L.locc_step_graph_capture.restype = ctypes.c_int
+    L.locc_train_step.argtypes = [vp, vp, i32, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, vp, vp, vp]
+    L.locc_train_step.restype = ctypes.c_int
+    L.locc_get_weights.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
+    L.locc_get_weights.restype = ctypes.c_int
     L.locc_pose_gradients.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp, vp]
     L.locc_pose_gradients.restype = ctypes.c_int
     L.locc_voxel_weight_count.argtypes = []
@@ -359,6 +365,29 @@ class Context:
         _check(load().locc_pose_gradients(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(grad), _ptr(out),
                                           _ptr(amax), self._stream(stream)))
         return (grad, out, amax) if want_argmax else (grad, out)
+
+    def train_step(self, objs, pairs, labels, alpha=0.5, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, loss=None,
+                   want_argmax=False, stream=None):
+        """One Adam step on a labelled batch (FP32 context).  labels: float32 [P] device tensor.
+        Returns the loss terms (float32 [2] device tensor: cross-entropy, alpha x feature norm) and
+        optionally the argmax rows uint8 [P, 2, enc_h2]."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        if loss is None:
+            loss = torch.empty(2, dtype=torch.float32, device=objs.device)
+        amax = torch.empty((P, 2, self.cfg.enc_h2), dtype=torch.uint8, device=objs.device) if want_argmax else None
+        _check(load().locc_train_step(self._h, _ptr(objs), n_objs, _ptr(pairs), _ptr(labels), P, alpha, lr, beta1,
+                                      beta2, eps, _ptr(loss), _ptr(amax), self._stream(stream)))
+        return (loss, amax) if want_argmax else loss
+
+    def get_weights(self, which: int = 0) -> np.ndarray:
+        """The flat FP32 weights (0), the last training gradient (1) or the Adam moments (2, 3), host copy."""
+        c = self.cfg
+        n = (c.enc_h1 * 6 + c.enc_h1 + c.enc_h2 * c.enc_h1 + c.enc_h2 + c.head_h * 2 * c.enc_h2 + c.head_h
+             + c.head_h * c.head_h + c.head_h + 8 * c.head_h + 8)
+        out = np.empty(n, np.float32)
+        _check(load().locc_get_weights(self._h, int(which), out.ctypes.data, n))
+        return out
 
     def broad_phase(self, objs, env_offsets, pairs, count, stream=None):
         """Overlapping pairs per environment into pairs (int32 [capacity, 2], device) and

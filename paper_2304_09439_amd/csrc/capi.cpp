@@ -458,6 +458,9 @@ void locc_destroy(locc_ctx* c) {
   (void)hipFree(c->d_wfp8);
   (void)hipFree(c->d_wraw);
   (void)hipFree(c->d_wgrad);
+  (void)hipFree(c->d_pack_idx);
+  (void)hipFree(c->d_tr_idx);
+  (void)hipFree(c->d_train);
   (void)hipFree(c->d_amax);
   (void)hipFree(c->d_queue);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -507,6 +510,32 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     if (!c->d_wgrad) HIP_TRY(hipMalloc(&c->d_wgrad, t.size() * sizeof(float)));
     HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_wgrad, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    // training: where each packed value comes from (the packing is positional, so packing the
+    // vector of indices + 1 gives the map; floats hold these integers exactly)
+    std::vector<float> ix(n);
+    for (size_t k = 0; k < n; ++k) ix[k] = (float)(k + 1);
+    const float* X = ix.data();
+    const float* xb1 = X + (b1 - W1);
+    std::vector<float> pk(pack.size());
+    fp32_pack(X, xb1, X + (W2 - W1), X + (b2 - W1), X + (H1 - W1), X + (c1 - W1), X + (H2 - W1),
+              X + (c2 - W1), X + (H3 - W1), X + (c3 - W1), h1, h2, hh, pk.data());
+    std::vector<int32_t> pidx(pk.size()), tidx(t.size());
+    for (size_t k = 0; k < pk.size(); ++k) pidx[k] = (int32_t)pk[k] - 1;
+    const size_t oH1 = (size_t)(H1 - W1), oH2 = (size_t)(H2 - W1), oW2 = (size_t)(W2 - W1);
+    for (int o = 0; o < hh; ++o)
+      for (int k = 0; k < 2 * h2; ++k) tidx[(size_t)k * hh + o] = (int32_t)(oH1 + (size_t)o * 2 * h2 + k);
+    int32_t* ti2 = tidx.data() + (size_t)2 * h2 * hh;
+    for (int o = 0; o < hh; ++o)
+      for (int k = 0; k < hh; ++k) ti2[(size_t)k * hh + o] = (int32_t)(oH2 + (size_t)o * hh + k);
+    int32_t* ti3 = ti2 + (size_t)hh * hh;
+    for (int cc = 0; cc < h2; ++cc)
+      for (int k = 0; k < h1; ++k) ti3[(size_t)k * h2 + cc] = (int32_t)(oW2 + (size_t)cc * h1 + k);
+    if (!c->d_pack_idx) HIP_TRY(hipMalloc(&c->d_pack_idx, pidx.size() * sizeof(int32_t)));
+    if (!c->d_tr_idx) HIP_TRY(hipMalloc(&c->d_tr_idx, tidx.size() * sizeof(int32_t)));
+    HIP_TRY(hipMemcpy(c->d_pack_idx, pidx.data(), pidx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_tr_idx, tidx.data(), tidx.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->train_t = 0;  // new weights start a new optimisation
+    if (c->d_train) HIP_TRY(hipMemset(c->d_train, 0, 3 * n * sizeof(float)));
   }
   if (c->cfg.precision == LOCC_BF16) {
     const Bf16Layout L = bf16_layout(h1, h2, hh);
@@ -1021,6 +1050,130 @@ locc_status locc_pose_gradients(locc_ctx* c, const locc_object* objs, int32_t n_
   ga.W2t = ga.H2t + (size_t)hh * hh;
   ga.argmax_b = argmax_b;
   HIP_TRY(timed(c, "pose_grad", s, [&] { return launch_pose_gradients(ga, h1, h2, hh, s); }));
+  return LOCC_OK;
+}
+
+locc_status locc_train_step(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
+                            const float* labels, int32_t n_pairs, float alpha, float lr, float beta1, float beta2,
+                            float eps, float* loss, uint8_t* argmax, void* stream) {
+  locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
+  if (st != LOCC_OK) return st;
+  if (c->cfg.precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "training needs an FP32 context");
+  if (n_pairs <= 0 || !labels || !loss) return fail(LOCC_ERR_INVALID_ARG, "empty batch, null labels or loss");
+  if (!(alpha >= 0.f) || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(LOCC_ERR_INVALID_ARG, "alpha >= 0, lr > 0, 0 <= beta < 1 and eps > 0 are required");
+  HIP_TRY(hipSetDevice(c->device));
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h, K = c->cfg.K;
+  const size_t n = weight_floats(h1, h2, hh);
+  if (!c->d_train) {
+    HIP_TRY(hipMalloc(&c->d_train, 3 * n * sizeof(float)));
+    HIP_TRY(hipMemset(c->d_train, 0, 3 * n * sizeof(float)));
+    c->train_t = 0;
+  }
+  const size_t P = (size_t)n_pairs;
+  const size_t base = workspace_bytes(c, n_pairs);
+  const size_t b_amax = align256(P * 2 * h2), b_act = align256(P * hh * sizeof(float));
+  const size_t b_dm = align256(P * 2 * h2 * sizeof(float)), b_p = align256(P * 3 * sizeof(float));
+  const size_t b_w1 = align256((size_t)h2 * h1 * 7 * sizeof(float));
+  st = ensure_workspace(c, base + b_amax + 4 * b_act + b_dm + b_p + b_w1);
+  if (st != LOCC_OK) return st;
+  Workspace w{};
+  st = carve(c, n_pairs, &w, nullptr);
+  if (st != LOCC_OK) return st;
+  char* e = static_cast<char*>(c->d_ws) + base;
+  uint8_t* amax = reinterpret_cast<uint8_t*>(e);
+  e += b_amax;
+  TrainArgs ta{};
+  float* act[4];
+  for (int k = 0; k < 4; ++k) {
+    act[k] = reinterpret_cast<float*>(e);
+    e += b_act;
+  }
+  ta.g1 = act[0];
+  ta.g2 = act[1];
+  ta.du2 = act[2];
+  ta.du1 = act[3];
+  ta.dmv = reinterpret_cast<float*>(e);
+  e += b_dm;
+  ta.dx = reinterpret_cast<float*>(e);
+  ta.lossp = ta.dx + P;
+  e += b_p;
+  ta.w1part = reinterpret_cast<float*>(e);
+  CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), K, c->cfg.pad_m,
+              nullptr, nullptr, w.meta, w.rows, nullptr, c->d_err, w.setup};
+  HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));
+  const Fp32Net net = fp32_view(c->d_wfp32, h1, h2, hh);
+  NetArgs na{w.rows, w.meta, objs, n_pairs, nullptr, K, w.z, nullptr, nullptr, amax};
+  HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+  ta.n_pairs = n_pairs;
+  ta.meta = w.meta;
+  ta.rows = w.rows;
+  ta.z = w.z;
+  ta.amax = amax;
+  ta.labels = labels;
+  ta.K = K;
+  ta.alpha = alpha;
+  ta.raw = c->d_wraw;
+  size_t o = 0;
+  ta.off.W1 = o;
+  o += (size_t)h1 * 6;
+  ta.off.b1 = o;
+  o += h1;
+  ta.off.W2 = o;
+  o += (size_t)h2 * h1;
+  ta.off.b2 = o;
+  o += h2;
+  ta.off.H1 = o;
+  o += (size_t)hh * 2 * h2;
+  ta.off.c1 = o;
+  o += hh;
+  ta.off.H2 = o;
+  o += (size_t)hh * hh;
+  ta.off.c2 = o;
+  o += hh;
+  ta.off.H3 = o;
+  o += (size_t)8 * hh;
+  ta.off.c3 = o;
+  ta.H1t = c->d_wgrad;
+  ta.H2t = c->d_wgrad + (size_t)2 * h2 * hh;
+  ta.grad = c->d_train;
+  ta.m = c->d_train + n;
+  ta.v = c->d_train + 2 * n;
+  ta.n = n;
+  const int64_t t_next = c->train_t + 1;
+  ta.lr = lr;
+  ta.beta1 = beta1;
+  ta.beta2 = beta2;
+  ta.eps = eps;
+  ta.corr1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)t_next)));
+  ta.corr2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)t_next)));
+  ta.loss = loss;
+  ta.pack_dst = c->d_wfp32;
+  ta.pack_idx = c->d_pack_idx;
+  ta.pack_n = fp32_pack_floats(h1, h2, hh);
+  ta.tr_dst = c->d_wgrad;
+  ta.tr_idx = c->d_tr_idx;
+  ta.tr_n = (size_t)2 * h2 * hh + (size_t)hh * hh + (size_t)h1 * h2;
+  if (argmax) HIP_TRY(hipMemcpyAsync(argmax, amax, P * 2 * h2, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(timed(c, "train", s, [&] { return launch_train_step(ta, h1, h2, hh, s); }));
+  c->train_t = t_next;
+  return LOCC_OK;
+}
+
+locc_status locc_get_weights(locc_ctx* c, int which, float* h_out, size_t n) {
+  if (!c || !h_out) return fail(LOCC_ERR_INVALID_ARG, "null context or output");
+  if (c->cfg.precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "FP32 contexts keep the flat weights");
+  if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
+  if (which < 0 || which > 3) return fail(LOCC_ERR_INVALID_ARG, "which=%d (0 weights, 1 gradient, 2-3 moments)", which);
+  if (which > 0 && !c->d_train) return fail(LOCC_ERR_NOT_READY, "no training step run yet");
+  const size_t want = weight_floats(c->cfg.enc_h1, c->cfg.enc_h2, c->cfg.head_h);
+  if (n != want) return fail(LOCC_ERR_INVALID_ARG, "weights: %zu floats asked, %zu held", n, want);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(hipDeviceSynchronize());
+  const float* src = which == 0 ? c->d_wraw : c->d_train + (size_t)(which - 1) * n;
+  HIP_TRY(hipMemcpy(h_out, src, n * sizeof(float), hipMemcpyDeviceToHost));
   return LOCC_OK;
 }
 

@@ -25,6 +25,12 @@ struct locc_ctx {
   unsigned char* d_wfp8 = nullptr;
   float* d_wraw = nullptr;         // FP8 and FP32: the flat FP32 weights (calibration, pose gradients)
   float* d_wgrad = nullptr;        // FP32: H1^T [2 h2][hh], H2^T [hh][hh], W2^T [h1][h2], for the pose gradients
+  // FP32 training: source index of every packed weight (d_wfp32, d_wgrad) in the flat vector (-1: zero),
+  // the gradient and the two Adam moments [3][n], and the step count
+  int32_t* d_pack_idx = nullptr;
+  int32_t* d_tr_idx = nullptr;
+  float* d_train = nullptr;
+  int64_t train_t = 0;
   std::vector<float> h_w1b1;       // FP8: W1 then b1 (host), repacked when the activation scale changes
   float fp8_wscale[3] = {1, 1, 1}; // FP8: s_w2, s_h1, s_h2
   float fp8_amax[3] = {0, 0, 0};   // FP8: activation maxima (layer-1 output, pooled z, head layer 1)

@@ -36,4 +36,43 @@ struct GradArgs {
 // encoder backward at the argmax rows and the chain to the poses.
 hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipStream_t s);
 
+// One training step of the FP32 network (crop and encoder already run, with
+// argmax rows): loss terms, weight gradients, Adam, and the repacking of the
+// updated weights into the layouts the kernels read.
+struct TrainArgs {
+  int32_t n_pairs;
+  const PairMeta* meta;   // [P]
+  const float* rows;      // [P][2K][8]
+  const float* z;         // [P][2 h2]
+  const uint8_t* amax;    // [P][2][h2]
+  const float* labels;    // [P] 0 / 1
+  int32_t K;
+  float alpha;            // feature-norm weight
+  float* raw;             // flat FP32 master weights (updated in place)
+  GradOffsets off;
+  const float* H1t;       // [2 h2][hh] (of the weights before the step)
+  const float* H2t;       // [hh][hh]
+  // workspace
+  float *g1, *g2, *du2, *du1;  // [P][hh]
+  float* dmv;             // [P][2 h2]
+  float* dx;              // [P]
+  float* lossp;           // [P][2]: cross-entropy, squared feature norm
+  float* w1part;          // [h2][h1][7]
+  // context state
+  float* grad;            // [n] flat, same layout as the weights
+  float *m, *v;           // Adam moments [n]
+  size_t n;
+  float lr, beta1, beta2, eps, corr1, corr2;  // corr = 1 / (1 - beta^t)
+  float* loss;            // [2] out: mean cross-entropy, alpha x mean squared feature norm
+  // repacking: dst[i] = src_idx[i] >= 0 ? raw[src_idx[i]] : 0
+  float* pack_dst;
+  const int32_t* pack_idx;
+  size_t pack_n;
+  float* tr_dst;          // H1^T, H2^T, W2^T
+  const int32_t* tr_idx;
+  size_t tr_n;
+};
+
+hipError_t launch_train_step(const TrainArgs& a, int h1, int h2, int hh, hipStream_t s);
+
 }  // namespace locc

@@ -296,3 +296,387 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 }
 
 }  // namespace locc
+
+// ------------------------------------------------------------------ training
+//
+// One step of fitting the FP32 network to collision labels (binary
+// cross-entropy of the logit plus alpha times the squared norm of the pooled
+// features, Adam): head_train_kernel (32 pairs per workgroup, the head
+// forward and backward on matrix cores, keeping per pair g1, g2, du2, du1,
+// the pooled features' gradient dm, dx and the two loss terms);
+// outer_sum_kernel / colsum_kernel reduce the head's weight gradients over
+// the pairs in a fixed order; enc_grad_kernel (one workgroup per channel)
+// walks every pair and object in order, staging 128 argmax rows at a time in
+// LDS, for dW2, db2 and per-channel partials of dW1, db1, which
+// w1_reduce_kernel sums; adam_kernel updates the master weights; two gathers
+// repack them into the layouts the forward and gradient kernels read.  Every
+// reduction has a fixed order, so a step is reproducible bit for bit.
+namespace locc {
+namespace {
+
+template <int Z, int HH>
+__global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB) {
+  constexpr int H2 = Z / 2;
+  constexpr int CT = HH / 64, CTZ = Z / 64;
+  constexpr int LA = (Z > HH ? Z : HH) + 4, LB = HH + 4;
+  extern __shared__ __align__(16) float smem[];
+  float* As = smem;
+  float* Bs = smem + kGT * LA;
+  __shared__ float dxs[kGT];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int p0 = blockIdx.x * kGT;
+  const int n = A.n_pairs - p0 < kGT ? A.n_pairs - p0 : kGT;
+  for (int e = t; e < kGT * Z; e += 256) {
+    const int r = e / Z, k = e % Z;
+    const float v = r < n ? A.z[(size_t)(p0 + r) * Z + k] : 0.f;
+    As[r * LA + k] = v == v ? v : 0.f;  // invalid pair: NaN features, no loss
+  }
+  __syncthreads();
+  const float* raw = A.raw;
+  const float* H1 = raw + A.off.H1;
+  const float* c1 = raw + A.off.c1;
+  const float* H2m = raw + A.off.H2;
+  const float* c2 = raw + A.off.c2;
+  const float* h3 = raw + A.off.H3;
+  // squared feature norm per pair (a wave per 8 pairs)
+  for (int q = 0; q < kGT / 4; ++q) {
+    const int r = wave * (kGT / 4) + q;
+    float s2 = 0.f;
+    for (int k = lane; k < Z; k += 64) s2 = fmaf(As[r * LA + k], As[r * LA + k], s2);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s2 += __shfl_xor(s2, d, 64);
+    if (lane == 0 && r < n) A.lossp[(size_t)(p0 + r) * 2 + 1] = A.meta[p0 + r].a >= 0 ? s2 : 0.f;
+  }
+  const int c0 = wave * (HH / 4);
+  f32x4 acc[2][CT];
+  // g1 = ReLU(f H1^T + c1) -> B
+  mfma_rows32<CT, Z>(As, LA, H1, Z, c0, lane, acc);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
+    const float b = c1[col];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * g + r;
+        const float u = acc[rt][ct][r] + b;
+        const float v = u > 0.f ? u : 0.f;
+        Bs[row * LB + col] = v;
+        if (row < n) A.g1[(size_t)(p0 + row) * HH + col] = v;
+      }
+  }
+  __syncthreads();
+  // g2 = ReLU(g1 H2^T + c2) -> A (f is no longer needed in LDS)
+  mfma_rows32<CT, HH>(Bs, LB, H2m, HH, c0, lane, acc);
+  __syncthreads();
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
+    const float b = c2[col];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * g + r;
+        const float u = acc[rt][ct][r] + b;
+        const float v = u > 0.f ? u : 0.f;
+        As[row * LA + col] = v;
+        if (row < n) A.g2[(size_t)(p0 + row) * HH + col] = v;
+      }
+  }
+  __syncthreads();
+  // logit, dx = (sigmoid(x) - y) / B and the cross-entropy (a wave per 8 pairs)
+  for (int q = 0; q < kGT / 4; ++q) {
+    const int r = wave * (kGT / 4) + q;
+    float x = 0.f;
+    for (int k = lane; k < HH; k += 64) x = fmaf(As[r * LA + k], h3[k], x);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    if (lane == 0) {
+      float dxv = 0.f;
+      if (r < n) {
+        float bce = 0.f;
+        if (A.meta[p0 + r].a >= 0) {
+          x += raw[A.off.c3];
+          const float y = A.labels[p0 + r];
+          dxv = (1.f / (1.f + expf(-x)) - y) * invB;
+          bce = fmaxf(x, 0.f) - x * y + log1pf(expf(-fabsf(x)));
+        }
+        A.dx[p0 + r] = dxv;
+        A.lossp[(size_t)(p0 + r) * 2] = bce;
+      }
+      dxs[r] = dxv;
+    }
+  }
+  __syncthreads();
+  // du2 = dx H3[0] (g2 > 0) -> A
+  for (int e = t; e < kGT * HH; e += 256) {
+    const int r = e / HH, col = e % HH;
+    const float v = As[r * LA + col] > 0.f ? dxs[r] * h3[col] : 0.f;
+    As[r * LA + col] = v;
+    if (r < n) A.du2[(size_t)(p0 + r) * HH + col] = v;
+  }
+  __syncthreads();
+  // du1 = (du2 H2) (g1 > 0) -> B
+  mfma_rows32<CT, HH>(As, LA, A.H2t, HH, c0, lane, acc);
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    const int col = c0 + 16 * ct + j;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * g + r;
+        float* e = Bs + row * LB + col;
+        const float v = *e > 0.f ? acc[rt][ct][r] : 0.f;
+        *e = v;
+        if (row < n) A.du1[(size_t)(p0 + row) * HH + col] = v;
+      }
+  }
+  __syncthreads();
+  // dz = du1 H1 + (2 alpha / B) f; dm = dz (f > 0), both objects
+  f32x4 accz[2][CTZ];
+  const int d0 = wave * (Z / 4);
+  mfma_rows32<CTZ, HH>(Bs, LB, A.H1t, HH, d0, lane, accz);
+  const float reg = 2.f * A.alpha * invB;
+#pragma unroll
+  for (int ct = 0; ct < CTZ; ++ct) {
+    const int col = d0 + 16 * ct + j;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * rt + 4 * g + r;
+        if (row < n) {
+          const float f = A.z[(size_t)(p0 + row) * Z + col];
+          A.dmv[(size_t)(p0 + row) * Z + col] = f > 0.f ? fmaf(reg, f, accz[rt][ct][r]) : 0.f;
+        }
+      }
+  }
+}
+
+// D[o][k] = sum_p X[p][o] Y[p][k] (NaN in Y read as 0), 64 x 64 outputs per workgroup, 4 x 4 per
+// thread, 16 pairs at a time through LDS; pairs in ascending order.
+__global__ __launch_bounds__(256) void outer_sum_kernel(const float* X, int ldx, int NO, const float* Y, int ldy,
+                                                        int NK, int P, float* D, int ldd) {
+  __shared__ float xs[16][64], ys[16][64];
+  const int t = threadIdx.x, to = t >> 4, tk = t & 15;
+  const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  float acc[4][4] = {};
+  for (int pb = 0; pb < P; pb += 16) {
+    for (int e = t; e < 16 * 64; e += 256) {
+      const int pp = e >> 6, c = e & 63, p = pb + pp;
+      float xv = 0.f, yv = 0.f;
+      if (p < P && o0 + c < NO) xv = X[(size_t)p * ldx + o0 + c];
+      if (p < P && k0 + c < NK) {
+        yv = Y[(size_t)p * ldy + k0 + c];
+        yv = yv == yv ? yv : 0.f;
+      }
+      xs[pp][c] = xv;
+      ys[pp][c] = yv;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int pp = 0; pp < 16; ++pp) {
+      float xv[4], yv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        xv[a] = xs[pp][4 * to + a];
+        yv[a] = ys[pp][4 * tk + a];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(xv[a], yv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int o = o0 + 4 * to + a, k = k0 + 4 * tk + b;
+      if (o < NO && k < NK) D[(size_t)o * ldd + k] = acc[a][b];
+    }
+}
+
+// out[o] = sum_p X[p][o], pairs in ascending order.
+__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int ldx, int NO, int P, float* out) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= NO) return;
+  float s = 0.f;
+  for (int p = 0; p < P; ++p) s += X[(size_t)p * ldx + o];
+  out[o] = s;
+}
+
+// One workgroup per channel c: dW2[c], db2[c] and the channel's partials of dW1 and db1.
+template <int H1, int H2>
+__global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
+  __shared__ float srow[128][6];
+  __shared__ float sdm[128];
+  const int c = blockIdx.x, t = threadIdx.x;
+  float wk[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bk = 0.f, w2ck = 0.f;
+  if (t < H1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) wk[q] = A.raw[A.off.W1 + 6 * t + q];
+    bk = A.raw[A.off.b1 + t];
+    w2ck = A.raw[A.off.W2 + (size_t)c * H1 + t];
+  }
+  float dw2 = 0.f, db2 = 0.f, dw1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, db1 = 0.f;
+  const int E = 2 * A.n_pairs;
+  for (int base = 0; base < E; base += 128) {
+    const int e = base + t;
+    float dm = 0.f, row[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (e < E) {
+      const int p = e >> 1, side = e & 1;
+      const PairMeta mt = A.meta[p];
+      if (mt.a >= 0 && (side ? mt.m_b : mt.m_a) > 0) {
+        dm = A.dmv[(size_t)p * 2 * H2 + side * H2 + c];
+        if (dm != 0.f) {
+          const int r = A.amax[((size_t)p * 2 + side) * H2 + c];
+          const float* rw = A.rows + ((size_t)p * 2 * A.K + side * A.K + r) * kRowFloats;
+          const float4 lo = *reinterpret_cast<const float4*>(rw), hi = *reinterpret_cast<const float4*>(rw + 4);
+          row[0] = lo.x;  // stored (x, z, ny, 1 | y, nx, nz, 0)
+          row[1] = hi.x;
+          row[2] = lo.y;
+          row[3] = hi.y;
+          row[4] = lo.z;
+          row[5] = hi.z;
+        }
+      }
+    }
+    sdm[t] = dm;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) srow[t][q] = row[q];
+    __syncthreads();
+    const int cnt = E - base < 128 ? E - base : 128;
+    for (int i = 0; i < cnt; ++i) {
+      const float d = sdm[i];
+      if (d == 0.f) continue;  // uniform
+      db2 += d;
+      const float* rr = srow[i];
+      const float pre = ((((wk[0] * rr[0] + wk[1] * rr[1]) + wk[2] * rr[2]) + wk[3] * rr[3]) + wk[4] * rr[4]) +
+                        wk[5] * rr[5] + bk;
+      if (pre > 0.f) {
+        dw2 = fmaf(d, pre, dw2);
+        const float dh = w2ck * d;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) dw1[q] = fmaf(dh, rr[q], dw1[q]);
+        db1 += dh;
+      }
+    }
+    __syncthreads();
+  }
+  if (t < H1) {
+    A.grad[A.off.W2 + (size_t)c * H1 + t] = dw2;
+    float* part = A.w1part + ((size_t)c * H1 + t) * 7;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) part[q] = dw1[q];
+    part[6] = db1;
+  }
+  if (t == 0) A.grad[A.off.b2 + c] = db2;
+}
+
+// dW1[k][q], db1[k]: the channels' partials summed in channel order.
+template <int H1, int H2>
+__global__ __launch_bounds__(256) void w1_reduce_kernel(TrainArgs A) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= H1 * 7) return;
+  const int k = id / 7, q = id % 7;
+  float s = 0.f;
+  for (int c = 0; c < H2; ++c) s += A.w1part[((size_t)c * H1 + k) * 7 + q];
+  if (q < 6)
+    A.grad[A.off.W1 + 6 * k + q] = s;
+  else
+    A.grad[A.off.b1 + k] = s;
+}
+
+// Mean loss terms, summed in a fixed order by one workgroup.
+__global__ __launch_bounds__(256) void loss_kernel(TrainArgs A, float invB) {
+  __shared__ float part[2][256];
+  const int t = threadIdx.x;
+  float s0 = 0.f, s1 = 0.f;
+  for (int p = t; p < A.n_pairs; p += 256) {
+    s0 += A.lossp[(size_t)p * 2];
+    s1 += A.lossp[(size_t)p * 2 + 1];
+  }
+  part[0][t] = s0;
+  part[1][t] = s1;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (t < w) {
+      part[0][t] += part[0][t + w];
+      part[1][t] += part[1][t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    A.loss[0] = part[0][0] * invB;
+    A.loss[1] = A.alpha * part[1][0] * invB;
+  }
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(TrainArgs A) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= A.n) return;
+  const float gr = A.grad[i];
+  const float m = A.beta1 * A.m[i] + (1.f - A.beta1) * gr;
+  const float v = A.beta2 * A.v[i] + (1.f - A.beta2) * gr * gr;
+  A.m[i] = m;
+  A.v[i] = v;
+  A.raw[i] -= A.lr * (m * A.corr1) / (sqrtf(v * A.corr2) + A.eps);
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(float* dst, const int32_t* idx, size_t n, const float* src) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k = idx[i];
+  dst[i] = k >= 0 ? src[k] : 0.f;
+}
+
+template <int H1, int H2, int HH>
+hipError_t run_train(const TrainArgs& a, hipStream_t s) {
+  constexpr int Z = 2 * H2;
+  const float invB = 1.f / (float)a.n_pairs;
+  hipError_t e = hipMemsetAsync(a.grad, 0, a.n * sizeof(float), s);
+  if (e != hipSuccess) return e;
+  const size_t smem = backward_smem<Z, HH>();
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_train_kernel<Z, HH>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+  if (e != hipSuccess) return e;
+  const int P = a.n_pairs;
+  hipLaunchKernelGGL((head_train_kernel<Z, HH>), dim3((P + kGT - 1) / kGT), dim3(256), smem, s, a, invB);
+  const GradOffsets& o = a.off;
+  // dH3[0], dc3[0]; dH2, dc2; dH1, dc1
+  hipLaunchKernelGGL(outer_sum_kernel, dim3((HH + 63) / 64, 1), dim3(256), 0, s, a.dx, 1, 1, a.g2, HH, HH, P,
+                     a.grad + o.H3, HH);
+  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, a.dx, 1, 1, P, a.grad + o.c3);
+  hipLaunchKernelGGL(outer_sum_kernel, dim3((HH + 63) / 64, (HH + 63) / 64), dim3(256), 0, s, a.du2, HH, HH, a.g1,
+                     HH, HH, P, a.grad + o.H2, HH);
+  hipLaunchKernelGGL(colsum_kernel, dim3((HH + 255) / 256), dim3(256), 0, s, a.du2, HH, HH, P, a.grad + o.c2);
+  hipLaunchKernelGGL(outer_sum_kernel, dim3((Z + 63) / 64, (HH + 63) / 64), dim3(256), 0, s, a.du1, HH, HH, a.z,
+                     Z, Z, P, a.grad + o.H1, Z);
+  hipLaunchKernelGGL(colsum_kernel, dim3((HH + 255) / 256), dim3(256), 0, s, a.du1, HH, HH, P, a.grad + o.c1);
+  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((w1_reduce_kernel<H1, H2>), dim3((H1 * 7 + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, a, invB);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
+                     a.pack_idx, a.pack_n, (const float*)a.raw);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.tr_n + 255) / 256)), dim3(256), 0, s, a.tr_dst, a.tr_idx,
+                     a.tr_n, (const float*)a.raw);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_train_step(const TrainArgs& a, int h1, int h2, int hh, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (h1 == 64 && h2 == 128 && hh == 256) return run_train<64, 128, 256>(a, s);
+  if (h1 == 128 && h2 == 256 && hh == 512) return run_train<128, 256, 512>(a, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace locc
