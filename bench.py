@@ -538,6 +538,65 @@ def time_pose_grad(args, scene, K, widths, w):
                      "workgroup), encoder backward at the argmax rows and float64 chain to the poses")
 
 
+def train_flops(widths):
+    """FLOPs per pair of the training kernels (the crop and the forward encoder are timed apart): the
+    head forward and backward (u1, u2, du1, dz), the head weight gradients (dH3[0], dH2, dH1) and the
+    encoder weight gradients at the argmax rows of both objects (14 multiply-adds per hidden unit)."""
+    h1, h2, hh = widths.h1, widths.h2, widths.hh
+    head = 2 * (2 * h2 * hh + hh * hh + hh * hh + hh * 2 * h2)
+    wgrad = 2 * (hh + hh * hh + hh * 2 * h2)
+    enc = 2 * (2 * h2 * h1 * 14)
+    return head + wgrad + enc
+
+
+def time_train(args):
+    """Training throughput of the FP32 network (64-128 / 256-256-256, K = 64) on 4096 labelled sphere
+    pairs per step: crop, encoder with argmax rows, then the training kernels (loss, gradients, Adam,
+    repacking)."""
+    import numpy as np
+    import torch
+    from paper_2304_09439_amd import binding as B
+    from paper_2304_09439_amd import inputs as I
+    wd = I.Widths(64, 128, 256)
+    sc, y = I.sphere_training_set(n_pairs=4096)
+    ctx = B.context_for_scene(sc, 64, (wd.h1, wd.h2, wd.hh), I.flatten_weights(I.gaussian_weights(wd, seed=1)),
+                              precision="fp32")
+    objs, pairs = B.scene_tensors(sc)
+    lab = torch.from_numpy(y).cuda()
+    loss = torch.empty(2, dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        ctx.train_step(objs, pairs, lab, loss=loss)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        ctx.train_step(objs, pairs, lab, loss=loss)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(False)
+    kt = ctx.profile_read()
+    last = loss.cpu().numpy().tolist()
+    ctx.close()
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    kernels = {name: dict(avg_ms=round(tot / max(n, 1), 4), launches=int(n)) for name, (n, tot) in sorted(kt.items())}
+    P = sc.n_pairs
+    t = kernels.get("train")
+    if t:
+        achieved = train_flops(wd) * P / (t["avg_ms"] * 1e-3) / 1e12
+        t.update(bound="alu", achieved=round(achieved, 2), peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
+                 frac=round(achieved / PEAK_TFLOPS["fp32"], 4), flops_per_pair=train_flops(wd))
+    ms = 1000.0 * wall / args.steps
+    return dict(value=round(P / (ms * 1e-3), 1), unit="training pairs/s", batch=P, ms_per_step=round(ms, 4),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4), kernels=kernels,
+                loss_after=last, path="FP32 training step: crop, encoder with argmax rows, head forward/backward "
+                                      "on matrix cores, fixed-order weight-gradient reductions, Adam, repacking")
+
+
 def envs_widths():
     from paper_2304_09439_amd import inputs as I
     wd = I.SCALE_WIDTHS
@@ -591,6 +650,8 @@ def run(args):
         line["voxel_variant"] = time_voxel(args, scene)
     if not args.no_pose_grad:
         line["pose_gradients"] = time_pose_grad(args, scene, K, widths, w)
+    if not args.no_train:
+        line["training"] = time_train(args)
     if args.serve_requests > 0:
         line["serving"] = serve_bench(args, w)
     if args.env_steps > 0:
@@ -678,6 +739,7 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=16384)
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-embedding variant's leg")
     ap.add_argument("--no-pose-grad", action="store_true", help="skip the pose-gradient leg")
+    ap.add_argument("--no-train", action="store_true", help="skip the training leg")
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--kernel", default="encoder_fp32")

@@ -1076,8 +1076,11 @@ locc_status locc_train_step(locc_ctx* c, const locc_object* objs, int32_t n_objs
   const size_t base = workspace_bytes(c, n_pairs);
   const size_t b_amax = align256(P * 2 * h2), b_act = align256(P * hh * sizeof(float));
   const size_t b_dm = align256(P * 2 * h2 * sizeof(float)), b_p = align256(P * 3 * sizeof(float));
-  const size_t b_w1 = align256((size_t)h2 * h1 * 7 * sizeof(float));
-  st = ensure_workspace(c, base + b_amax + 4 * b_act + b_dm + b_p + b_w1);
+  const size_t b_w1 = align256((size_t)kEncSplit * h2 * h1 * 7 * sizeof(float));
+  const size_t b_w2 = align256((size_t)kEncSplit * h2 * (h1 + 1) * sizeof(float));
+  const size_t nk = (size_t)(hh > 2 * h2 ? hh : 2 * h2) + 1;
+  const size_t b_op = align256((size_t)kOuterSplit * hh * nk * sizeof(float));
+  st = ensure_workspace(c, base + b_amax + 4 * b_act + b_dm + b_p + b_w1 + b_w2 + b_op);
   if (st != LOCC_OK) return st;
   Workspace w{};
   st = carve(c, n_pairs, &w, nullptr);
@@ -1101,6 +1104,10 @@ locc_status locc_train_step(locc_ctx* c, const locc_object* objs, int32_t n_objs
   ta.lossp = ta.dx + P;
   e += b_p;
   ta.w1part = reinterpret_cast<float*>(e);
+  e += b_w1;
+  ta.w2part = reinterpret_cast<float*>(e);
+  e += b_w2;
+  ta.opart = reinterpret_cast<float*>(e);
   CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), K, c->cfg.pad_m,
               nullptr, nullptr, w.meta, w.rows, nullptr, c->d_err, w.setup};
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));

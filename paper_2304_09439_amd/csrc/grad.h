@@ -39,6 +39,9 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 // One training step of the FP32 network (crop and encoder already run, with
 // argmax rows): loss terms, weight gradients, Adam, and the repacking of the
 // updated weights into the layouts the kernels read.
+constexpr int kEncSplit = 8;     // pair ranges of the encoder weight gradients
+constexpr int kOuterSplit = 16;  // pair ranges of the head weight gradients
+
 struct TrainArgs {
   int32_t n_pairs;
   const PairMeta* meta;   // [P]
@@ -57,7 +60,9 @@ struct TrainArgs {
   float* dmv;             // [P][2 h2]
   float* dx;              // [P]
   float* lossp;           // [P][2]: cross-entropy, squared feature norm
-  float* w1part;          // [h2][h1][7]
+  float* w1part;          // [kEncSplit][h2][h1][7]: per pair-range and channel partials of dW1, db1
+  float* w2part;          // [kEncSplit][h2][h1 + 1]: partials of dW2 and db2
+  float* opart;           // [kOuterSplit][hh][max(hh, 2 h2) + 1]: partial outer sums
   // context state
   float* grad;            // [n] flat, same layout as the weights
   float *m, *v;           // Adam moments [n]

@@ -304,11 +304,11 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 // features, Adam): head_train_kernel (32 pairs per workgroup, the head
 // forward and backward on matrix cores, keeping per pair g1, g2, du2, du1,
 // the pooled features' gradient dm, dx and the two loss terms);
-// outer_sum_kernel / colsum_kernel reduce the head's weight gradients over
-// the pairs in a fixed order; enc_grad_kernel (one workgroup per channel)
-// walks every pair and object in order, staging 128 argmax rows at a time in
-// LDS, for dW2, db2 and per-channel partials of dW1, db1, which
-// w1_reduce_kernel sums; adam_kernel updates the master weights; two gathers
+// outer_sum_kernel reduces the head's weight and bias gradients over 16
+// ranges of pairs and outer_reduce_kernel sums the ranges; enc_grad_kernel
+// (one workgroup per channel and range of pairs) walks its (pair, object)
+// entries in order, staging 128 argmax rows at a time in LDS, and
+// enc_reduce_kernel sums the partials of dW2, db2, dW1, db1; adam_kernel updates the master weights; two gathers
 // repack them into the layouts the forward and gradient kernels read.  Every
 // reduction has a fixed order, so a step is reproducible bit for bit.
 namespace locc {
@@ -457,21 +457,25 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
 }
 
-// D[o][k] = sum_p X[p][o] Y[p][k] (NaN in Y read as 0), 64 x 64 outputs per workgroup, 4 x 4 per
-// thread, 16 pairs at a time through LDS; pairs in ascending order.
+// Partial outer sums: part[z][o][k] = sum_{p in range z} X[p][o] Y[p][k] for k < NK, and column NK the
+// plain sum of X[p][o] (a column of ones in Y; the bias gradient).  NaN in Y is read as 0 (an invalid
+// pair's features; its X is 0).  64 x 64 outputs per workgroup, 4 x 4 per thread, 16 pairs at a time
+// through LDS, pairs in ascending order within the range.
 __global__ __launch_bounds__(256) void outer_sum_kernel(const float* X, int ldx, int NO, const float* Y, int ldy,
-                                                        int NK, int P, float* D, int ldd) {
+                                                        int NK, int P, float* part) {
   __shared__ float xs[16][64], ys[16][64];
   const int t = threadIdx.x, to = t >> 4, tk = t & 15;
-  const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64;
+  const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64, z = blockIdx.z;
+  const int chunk = (P + kOuterSplit - 1) / kOuterSplit;
+  const int pa = z * chunk, pe = pa + chunk < P ? pa + chunk : P;
   float acc[4][4] = {};
-  for (int pb = 0; pb < P; pb += 16) {
+  for (int pb = pa; pb < pe; pb += 16) {
     for (int e = t; e < 16 * 64; e += 256) {
       const int pp = e >> 6, c = e & 63, p = pb + pp;
       float xv = 0.f, yv = 0.f;
-      if (p < P && o0 + c < NO) xv = X[(size_t)p * ldx + o0 + c];
-      if (p < P && k0 + c < NK) {
-        yv = Y[(size_t)p * ldy + k0 + c];
+      if (p < pe && o0 + c < NO) xv = X[(size_t)p * ldx + o0 + c];
+      if (p < pe && k0 + c <= NK) {
+        yv = k0 + c < NK ? Y[(size_t)p * ldy + k0 + c] : 1.f;
         yv = yv == yv ? yv : 0.f;
       }
       xs[pp][c] = xv;
@@ -493,30 +497,38 @@ __global__ __launch_bounds__(256) void outer_sum_kernel(const float* X, int ldx,
     }
     __syncthreads();
   }
+  float* dst = part + (size_t)z * NO * (NK + 1);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int o = o0 + 4 * to + a, k = k0 + 4 * tk + b;
-      if (o < NO && k < NK) D[(size_t)o * ldd + k] = acc[a][b];
+      if (o < NO && k <= NK) dst[(size_t)o * (NK + 1) + k] = acc[a][b];
     }
 }
 
-// out[o] = sum_p X[p][o], pairs in ascending order.
-__global__ __launch_bounds__(256) void colsum_kernel(const float* X, int ldx, int NO, int P, float* out) {
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  if (o >= NO) return;
+// D[o][k] = sum_z part[z][o][k] (ranges in order); column NK goes to Dbias[o].
+__global__ __launch_bounds__(256) void outer_reduce_kernel(const float* part, int NO, int NK, float* D, int ldd,
+                                                           float* Dbias) {
+  const int id = blockIdx.x * 256 + threadIdx.x;
+  if (id >= NO * (NK + 1)) return;
+  const int o = id / (NK + 1), k = id % (NK + 1);
   float s = 0.f;
-  for (int p = 0; p < P; ++p) s += X[(size_t)p * ldx + o];
-  out[o] = s;
+  for (int z = 0; z < kOuterSplit; ++z) s += part[(size_t)z * NO * (NK + 1) + id];
+  if (k < NK)
+    D[(size_t)o * ldd + k] = s;
+  else
+    Dbias[o] = s;
 }
 
-// One workgroup per channel c: dW2[c], db2[c] and the channel's partials of dW1 and db1.
+// Encoder weight-gradient partials: workgroup (c, z) walks the (pair, object) entries of range z in
+// order, staging 128 argmax rows at a time in LDS, for channel c's dW2 row and db2 and its partials of
+// dW1, db1.
 template <int H1, int H2>
 __global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
   __shared__ float srow[128][6];
   __shared__ float sdm[128];
-  const int c = blockIdx.x, t = threadIdx.x;
+  const int c = blockIdx.x, z = blockIdx.y, t = threadIdx.x;
   float wk[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bk = 0.f, w2ck = 0.f;
   if (t < H1) {
 #pragma unroll
@@ -526,10 +538,12 @@ __global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
   }
   float dw2 = 0.f, db2 = 0.f, dw1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, db1 = 0.f;
   const int E = 2 * A.n_pairs;
-  for (int base = 0; base < E; base += 128) {
+  const int chunk = (E + kEncSplit - 1) / kEncSplit;
+  const int ea = z * chunk, ee = ea + chunk < E ? ea + chunk : E;
+  for (int base = ea; base < ee; base += 128) {
     const int e = base + t;
     float dm = 0.f, row[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (e < E) {
+    if (e < ee) {
       const int p = e >> 1, side = e & 1;
       const PairMeta mt = A.meta[p];
       if (mt.a >= 0 && (side ? mt.m_b : mt.m_a) > 0) {
@@ -551,7 +565,7 @@ __global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) srow[t][q] = row[q];
     __syncthreads();
-    const int cnt = E - base < 128 ? E - base : 128;
+    const int cnt = ee - base < 128 ? ee - base : 128;
     for (int i = 0; i < cnt; ++i) {
       const float d = sdm[i];
       if (d == 0.f) continue;  // uniform
@@ -569,24 +583,37 @@ __global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
     }
     __syncthreads();
   }
+  float* w2p = A.w2part + ((size_t)z * H2 + c) * (H1 + 1);
   if (t < H1) {
-    A.grad[A.off.W2 + (size_t)c * H1 + t] = dw2;
-    float* part = A.w1part + ((size_t)c * H1 + t) * 7;
+    w2p[t] = dw2;
+    float* part = A.w1part + (((size_t)z * H2 + c) * H1 + t) * 7;
 #pragma unroll
     for (int q = 0; q < 6; ++q) part[q] = dw1[q];
     part[6] = db1;
   }
-  if (t == 0) A.grad[A.off.b2 + c] = db2;
+  if (t == 0) w2p[H1] = db2;
 }
 
-// dW1[k][q], db1[k]: the channels' partials summed in channel order.
+// dW2, db2: ranges summed in order; dW1, db1: ranges and channels summed in order.
 template <int H1, int H2>
-__global__ __launch_bounds__(256) void w1_reduce_kernel(TrainArgs A) {
+__global__ __launch_bounds__(256) void enc_reduce_kernel(TrainArgs A) {
   const int id = blockIdx.x * 256 + threadIdx.x;
-  if (id >= H1 * 7) return;
-  const int k = id / 7, q = id % 7;
+  if (id < H2 * (H1 + 1)) {
+    float s = 0.f;
+    for (int z = 0; z < kEncSplit; ++z) s += A.w2part[(size_t)z * H2 * (H1 + 1) + id];
+    const int c = id / (H1 + 1), k = id % (H1 + 1);
+    if (k < H1)
+      A.grad[A.off.W2 + (size_t)c * H1 + k] = s;
+    else
+      A.grad[A.off.b2 + c] = s;
+    return;
+  }
+  const int jd = id - H2 * (H1 + 1);
+  if (jd >= H1 * 7) return;
+  const int k = jd / 7, q = jd % 7;
   float s = 0.f;
-  for (int c = 0; c < H2; ++c) s += A.w1part[((size_t)c * H1 + k) * 7 + q];
+  for (int z = 0; z < kEncSplit; ++z)
+    for (int c = 0; c < H2; ++c) s += A.w1part[(((size_t)z * H2 + c) * H1 + k) * 7 + q];
   if (q < 6)
     A.grad[A.off.W1 + 6 * k + q] = s;
   else
@@ -649,18 +676,18 @@ hipError_t run_train(const TrainArgs& a, hipStream_t s) {
   const int P = a.n_pairs;
   hipLaunchKernelGGL((head_train_kernel<Z, HH>), dim3((P + kGT - 1) / kGT), dim3(256), smem, s, a, invB);
   const GradOffsets& o = a.off;
-  // dH3[0], dc3[0]; dH2, dc2; dH1, dc1
-  hipLaunchKernelGGL(outer_sum_kernel, dim3((HH + 63) / 64, 1), dim3(256), 0, s, a.dx, 1, 1, a.g2, HH, HH, P,
-                     a.grad + o.H3, HH);
-  hipLaunchKernelGGL(colsum_kernel, dim3(1), dim3(256), 0, s, a.dx, 1, 1, P, a.grad + o.c3);
-  hipLaunchKernelGGL(outer_sum_kernel, dim3((HH + 63) / 64, (HH + 63) / 64), dim3(256), 0, s, a.du2, HH, HH, a.g1,
-                     HH, HH, P, a.grad + o.H2, HH);
-  hipLaunchKernelGGL(colsum_kernel, dim3((HH + 255) / 256), dim3(256), 0, s, a.du2, HH, HH, P, a.grad + o.c2);
-  hipLaunchKernelGGL(outer_sum_kernel, dim3((Z + 63) / 64, (HH + 63) / 64), dim3(256), 0, s, a.du1, HH, HH, a.z,
-                     Z, Z, P, a.grad + o.H1, Z);
-  hipLaunchKernelGGL(colsum_kernel, dim3((HH + 255) / 256), dim3(256), 0, s, a.du1, HH, HH, P, a.grad + o.c1);
-  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2), dim3(128), 0, s, a);
-  hipLaunchKernelGGL((w1_reduce_kernel<H1, H2>), dim3((H1 * 7 + 255) / 256), dim3(256), 0, s, a);
+  // dH3[0], dc3[0]; dH2, dc2; dH1, dc1: partial outer sums over pair ranges, then ordered reductions
+  auto outer = [&](const float* X, int ldx, int NO, const float* Y, int ldy, int NK, float* D, float* Db) {
+    hipLaunchKernelGGL(outer_sum_kernel, dim3((NK + 1 + 63) / 64, (NO + 63) / 64, kOuterSplit), dim3(256), 0, s, X,
+                       ldx, NO, Y, ldy, NK, P, a.opart);
+    hipLaunchKernelGGL(outer_reduce_kernel, dim3((NO * (NK + 1) + 255) / 256), dim3(256), 0, s,
+                       (const float*)a.opart, NO, NK, D, NK, Db);
+  };
+  outer(a.dx, 1, 1, a.g2, HH, HH, a.grad + o.H3, a.grad + o.c3);
+  outer(a.du2, HH, HH, a.g1, HH, HH, a.grad + o.H2, a.grad + o.c2);
+  outer(a.du1, HH, HH, a.z, Z, Z, a.grad + o.H1, a.grad + o.c1);
+  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(128), 0, s, a);
+  hipLaunchKernelGGL((enc_reduce_kernel<H1, H2>), dim3((H2 * (H1 + 1) + H1 * 7 + 255) / 256), dim3(256), 0, s, a);
   hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, a, invB);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
