@@ -16,9 +16,12 @@
 //   A[i][k]: i = l % 32, k = (K/2) (l / 32) + e;  B[k][j]: j = l % 32, same k;
 //   D[i][j]: j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4 for register r.
 // Encoder layer 1 is computed transposed (features x points), so each lane
-// holds 16 features of one point per 32-feature tile; those registers are
-// layer 2's A operand once layer 2's reduction index is permuted to
-// F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4 (the host packs W2 so).
+// holds 16 features of one point per 32-feature tile; in that order they are
+// 16-byte pieces of layer 2's A operand once layer 2's reduction index is
+// permuted to F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4 (the host packs W2
+// so).  With h1 = 128 each wave computes one feature tile of every 32-row
+// tile and shares it through a double-buffered LDS tile (one barrier per row
+// tile), instead of every wave computing all of layer 1.
 // Wave w owns h2/4 encoder output columns; its W2 slice (64 VGPRs at h2 =
 // 256) is loaded once and stays in registers for the whole kernel.
 //
@@ -80,10 +83,12 @@ struct Smem {
   static constexpr int T = kFusedTile;
   static constexpr int ZS = (2 * H2 > HH ? 2 * H2 : HH) + 8;  // row stride (bf16) of the z / g2 tile
   static constexpr int GS = HH + 8;                           // row stride of the g1 tile
+  static constexpr int HS = H1 + 8;                           // row stride of the layer-1 tiles
   union {
     struct {
       CropShared crop;
-      unsigned short rows[2 * kMaxK * 8];  // encoder rows (x, y, z, nx, ny, nz, 1, 0), bf16
+      alignas(16) unsigned short rows[2 * kMaxK * 8];  // encoder rows (x, y, z, nx, ny, nz, 1, 0), bf16
+      alignas(16) unsigned short h1t[2][T * HS];       // layer-1 output of a 32-row tile, [row][permuted feature]
     } c;
     unsigned short g[T * GS];
   } u;
@@ -181,6 +186,8 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
   using S_t = Smem<H1, H2, HH>;
   constexpr int T = S_t::T, ZS = S_t::ZS;
   constexpr int FT = H1 / 32;    // layer-1 feature tiles
+  constexpr int FW = (FT + 3) / 4;  // layer-1 feature tiles per wave (tiles wave, wave + 4, ...)
+  constexpr int HS = S_t::HS;
   constexpr int KS2 = H1 / 16;   // layer-2 k-steps
   constexpr int CT = H2 / 128;   // encoder column tiles per wave
   static_assert(H1 % 32 == 0 && H2 % 128 == 0 && HH % 128 == 0, "widths");
@@ -204,9 +211,10 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       w2f[ct][s] = reinterpret_cast<const u16x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
     bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
   }
-  s16x4 w1f[FT];
+  s16x4 w1f[FW];
 #pragma unroll
-  for (int ft = 0; ft < FT; ++ft) w1f[ft] = reinterpret_cast<const s16x4*>(A.w1p)[(size_t)ft * 64 + lane];
+  for (int i = 0; i < FW; ++i)
+    w1f[i] = wave + 4 * i < FT ? reinterpret_cast<const s16x4*>(A.w1p)[(size_t)(wave + 4 * i) * 64 + lane] : s16x4{};
 
   int slot = 0;
   for (int iter = 0;; ++iter) {
@@ -221,14 +229,15 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
     // split schedule: each thread carries the next pair's record and up to two
     // 16-byte encoder rows of it in registers, loaded while the current pair
     // computes
-    uint4 nxt[2];
+    // (two named registers rather than an array, which the compiler would
+    // move to LDS)
+    uint4 nxt0{}, nxt1{};
     PairMeta nmeta{};
+    const uint4* rows_g = reinterpret_cast<const uint4*>(A.rows_bf16);
     if constexpr (PRE) {
       nmeta = A.meta[base];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (tid + 256 * i < 2 * K)
-          nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)base * 2 * K + tid + 256 * i];
+      if (tid < 2 * K) nxt0 = rows_g[(size_t)base * 2 * K + tid];
+      if (tid + 256 < 2 * K) nxt1 = rows_g[(size_t)base * 2 * K + tid + 256];
     }
     for (int c = 0; c < n_claim; ++c) {
       const int p = base + c;
@@ -243,15 +252,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
         valid = a >= 0;
         m_a = valid ? mt.m_a : 0;
         m_b = valid ? mt.m_b : 0;
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          if (tid + 256 * i < 2 * K) reinterpret_cast<uint4*>(S.u.c.rows)[tid + 256 * i] = nxt[i];
+        if (tid < 2 * K) reinterpret_cast<uint4*>(S.u.c.rows)[tid] = nxt0;
+        if (tid + 256 < 2 * K) reinterpret_cast<uint4*>(S.u.c.rows)[tid + 256] = nxt1;
         if (c + 1 < n_claim) {  // the next pair's record and rows load while this pair computes
           nmeta = A.meta[p + 1];
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-            if (tid + 256 * i < 2 * K)
-              nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)(p + 1) * 2 * K + tid + 256 * i];
+          if (tid < 2 * K) nxt0 = rows_g[(size_t)(p + 1) * 2 * K + tid];
+          if (tid + 256 < 2 * K) nxt1 = rows_g[(size_t)(p + 1) * 2 * K + tid + 256];
         }
       } else {
       locc_object oa, ob;
@@ -306,34 +312,64 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       // column afterwards: fl(max_r a_r + b) = max_r fl(a_r + b) because
       // rounding is monotone, and ReLU is monotone (an empty set gives
       // max(-inf + b, 0) = 0)
+      // Row tiles t = 0, 1, ...: this wave's layer-1 features of tile t + 1
+      // are computed while layer 2 of tile t runs, then stored to the other
+      // LDS buffer; one barrier per tile publishes them (the buffer written in
+      // tile t was last read in tile t - 1, before the previous barrier).
       for (int side = 0; side < 2; ++side) {
         const int m = side ? m_b : m_a;
+        const int nt = (m + 31) >> 5;  // uniform over the workgroup
+        const unsigned short* xrow = &S.u.c.rows[(side * K + l32) * 8 + 4 * g];
         float run[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
-        for (int r0 = 0; r0 < m; r0 += 32) {
-          const s16x4 xb = *reinterpret_cast<const s16x4*>(&S.u.c.rows[(side * K + r0 + l32) * 8 + 4 * g]);
+        f32x16 acc1[FW];
+        // the input operand of the next row tile is read one tile ahead
+        s16x4 xb = *reinterpret_cast<const s16x4*>(xrow);
+        auto layer1_issue = [&](int t) {
+#pragma unroll
+          for (int i = 0; i < FW; ++i)
+            if (FT % 4 == 0 || wave + 4 * i < FT) acc1[i] = mfma_k8(w1f[i], xb, f32x16{});
+          if (t + 1 < nt) xb = *reinterpret_cast<const s16x4*>(xrow + (t + 1) * 32 * 8);
+        };
+        auto layer1_store = [&](int buf) {
+#pragma unroll
+          for (int i = 0; i < FW; ++i) {
+            const int ft = wave + 4 * i;
+            if (FT % 4 == 0 || ft < FT) {
+#pragma unroll
+              for (int hf = 0; hf < 2; ++hf) {
+                u32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] = bf16x2_relu(acc1[i][8 * hf + 2 * e], acc1[i][8 * hf + 2 * e + 1]);
+                *reinterpret_cast<u32x4*>(&S.u.c.h1t[buf][l32 * HS + 16 * (2 * ft + hf) + 8 * g]) = w;
+              }
+            }
+          }
+        };
+        if (nt > 0) {
+          layer1_issue(0);
+          layer1_store(0);
+        }
+        __syncthreads();
+        for (int t = 0; t < nt; ++t) {
+          const bool more = t + 1 < nt;
+          // all of this tile's layer-2 A fragments are requested before the
+          // first product
+          const unsigned short* h = &S.u.c.h1t[t & 1][l32 * HS + 8 * g];
+          u16x8 av[KS2];
+#pragma unroll
+          for (int s = 0; s < KS2; ++s) av[s] = *reinterpret_cast<const u16x8*>(h + 16 * s);
+          if (more) layer1_issue(t + 1);
           f32x16 acc2[CT];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
-          // layer-1 tiles one at a time (the next one issued a step ahead) keep
-          // only two 32x32 layer-1 accumulators live
-          f32x16 acc1 = mfma_k8(w1f[0], xb, f32x16{});
 #pragma unroll
-          for (int ft = 0; ft < FT; ++ft) {
-            f32x16 acc1n = acc1;
-            if (ft + 1 < FT) acc1n = mfma_k8(w1f[ft + 1 < FT ? ft + 1 : ft], xb, f32x16{});
+          for (int s = 0; s < KS2; ++s)
 #pragma unroll
-            for (int hf = 0; hf < 2; ++hf) {
-              u32x4 w;
-#pragma unroll
-              for (int e = 0; e < 4; ++e) w[e] = bf16x2_relu(acc1[8 * hf + 2 * e], acc1[8 * hf + 2 * e + 1]);
-              const u16x8 av = __builtin_bit_cast(u16x8, w);
-#pragma unroll
-              for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av, w2f[ct][2 * ft + hf], acc2[ct]);
-            }
-            acc1 = acc1n;
-          }
+            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av[s], w2f[ct][s], acc2[ct]);
+          if (more) layer1_store((t + 1) & 1);
+          const int r0 = 32 * t;
           if (r0 + 32 <= m) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
@@ -348,6 +384,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
                 if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
               }
           }
+          __syncthreads();
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {

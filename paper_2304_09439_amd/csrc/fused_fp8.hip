@@ -14,10 +14,13 @@
 // is applied once per output in the epilogue (before the bias).  The
 // encoder's max-pool runs on the raw sums: with a positive scale,
 // fl(fl(max_r a_r s) + b) = max_r fl(fl(a_r s) + b) (rounding is monotone).
-// As in the BF16 kernel, layer 1's output registers feed layer 2's A
-// operand directly; each 64-wide k-step takes two 32-feature tiles, and W2
-// is packed so that lane group g, byte e of k-step s is feature
-// F(2 s + e / 16, g, e % 16), F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4.
+// As in the BF16 kernel, each wave computes one 32-feature tile of layer 1
+// per 32-row tile and shares it through a double-buffered LDS tile; a lane's
+// 16 layer-1 outputs (one point, lane group g) are 16 bytes of layer 2's A
+// operand: each 64-wide k-step takes two 32-feature tiles, and W2 is packed
+// so that lane group g, byte e of k-step s is feature F(2 s + e / 16, g,
+// e % 16), F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4.  In the LDS tile a
+// row holds, per k-step s and lane group g, those 32 bytes contiguously.
 #include "fused.h"
 #include "geometry.h"
 #include "post.h"
@@ -64,8 +67,12 @@ struct Smem8 {
   static constexpr int ZB = 2 * H2 + 16;  // bytes per row of the fp8 z tile
   static constexpr int GB = HH + 16;      // bytes per row of the fp8 g1 tile
   static constexpr int G2 = HH + 8;       // bf16 elements per row of the g2 tile
+  static constexpr int HB = H1 + 16;      // bytes per row of the fp8 layer-1 tiles
   union alignas(16) {
-    unsigned short rows[2 * kMaxK * 8];   // encoder rows of the current pair (bf16)
+    struct {
+      alignas(16) unsigned short rows[2 * kMaxK * 8];  // encoder rows of the current pair (bf16)
+      alignas(16) unsigned char h1t[2][T * HB];        // layer-1 output of a 32-row tile (e4m3)
+    } e;
     unsigned short g2[T * G2];            // head layer-2 output (bf16)
   } u;
   alignas(16) unsigned char z[T * ZB];
@@ -166,7 +173,9 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
   using S_t = Smem8<H1, H2, HH>;
   constexpr int T = S_t::T, ZB = S_t::ZB;
   constexpr int FT = H1 / 32;    // layer-1 feature tiles
+  constexpr int FW = (FT + 3) / 4;  // layer-1 feature tiles per wave (tiles wave, wave + 4, ...)
   constexpr int KS2 = H1 / 64;   // layer-2 fp8 k-steps (two feature tiles each)
+  constexpr int HB = S_t::HB;
   constexpr int CT = H2 / 128;   // encoder column tiles per wave
   static_assert(H1 % 64 == 0 && H2 % 128 == 0 && HH % 128 == 0, "widths");
   __shared__ S_t S;
@@ -184,9 +193,10 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
       w2f[ct][s] = reinterpret_cast<const i32x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
     bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
   }
-  s16x4 w1f[FT];
+  s16x4 w1f[FW];
 #pragma unroll
-  for (int ft = 0; ft < FT; ++ft) w1f[ft] = reinterpret_cast<const s16x4*>(A.w1p)[(size_t)ft * 64 + lane];
+  for (int i = 0; i < FW; ++i)
+    w1f[i] = wave + 4 * i < FT ? reinterpret_cast<const s16x4*>(A.w1p)[(size_t)(wave + 4 * i) * 64 + lane] : s16x4{};
 
   int slot = 0;
   for (int iter = 0;; ++iter) {
@@ -197,26 +207,25 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
     __syncthreads();
     if (base >= P) break;
     const int n_claim = P - base < A.claim ? P - base : A.claim;
-    // the next pair's record and rows are carried in registers, loaded while the current pair computes
-    uint4 nxt[2];
+    // the next pair's record and rows are carried in registers (two named
+    // registers: an array would be moved to LDS), loaded while the current
+    // pair computes
+    const uint4* rows_g = reinterpret_cast<const uint4*>(A.rows_bf16);
+    uint4 nxt0{}, nxt1{};
     PairMeta nmeta = A.meta[base];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      if (tid + 256 * i < 2 * K) nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)base * 2 * K + tid + 256 * i];
+    if (tid < 2 * K) nxt0 = rows_g[(size_t)base * 2 * K + tid];
+    if (tid + 256 < 2 * K) nxt1 = rows_g[(size_t)base * 2 * K + tid + 256];
     for (int c = 0; c < n_claim; ++c) {
       const int p = base + c;
       const PairMeta mt = nmeta;
       const bool valid = mt.a >= 0;
       const int m_a = valid ? mt.m_a : 0, m_b = valid ? mt.m_b : 0;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (tid + 256 * i < 2 * K) reinterpret_cast<uint4*>(S.u.rows)[tid + 256 * i] = nxt[i];
+      if (tid < 2 * K) reinterpret_cast<uint4*>(S.u.e.rows)[tid] = nxt0;
+      if (tid + 256 < 2 * K) reinterpret_cast<uint4*>(S.u.e.rows)[tid + 256] = nxt1;
       if (c + 1 < n_claim) {
         nmeta = A.meta[p + 1];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          if (tid + 256 * i < 2 * K)
-            nxt[i] = reinterpret_cast<const uint4*>(A.rows_bf16)[(size_t)(p + 1) * 2 * K + tid + 256 * i];
+        if (tid < 2 * K) nxt0 = rows_g[(size_t)(p + 1) * 2 * K + tid];
+        if (tid + 256 < 2 * K) nxt1 = rows_g[(size_t)(p + 1) * 2 * K + tid + 256];
       }
       if (tid == 0) {
         S.pair[slot] = p;
@@ -224,29 +233,69 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
         S.swapped[slot] = mt.swapped;
       }
       __syncthreads();
+      // Row tiles t = 0, 1, ...: this wave's layer-1 features of tile t + 1
+      // are computed while layer 2 of tile t runs, then stored to the other
+      // LDS buffer; one barrier per tile publishes them (the buffer written in
+      // tile t was last read in tile t - 1, before the previous barrier).
       for (int side = 0; side < 2; ++side) {
         const int m = side ? m_b : m_a;
+        const int nt = (m + 31) >> 5;  // uniform over the workgroup
+        const unsigned short* xrow = &S.u.e.rows[(side * K + l32) * 8 + 4 * g];
         float run[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
-        for (int r0 = 0; r0 < m; r0 += 32) {
-          const s16x4 xb = *reinterpret_cast<const s16x4*>(&S.u.rows[(side * K + r0 + l32) * 8 + 4 * g]);
+        f32x16 acc1[FW];
+        // the input operand of the next row tile is read one tile ahead
+        s16x4 xb = *reinterpret_cast<const s16x4*>(xrow);
+        auto layer1_issue = [&](int t) {
+#pragma unroll
+          for (int i = 0; i < FW; ++i)
+            if (FT % 4 == 0 || wave + 4 * i < FT) acc1[i] = mfma_k8(w1f[i], xb, f32x16{});
+          if (t + 1 < nt) xb = *reinterpret_cast<const s16x4*>(xrow + (t + 1) * 32 * 8);
+        };
+        auto layer1_store = [&](int buf) {
+#pragma unroll
+          for (int i = 0; i < FW; ++i) {
+            const int ft = wave + 4 * i;
+            if (FT % 4 == 0 || ft < FT) {
+              uint4 q;
+              q.x = pack4_e4m3(acc1[i][0], acc1[i][1], acc1[i][2], acc1[i][3]);
+              q.y = pack4_e4m3(acc1[i][4], acc1[i][5], acc1[i][6], acc1[i][7]);
+              q.z = pack4_e4m3(acc1[i][8], acc1[i][9], acc1[i][10], acc1[i][11]);
+              q.w = pack4_e4m3(acc1[i][12], acc1[i][13], acc1[i][14], acc1[i][15]);
+              *reinterpret_cast<uint4*>(&S.u.e.h1t[buf][l32 * HB + 64 * (ft >> 1) + 32 * g + 16 * (ft & 1)]) = q;
+            }
+          }
+        };
+        if (nt > 0) {
+          layer1_issue(0);
+          layer1_store(0);
+        }
+        __syncthreads();
+        for (int t = 0; t < nt; ++t) {
+          const bool more = t + 1 < nt;
+          const unsigned char* h = &S.u.e.h1t[t & 1][l32 * HB + 32 * g];
+          i32x8 av[KS2];
+#pragma unroll
+          for (int s = 0; s < KS2; ++s) {
+            const uint4 a0 = *reinterpret_cast<const uint4*>(h + 64 * s);
+            const uint4 a1 = *reinterpret_cast<const uint4*>(h + 64 * s + 16);
+            av[s] = i32x8{(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+          }
+          if (more) layer1_issue(t + 1);
           f32x16 acc2[CT];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
 #pragma unroll
-          for (int s = 0; s < KS2; ++s) {
-            const f32x16 lo = mfma_k8(w1f[2 * s], xb, f32x16{});
-            const f32x16 hi = mfma_k8(w1f[2 * s + 1], xb, f32x16{});
-            i32x8 av;
+          for (int s = 0; s < KS2; ++s)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              av[q] = pack4_e4m3(lo[4 * q], lo[4 * q + 1], lo[4 * q + 2], lo[4 * q + 3]);
-              av[4 + q] = pack4_e4m3(hi[4 * q], hi[4 * q + 1], hi[4 * q + 2], hi[4 * q + 3]);
-            }
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_f8(av, w2f[ct][s], acc2[ct]);
-          }
+            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_f8(av[s], w2f[ct][s], acc2[ct]);
+          // stored unconditionally (after the last tile into the buffer no
+          // wave reads again before the next write), so that the compiler
+          // keeps it behind the layer-2 products instead of merging it with
+          // the conditional layer-1 issue ahead of them
+          layer1_store((t + 1) & 1);
+          const int r0 = 32 * t;
           if (r0 + 32 <= m) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
@@ -261,6 +310,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
                 if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
               }
           }
+          __syncthreads();
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
