@@ -11,6 +11,7 @@ namespace locc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kCropWaves = 2;  // object waves per workgroup of the crop kernel (1, 2, 4, 8 measured: 2 fastest)
 
 __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
   const int p = blockIdx.x * kThreads + threadIdx.x;
@@ -33,21 +34,36 @@ __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
   *reinterpret_cast<PairSetup*>(static_cast<char*>(A.setup) + (size_t)p * kPairSetupBytes) = r;
 }
 
-// One wave per object of a pair: workgroup 2p + side scans, selects and
+// One wave per object of a pair: wave item = 2p + side scans, selects and
 // gathers object `side` of pair p on its own (no barrier; the two objects of
 // a pair never wait for each other), so many more pairs are in flight per
-// compute unit than with a workgroup per pair.
+// compute unit than with a workgroup per pair.  W independent waves share a
+// workgroup (each with its own LDS), so that the compute unit's limit on
+// resident workgroups does not cap the resident waves.
 struct ObjectShared {
   unsigned long long mask[kMaxBlocks];  // one ballot per 64 stored points
   int32_t sel[kMaxK];
 };
 
-template <int U>
-__global__ __launch_bounds__(64) void crop_kernel(CropArgs A) {
-  __shared__ ObjectShared S;
-  const int p = blockIdx.x >> 1;
-  const int side = blockIdx.x & 1;
-  const int lane = threadIdx.x;
+// LDS written by some lanes of a wave and then read by others of the same
+// wave: the wave's LDS operations are performed in order, so it suffices that
+// the compiler keeps them in order and waits for the writes (workgroup-scope
+// fences); no other wave takes part.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int U, int W>
+__global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
+  __shared__ ObjectShared SW[W];
+  const int wave = W == 1 ? 0 : wave_index();
+  ObjectShared& S = SW[wave];
+  const int item = blockIdx.x * W + wave;
+  const int p = item >> 1;
+  const int side = item & 1;
+  const int lane = threadIdx.x & 63;
   const int K = A.K;
   if (p >= pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base)) return;  // uniform
 
@@ -108,7 +124,7 @@ __global__ __launch_bounds__(64) void crop_kernel(CropArgs A) {
     scanned = scanned + U < nblk ? scanned + U : nblk;
   }
   // found: every member when full, else at least min(K, members)
-  __syncthreads();  // the ballots (written by lane 0) are read by every lane
+  wave_lds_sync();  // the ballots (written by lane 0) are read by every lane
 
   // ordered first-K selection: block per lane (chunks of 64 blocks), the
   // exclusive prefix of the popcounts is each block's first position; block
@@ -134,7 +150,7 @@ __global__ __launch_bounds__(64) void crop_kernel(CropArgs A) {
     }
     carry += __shfl(incl, 63, 64);
   }
-  __syncthreads();  // the selected indices are read by other lanes
+  wave_lds_sync();  // the selected indices are read by other lanes
   const int m = found < K ? found : K;
   const int caller = side ^ swapped;  // position of this object in the caller's pair
   if (lane == 0) {
@@ -197,10 +213,12 @@ hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll) {
   if (a.n_pairs <= 0) return hipSuccess;
   if (!a.setup || (unroll != 2 && unroll != 4 && unroll != 8)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pair_setup_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  constexpr int W = kCropWaves;
+  const dim3 grid((2 * a.n_pairs + W - 1) / W), block(64 * W);
   switch (unroll) {
-    case 2: hipLaunchKernelGGL(crop_kernel<2>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(crop_kernel<4>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(crop_kernel<8>, dim3(2 * a.n_pairs), dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((crop_kernel<2, W>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((crop_kernel<4, W>), grid, block, 0, s, a); break;
+    case 8: hipLaunchKernelGGL((crop_kernel<8, W>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

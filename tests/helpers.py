@@ -107,3 +107,51 @@ def flag_agreement(logit_out, logit_ref, band: float = 0.0):
     if not keep.any():
         return 1.0
     return float(np.mean((logit_out[keep] > 0) == (logit_ref[keep] > 0)))
+
+
+
+def first_object_empty(pairs: np.ndarray, counts: np.ndarray) -> np.ndarray:
+    """Rows of pairs whose first object in canonical order (the lower index) selects no point while
+    the second selects some; counts are in the caller's order."""
+    i, j = pairs[:, 0], pairs[:, 1]
+    first = np.where(i < j, counts[:, 0], counts[:, 1])
+    second = np.where(i < j, counts[:, 1], counts[:, 0])
+    return np.flatnonzero((first == 0) & (second > 0))
+
+
+def with_first_object_empty(base: "I.Scene", n: int, every: int = 16, seed: int = 11):
+    """base plus n pairs whose first object in canonical order selects nothing: a sphere of radius
+    0.5 (the lower object index) and a sphere of radius 0.03 centred at (0.4, 0.4, 0.4) in the large
+    sphere's frame.  The crop box (the small sphere's box, padded, inside the large sphere's box)
+    lies at distance > 0.5 from the large sphere's centre, so it holds every point of the small
+    sphere and none of the large one's surface.  Random common orientations; every other pair is
+    given in reversed order.  The new pairs are placed at every `every`-th position among base's.
+    Returns (Scene, rows of the new pairs)."""
+    rng = np.random.default_rng(seed)
+    n_pts = int(base.lib.offsets[1] - base.lib.offsets[0])
+    sph = I.sphere_library(rng, 2, n_pts, radii=[0.5, 0.03])
+    lib = I.ShapeLibrary.concat([base.lib, sph])
+    big, small = base.lib.n_shapes, base.lib.n_shapes + 1
+    q = I.uniform_quaternions(rng, n).astype(np.float64)
+    w, v = q[:, :1], q[:, 1:]
+    c = np.array([0.4, 0.4, 0.4])
+    # R(q) c = c + 2 w (v x c) + 2 v x (v x c)
+    vc = np.cross(v, c)
+    off = c + 2 * w * vc + 2 * np.cross(v, vc)
+    pa = rng.uniform(-5, 5, (n, 3))
+    n0 = base.n_objects
+    pos = np.concatenate([base.pos, np.repeat(pa, 2, 0).astype(np.float32)])
+    pos[n0 + 1::2] = (pa + off).astype(np.float32)
+    quat = np.concatenate([base.quat, np.repeat(q, 2, 0).astype(np.float32)])
+    shape = np.concatenate([base.shape, np.tile([big, small], n).astype(np.int32)])
+    new = np.stack([n0 + 2 * np.arange(n), n0 + 2 * np.arange(n) + 1], 1).astype(np.int32)
+    new[1::2] = new[1::2, ::-1]
+    P = base.n_pairs + n
+    rows = np.arange(n) * every
+    assert rows[-1] < P
+    pairs = np.empty((P, 2), np.int32)
+    mask = np.zeros(P, bool)
+    mask[rows] = True
+    pairs[mask] = new
+    pairs[~mask] = base.pairs[:P - n]
+    return I.Scene(lib, pos, quat, shape, pairs), rows

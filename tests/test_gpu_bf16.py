@@ -17,7 +17,7 @@ from oracle import locc_oracle as O
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
 
-from helpers import field_errors, flag_agreement, normwise_errors
+from helpers import field_errors, first_object_empty, flag_agreement, normwise_errors, with_first_object_empty
 
 pytestmark = pytest.mark.gpu
 
@@ -198,3 +198,34 @@ def test_contacts_are_the_same_with_and_without_counts(torch, scale_scene, preci
         torch.cuda.synchronize()
         assert torch.equal(fused, fused_c)
     ctx.close()
+
+
+@pytest.fixture(scope="module")
+def one_sided_scene(scale_scene):
+    return with_first_object_empty(scale_scene, 256)
+
+
+@pytest.mark.parametrize("split", [True, False])
+def test_bf16_first_object_empty(torch, one_sided_scene, split):
+    """A pair whose first object (canonical order) selects nothing starts its row tiles with the second
+    object's rows.  Its contacts must be the same alone as in the full batch, whatever other pairs left
+    in the row buffers and in LDS, and a sample must match the oracle."""
+    sc, rows = one_sided_scene
+    w = _weights(LW)
+    sched = dict(wg_per_cu=2, claim=4, dynamic=True, split=split)
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision="bf16")
+    ctx.set_schedule(**sched)
+    objs, pairs = B.scene_tensors(sc)
+    full, counts = ctx.detect(objs, pairs)
+    found = first_object_empty(sc.pairs, counts.cpu().numpy())
+    say(f"bf16 split={split}: {len(found)} pairs whose first object selects nothing")
+    assert set(rows) <= set(found)
+    alone, _ = ctx.detect(objs, torch.from_numpy(sc.pairs[found]).cuda())
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(alone.cpu().numpy(), full.cpu().numpy()[found])
+    ctx.close()
+    sample = rows[::8]
+    out, counts, z, y, n_bad = _forward(torch, sc.subset(sample), 128, SCALE, w, sched)
+    assert n_bad == 0
+    ref = O.detect_scene(sc, w, SCALE, 128, rows=sample)
+    _check(out, counts, z, y, ref, "first object empty")

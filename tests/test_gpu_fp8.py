@@ -32,7 +32,7 @@ from oracle import quant_model as Q
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
 
-from helpers import field_errors, flag_agreement, normwise_errors
+from helpers import field_errors, first_object_empty, flag_agreement, normwise_errors, with_first_object_empty
 
 pytestmark = pytest.mark.gpu
 
@@ -216,4 +216,25 @@ def test_fp8_results_do_not_depend_on_the_schedule_or_graph(torch, scale_case):
         np.testing.assert_array_equal(out[:n].cpu().numpy(), ref.cpu().numpy())
         assert torch.all(out[n:] == 7.0)
     g.close()
+    ctx.close()
+
+
+def test_fp8_first_object_empty(torch, scale_case):
+    """A pair whose first object (canonical order) selects nothing starts its row tiles with the second
+    object's rows: its contacts must be the same alone as in the full batch, whatever other pairs left
+    in the row buffers and in LDS."""
+    c = scale_case
+    sc, rows = with_first_object_empty(c["full"], 256)
+    ctx = B.context_for_scene(sc, 128, SCALE, c["w"], precision="fp8")
+    ctx.set_activation_amax(c["amax"])
+    objs, pairs = B.scene_tensors(sc)
+    full, counts = ctx.detect(objs, pairs)
+    found = first_object_empty(sc.pairs, counts.cpu().numpy())
+    say(f"fp8: {len(found)} pairs whose first object selects nothing")
+    assert set(rows) <= set(found)
+    for sched in (dict(wg_per_cu=2, claim=4, dynamic=True), dict(wg_per_cu=1, claim=16, dynamic=False)):
+        ctx.set_schedule(**sched)
+        alone, _ = ctx.detect(objs, torch.from_numpy(sc.pairs[found]).cuda())
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(alone.cpu().numpy(), full.cpu().numpy()[found])
     ctx.close()
