@@ -39,8 +39,8 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 // One training step of the FP32 network (crop and encoder already run, with
 // argmax rows): loss terms, weight gradients, Adam, and the repacking of the
 // updated weights into the layouts the kernels read.
-constexpr int kEncSplit = 8;     // pair ranges of the encoder weight gradients
-constexpr int kOuterSplit = 16;  // pair ranges of the head weight gradients
+constexpr int kEncSplit = 16;    // pair ranges of the encoder weight gradients
+constexpr int kOuterSplit = 64;  // pair ranges of the head weight gradients
 
 struct TrainArgs {
   int32_t n_pairs;

@@ -304,11 +304,12 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 // features, Adam): head_train_kernel (32 pairs per workgroup, the head
 // forward and backward on matrix cores, keeping per pair g1, g2, du2, du1,
 // the pooled features' gradient dm, dx and the two loss terms);
-// outer_sum_kernel reduces the head's weight and bias gradients over 16
-// ranges of pairs and outer_reduce_kernel sums the ranges; enc_grad_kernel
-// (one workgroup per channel and range of pairs) walks its (pair, object)
-// entries in order, staging 128 argmax rows at a time in LDS, and
-// enc_reduce_kernel sums the partials of dW2, db2, dW1, db1; adam_kernel updates the master weights; two gathers
+// outer_sum_kernel reduces the head's weight and bias gradients over 64
+// ranges of pairs on matrix cores and outer_reduce_kernel sums the ranges;
+// enc_grad_kernel (one workgroup per channel and range of pairs) walks its
+// (pair, object) entries in order, staging 256 argmax rows at a time in LDS,
+// and the enc_reduce kernels sum the partials of dW2, db2, dW1, db1;
+// adam_kernel updates the master weights; two gathers
 // repack them into the layouts the forward and gradient kernels read.  Every
 // reduction has a fixed order, so a step is reproducible bit for bit.
 namespace locc {
@@ -459,52 +460,58 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
 
 // Partial outer sums: part[z][o][k] = sum_{p in range z} X[p][o] Y[p][k] for k < NK, and column NK the
 // plain sum of X[p][o] (a column of ones in Y; the bias gradient).  NaN in Y is read as 0 (an invalid
-// pair's features; its X is 0).  64 x 64 outputs per workgroup, 4 x 4 per thread, 16 pairs at a time
-// through LDS, pairs in ascending order within the range.
+// pair's features; its X is 0).  A 64 x 64 output tile per workgroup, one 32 x 32 quarter per wave on
+// v_mfma_f32_32x32x2f32 (A[i][q] = X[p + q][o0 + i], B[q][j] = Y[p + q][k0 + j]: lanes 0-31 carry pair
+// p, lanes 32-63 pair p + 1); 32 pairs at a time through LDS, in ascending order within the range.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 __global__ __launch_bounds__(256) void outer_sum_kernel(const float* X, int ldx, int NO, const float* Y, int ldy,
                                                         int NK, int P, float* part) {
-  __shared__ float xs[16][64], ys[16][64];
-  const int t = threadIdx.x, to = t >> 4, tk = t & 15;
+  constexpr int PS = 32;        // pairs per stage
+  constexpr int PT = PS / 4;    // stage rows loaded per thread (one column each of X and Y)
+  __shared__ float xs[PS][64], ys[PS][64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wo = wave >> 1, wk = wave & 1, l32 = lane & 31, half = lane >> 5;
   const int o0 = blockIdx.y * 64, k0 = blockIdx.x * 64, z = blockIdx.z;
   const int chunk = (P + kOuterSplit - 1) / kOuterSplit;
   const int pa = z * chunk, pe = pa + chunk < P ? pa + chunk : P;
-  float acc[4][4] = {};
-  for (int pb = pa; pb < pe; pb += 16) {
-    for (int e = t; e < 16 * 64; e += 256) {
-      const int pp = e >> 6, c = e & 63, p = pb + pp;
-      float xv = 0.f, yv = 0.f;
-      if (p < pe && o0 + c < NO) xv = X[(size_t)p * ldx + o0 + c];
-      if (p < pe && k0 + c <= NK) {
-        yv = k0 + c < NK ? Y[(size_t)p * ldy + k0 + c] : 1.f;
-        yv = yv == yv ? yv : 0.f;
-      }
-      xs[pp][c] = xv;
-      ys[pp][c] = yv;
+  // thread t loads rows t / 64 + 4 i (i < PT) of column t % 64 of a stage; the next stage's values are
+  // loaded into registers while the current one is multiplied
+  const int cc = t & 63, r0 = t >> 6;
+  const bool xin = o0 + cc < NO, yin = k0 + cc <= NK, yone = k0 + cc == NK;
+  float xv[PT], yv[PT];
+  auto load = [&](int pb) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      const int p = pb + r0 + 4 * i;
+      xv[i] = p < pe && xin ? X[(size_t)p * ldx + o0 + cc] : 0.f;
+      float y = 0.f;
+      if (p < pe && yin) y = yone ? 1.f : Y[(size_t)p * ldy + k0 + cc];
+      yv[i] = y == y ? y : 0.f;
+    }
+  };
+  f32x16 acc = f32x16{};
+  if (pa < pe) load(pa);
+  for (int pb = pa; pb < pe; pb += PS) {
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {
+      xs[r0 + 4 * i][cc] = xv[i];
+      ys[r0 + 4 * i][cc] = yv[i];
     }
     __syncthreads();
-#pragma unroll 4
-    for (int pp = 0; pp < 16; ++pp) {
-      float xv[4], yv[4];
+    if (pb + PS < pe) load(pb + PS);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        xv[a] = xs[pp][4 * to + a];
-        yv[a] = ys[pp][4 * tk + a];
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(xv[a], yv[b], acc[a][b]);
-    }
+    for (int q = 0; q < PS; q += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[q + half][32 * wo + l32], ys[q + half][32 * wk + l32], acc, 0,
+                                                 0, 0);
     __syncthreads();
   }
   float* dst = part + (size_t)z * NO * (NK + 1);
+  const int k = k0 + 32 * wk + l32;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int o = o0 + 4 * to + a, k = k0 + 4 * tk + b;
-      if (o < NO && k <= NK) dst[(size_t)o * (NK + 1) + k] = acc[a][b];
-    }
+  for (int r = 0; r < 16; ++r) {
+    const int o = o0 + 32 * wo + 8 * (r >> 2) + 4 * half + (r & 3);
+    if (o < NO && k <= NK) dst[(size_t)o * (NK + 1) + k] = acc[r];
+  }
 }
 
 // D[o][k] = sum_z part[z][o][k] (ranges in order); column NK goes to Dbias[o].
@@ -521,28 +528,31 @@ __global__ __launch_bounds__(256) void outer_reduce_kernel(const float* part, in
     Dbias[o] = s;
 }
 
-// Encoder weight-gradient partials: workgroup (c, z) walks the (pair, object) entries of range z in
-// order, staging 128 argmax rows at a time in LDS, for channel c's dW2 row and db2 and its partials of
-// dW1, db1.
+// Encoder weight-gradient partials: workgroup (c, z) stages the (pair, object) entries of range z, 256
+// at a time, in LDS (channel c's dm and argmax row); thread t handles hidden unit j = t % H1 and the
+// staged entries i = t / H1 (mod 256 / H1) in ascending order, for channel c's dW2 row and db2 and its
+// partials of dW1, db1; the 256 / H1 streams are then added in stream order.
 template <int H1, int H2>
-__global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
-  __shared__ float srow[128][6];
-  __shared__ float sdm[128];
-  const int c = blockIdx.x, z = blockIdx.y, t = threadIdx.x;
-  float wk[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, bk = 0.f, w2ck = 0.f;
-  if (t < H1) {
+__global__ __launch_bounds__(256) void enc_grad_kernel(TrainArgs A) {
+  constexpr int NS = 256 / H1;  // entry streams per hidden unit
+  static_assert(256 % H1 == 0, "hidden width");
+  __shared__ float srow[256][8];
+  __shared__ float sdm[256];
+  __shared__ float red[NS > 1 ? NS - 1 : 1][H1][9];
+  const int c = blockIdx.x, z = blockIdx.y, t = threadIdx.x, j = t % H1, st = t / H1;
+  float wk[6], bk, w2ck;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) wk[q] = A.raw[A.off.W1 + 6 * t + q];
-    bk = A.raw[A.off.b1 + t];
-    w2ck = A.raw[A.off.W2 + (size_t)c * H1 + t];
-  }
+  for (int q = 0; q < 6; ++q) wk[q] = A.raw[A.off.W1 + 6 * j + q];
+  bk = A.raw[A.off.b1 + j];
+  w2ck = A.raw[A.off.W2 + (size_t)c * H1 + j];
   float dw2 = 0.f, db2 = 0.f, dw1[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, db1 = 0.f;
   const int E = 2 * A.n_pairs;
   const int chunk = (E + kEncSplit - 1) / kEncSplit;
   const int ea = z * chunk, ee = ea + chunk < E ? ea + chunk : E;
-  for (int base = ea; base < ee; base += 128) {
+  for (int base = ea; base < ee; base += 256) {
     const int e = base + t;
-    float dm = 0.f, row[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float dm = 0.f;
+    float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
     if (e < ee) {
       const int p = e >> 1, side = e & 1;
       const PairMeta mt = A.meta[p];
@@ -551,73 +561,98 @@ __global__ __launch_bounds__(128) void enc_grad_kernel(TrainArgs A) {
         if (dm != 0.f) {
           const int r = A.amax[((size_t)p * 2 + side) * H2 + c];
           const float* rw = A.rows + ((size_t)p * 2 * A.K + side * A.K + r) * kRowFloats;
-          const float4 lo = *reinterpret_cast<const float4*>(rw), hi = *reinterpret_cast<const float4*>(rw + 4);
-          row[0] = lo.x;  // stored (x, z, ny, 1 | y, nx, nz, 0)
-          row[1] = hi.x;
-          row[2] = lo.y;
-          row[3] = hi.y;
-          row[4] = lo.z;
-          row[5] = hi.z;
+          lo = *reinterpret_cast<const float4*>(rw);  // stored (x, z, ny, 1 | y, nx, nz, 0)
+          hi = *reinterpret_cast<const float4*>(rw + 4);
         }
       }
     }
     sdm[t] = dm;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) srow[t][q] = row[q];
+    *reinterpret_cast<float4*>(&srow[t][0]) = make_float4(lo.x, hi.x, lo.y, hi.y);  // x, y, z, nx
+    *reinterpret_cast<float4*>(&srow[t][4]) = make_float4(lo.z, hi.z, 0.f, 0.f);    // ny, nz
     __syncthreads();
-    const int cnt = ee - base < 128 ? ee - base : 128;
-    for (int i = 0; i < cnt; ++i) {
+    const int cnt = ee - base < 256 ? ee - base : 256;
+    for (int i = st; i < cnt; i += NS) {
       const float d = sdm[i];
-      if (d == 0.f) continue;  // uniform
+      const float4 r0 = *reinterpret_cast<const float4*>(&srow[i][0]);
+      const float4 r1 = *reinterpret_cast<const float4*>(&srow[i][4]);
+      const float pre = ((((wk[0] * r0.x + wk[1] * r0.y) + wk[2] * r0.z) + wk[3] * r0.w) + wk[4] * r1.x) +
+                        wk[5] * r1.y + bk;
+      // an entry with d = 0 adds exact zeros
+      const float on = pre > 0.f ? d : 0.f;
       db2 += d;
-      const float* rr = srow[i];
-      const float pre = ((((wk[0] * rr[0] + wk[1] * rr[1]) + wk[2] * rr[2]) + wk[3] * rr[3]) + wk[4] * rr[4]) +
-                        wk[5] * rr[5] + bk;
-      if (pre > 0.f) {
-        dw2 = fmaf(d, pre, dw2);
-        const float dh = w2ck * d;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) dw1[q] = fmaf(dh, rr[q], dw1[q]);
-        db1 += dh;
-      }
+      dw2 = fmaf(on, pre, dw2);
+      const float dh = w2ck * on;
+      dw1[0] = fmaf(dh, r0.x, dw1[0]);
+      dw1[1] = fmaf(dh, r0.y, dw1[1]);
+      dw1[2] = fmaf(dh, r0.z, dw1[2]);
+      dw1[3] = fmaf(dh, r0.w, dw1[3]);
+      dw1[4] = fmaf(dh, r1.x, dw1[4]);
+      dw1[5] = fmaf(dh, r1.y, dw1[5]);
+      db1 += dh;
     }
     __syncthreads();
   }
-  float* w2p = A.w2part + ((size_t)z * H2 + c) * (H1 + 1);
-  if (t < H1) {
-    w2p[t] = dw2;
-    float* part = A.w1part + (((size_t)z * H2 + c) * H1 + t) * 7;
+  // streams 1.. hand their sums to stream 0, which adds them in stream order
+  if (NS > 1 && st > 0) {
+    float* rr = red[st - 1][j];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rr[q] = dw1[q];
+    rr[6] = db1;
+    rr[7] = dw2;
+    rr[8] = db2;
+  }
+  __syncthreads();
+  if (st == 0) {
+    for (int k = 0; k + 1 < NS; ++k) {
+      const float* rr = red[k][j];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) dw1[q] += rr[q];
+      db1 += rr[6];
+      dw2 += rr[7];
+      db2 += rr[8];
+    }
+    float* w2p = A.w2part + ((size_t)z * H2 + c) * (H1 + 1);
+    w2p[j] = dw2;
+    float* part = A.w1part + (((size_t)z * H2 + c) * H1 + j) * 7;
 #pragma unroll
     for (int q = 0; q < 6; ++q) part[q] = dw1[q];
     part[6] = db1;
+    if (j == 0) w2p[H1] = db2;  // every hidden unit's thread holds the same db2
   }
-  if (t == 0) w2p[H1] = db2;
 }
 
-// dW2, db2: ranges summed in order; dW1, db1: ranges and channels summed in order.
+// dW2, db2: one thread per output, ranges summed in order.
 template <int H1, int H2>
-__global__ __launch_bounds__(256) void enc_reduce_kernel(TrainArgs A) {
+__global__ __launch_bounds__(256) void enc_reduce_w2_kernel(TrainArgs A) {
   const int id = blockIdx.x * 256 + threadIdx.x;
-  if (id < H2 * (H1 + 1)) {
-    float s = 0.f;
-    for (int z = 0; z < kEncSplit; ++z) s += A.w2part[(size_t)z * H2 * (H1 + 1) + id];
-    const int c = id / (H1 + 1), k = id % (H1 + 1);
-    if (k < H1)
-      A.grad[A.off.W2 + (size_t)c * H1 + k] = s;
-    else
-      A.grad[A.off.b2 + c] = s;
-    return;
-  }
-  const int jd = id - H2 * (H1 + 1);
-  if (jd >= H1 * 7) return;
+  if (id >= H2 * (H1 + 1)) return;
+  float s = 0.f;
+  for (int z = 0; z < kEncSplit; ++z) s += A.w2part[(size_t)z * H2 * (H1 + 1) + id];
+  const int c = id / (H1 + 1), k = id % (H1 + 1);
+  if (k < H1)
+    A.grad[A.off.W2 + (size_t)c * H1 + k] = s;
+  else
+    A.grad[A.off.b2 + c] = s;
+}
+
+// dW1, db1: one wave per output (hidden unit k, column q) over the kEncSplit x H2 partials: lane l adds
+// partials l, l + 64, ... in order, then the lanes are combined by a fixed butterfly.
+template <int H1, int H2>
+__global__ __launch_bounds__(256) void enc_reduce_w1_kernel(TrainArgs A) {
+  constexpr int NP = kEncSplit * H2;
+  const int jd = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (jd >= H1 * 7) return;  // uniform per wave
   const int k = jd / 7, q = jd % 7;
   float s = 0.f;
-  for (int z = 0; z < kEncSplit; ++z)
-    for (int c = 0; c < H2; ++c) s += A.w1part[(((size_t)z * H2 + c) * H1 + k) * 7 + q];
-  if (q < 6)
-    A.grad[A.off.W1 + 6 * k + q] = s;
-  else
-    A.grad[A.off.b1 + k] = s;
+  for (int i = lane; i < NP; i += 64) s += A.w1part[((size_t)i * H1 + k) * 7 + q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) {
+    if (q < 6)
+      A.grad[A.off.W1 + 6 * k + q] = s;
+    else
+      A.grad[A.off.b1 + k] = s;
+  }
 }
 
 // Mean loss terms, summed in a fixed order by one workgroup.
@@ -686,8 +721,9 @@ hipError_t run_train(const TrainArgs& a, hipStream_t s) {
   outer(a.dx, 1, 1, a.g2, HH, HH, a.grad + o.H3, a.grad + o.c3);
   outer(a.du2, HH, HH, a.g1, HH, HH, a.grad + o.H2, a.grad + o.c2);
   outer(a.du1, HH, HH, a.z, Z, Z, a.grad + o.H1, a.grad + o.c1);
-  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(128), 0, s, a);
-  hipLaunchKernelGGL((enc_reduce_kernel<H1, H2>), dim3((H2 * (H1 + 1) + H1 * 7 + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((enc_reduce_w2_kernel<H1, H2>), dim3((H2 * (H1 + 1) + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((enc_reduce_w1_kernel<H1, H2>), dim3((H1 * 7 + 3) / 4), dim3(256), 0, s, a);
   hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, a, invB);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
