@@ -28,19 +28,20 @@ namespace locc {
 namespace {
 
 constexpr int kGT = 32;  // pairs per head-backward workgroup
+constexpr int kTT = 16;  // pairs per head-training workgroup (a 4,096-pair batch fills 256 workgroups)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// acc[rt][ct] = In[32 rows][K] . W^T for this wave's columns c0 + 16 ct + (0..15), W row-major [out][K]
+// acc[rt][ct] = In[16 RT rows][K] . W^T for this wave's columns c0 + 16 ct + (0..15), W row-major [out][K]
 // (ldw floats per row), with v_mfma_f32_16x16x4f32: A[i][k], B[k][j] with i, j = lane % 16 and the
 // reduction index permuted so that at k-step 4u + v lane group g = lane / 16 holds k = 16u + 4g + v,
 // which lets A (LDS rows) and B (weight rows) be read as float4.  D[i][j]: row 4g + r, column j.
-template <int CT, int K>
+template <int CT, int K, int RT = 2>
 __device__ __forceinline__ void mfma_rows32(const float* In, int IS, const float* __restrict__ W, int ldw, int c0,
-                                            int lane, f32x4 (&acc)[2][CT]) {
+                                            int lane, f32x4 (&acc)[RT][CT]) {
   const int j = lane & 15, g = lane >> 4;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
@@ -50,7 +51,7 @@ __device__ __forceinline__ void mfma_rows32(const float* In, int IS, const float
     for (int ct = 0; ct < CT; ++ct)
       b[ct] = *reinterpret_cast<const float4*>(W + (size_t)(c0 + 16 * ct + j) * ldw + 16 * u + 4 * g);
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
+    for (int rt = 0; rt < RT; ++rt) {
       const float4 a = *reinterpret_cast<const float4*>(In + (16 * rt + j) * IS + 16 * u + 4 * g);
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
@@ -270,9 +271,9 @@ __global__ __launch_bounds__(256) void pose_kernel(GradArgs A) {
 }
 
 template <int Z, int HH>
-size_t backward_smem() {
+size_t backward_smem(int rows = kGT) {
   constexpr int LA = (Z > HH ? Z : HH) + 4, LB = HH + 4;
-  return sizeof(float) * kGT * (LA + LB);
+  return sizeof(float) * rows * (LA + LB);
 }
 
 template <int H1, int H2, int HH>
@@ -317,18 +318,17 @@ namespace {
 
 template <int Z, int HH>
 __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB) {
-  constexpr int H2 = Z / 2;
-  constexpr int CT = HH / 64, CTZ = Z / 64;
+  constexpr int CT = HH / 64, CTZ = Z / 64, RT = kTT / 16;
   constexpr int LA = (Z > HH ? Z : HH) + 4, LB = HH + 4;
   extern __shared__ __align__(16) float smem[];
   float* As = smem;
-  float* Bs = smem + kGT * LA;
-  __shared__ float dxs[kGT];
+  float* Bs = smem + kTT * LA;
+  __shared__ float dxs[kTT];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int j = lane & 15, g = lane >> 4;
-  const int p0 = blockIdx.x * kGT;
-  const int n = A.n_pairs - p0 < kGT ? A.n_pairs - p0 : kGT;
-  for (int e = t; e < kGT * Z; e += 256) {
+  const int p0 = blockIdx.x * kTT;
+  const int n = A.n_pairs - p0 < kTT ? A.n_pairs - p0 : kTT;
+  for (int e = t; e < kTT * Z; e += 256) {
     const int r = e / Z, k = e % Z;
     const float v = r < n ? A.z[(size_t)(p0 + r) * Z + k] : 0.f;
     As[r * LA + k] = v == v ? v : 0.f;  // invalid pair: NaN features, no loss
@@ -341,8 +341,8 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   const float* c2 = raw + A.off.c2;
   const float* h3 = raw + A.off.H3;
   // squared feature norm per pair (a wave per 8 pairs)
-  for (int q = 0; q < kGT / 4; ++q) {
-    const int r = wave * (kGT / 4) + q;
+  for (int q = 0; q < kTT / 4; ++q) {
+    const int r = wave * (kTT / 4) + q;
     float s2 = 0.f;
     for (int k = lane; k < Z; k += 64) s2 = fmaf(As[r * LA + k], As[r * LA + k], s2);
 #pragma unroll
@@ -350,15 +350,15 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
     if (lane == 0 && r < n) A.lossp[(size_t)(p0 + r) * 2 + 1] = A.meta[p0 + r].a >= 0 ? s2 : 0.f;
   }
   const int c0 = wave * (HH / 4);
-  f32x4 acc[2][CT];
+  f32x4 acc[RT][CT];
   // g1 = ReLU(f H1^T + c1) -> B
-  mfma_rows32<CT, Z>(As, LA, H1, Z, c0, lane, acc);
+  mfma_rows32<CT, Z, RT>(As, LA, H1, Z, c0, lane, acc);
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int col = c0 + 16 * ct + j;
     const float b = c1[col];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * rt + 4 * g + r;
@@ -370,14 +370,14 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
   __syncthreads();
   // g2 = ReLU(g1 H2^T + c2) -> A (f is no longer needed in LDS)
-  mfma_rows32<CT, HH>(Bs, LB, H2m, HH, c0, lane, acc);
+  mfma_rows32<CT, HH, RT>(Bs, LB, H2m, HH, c0, lane, acc);
   __syncthreads();
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int col = c0 + 16 * ct + j;
     const float b = c2[col];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * rt + 4 * g + r;
@@ -389,8 +389,8 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
   __syncthreads();
   // logit, dx = (sigmoid(x) - y) / B and the cross-entropy (a wave per 8 pairs)
-  for (int q = 0; q < kGT / 4; ++q) {
-    const int r = wave * (kGT / 4) + q;
+  for (int q = 0; q < kTT / 4; ++q) {
+    const int r = wave * (kTT / 4) + q;
     float x = 0.f;
     for (int k = lane; k < HH; k += 64) x = fmaf(As[r * LA + k], h3[k], x);
 #pragma unroll
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
   __syncthreads();
   // du2 = dx H3[0] (g2 > 0) -> A
-  for (int e = t; e < kGT * HH; e += 256) {
+  for (int e = t; e < kTT * HH; e += 256) {
     const int r = e / HH, col = e % HH;
     const float v = As[r * LA + col] > 0.f ? dxs[r] * h3[col] : 0.f;
     As[r * LA + col] = v;
@@ -421,12 +421,12 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
   __syncthreads();
   // du1 = (du2 H2) (g1 > 0) -> B
-  mfma_rows32<CT, HH>(As, LA, A.H2t, HH, c0, lane, acc);
+  mfma_rows32<CT, HH, RT>(As, LA, A.H2t, HH, c0, lane, acc);
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int col = c0 + 16 * ct + j;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * rt + 4 * g + r;
@@ -438,15 +438,15 @@ __global__ __launch_bounds__(256) void head_train_kernel(TrainArgs A, float invB
   }
   __syncthreads();
   // dz = du1 H1 + (2 alpha / B) f; dm = dz (f > 0), both objects
-  f32x4 accz[2][CTZ];
+  f32x4 accz[RT][CTZ];
   const int d0 = wave * (Z / 4);
-  mfma_rows32<CTZ, HH>(Bs, LB, A.H1t, HH, d0, lane, accz);
+  mfma_rows32<CTZ, HH, RT>(Bs, LB, A.H1t, HH, d0, lane, accz);
   const float reg = 2.f * A.alpha * invB;
 #pragma unroll
   for (int ct = 0; ct < CTZ; ++ct) {
     const int col = d0 + 16 * ct + j;
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * rt + 4 * g + r;
@@ -704,12 +704,12 @@ hipError_t run_train(const TrainArgs& a, hipStream_t s) {
   const float invB = 1.f / (float)a.n_pairs;
   hipError_t e = hipMemsetAsync(a.grad, 0, a.n * sizeof(float), s);
   if (e != hipSuccess) return e;
-  const size_t smem = backward_smem<Z, HH>();
+  const size_t smem = backward_smem<Z, HH>(kTT);
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_train_kernel<Z, HH>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int P = a.n_pairs;
-  hipLaunchKernelGGL((head_train_kernel<Z, HH>), dim3((P + kGT - 1) / kGT), dim3(256), smem, s, a, invB);
+  hipLaunchKernelGGL((head_train_kernel<Z, HH>), dim3((P + kTT - 1) / kTT), dim3(256), smem, s, a, invB);
   const GradOffsets& o = a.off;
   // dH3[0], dc3[0]; dH2, dc2; dH1, dc1: partial outer sums over pair ranges, then ordered reductions
   auto outer = [&](const float* X, int ldx, int NO, const float* Y, int ldy, int NK, float* D, float* Db) {
