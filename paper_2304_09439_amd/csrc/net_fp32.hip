@@ -47,8 +47,13 @@ __host__ __device__ constexpr int perm_feature(int ft, int g, int r) { return 32
 // -------------------------------------------------------------------- encoder
 // ARGMAX: also record, per object and channel, the row of the largest raw
 // sum (the first such row on ties), for the pose-gradient path.
+// Workgroups per compute unit: two where the registers allow (widths 64 / 128),
+// so that one workgroup's matrix-core work hides the other's waits.
+template <int H1>
+constexpr int encoder_wg_per_cu() { return H1 <= 64 ? 2 : 1; }
+
 template <int H1, int H2, bool ARGMAX>
-__global__ __launch_bounds__(256, 1) void encoder_fp32_kernel(Fp32Net W, NetArgs A) {
+__global__ __launch_bounds__(256, encoder_wg_per_cu<H1>()) void encoder_fp32_kernel(Fp32Net W, NetArgs A) {
   constexpr int FT = H1 / 32;   // 32-feature tiles of layer 1
   constexpr int KS = H1 / 2;    // layer-2 k-steps
   constexpr int CT = H2 / 128;  // 32-column tiles per wave
@@ -283,7 +288,8 @@ size_t head_smem_bytes() {
 
 template <int H1, int H2>
 hipError_t run_encoder(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s) {
-  int grid = a.n_pairs < n_cu ? a.n_pairs : n_cu;
+  const int slots = encoder_wg_per_cu<H1>() * n_cu;
+  int grid = a.n_pairs < slots ? a.n_pairs : slots;
   if (a.amax)
     hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2, true>), dim3(grid), dim3(256), 0, s, w, a);
   else
