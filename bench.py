@@ -83,7 +83,7 @@ def per_pair_work(K, widths, n_points):
     enc_flops = 2 * (2 * K) * (6 * h1 + h1 * h2)
     head_flops = 2 * (2 * h2 * hh + hh * hh + 8 * hh)
     crop_bytes = 2 * n_points * 12 + 2 * K * 24 + 2 * 32 + 8 + 8   # scan xyz, gather rows, poses, pair, counts
-    return dict(enc_flops=enc_flops, head_flops=head_flops, crop_bytes=crop_bytes, contact_bytes=32)
+    return dict(enc_flops=enc_flops, head_flops=head_flops, crop_bytes=crop_bytes, contact_bytes=32, K=K)
 
 
 def source_hash(kernel: str) -> str:
@@ -153,12 +153,20 @@ def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True)
         P_launch = P * steps / max(launches, 1)
         entry = dict(avg_ms=round(avg, 4), launches=int(launches), pairs_per_launch=round(P_launch, 1))
         if name == "crop":
-            achieved = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
-            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+            # HBM: what a crop has to move (poses, pair, counts, the 2K rows it writes in this path's row
+            # format); the scans read the shape library (32 x 2048 points x 24 B = 1.5 MB) from L2.
+            row_bytes = 32 if precision == "fp32" else 16
+            hbm = 2 * 32 + 8 + 8 + 2 * work["K"] * row_bytes
+            achieved = hbm * P_launch / (avg * 1e-3) / 1e9
+            scan = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
+            entry.update(bound="latency", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
                          frac=round(achieved / PEAK_HBM_GBPS, 4),
-                         bytes_basis="full scans of both objects (2N x 12 B per pair) + 2K gathered rows" + (
-                             "" if full_scan else "; member counts not requested, so each scan stops at K "
-                                                  "members and this overstates the bytes the algorithm reads"))
+                         bytes_basis=f"{hbm} B per pair to or from HBM: poses (2 x 32 B), pair (8 B), counts (8 B), "
+                                     f"2K rows of {row_bytes} B",
+                         scan_GBps=round(scan, 1),
+                         scan_basis="full scans of both objects (2N x 12 B per pair) + 2K gathered rows, mostly "
+                                    "served by L2" + ("" if full_scan else "; member counts not requested, so each "
+                                                      "scan stops at K members and this overstates them"))
         else:
             if name.startswith("encoder_head") or name.startswith("fused"):
                 flops = (work["enc_flops"] + work["head_flops"]) * P_launch
