@@ -41,7 +41,6 @@ __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
 // workgroup (each with its own LDS), so that the compute unit's limit on
 // resident workgroups does not cap the resident waves.
 struct ObjectShared {
-  unsigned long long mask[kMaxBlocks];  // one ballot per 64 stored points
   int32_t sel[kMaxK];
 };
 
@@ -94,7 +93,11 @@ __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
   const float* __restrict__ py = A.lib.py + off;
   const float* __restrict__ pz = A.lib.pz + off;
 
-  // membership scan: U blocks of 64 points per round, loads in flight together
+  // membership scan: U blocks of 64 points per round, loads in flight
+  // together.  The wave tests the blocks in stored order and keeps the number
+  // of members before each block (a scalar), so a member's ordered position
+  // is that number plus its rank in the block's ballot: the first K members
+  // are placed during the scan.
   const int nblk = (n + 63) >> 6;
   int scanned = 0, found = 0;  // wave-uniform
   while (scanned < nblk && (full || found < K)) {
@@ -117,39 +120,15 @@ __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
         bool in = false;
         if (k < (unsigned)n) in = side ? geo_member_b(&rec->g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
         const unsigned long long m = __ballot(in);
-        if (lane == 0) S.mask[blk] = m;
+        const int pos = found + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (in && pos < K) S.sel[pos] = (int)k;
         found += __popcll(m);
       }
     }
     scanned = scanned + U < nblk ? scanned + U : nblk;
   }
   // found: every member when full, else at least min(K, members)
-  wave_lds_sync();  // the ballots (written by lane 0) are read by every lane
-
-  // ordered first-K selection: block per lane (chunks of 64 blocks), the
-  // exclusive prefix of the popcounts is each block's first position; block
-  // after block while positions stay below K, the block's ballot and start
-  // go to scalar registers and every lane places its own point at start +
-  // (members below it in the block).
-  int carry = 0;
-  for (int base = 0; base < scanned && carry < K; base += 64) {
-    const int blk = base + lane;
-    const unsigned long long m = blk < scanned ? S.mask[blk] : 0ull;
-    const int c = __popcll(m);
-    const int incl = geo_wave_inclusive_scan(c, lane);
-    const int start = carry + incl - c;
-    const int nb = scanned - base < 64 ? scanned - base : 64;
-    const unsigned m_lo = (unsigned)m, m_hi = (unsigned)(m >> 32);
-    for (int j = 0; j < nb; ++j) {
-      const int sj = __builtin_amdgcn_readlane(start, j);
-      if (sj >= K) break;
-      const unsigned lo = __builtin_amdgcn_readlane(m_lo, j), hi = __builtin_amdgcn_readlane(m_hi, j);
-      const unsigned mine = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
-      const int pos = sj + (int)__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
-      if (mine && pos < K) S.sel[pos] = ((base + j) << 6) + lane;
-    }
-    carry += __shfl(incl, 63, 64);
-  }
   wave_lds_sync();  // the selected indices are read by other lanes
   const int m = found < K ? found : K;
   const int caller = side ^ swapped;  // position of this object in the caller's pair

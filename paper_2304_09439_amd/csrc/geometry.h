@@ -214,6 +214,16 @@ __device__ __forceinline__ bool geo_member_a(const PairScreen& sc, float x, floa
          (z <= sc.ahi[2]);
 }
 
+// The exact float64 test of a b-point, for the points the float32 screen
+// cannot decide (rare): out of line, so that its float64 state does not take
+// registers from the scan loop around it.
+__device__ __attribute__((noinline)) bool geo_member_b_exact(const PairGeom* __restrict__ gp, float x, float y,
+                                                             float z) {
+  double q[3];
+  geo_xform(*gp, x, y, z, q);
+  return geo_inside(*gp, q[0], q[1], q[2]);
+}
+
 // gp: the pair's float64 geometry, read only for the points the screen cannot
 // decide (a pointer, so that a caller holding it in memory keeps it there)
 __device__ __forceinline__ bool geo_member_b(const PairGeom* __restrict__ gp, const PairScreen& sc, float x, float y,
@@ -226,9 +236,7 @@ __device__ __forceinline__ bool geo_member_b(const PairGeom* __restrict__ gp, co
   const bool out = (q0 < sc.out_lo[0]) | (q0 > sc.out_hi[0]) | (q1 < sc.out_lo[1]) | (q1 > sc.out_hi[1]) |
                    (q2 < sc.out_lo[2]) | (q2 > sc.out_hi[2]);
   if (in | out) return in;
-  double q[3];
-  geo_xform(*gp, x, y, z, q);
-  return geo_inside(*gp, q[0], q[1], q[2]);
+  return geo_member_b_exact(gp, x, y, z);
 }
 
 // Membership scan and ordered first-K selection for one pair, by a
