@@ -15,11 +15,13 @@
 //   D[i][j] in 16 registers r: j = l % 32, i = 8 (r / 4) + 4 (l / 32) + r % 4.
 // Encoder: layer 1 is computed transposed (h1^T = [W1 | b1] [r; 1]), so each
 // lane ends up holding 16 features of ONE point per 32-feature tile.  Those
-// registers are exactly layer 2's A operand if layer 2's reduction index is
-// permuted to F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4; the host packs
-// W2 in that order.  Both layers stay in registers; W2's slice for the wave
-// (h2 / 4 output columns) is loaded once per workgroup and reused for every
-// pair the persistent workgroup processes.
+// values are layer 2's A operand if layer 2's reduction index is permuted to
+// F(ft, g, r) = 32 ft + 8 (r / 4) + 4 g + r % 4; the host packs W2 in that
+// order.  Each wave computes its share of layer 1's feature tiles and stores
+// them, in the order its lanes hold them, to an LDS tile that all four waves
+// read back four reduction steps at a time.  W2's slice for the wave (h2 / 4
+// output columns) is loaded once per workgroup and stays in registers for
+// every pair the persistent workgroup processes.
 #include "locc_internal.h"
 
 #include <cmath>
@@ -47,27 +49,37 @@ __host__ __device__ constexpr int perm_feature(int ft, int g, int r) { return 32
 // -------------------------------------------------------------------- encoder
 // ARGMAX: also record, per object and channel, the row of the largest raw
 // sum (the first such row on ties), for the pose-gradient path.
-// Workgroups per compute unit: two where the registers allow (widths 64 / 128),
-// so that one workgroup's matrix-core work hides the other's waits.
+// Workgroups per compute unit: with layer 1 shared through LDS a wave needs
+// at most 244 registers at widths 128 / 256 (two workgroups per CU) and 122 at
+// 64 / 128 (four), so that one workgroup's matrix-core work hides another's
+// waits.
 template <int H1>
-constexpr int encoder_wg_per_cu() { return H1 <= 64 ? 2 : 1; }
+constexpr int encoder_wg_per_cu() { return H1 <= 64 ? 4 : 2; }
 
 template <int H1, int H2, bool ARGMAX>
 __global__ __launch_bounds__(256, encoder_wg_per_cu<H1>()) void encoder_fp32_kernel(Fp32Net W, NetArgs A) {
   constexpr int FT = H1 / 32;   // 32-feature tiles of layer 1
   constexpr int KS = H1 / 2;    // layer-2 k-steps
   constexpr int CT = H2 / 128;  // 32-column tiles per wave
+  constexpr int FW = (FT + 3) / 4;  // layer-1 feature tiles per wave (tiles wave, wave + 4, ...)
+  constexpr int HR = FT * 16 + 4;   // floats per (lane group, point) row of the layer-1 tile
   static_assert(H1 % 32 == 0 && H2 % 128 == 0, "widths");
+  // layer-1 output of a 32-row tile, double-buffered: [g][point][ft][16] in
+  // the order each lane holds it (feature perm_feature(ft, g, r) at r), rows
+  // padded to 4 mod 32 floats so that float4 accesses by 8 lanes hit 32 banks
+  __shared__ __align__(16) float h1s[2][64 * HR];
   const int lane = threadIdx.x & 63;
   const int wave = wave_index();
   const int g = lane >> 5;
+  const int l32 = lane & 31;
   const int K = A.K;
 
-  float w1f[FT][4];
+  float w1f[FW][4];
 #pragma unroll
-  for (int ft = 0; ft < FT; ++ft)
+  for (int i = 0; i < FW; ++i)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) w1f[ft][s] = W.w1pack[(ft * 4 + s) * 64 + lane];
+    for (int s = 0; s < 4; ++s)
+      w1f[i][s] = wave + 4 * i < FT ? W.w1pack[((wave + 4 * i) * 4 + s) * 64 + lane] : 0.f;
   float w2f[CT][KS];
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct)
@@ -102,27 +114,63 @@ __global__ __launch_bounds__(256, encoder_wg_per_cu<H1>()) void encoder_fp32_ker
         arg[ct] = 255;
       }
       const float* rbase = A.rows + ((size_t)p * 2 * K + side * K) * kRowFloats;
-      for (int r0 = 0; r0 < m; r0 += 32) {
-        const float4 xv = *reinterpret_cast<const float4*>(rbase + (r0 + (lane & 31)) * kRowFloats + 4 * g);
+      // Row tiles t = 0, 1, ...: each wave computes its layer-1 feature tiles
+      // of tile t + 1 while layer 2 of tile t runs and stores them (ReLU
+      // applied) to the other LDS buffer; one barrier per tile publishes them
+      // (the buffer written in tile t was last read in tile t - 1, before the
+      // previous barrier).
+      const int nt = (m + 31) >> 5;  // uniform over the workgroup
+      f32x16 acc1[FW];
+      float4 xv = *reinterpret_cast<const float4*>(rbase + l32 * kRowFloats + 4 * g);
+      auto layer1_issue = [&](int t) {
         const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-        f32x16 acc1[FT];
 #pragma unroll
-        for (int ft = 0; ft < FT; ++ft) {
-          acc1[ft] = f32x16{};
+        for (int i = 0; i < FW; ++i)
+          if (FT % 4 == 0 || wave + 4 * i < FT) {
+            acc1[i] = f32x16{};
 #pragma unroll
-          for (int s = 0; s < 4; ++s) acc1[ft] = mfma32x32x2(w1f[ft][s], xs[s], acc1[ft]);
+            for (int s = 0; s < 4; ++s) acc1[i] = mfma32x32x2(w1f[i][s], xs[s], acc1[i]);
+          }
+        if (t + 1 < nt) xv = *reinterpret_cast<const float4*>(rbase + ((t + 1) * 32 + l32) * kRowFloats + 4 * g);
+      };
+      auto layer1_store = [&](int buf) {
+        float* dst = &h1s[buf][(g * 32 + l32) * HR];
+#pragma unroll
+        for (int i = 0; i < FW; ++i) {
+          const int ft = wave + 4 * i;
+          if (FT % 4 == 0 || ft < FT)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              *reinterpret_cast<float4*>(dst + ft * 16 + 4 * j) =
+                  make_float4(vmax(acc1[i][4 * j], 0.f), vmax(acc1[i][4 * j + 1], 0.f),
+                              vmax(acc1[i][4 * j + 2], 0.f), vmax(acc1[i][4 * j + 3], 0.f));
         }
+      };
+      if (nt > 0) {
+        layer1_issue(0);
+        layer1_store(0);
+      }
+      __syncthreads();
+      for (int t = 0; t < nt; ++t) {
+        const int r0 = 32 * t;
+        const bool more = t + 1 < nt;
+        if (more) layer1_issue(t + 1);
+        const float* src = &h1s[t & 1][(g * 32 + l32) * HR];
         f32x16 acc2[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
 #pragma unroll
         for (int ft = 0; ft < FT; ++ft)
 #pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const float h = vmax(acc1[ft][r], 0.f);
+          for (int j = 0; j < 4; ++j) {
+            const float4 a = *reinterpret_cast<const float4*>(src + ft * 16 + 4 * j);
+            const float h[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h, w2f[ct][ft * 16 + r], acc2[ct]);
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma32x32x2(h[e], w2f[ct][ft * 16 + 4 * j + e], acc2[ct]);
           }
+        if (more) layer1_store((t + 1) & 1);
         if (ARGMAX) {
           // a lane's rows ascend with r, and blocks ascend with r0: strict > keeps the first maximum
 #pragma unroll
@@ -149,6 +197,7 @@ __global__ __launch_bounds__(256, encoder_wg_per_cu<H1>()) void encoder_fp32_ker
               if (row < m) run[ct] = vmax(run[ct], acc2[ct][r]);
             }
         }
+        __syncthreads();
       }
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) {
