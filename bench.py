@@ -83,7 +83,8 @@ def per_pair_work(K, widths, n_points):
     enc_flops = 2 * (2 * K) * (6 * h1 + h1 * h2)
     head_flops = 2 * (2 * h2 * hh + hh * hh + 8 * hh)
     crop_bytes = 2 * n_points * 12 + 2 * K * 24 + 2 * 32 + 8 + 8   # scan xyz, gather rows, poses, pair, counts
-    return dict(enc_flops=enc_flops, head_flops=head_flops, crop_bytes=crop_bytes, contact_bytes=32, K=K)
+    return dict(enc_flops=enc_flops, head_flops=head_flops, crop_bytes=crop_bytes, contact_bytes=32, K=K,
+                row_flops=2 * (6 * h1 + h1 * h2))
 
 
 def source_hash(kernel: str) -> str:
@@ -144,7 +145,7 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
 
 # ------------------------------------------------------------------ GPU run
 
-def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True):
+def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True, exec_rows=None):
     """Per kernel: average launch duration and the algorithmic rate of one launch (a step of P pairs may
     run a kernel several times, once per chunk of pairs)."""
     kernels = {}
@@ -153,20 +154,22 @@ def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True)
         P_launch = P * steps / max(launches, 1)
         entry = dict(avg_ms=round(avg, 4), launches=int(launches), pairs_per_launch=round(P_launch, 1))
         if name == "crop":
-            # HBM: what a crop has to move (poses, pair, counts, the 2K rows it writes in this path's row
-            # format); the scans read the shape library (32 x 2048 points x 24 B = 1.5 MB) from L2.
+            # algorithmic bytes (the denominator of the roofline): full scans of both objects, the 2K
+            # gathered rows, poses, pair, counts.  Beside it, what a crop has to move through HBM (poses,
+            # pair, counts, the 2K rows it writes in this path's format): the scans read the 1.5 MB shape
+            # library from L2.
+            achieved = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
             row_bytes = 32 if precision == "fp32" else 16
             hbm = 2 * 32 + 8 + 8 + 2 * work["K"] * row_bytes
-            achieved = hbm * P_launch / (avg * 1e-3) / 1e9
-            scan = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
-            entry.update(bound="latency", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+            hbm_rate = hbm * P_launch / (avg * 1e-3) / 1e9
+            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
                          frac=round(achieved / PEAK_HBM_GBPS, 4),
-                         bytes_basis=f"{hbm} B per pair to or from HBM: poses (2 x 32 B), pair (8 B), counts (8 B), "
-                                     f"2K rows of {row_bytes} B",
-                         scan_GBps=round(scan, 1),
-                         scan_basis="full scans of both objects (2N x 12 B per pair) + 2K gathered rows, mostly "
-                                    "served by L2" + ("" if full_scan else "; member counts not requested, so each "
-                                                      "scan stops at K members and this overstates them"))
+                         bytes_basis="algorithmic: full scans of both objects (2N x 12 B per pair) + 2K gathered rows "
+                                     "(24 B) + poses, pair, counts; the scans read the shape library from L2" + (
+                                         "" if full_scan else ", and without member counts each scan stops at K "
+                                                              "members, so the rate exceeds the HBM peak"),
+                         hbm_bytes_per_pair=hbm, hbm_GBps=round(hbm_rate, 1),
+                         hbm_frac=round(hbm_rate / PEAK_HBM_GBPS, 4))
         else:
             if name.startswith("encoder_head") or name.startswith("fused"):
                 flops = (work["enc_flops"] + work["head_flops"]) * P_launch
@@ -181,6 +184,15 @@ def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True)
             achieved = flops / (avg * 1e-3) / 1e12
             entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
                          frac=round(achieved / PEAK_TFLOPS[prec], 4))
+            if exec_rows is not None and not name.startswith("head"):
+                # the kernels skip the 32-row tiles past each object's member count: the work they run
+                run = exec_rows * work["row_flops"] * P_launch / P
+                if name.startswith("encoder_head") or name.startswith("fused"):
+                    run += work["head_flops"] * P_launch
+                ex = run / (avg * 1e-3) / 1e12
+                entry.update(executed_TFLOPs=round(ex, 2), executed_frac=round(ex / PEAK_TFLOPS[prec], 4),
+                             executed_basis="encoder rows in the 32-row tiles run (min(count, K) per object rounded "
+                                            "up to 32), head on every pair")
         entry["traffic"] = counter_traffic(f"crop_{precision}" if name == "crop" else name, workload_name)
         kernels[name] = entry
     return kernels
@@ -227,6 +239,7 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     kt = ctx.profile_read()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     extra = {}
+    full = counts
     if counts is None:   # the same schedule with member counts requested (every point of both objects tested)
         full = torch.empty((P, 2), dtype=torch.int32, device="cuda")
         ctx.detect(objs, pairs, out, full)
@@ -238,8 +251,12 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
         extra["ms_per_step_with_member_counts"] = round(1000.0 * (time.perf_counter() - t1) / args.steps, 4)
     n_bad = ctx.device_errors()
     ctx.close()
+    c = full.cpu().numpy()
+    c = np.clip(c[c[:, 0] >= 0], 0, K)
+    exec_rows = int((((c + 31) // 32) * 32).sum())   # encoder rows in the row tiles the kernels run
     ms = 1000.0 * wall / args.steps
-    kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision, full_scan=counts is not None)
+    kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision, full_scan=counts is not None,
+                             exec_rows=exec_rows)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
