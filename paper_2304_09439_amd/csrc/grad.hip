@@ -302,7 +302,7 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 //
 // One step of fitting the FP32 network to collision labels (binary
 // cross-entropy of the logit plus alpha times the squared norm of the pooled
-// features, Adam): head_train_kernel (32 pairs per workgroup, the head
+// features, Adam): head_train_kernel (16 pairs per workgroup, the head
 // forward and backward on matrix cores, keeping per pair g1, g2, du2, du1,
 // the pooled features' gradient dm, dx and the two loss terms);
 // outer_sum_kernel reduces the head's weight and bias gradients over 64
