@@ -89,7 +89,7 @@ struct Smem8 {
 template <int KDIM, int SB, int DS, int CTH, bool DST_BF16>
 __device__ __forceinline__ void head_layer8(const unsigned char* __restrict__ pack, const float* __restrict__ bias,
                                             float scale, float dst_inv, const unsigned char* src, void* dst) {
-  constexpr int KS = KDIM / 64, D = 2;  // weight fragments D k-steps ahead, in a ring of registers
+  constexpr int KS = KDIM / 64, D = 1;  // weight fragments D k-steps ahead, in a ring of registers
   static_assert(KS % D == 0, "k-steps per head layer");
   const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const i32x8* bp = reinterpret_cast<const i32x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
