@@ -309,8 +309,8 @@ hipError_t launch_pose_gradients(const GradArgs& a, int h1, int h2, int hh, hipS
 // ranges of pairs on matrix cores and outer_reduce_kernel sums the ranges;
 // enc_grad_kernel (one workgroup per channel and range of pairs) walks its
 // (pair, object) entries in order, staging 256 argmax rows at a time in LDS,
-// and the enc_reduce kernels sum the partials of dW2, db2, dW1, db1;
-// adam_kernel updates the master weights; two gathers
+// and train_reduce_kernel sums the partials of dW2, db2, dW1, db1 and the
+// loss terms; adam_kernel updates the master weights; two gathers
 // repack them into the layouts the forward and gradient kernels read.  Every
 // reduction has a fixed order, so a step is reproducible bit for bit.
 namespace locc {
@@ -623,8 +623,8 @@ __global__ __launch_bounds__(256) void enc_grad_kernel(TrainArgs A) {
 
 // dW2, db2: one thread per output, ranges summed in order.
 template <int H1, int H2>
-__global__ __launch_bounds__(256) void enc_reduce_w2_kernel(TrainArgs A) {
-  const int id = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void enc_reduce_w2(const TrainArgs& A, int block) {
+  const int id = block * 256 + threadIdx.x;
   if (id >= H2 * (H1 + 1)) return;
   float s = 0.f;
   for (int z = 0; z < kEncSplit; ++z) s += A.w2part[(size_t)z * H2 * (H1 + 1) + id];
@@ -638,9 +638,9 @@ __global__ __launch_bounds__(256) void enc_reduce_w2_kernel(TrainArgs A) {
 // dW1, db1: one wave per output (hidden unit k, column q) over the kEncSplit x H2 partials: lane l adds
 // partials l, l + 64, ... in order, then the lanes are combined by a fixed butterfly.
 template <int H1, int H2>
-__global__ __launch_bounds__(256) void enc_reduce_w1_kernel(TrainArgs A) {
+__device__ __forceinline__ void enc_reduce_w1(const TrainArgs& A, int block) {
   constexpr int NP = kEncSplit * H2;
-  const int jd = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int jd = block * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (jd >= H1 * 7) return;  // uniform per wave
   const int k = jd / 7, q = jd % 7;
   float s = 0.f;
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(256) void enc_reduce_w1_kernel(TrainArgs A) {
 }
 
 // Mean loss terms, summed in a fixed order by one workgroup.
-__global__ __launch_bounds__(256) void loss_kernel(TrainArgs A, float invB) {
+__device__ __forceinline__ void loss_sum(const TrainArgs& A, float invB) {
   __shared__ float part[2][256];
   const int t = threadIdx.x;
   float s0 = 0.f, s1 = 0.f;
@@ -678,6 +678,20 @@ __global__ __launch_bounds__(256) void loss_kernel(TrainArgs A, float invB) {
     A.loss[0] = part[0][0] * invB;
     A.loss[1] = A.alpha * part[1][0] * invB;
   }
+}
+
+// The reductions after enc_grad_kernel in one launch: blocks [0, B2) reduce dW2 / db2, the next B1 blocks
+// dW1 / db1, the last one the loss terms.
+template <int H1, int H2>
+__global__ __launch_bounds__(256) void train_reduce_kernel(TrainArgs A, float invB) {
+  constexpr int B2 = (H2 * (H1 + 1) + 255) / 256, B1 = (H1 * 7 + 3) / 4;
+  const int b = blockIdx.x;  // uniform
+  if (b < B2)
+    enc_reduce_w2<H1, H2>(A, b);
+  else if (b < B2 + B1)
+    enc_reduce_w1<H1, H2>(A, b - B2);
+  else
+    loss_sum(A, invB);
 }
 
 __global__ __launch_bounds__(256) void adam_kernel(TrainArgs A) {
@@ -702,10 +716,10 @@ template <int H1, int H2, int HH>
 hipError_t run_train(const TrainArgs& a, hipStream_t s) {
   constexpr int Z = 2 * H2;
   const float invB = 1.f / (float)a.n_pairs;
-  hipError_t e = hipMemsetAsync(a.grad, 0, a.n * sizeof(float), s);
-  if (e != hipSuccess) return e;
+  // the gradient entries no kernel writes (the untrained outputs' rows of H3 and c3) stay zero from the
+  // upload of the weights
   const size_t smem = backward_smem<Z, HH>(kTT);
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_train_kernel<Z, HH>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_train_kernel<Z, HH>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int P = a.n_pairs;
@@ -722,9 +736,8 @@ hipError_t run_train(const TrainArgs& a, hipStream_t s) {
   outer(a.du2, HH, HH, a.g1, HH, HH, a.grad + o.H2, a.grad + o.c2);
   outer(a.du1, HH, HH, a.z, Z, Z, a.grad + o.H1, a.grad + o.c1);
   hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((enc_reduce_w2_kernel<H1, H2>), dim3((H2 * (H1 + 1) + 255) / 256), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((enc_reduce_w1_kernel<H1, H2>), dim3((H1 * 7 + 3) / 4), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, s, a, invB);
+  hipLaunchKernelGGL((train_reduce_kernel<H1, H2>), dim3((H2 * (H1 + 1) + 255) / 256 + (H1 * 7 + 3) / 4 + 1),
+                     dim3(256), 0, s, a, invB);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
                      a.pack_idx, a.pack_n, (const float*)a.raw);
