@@ -385,12 +385,19 @@ def serve_run(B, srv, reqs, arrivals):
             pending[rid] = (k, lag * 1e3)
             k += 1
             now = time.perf_counter() - t0
-        done = []
+        # poll the oldest requests first, up to 64 unfinished ones a pass (completions are roughly in
+        # submission order; the library stamps each completion itself, so the latency does not depend
+        # on when it is polled)
+        done, misses = [], 0
         for rid, (j, lag) in pending.items():
             r = srv.poll(rid)
             if r is not None:
                 lat[j] = lag + r[2]
                 done.append(rid)
+            else:
+                misses += 1
+                if misses == 64:
+                    break
         for rid in done:
             del pending[rid]
     return lat, time.perf_counter() - t0
@@ -449,10 +456,19 @@ def serve_bench(args, w):
         ctx.close()
     ctx, srv = server("bf16", True)
     serve_run(B, srv, reqs[:200], None)
+    st0 = srv.stats()
     lat, wall = serve_run(B, srv, reqs, None)
+    st = srv.stats()
     srv.stop()
     ctx.close()
-    out["bf16_batched_saturated"] = summary(lat, wall)
+    sat = summary(lat, wall)
+    busy = st["busy_ms"] - st0["busy_ms"]
+    nb = int(st["batches"] - st0["batches"])
+    sat.update(batches=nb, requests_per_batch=round(len(reqs) / max(nb, 1), 2), server_busy_ms=round(busy, 3),
+               note="requests reach the queue at the rate of the Python submit loop (one ctypes call each), and the "
+                    "worker takes whatever is queued as soon as a slot frees, so batches stay small and this "
+                    "throughput is bounded by the submit loop, not by the server")
+    out["bf16_batched_saturated"] = sat
     return out
 
 

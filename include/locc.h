@@ -393,13 +393,17 @@ LOCC_API locc_status locc_step_graph_capture(locc_ctx* ctx, const locc_object* d
  * (device buffers sized from the memory budget) is free, and up to `slots`
  * batches are in flight at once on separate streams.
  *
- * Batches are formed first in, first out: the first queued request that
- * does not fit the slot, or that conflicts with a request in flight or in
- * the same batch (it updates an object another one reads or updates, or
- * reads one another updates), waits for the next batch.  A request's pairs
- * therefore see the object table after its own updates and after every
- * earlier request's, and its result is the same whether it runs alone or
- * in a mix.  While a server runs, no other call may use its context.
+ * Batches are formed by scanning the queue in submission order: a request
+ * joins the batch if it fits the slot and conflicts (updates an object
+ * another one reads or updates, or reads one another updates) with no
+ * request in flight, in the batch, or still waiting ahead of it; otherwise
+ * it waits, and the objects it touches are closed to the requests behind it
+ * for this batch.  A request's pairs therefore see the object table after
+ * its own updates and after those of every earlier request that touches
+ * the same objects, as in submission order, and its result is the same
+ * whether it runs alone or in a mix; requests on disjoint objects may
+ * complete out of order.  While a server runs, no other call may use its
+ * context.
  *
  *   max_objects        size of the resident object table
  *   max_batch_pairs    pairs per batch; 0 = as many as the budget allows

@@ -3,12 +3,14 @@
 // A worker thread owns the GPU side.  Its loop: (1) retire every slot whose
 // completion event has fired, copying each request's slice of the slot's
 // pinned output buffers into the request and stamping its completion time;
-// (2) for every free slot, take queued requests first in, first out while
-// they fit the slot (pairs, pose updates) and conflict with nothing in
-// flight or already in the batch, copy them into the slot's pinned staging
-// buffers and enqueue on the slot's stream: H2D copies, the pose scatter,
-// the detect path with the slot's own scratch and queue, D2H copies and the
-// completion event; (3) sleep briefly when idle.  Slots run on separate
+// (2) for every free slot, scan the queue in submission order and take each
+// request that fits the slot (pairs, pose updates) and conflicts with
+// nothing in flight, in the batch, or left waiting ahead of it (a request
+// left behind blocks the objects it touches for the requests after it), copy
+// them into the slot's pinned staging buffers and enqueue on the slot's
+// stream: H2D copies, the pose scatter, the detect path with the slot's own
+// scratch and queue, D2H copies and the completion event; (3) sleep briefly
+// when idle.  Slots run on separate
 // streams, so a batch that forms while others are on the GPU starts as soon
 // as a slot frees up and overlaps with them on the device.
 #include <algorithm>
@@ -16,7 +18,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
-#include <deque>
+#include <list>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -81,7 +83,7 @@ struct locc_server {
   std::vector<Slot> slots;
   // host state, guarded by mu
   std::mutex mu;
-  std::deque<Request*> queue;
+  std::list<Request*> queue;
   std::unordered_map<uint64_t, Request*> reqs;
   int64_t queued_pairs = 0;
   uint64_t next_id = 1;
@@ -89,6 +91,8 @@ struct locc_server {
   bool stopping = false;
   // worker-only state
   std::vector<int32_t> upd_busy, ref_busy;  // in-flight / batched requests updating / reading each object
+  std::vector<uint8_t> upd_blocked, ref_blocked;  // objects a request left waiting during a scan updates / reads
+  std::vector<int32_t> blocked_ids;               // entries to clear after the scan
   std::thread worker;
   std::atomic<int> worker_status{LOCC_OK};
 };
@@ -104,6 +108,30 @@ bool fits_and_free(locc_server* S, const Request* r, int pairs_used, int upd_use
     if (S->upd_busy[id]) return false;
   return true;
 }
+
+// Whether r touches an object a request left waiting ahead of it in this scan
+// updates, or updates one it reads: r must not overtake that request.
+bool blocked(const locc_server* S, const Request* r) {
+  for (int32_t id : r->upd_ids)
+    if (S->upd_blocked[id] || S->ref_blocked[id]) return true;
+  for (int32_t id : r->refs)
+    if (S->upd_blocked[id]) return true;
+  return false;
+}
+
+void block(locc_server* S, const Request* r) {
+  for (int32_t id : r->upd_ids) {
+    S->upd_blocked[id] = 1;
+    S->blocked_ids.push_back(id);
+  }
+  for (int32_t id : r->refs) {
+    S->ref_blocked[id] = 1;
+    S->blocked_ids.push_back(id);
+  }
+}
+
+// Requests examined per batch at most (bounds the scan when the queue is long).
+constexpr int kMaxScan = 1024;
 
 void mark(locc_server* S, const Request* r, int d) {
   for (int32_t id : r->upd_ids) S->upd_busy[id] += d;
@@ -175,18 +203,25 @@ void worker_loop(locc_server* S) {
       if (sl.busy) continue;
       {
         std::lock_guard<std::mutex> lk(S->mu);
-        int np = 0, nu = 0;
-        while (!S->queue.empty()) {
-          Request* r = S->queue.front();
-          if (!fits_and_free(S, r, np, nu)) break;
-          S->queue.pop_front();
-          mark(S, r, +1);
-          np += (int)r->pairs.size() / 2;
-          nu += (int)r->upd_ids.size();
-          S->queued_pairs -= (int64_t)r->pairs.size() / 2;
-          sl.reqs.push_back(r);
-          if (!S->cfg.batching) break;
+        int np = 0, nu = 0, scanned = 0;
+        for (auto it = S->queue.begin(); it != S->queue.end() && scanned < kMaxScan; ++scanned) {
+          Request* r = *it;
+          if (fits_and_free(S, r, np, nu) && !blocked(S, r)) {
+            it = S->queue.erase(it);
+            mark(S, r, +1);
+            np += (int)r->pairs.size() / 2;
+            nu += (int)r->upd_ids.size();
+            S->queued_pairs -= (int64_t)r->pairs.size() / 2;
+            sl.reqs.push_back(r);
+            if (!S->cfg.batching) break;
+            continue;
+          }
+          if (!S->cfg.batching) break;  // one request per launch, strictly in order
+          block(S, r);
+          ++it;
         }
+        for (int32_t id : S->blocked_ids) S->upd_blocked[id] = S->ref_blocked[id] = 0;
+        S->blocked_ids.clear();
       }
       if (sl.reqs.empty()) continue;
       const locc_status st = launch_slot(S, sl);
@@ -289,6 +324,8 @@ locc_status locc_serve_start(locc_ctx* c, const locc_serve_config* cfg, const lo
   c->profiling = false;  // the worker thread must not touch the profiling lists
   S->upd_busy.assign(cfg->max_objects, 0);
   S->ref_busy.assign(cfg->max_objects, 0);
+  S->upd_blocked.assign(cfg->max_objects, 0);
+  S->ref_blocked.assign(cfg->max_objects, 0);
   S->slots.resize(slots);
   hipError_t e = hipMalloc(&S->d_objs, table);
   if (e == hipSuccess && n_objs > 0)

@@ -170,3 +170,39 @@ def test_poisson_stream_reports_latencies(torch, rs):
     say(f"  200 requests at 2000/s: p50 {np.percentile(lat, 50):.3f} ms, p99 {np.percentile(lat, 99):.3f} ms")
     assert np.all(lat > 0) and np.percentile(lat, 50) < 1000
     ctx.close()
+
+
+def test_waiting_requests_are_overtaken_only_on_disjoint_objects(torch, rs):
+    """Two versions of each of 40 requests on disjoint objects, submitted version after version: a
+    second version conflicts with its first (same objects) and must wait for it, while the other
+    requests may join the batch past it.  With one slot, strict first-in-first-out batches would
+    hold one environment change each (at least 40 batches); every result equals the request run
+    alone on its own poses."""
+    ctx = _ctx(rs, "bf16")
+    srv = B.Server(ctx, _table(rs), batching=True, slots=1, max_batch_pairs=16384, max_batch_updates=16384)
+    used, envs = set(), []   # 40 requests on pairwise disjoint objects
+    for req in rs.requests:
+        objs = set(req[0].tolist()) | set(np.asarray(req[3]).ravel().tolist())
+        if not objs & used:
+            used |= objs
+            envs.append(req)
+        if len(envs) == 40:
+            break
+    assert len(envs) == 40
+    rng = np.random.default_rng(7)
+    reqs = []
+    for req in envs:
+        ids, pos, quat, pairs = req
+        reqs.append(req)
+        reqs.append((ids, pos + rng.normal(0, 0.003, pos.shape).astype(np.float32), quat, pairs))
+    ids = [srv.submit(*_upd(rs, r)) for r in reqs]
+    res = _drain(srv, ids)
+    st = srv.stats()
+    srv.stop()
+    say(f"  {len(reqs)} requests in {st['batches']} batches")
+    assert st["completed"] == len(reqs) and st["batches"] < 20
+    for rid, req in zip(ids, reqs):
+        ref_out, ref_counts = _alone(torch, ctx, rs, req)
+        np.testing.assert_array_equal(res[rid][0], ref_out)
+        np.testing.assert_array_equal(res[rid][1], ref_counts)
+    ctx.close()
