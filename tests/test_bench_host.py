@@ -1,0 +1,48 @@
+"""bench.py's accounting on the host: the per-pair work matches the figures the
+measurement plan prints (FLOPs per pair with the fixed 2K encoder rows, crop
+bytes with and without the contact store), and a kernel entry turns synthetic
+launch times into rates and roofline fractions as stated."""
+
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import bench  # noqa: E402
+from paper_2304_09439_amd import inputs as I  # noqa: E402
+
+
+@pytest.mark.parametrize("K,widths,n_points,mflop,crop_b", [
+    (64, I.SMALL_WIDTHS, 1024, 2.462, 27_760),     # C0
+    (128, I.SCALE_WIDTHS, 2048, 18.227, 55_408),   # C1-C3
+    (128, I.SCALE_WIDTHS, 4096, 18.227, 104_560),  # C4 (4096 points per shape)
+])
+def test_per_pair_work_matches_the_plan(K, widths, n_points, mflop, crop_b):
+    w = bench.per_pair_work(K, widths, n_points)
+    assert (w["enc_flops"] + w["head_flops"]) / 1e6 == pytest.approx(mflop, abs=5e-4)
+    assert w["crop_bytes"] + w["contact_bytes"] == crop_b   # the contact store is charged to the head
+    assert w["row_flops"] * 2 * K == w["enc_flops"]
+
+
+def test_kernel_entries_rates_and_fractions():
+    w = bench.per_pair_work(128, I.SCALE_WIDTHS, 2048)
+    P, steps = 16384, 20
+    kt = {"crop": (steps, 0.1 * steps), "encoder_head_bf16": (steps, 0.2 * steps)}
+    rows = P * 2 * 96   # 96 of the 128 rows of every object in the tiles run
+    k = bench.kernel_entries(kt, w, P, "scale", steps, "bf16", full_scan=False, exec_rows=rows)
+    enc = k["encoder_head_bf16"]
+    flops = (w["enc_flops"] + w["head_flops"]) * P
+    assert enc["achieved"] == pytest.approx(flops / 0.2e-3 / 1e12, rel=1e-4)
+    assert enc["frac"] == pytest.approx(enc["achieved"] / 2500.0, rel=1e-3)
+    run = rows * w["row_flops"] + w["head_flops"] * P
+    assert enc["executed_TFLOPs"] == pytest.approx(run / 0.2e-3 / 1e12, rel=1e-4)
+    assert enc["executed_frac"] < enc["frac"]
+    crop = k["crop"]
+    assert crop["bound"] == "hbm"
+    assert crop["achieved"] == pytest.approx(w["crop_bytes"] * P / 0.1e-3 / 1e9, rel=1e-4)
+    assert crop["hbm_bytes_per_pair"] == 2 * 32 + 8 + 8 + 2 * 128 * 16
+    assert crop["hbm_GBps"] == pytest.approx(crop["hbm_bytes_per_pair"] * P / 0.1e-3 / 1e9, rel=1e-4)
+    k32 = bench.kernel_entries({"crop": (1, 0.1)}, w, P, "scale", 1, "fp32")
+    assert k32["crop"]["hbm_bytes_per_pair"] == 2 * 32 + 8 + 8 + 2 * 128 * 32
