@@ -54,6 +54,70 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Raw buffer view of n floats at p: a load at a byte offset >= 4n returns 0
+// and reads no memory (the buffer unit's range check), so the last, partial
+// block of a shape needs no per-lane branch.  Word 3 is the gfx9 raw-buffer
+// format word (32-bit data, no swizzle, no index stride).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t crop_view(const float* p, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, n * 4, 0x00020000);
+}
+__device__ __forceinline__ float crop_load(__amdgpu_buffer_rsrc_t v, int byte_offset) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v, byte_offset, 0, 0));
+}
+// A wave-uniform float copied once into a vector register, so that an fma
+// taking it with a scalar coefficient needs no copy per use (one scalar
+// operand per vector instruction).
+__device__ __forceinline__ float crop_to_vgpr(float s) {
+  float v;
+  asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
+// Membership scan of one object (B: the transformed object b) by one wave:
+// U blocks of 64 points per round, loads in flight together.  The wave tests
+// the blocks in stored order and keeps the number of members before each
+// block (a scalar), so a member's ordered position is that number plus its
+// rank in the block's ballot: the first K members are placed during the scan.
+// Without `full` the scan stops at the first block after which K members are
+// known.  Returns the members found (all of them when full, else at least
+// min(K, members)).
+template <int U, bool B>
+__device__ __forceinline__ int crop_scan(const PairSetup* __restrict__ rec, const PairScreen& sc, const float* px,
+                                         const float* py, const float* pz, int n, int K, bool full, int lane,
+                                         ObjectShared& S) {
+  const int nblk = (n + 63) >> 6;
+  int scanned = 0, found = 0;  // wave-uniform
+  while (scanned < nblk && (full || found < K)) {
+    const int base = scanned << 6;
+    const int rem = n - base;  // > 0 points from base on
+    const __amdgpu_buffer_rsrc_t vx = crop_view(px + base, rem), vy = crop_view(py + base, rem),
+                                 vz = crop_view(pz + base, rem);
+    float x[U], y[U], z[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int o = (64 * u + lane) * 4;
+      x[u] = crop_load(vx, o);
+      y[u] = crop_load(vy, o);
+      z[u] = crop_load(vz, o);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (scanned + u < nblk && (full || found < K)) {  // uniform
+        const int j = 64 * u + lane;  // point base + j
+        const bool in =
+            (B ? geo_member_b(&rec->g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u])) & (j < rem);
+        const unsigned long long m = __ballot(in);
+        const int pos = found + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (in && pos < K) S.sel[pos] = base + j;
+        found += __popcll(m);
+      }
+    }
+    scanned = scanned + U < nblk ? scanned + U : nblk;
+  }
+  return found;
+}
+
 template <int U, int W>
 __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
   __shared__ ObjectShared SW[W];
@@ -87,46 +151,18 @@ __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
   const int swapped = rec->swapped;
   const int n = side ? rec->n_b : rec->n_a;
   const int off = side ? rec->off_b : rec->off_a;
-  const PairScreen sc = rec->sc;
+  PairScreen sc = rec->sc;
   const bool full = A.counts_out != nullptr;  // else stop once K members are known
   const float* __restrict__ px = A.lib.px + off;
   const float* __restrict__ py = A.lib.py + off;
   const float* __restrict__ pz = A.lib.pz + off;
-
-  // membership scan: U blocks of 64 points per round, loads in flight
-  // together.  The wave tests the blocks in stored order and keeps the number
-  // of members before each block (a scalar), so a member's ordered position
-  // is that number plus its rank in the block's ballot: the first K members
-  // are placed during the scan.
-  const int nblk = (n + 63) >> 6;
-  int scanned = 0, found = 0;  // wave-uniform
-  while (scanned < nblk && (full || found < K)) {
-    float x[U], y[U], z[U];
+  int found;
+  if (side) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const unsigned k = ((unsigned)(scanned + u) << 6) + (unsigned)lane;
-      x[u] = y[u] = z[u] = 0.f;
-      if (k < (unsigned)n) {
-        x[u] = px[k];
-        y[u] = py[k];
-        z[u] = pz[k];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int blk = scanned + u;
-      if (blk < nblk) {  // uniform
-        const unsigned k = ((unsigned)blk << 6) + (unsigned)lane;
-        bool in = false;
-        if (k < (unsigned)n) in = side ? geo_member_b(&rec->g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u]);
-        const unsigned long long m = __ballot(in);
-        const int pos = found + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (in && pos < K) S.sel[pos] = (int)k;
-        found += __popcll(m);
-      }
-    }
-    scanned = scanned + U < nblk ? scanned + U : nblk;
+    for (int i = 0; i < 3; ++i) sc.t[i] = crop_to_vgpr(sc.t[i]);
+    found = crop_scan<U, true>(rec, sc, px, py, pz, n, K, full, lane, S);
+  } else {
+    found = crop_scan<U, false>(rec, sc, px, py, pz, n, K, full, lane, S);
   }
   // found: every member when full, else at least min(K, members)
   wave_lds_sync();  // the selected indices are read by other lanes

@@ -133,20 +133,25 @@ __device__ __forceinline__ int geo_wave_inclusive_scan(int v, int lane) {
 //  * a points are float32, so p >= lo (float64) holds iff p >= the smallest
 //    float >= lo, and p <= hi iff p <= the largest float <= hi: the a-side
 //    test is exact in float32 with outward-rounded bounds.
-//  * b points: q' = fma(R'_i2, z, fma(R'_i1, y, fma(R'_i0, x, t'_i))) with
-//    R', t' the float32 roundings of R_ab, t_ab differs from the float64 q_i
-//    by less than 2^-21 S_i, S_i = sum_j |R_ij| max|p_j| + |t_i|.  With the
-//    margin E_i = 2^-19 S_i + 2^-20 (|lo_i| + |hi_i|) (which also covers the
-//    rounding of the bounds to float32), q' inside [lo + E, hi - E] on every
-//    axis implies membership and q' outside [lo - E, hi + E] on some axis
-//    implies non-membership; only the points in between take the exact
-//    float64 test.  NaN bounds make every point undecided, and the exact
-//    test then rejects it.
+//  * b points are screened in the box's normalised coordinates
+//    u_i = (q_i - c_i) / h_i (c_i, h_i: centre and half-width of
+//    [lo_i, hi_i]), where membership is max_i |u_i| <= 1.  The map p -> u is
+//    rounded to float32 (R', t') and evaluated with fmas; u' differs from u by
+//    less than 2^-21 S'_i, S'_i = sum_j |R'_ij| max|p_j| + |t'_i|.  The float64
+//    q of the exact test and the float64 c, h move the boundary by less than
+//    (2^-50 S_i + 2^-52 (|lo_i| + |hi_i|)) / h_i, S_i being the same sum over
+//    R_ab, t_ab.  With M the largest over the axes of
+//    2^-19 (S'_i + (S_i + |lo_i| + |hi_i|) / h_i), max |u'| <= 1 - M implies
+//    membership and max |u'| > 1 + M non-membership; only the points in
+//    between take the exact float64 test.
+//  * A box with lo_i > hi_i or a NaN bound holds no point: every b point is
+//    screened out.  A box too thin to normalise (h_i < 2^-960, which
+//    includes lo_i == hi_i) or whose map is not finite screens nothing: every
+//    b point takes the exact test.
 struct PairScreen {
   float alo[3], ahi[3];           // exact a-side bounds
-  float R[9], t[3];               // float32 R_ab, t_ab
-  float in_lo[3], in_hi[3];       // definitely inside
-  float out_lo[3], out_hi[3];     // definitely outside beyond these
+  float R[9], t[3];               // float32 map from a b point to u
+  float thr_in, thr_out;          // max |u'| <= thr_in: member; > thr_out: not
 };
 
 // One float32 step towards +inf (up) or -inf (down) from a finite f.
@@ -175,20 +180,44 @@ __device__ __forceinline__ void geo_screen_values(const PairGeom& g, const Shape
   double P[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) P[k] = fmax(fabs((double)db.lo[k]), fabs((double)db.hi[k]));
+  bool empty = false, exact_only = false;
+  double M = 0.0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     sc.alo[i] = geo_f32_ceil(g.lo[i]);
     sc.ahi[i] = geo_f32_floor(g.hi[i]);
-    const double S = fabs(g.R[3 * i]) * P[0] + fabs(g.R[3 * i + 1]) * P[1] + fabs(g.R[3 * i + 2]) * P[2] + fabs(g.t[i]);
-    const double E = 0x1p-19 * S + 0x1p-20 * (fabs(g.lo[i]) + fabs(g.hi[i]));
-    sc.in_lo[i] = (float)(g.lo[i] + E);
-    sc.in_hi[i] = (float)(g.hi[i] - E);
-    sc.out_lo[i] = (float)(g.lo[i] - E);
-    sc.out_hi[i] = (float)(g.hi[i] + E);
-    sc.t[i] = (float)g.t[i];
-  }
+    const double lo = g.lo[i], hi = g.hi[i];
+    empty |= !(lo <= hi);
+    const double c = 0.5 * (lo + hi);
+    const double h = 0.5 * (hi - lo);
+    exact_only |= !(h >= 0x1p-960);
+    const double inv = 1.0 / h;
+    double S = fabs(g.t[i]), S2 = 0.0;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) sc.R[k] = (float)g.R[k];
+    for (int j = 0; j < 3; ++j) {
+      const float r = (float)(g.R[3 * i + j] * inv);
+      sc.R[3 * i + j] = r;
+      S += fabs(g.R[3 * i + j]) * P[j];
+      S2 += fabs((double)r) * P[j];
+    }
+    const float tt = (float)((g.t[i] - c) * inv);
+    sc.t[i] = tt;
+    S2 += fabs((double)tt);
+    const double m = 0x1p-19 * (S2 + (S + fabs(lo) + fabs(hi)) * inv);
+    exact_only |= !(m <= 0x1.fffffffffffffp+1023);  // inf or NaN
+    M = m > M ? m : M;
+  }
+  if (empty || exact_only) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sc.R[k] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) sc.t[i] = 0.f;
+    sc.thr_in = -1.f;                             // u' = 0: never inside
+    sc.thr_out = empty ? -1.f : __int_as_float(0x7f800000);  // always / never outside
+  } else {
+    sc.thr_in = geo_f32_floor(1.0 - M);
+    sc.thr_out = geo_f32_ceil(1.0 + M);
+  }
 }
 
 // Screening constants when every thread of the workgroup computed the same
@@ -199,14 +228,12 @@ __device__ __forceinline__ void geo_screen(const PairGeom& g, const ShapeDesc& d
   for (int i = 0; i < 3; ++i) {
     sc.alo[i] = geo_uniform(sc.alo[i]);
     sc.ahi[i] = geo_uniform(sc.ahi[i]);
-    sc.in_lo[i] = geo_uniform(sc.in_lo[i]);
-    sc.in_hi[i] = geo_uniform(sc.in_hi[i]);
-    sc.out_lo[i] = geo_uniform(sc.out_lo[i]);
-    sc.out_hi[i] = geo_uniform(sc.out_hi[i]);
     sc.t[i] = geo_uniform(sc.t[i]);
   }
 #pragma unroll
   for (int k = 0; k < 9; ++k) sc.R[k] = geo_uniform(sc.R[k]);
+  sc.thr_in = geo_uniform(sc.thr_in);
+  sc.thr_out = geo_uniform(sc.thr_out);
 }
 
 __device__ __forceinline__ bool geo_member_a(const PairScreen& sc, float x, float y, float z) {
@@ -231,10 +258,10 @@ __device__ __forceinline__ bool geo_member_b(const PairGeom* __restrict__ gp, co
   const float q0 = __builtin_fmaf(sc.R[2], z, __builtin_fmaf(sc.R[1], y, __builtin_fmaf(sc.R[0], x, sc.t[0])));
   const float q1 = __builtin_fmaf(sc.R[5], z, __builtin_fmaf(sc.R[4], y, __builtin_fmaf(sc.R[3], x, sc.t[1])));
   const float q2 = __builtin_fmaf(sc.R[8], z, __builtin_fmaf(sc.R[7], y, __builtin_fmaf(sc.R[6], x, sc.t[2])));
-  const bool in = (sc.in_lo[0] <= q0) & (q0 <= sc.in_hi[0]) & (sc.in_lo[1] <= q1) & (q1 <= sc.in_hi[1]) &
-                  (sc.in_lo[2] <= q2) & (q2 <= sc.in_hi[2]);
-  const bool out = (q0 < sc.out_lo[0]) | (q0 > sc.out_hi[0]) | (q1 < sc.out_lo[1]) | (q1 > sc.out_hi[1]) |
-                   (q2 < sc.out_lo[2]) | (q2 > sc.out_hi[2]);
+  // NaN only when a coordinate is NaN, and then on every axis: both tests fail
+  const float d = fmaxf(fmaxf(fabsf(q0), fabsf(q1)), fabsf(q2));
+  const bool in = d <= sc.thr_in;
+  const bool out = d > sc.thr_out;
   if (in | out) return in;
   return geo_member_b_exact(gp, x, y, z);
 }

@@ -106,6 +106,73 @@ def test_points_on_box_faces_are_members_on_the_gpu(torch):
     np.testing.assert_array_equal(idx[1], idx[0][::-1])
 
 
+def _near_face_scene(seed=5, n_pairs=32):
+    """Pairs whose b points land within float32 rounding of the crop-box faces
+    in a's frame, so that the b-side float32 screen leaves many of them to the
+    exact float64 test.  b's stored box is set by 8 far corners (the crop box is
+    then a's box widened by the pad) and b's frame origin lies up to 60 units
+    away, which widens the screen's undecided band."""
+    rng = np.random.default_rng(seed)
+    half = rng.uniform(0.3, 1.5, 3)
+    pts_a = np.concatenate([rng.uniform(-half, half, (64, 3)), rng.normal(size=(64, 3))], 1).astype(np.float32)
+    lo_a, hi_a = O.aabb(pts_a)
+    quat = rng.normal(size=(2 * n_pairs, 4)).astype(np.float32)
+    quat /= np.linalg.norm(quat, axis=1, keepdims=True)
+    pos = np.empty((2 * n_pairs, 3), np.float32)
+    pos[0::2] = rng.uniform(-20, 20, (n_pairs, 3))
+    pos[1::2] = pos[0::2] + rng.uniform(-60, 60, (n_pairs, 3))
+    shapes, offsets = [pts_a], [0, len(pts_a)]
+    for p in range(n_pairs):
+        Rab, tab = O.relative_pose(O.rotation(quat[2 * p]), pos[2 * p].astype(np.float64),
+                                   O.rotation(quat[2 * p + 1]), pos[2 * p + 1].astype(np.float64))
+        L = np.ceil(np.abs(tab).max()) + 4.0
+        corners = np.array([[sx, sy, sz] for sx in (-L, L) for sy in (-L, L) for sz in (-L, L)])
+        lo, hi = lo_a - O.PAD_M, hi_a + O.PAD_M
+        q = rng.uniform(lo, hi, (248, 3))
+        ax = rng.integers(0, 3, 248)
+        side = rng.integers(0, 2, 248)
+        q[np.arange(248), ax] = np.where(side == 1, hi[ax], lo[ax])
+        q[:8] = np.array([[(lo, hi)[(c >> k) & 1][k] for k in range(3)] for c in range(8)])  # box corners
+        pb = ((q - tab) @ Rab).astype(np.float32)  # Rab^T (q - tab), rounded
+        xyz = np.concatenate([corners.astype(np.float32), pb])
+        shapes.append(np.concatenate([xyz, rng.normal(size=(len(xyz), 3))], 1).astype(np.float32))
+        offsets.append(offsets[-1] + len(xyz))
+    lib = I.ShapeLibrary(np.concatenate(shapes), np.array(offsets, np.int64), np.full(len(shapes), np.nan, np.float32))
+    shape = np.zeros(2 * n_pairs, np.int32)
+    shape[1::2] = np.arange(1, n_pairs + 1)
+    pairs = np.stack([np.arange(0, 2 * n_pairs, 2), np.arange(1, 2 * n_pairs, 2)], 1).astype(np.int32)
+    return I.Scene(lib, pos, quat, shape, pairs)
+
+
+def test_b_points_on_rotated_box_faces_match_oracle(torch):
+    sc = _near_face_scene()
+    say("crop parity: b points within rounding of rotated crop-box faces, K=256")
+    idx, counts = _run_crop(torch, sc, 256, SMALL)
+    _, ridx, rcounts = O.crop(sc.lib.pts, sc.lib.offsets, sc.pos, sc.quat, sc.shape, sc.pairs, 256)
+    nb = rcounts[:, 1]
+    assert nb.min() >= 8 and (nb < 256).all() and (nb > 8 + 40).all()  # near-face points fall on both sides
+    np.testing.assert_array_equal(counts, rcounts)
+    np.testing.assert_array_equal(idx, ridx)   # every b member, in order
+
+
+def test_flat_and_separated_boxes_match_oracle(torch):
+    """A zero-width crop box (coplanar flat shapes, no pad) takes every b point
+    to the exact test; a pair whose boxes do not overlap has an empty box."""
+    rng = np.random.default_rng(9)
+    flat = np.concatenate([rng.uniform(-1, 1, (100, 2)), np.zeros((100, 1)), rng.normal(size=(100, 3))], 1)
+    flat = flat.astype(np.float32)
+    lib = I.ShapeLibrary(flat, np.array([0, 100], np.int64), np.full(1, np.nan, np.float32))
+    pos = np.array([[0, 0, 0], [0.5, 0.25, 0], [0, 0, 0], [40, 0, 0]], np.float32)
+    quat = np.tile(np.float32([1, 0, 0, 0]), (4, 1))
+    sc = I.Scene(lib, pos, quat, np.zeros(4, np.int32), np.array([[0, 1], [2, 3]], np.int32))
+    say("crop parity: coplanar flat shapes with pad 0, and a separated pair")
+    idx, counts = _run_crop(torch, sc, 128, SMALL, pad=0.0)
+    _, ridx, rcounts = O.crop(sc.lib.pts, sc.lib.offsets, sc.pos, sc.quat, sc.shape, sc.pairs, 128, pad=0.0)
+    assert rcounts[0, 1] > 20 and list(rcounts[1]) == [0, 0]
+    np.testing.assert_array_equal(counts, rcounts)
+    np.testing.assert_array_equal(idx, ridx)
+
+
 # ------------------------------------------------------------------ forward
 
 @pytest.mark.parametrize("bias", [0.0, 0.1])
