@@ -10,7 +10,9 @@
 namespace locc {
 namespace {
 
-constexpr int kThreads = 256;
+// one thread per pair, 64 per workgroup: a batch of 16384 pairs spreads over
+// 256 workgroups, one per compute unit, for this latency-bound float64 work
+constexpr int kThreads = 64;
 constexpr int kCropWaves = 2;  // object waves per workgroup of the crop kernel (1, 2, 4, 8 measured: 2 fastest)
 
 __global__ __launch_bounds__(kThreads) void pair_setup_kernel(CropArgs A) {
