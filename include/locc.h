@@ -222,7 +222,8 @@ typedef struct {
   int32_t claim;
   int32_t dynamic;
   int32_t split;
-  int32_t crop_unroll; /* 2, 4 or 8: 64-point blocks whose loads a crop wave issues together */
+  int32_t crop_unroll; /* 2, 4 or 8: a crop wave issues the loads of max(1, crop_unroll / 4)
+                          blocks of 256 stored points together (2 and 4 run the same kernel) */
   int32_t chunks;
   int32_t reserved[2]; /* must be 0 */
 } locc_schedule;

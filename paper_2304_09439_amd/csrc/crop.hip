@@ -66,6 +66,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t crop_view(const float* p, int 
 __device__ __forceinline__ float crop_load(__amdgpu_buffer_rsrc_t v, int byte_offset) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v, byte_offset, 0, 0));
 }
+__device__ __forceinline__ float4 crop_load4(__amdgpu_buffer_rsrc_t v, int byte_offset) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(v, byte_offset, 0, 0));
+}
 // A wave-uniform float copied once into a vector register, so that an fma
 // taking it with a scalar coefficient needs no copy per use (one scalar
 // operand per vector instruction).
@@ -75,47 +78,72 @@ __device__ __forceinline__ float crop_to_vgpr(float s) {
   return v;
 }
 
-// Membership scan of one object (B: the transformed object b) by one wave:
-// U blocks of 64 points per round, loads in flight together.  The wave tests
-// the blocks in stored order and keeps the number of members before each
-// block (a scalar), so a member's ordered position is that number plus its
-// rank in the block's ballot: the first K members are placed during the scan.
-// Without `full` the scan stops at the first block after which K members are
-// known.  Returns the members found (all of them when full, else at least
-// min(K, members)).
-template <int U, bool B>
+// Membership scan of one object (B: the transformed object b) by one wave,
+// over blocks of 256 stored points: lane l holds points 4l .. 4l + 3 of a
+// block, fetched by one 16-byte load per coordinate (a quarter of the
+// address-unit work of one load per point), QU blocks' loads in flight
+// together.  The wave tests the blocks in stored order and keeps the number of
+// members before each block (a scalar), so a member's ordered position is that
+// number, plus the members of the lanes below it (one ballot per point slot),
+// plus its own members before it: the first K members are placed during the
+// scan.  Without `full` the scan stops at the first block after which K
+// members are known.  Returns the members found (all of them when full, else
+// at least min(K, members)).
+template <int QU, bool B>
 __device__ __forceinline__ int crop_scan(const PairSetup* __restrict__ rec, const PairScreen& sc, const float* px,
                                          const float* py, const float* pz, int n, int K, bool full, int lane,
                                          ObjectShared& S) {
-  const int nblk = (n + 63) >> 6;
+  const int nblk = (n + 255) >> 8;
   int scanned = 0, found = 0;  // wave-uniform
   while (scanned < nblk && (full || found < K)) {
-    const int base = scanned << 6;
+    const int base = scanned << 8;
     const int rem = n - base;  // > 0 points from base on
     const __amdgpu_buffer_rsrc_t vx = crop_view(px + base, rem), vy = crop_view(py + base, rem),
                                  vz = crop_view(pz + base, rem);
-    float x[U], y[U], z[U];
+    float4 X[QU], Y[QU], Z[QU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int o = (64 * u + lane) * 4;
-      x[u] = crop_load(vx, o);
-      y[u] = crop_load(vy, o);
-      z[u] = crop_load(vz, o);
+    for (int u = 0; u < QU; ++u) {
+      const int o = (256 * u + 4 * lane) * 4;
+      X[u] = crop_load4(vx, o);
+      Y[u] = crop_load4(vy, o);
+      Z[u] = crop_load4(vz, o);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
+    for (int u = 0; u < QU; ++u) {
       if (scanned + u < nblk && (full || found < K)) {  // uniform
-        const int j = 64 * u + lane;  // point base + j
-        const bool in =
-            (B ? geo_member_b(&rec->g, sc, x[u], y[u], z[u]) : geo_member_a(sc, x[u], y[u], z[u])) & (j < rem);
-        const unsigned long long m = __ballot(in);
-        const int pos = found + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                               __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (in && pos < K) S.sel[pos] = base + j;
-        found += __popcll(m);
+        const int j0 = 256 * u + 4 * lane;  // this lane's first point: base + j0
+        const int left = rem - j0;          // of its four points, those below n
+        float x[4] = {X[u].x, X[u].y, X[u].z, X[u].w};
+        float y[4] = {Y[u].x, Y[u].y, Y[u].z, Y[u].w};
+        float z[4] = {Z[u].x, Z[u].y, Z[u].z, Z[u].w};
+        if (left > 0 && left < 4) {  // the shape's last, partial four: point by point
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            x[k] = crop_load(vx, (j0 + k) * 4);
+            y[k] = crop_load(vy, (j0 + k) * 4);
+            z[k] = crop_load(vz, (j0 + k) * 4);
+          }
+        }
+        bool in[4];
+        unsigned long long m[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          in[k] = (B ? geo_member_b(&rec->g, sc, x[k], y[k], z[k]) : geo_member_a(sc, x[k], y[k], z[k])) & (k < left);
+          m[k] = __ballot(in[k]);
+        }
+        unsigned pos = (unsigned)found;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          pos = __builtin_amdgcn_mbcnt_hi((unsigned)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[k], pos));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (in[k] && (int)pos < K) S.sel[pos] = base + j0 + k;
+          pos += in[k] ? 1u : 0u;
+        }
+        found += __popcll(m[0]) + __popcll(m[1]) + __popcll(m[2]) + __popcll(m[3]);
       }
     }
-    scanned = scanned + U < nblk ? scanned + U : nblk;
+    scanned = scanned + QU < nblk ? scanned + QU : nblk;
   }
   return found;
 }
@@ -162,9 +190,9 @@ __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
   if (side) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) sc.t[i] = crop_to_vgpr(sc.t[i]);
-    found = crop_scan<U, true>(rec, sc, px, py, pz, n, K, full, lane, S);
+    found = crop_scan<(U >= 8 ? 2 : 1), true>(rec, sc, px, py, pz, n, K, full, lane, S);
   } else {
-    found = crop_scan<U, false>(rec, sc, px, py, pz, n, K, full, lane, S);
+    found = crop_scan<(U >= 8 ? 2 : 1), false>(rec, sc, px, py, pz, n, K, full, lane, S);
   }
   // found: every member when full, else at least min(K, members)
   wave_lds_sync();  // the selected indices are read by other lanes

@@ -92,6 +92,29 @@ def test_crop_matches_oracle_on_tiny_shapes_and_non_unit_quaternions(torch, K):
     np.testing.assert_array_equal(idx, ridx)
 
 
+@pytest.mark.parametrize("K", [32, 64])
+def test_crop_matches_oracle_on_ragged_shape_sizes(torch, K):
+    """Shape sizes that end inside a lane's group of four points and inside a
+    256-point block, on both objects of a pair."""
+    rng = np.random.default_rng(41)
+    sizes = [1, 2, 3, 5, 6, 7, 63, 65, 255, 257, 258, 259, 513, 1023]
+    half = rng.uniform(0.05, 0.3, (len(sizes), 3))
+    pts = [np.concatenate([rng.uniform(-h, h, (m, 3)), rng.normal(size=(m, 3))], 1) for h, m in zip(half, sizes)]
+    lib = I.ShapeLibrary(np.concatenate(pts).astype(np.float32), np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64),
+                         np.full(len(sizes), np.nan, np.float32))
+    n = 300
+    sa, sb = rng.integers(0, len(sizes), n), rng.integers(0, len(sizes), n)
+    ta, qa, tb, qb = I.overlapping_pair_poses(rng, lib, sa, sb)
+    sc = I._pack_pair_scene(lib, ta, qa, tb, qb, sa.astype(np.int32), sb.astype(np.int32),
+                            I._interleave_pairs(rng, n))
+    say(f"crop parity: ragged shape sizes, K={K}")
+    idx, counts = _run_crop(torch, sc, K, SMALL)
+    _, ridx, rcounts = O.crop(sc.lib.pts, sc.lib.offsets, sc.pos, sc.quat, sc.shape, sc.pairs, K)
+    assert (rcounts % 4 != 0).sum() > 50 and (rcounts > K).sum() > 20
+    np.testing.assert_array_equal(counts, rcounts)
+    np.testing.assert_array_equal(idx, ridx)
+
+
 def test_points_on_box_faces_are_members_on_the_gpu(torch):
     import test_oracle_geometry as TG
     pa, pb = TG._on_face_shapes()
