@@ -57,9 +57,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Raw buffer view of n floats at p: a load at a byte offset >= 4n returns 0
-// and reads no memory (the buffer unit's range check), so the last, partial
-// block of a shape needs no per-lane branch.  Word 3 is the gfx9 raw-buffer
-// format word (32-bit data, no swizzle, no index stride).
+// and reads no memory (the buffer unit's range check), so lanes past a
+// shape's last point need no branch of their own.  Word 3 is the gfx9
+// raw-buffer format word (32-bit data, no swizzle, no index stride).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t crop_view(const float* p, int n) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, n * 4, 0x00020000);
 }

@@ -87,8 +87,9 @@ struct CropArgs {
 // order) the pair set-up kernel writes for the crop kernel.
 constexpr size_t kPairSetupBytes = 320;
 
-// Pair set-up (one thread per pair), then the crop (one workgroup per pair).
-// unroll: blocks of 64 points whose loads a wave issues together (2, 4 or 8)
+// Pair set-up (one thread per pair), then the crop (one wave per object of a
+// pair, the two waves of a pair in one workgroup).  unroll (2, 4 or 8): a
+// wave issues the loads of max(1, unroll / 4) blocks of 256 points together.
 hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll = 8);
 
 // Broad phase over environments: world boxes, then every overlapping pair
