@@ -364,10 +364,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
           f32x16 acc2[CT];
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) acc2[ct] = f32x16{};
+          __builtin_amdgcn_s_setprio(1);  // issue priority while this wave feeds the matrix core
 #pragma unroll
           for (int s = 0; s < KS2; ++s)
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct) acc2[ct] = mfma_k16(av[s], w2f[ct][s], acc2[ct]);
+          __builtin_amdgcn_s_setprio(0);
           if (more) layer1_store((t + 1) & 1);
           const int r0 = 32 * t;
           if (r0 + 32 <= m) {
