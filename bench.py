@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 METRIC = "pair-CD queries/sec at 1 GPU (BF16 batched vs FP32 plain); p99 step latency"
 UNIT = "pair-queries/s"
 
+# step-latency percentiles are taken over at least this many steps
+LATENCY_SAMPLES = 200
+
 # MI355X published peaks
 PEAK_HBM_GBPS = 8000.0
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
@@ -125,8 +128,33 @@ def _cpu_chunk(rows):
     return len(rows)
 
 
-def cpu_baseline(scene, w, widths, K, n_pairs):
-    """The oracle on the first n_pairs pairs over a fork pool (one BLAS thread per worker)."""
+def cpu_model() -> str:
+    """The host CPU's model name as /proc/cpuinfo gives it."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _one_core(scene, w, widths, K, rows):
+    """The oracle on `rows` of `scene` in this process with one BLAS thread; pairs/s."""
+    from threadpoolctl import threadpool_limits
+    from oracle import locc_oracle as O
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        O.detect_scene(scene, w, (widths.h1, widths.h2, widths.hh), K, rows=rows)
+        dt = time.perf_counter() - t0
+    return len(rows) / dt, dt
+
+
+def cpu_baseline(scene, w, widths, K, n_pairs, small=None, single_pairs=1024):
+    """The oracle on the host: the first n_pairs pairs over a fork pool (one BLAS thread per worker, all
+    affinity cores up to 16), then on one core the first `single_pairs` pairs of the same workload and, when
+    given, the whole small workload (small = (scene, weights, widths, K))."""
     import multiprocessing as mp
     import numpy as np
     _CPU.update(scene=scene, w=w, widths=(widths.h1, widths.h2, widths.hh), K=K)
@@ -138,64 +166,88 @@ def cpu_baseline(scene, w, widths, K, n_pairs):
     with ctx.Pool(workers) as pool:
         done = sum(pool.map(_cpu_chunk, chunks))
     dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit=UNIT, cores=workers, kind="oracle",
+    single = {}
+    rate, t1 = _one_core(scene, w, widths, K, np.arange(min(single_pairs, scene.n_pairs)))
+    single["scale_pairs_0_%d" % min(single_pairs, scene.n_pairs)] = dict(value=round(rate, 1), unit=UNIT,
+                                                                        seconds=round(t1, 2))
+    if small is not None:
+        s_scene, s_w, s_widths, s_K = small
+        rate, t1 = _one_core(s_scene, s_w, s_widths, s_K, np.arange(s_scene.n_pairs))
+        single["small_all_%d_pairs" % s_scene.n_pairs] = dict(value=round(rate, 1), unit=UNIT, seconds=round(t1, 2))
+    return dict(value=done / dt, unit=UNIT, cores=workers, kind="oracle", cpu_model=cpu_model(),
+                affinity_cores=len(os.sched_getaffinity(0)),
                 sample=f"first {done} pairs of the same workload, float64 NumPy oracle (crop + network + "
-                       f"outputs), {workers} worker processes x 1 BLAS thread, {dt:.2f} s wall")
+                       f"outputs), {workers} worker processes x 1 BLAS thread, {dt:.2f} s wall",
+                single_core=single)
 
 
 # ------------------------------------------------------------------ GPU run
 
-def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True, exec_rows=None):
-    """Per kernel: average launch duration and the algorithmic rate of one launch (a step of P pairs may
-    run a kernel several times, once per chunk of pairs)."""
+def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True, rows=None):
+    """Per kernel: average launch duration and the rate of one launch (a step of P pairs may run a kernel
+    several times, once per chunk of pairs).
+
+    Encoder kernels are charged the method's own work: `rows` = (valid, tiles), the encoder rows of the
+    step's objects, valid = min(count, K) per object (the rows the method defines), tiles = those rows
+    rounded up to the 32-row tiles the kernels run.  `frac` is on the valid rows (plus the head on every
+    pair); the fixed-2K-row count of the measurement plan and the tile count are reported beside it.
+    The crop is charged the HBM bytes it has to move (poses, pair, counts, the 2K rows it writes in this
+    path's format); its scans read the shape library from L2 and stop at K members unless member counts
+    are requested, so their algorithmic byte rate is reported without a fraction."""
     kernels = {}
     for name, (launches, total_ms) in sorted(kt.items()):
         avg = total_ms / max(launches, 1)
         P_launch = P * steps / max(launches, 1)
         entry = dict(avg_ms=round(avg, 4), launches=int(launches), pairs_per_launch=round(P_launch, 1))
         if name == "crop":
-            # algorithmic bytes (the denominator of the roofline): full scans of both objects, the 2K
-            # gathered rows, poses, pair, counts.  Beside it, what a crop has to move through HBM (poses,
-            # pair, counts, the 2K rows it writes in this path's format): the scans read the 1.5 MB shape
-            # library from L2.
-            achieved = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
             row_bytes = 32 if precision == "fp32" else 16
             hbm = 2 * 32 + 8 + 8 + 2 * work["K"] * row_bytes
             hbm_rate = hbm * P_launch / (avg * 1e-3) / 1e9
-            entry.update(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
-                         frac=round(achieved / PEAK_HBM_GBPS, 4),
-                         bytes_basis="algorithmic: full scans of both objects (2N x 12 B per pair) + 2K gathered rows "
-                                     "(24 B) + poses, pair, counts; the scans read the shape library from L2" + (
-                                         "" if full_scan else ", and without member counts each scan stops at K "
-                                                              "members, so the rate exceeds the HBM peak"),
-                         hbm_bytes_per_pair=hbm, hbm_GBps=round(hbm_rate, 1),
-                         hbm_frac=round(hbm_rate / PEAK_HBM_GBPS, 4))
+            scan_rate = work["crop_bytes"] * P_launch / (avg * 1e-3) / 1e9
+            entry.update(bound="hbm", achieved=round(hbm_rate, 1), peak=PEAK_HBM_GBPS, unit="GB/s",
+                         frac=round(hbm_rate / PEAK_HBM_GBPS, 4), hbm_bytes_per_pair=hbm,
+                         bytes_basis="HBM bytes a crop moves: poses, pair, counts and the 2K encoder rows it writes; "
+                                     "the kernel is bound by the latency of its dependent scan-select-gather chain, "
+                                     "not by bandwidth",
+                         scan_GBps=round(scan_rate, 1),
+                         scan_basis="the measurement plan's algorithmic bytes (full scans of both objects, 2N x 12 B "
+                                    "per pair, + 2K gathered rows + poses, pair, counts) per launch time; the scans "
+                                    "read the shape library from L2" + (
+                                        "" if full_scan else " and stop at K members without member counts"))
         else:
-            if name.startswith("encoder_head") or name.startswith("fused"):
-                flops = (work["enc_flops"] + work["head_flops"]) * P_launch
-            elif name.startswith("encoder"):
-                flops = work["enc_flops"] * P_launch
-            elif name.startswith("head"):
-                flops = work["head_flops"] * P_launch
-            if name.startswith("fused"):  # crop inside: its bytes too
-                gbps = (work["crop_bytes"] + work["contact_bytes"]) * P_launch / (avg * 1e-3) / 1e9
-                entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
+            enc = name.startswith("encoder") or name.startswith("fused")
+            with_head = name.startswith("encoder_head") or name.startswith("fused")
             prec = name.split("_")[-1]
-            achieved = flops / (avg * 1e-3) / 1e12
-            entry.update(bound="mfma", achieved=round(achieved, 2), peak=PEAK_TFLOPS[prec], unit="TFLOP/s",
-                         frac=round(achieved / PEAK_TFLOPS[prec], 4))
-            if exec_rows is not None and not name.startswith("head"):
-                # the kernels skip the 32-row tiles past each object's member count: the work they run
-                run = exec_rows * work["row_flops"] * P_launch / P
-                if name.startswith("encoder_head") or name.startswith("fused"):
-                    run += work["head_flops"] * P_launch
-                ex = run / (avg * 1e-3) / 1e12
-                entry.update(executed_TFLOPs=round(ex, 2), executed_frac=round(ex / PEAK_TFLOPS[prec], 4),
-                             executed_basis="encoder rows in the 32-row tiles run (min(count, K) per object rounded "
-                                            "up to 32), head on every pair")
+            peak = PEAK_TFLOPS[prec]
+            head = work["head_flops"] * P_launch if (with_head or name.startswith("head")) else 0.0
+            fixed = (work["enc_flops"] * P_launch if enc else 0.0) + head
+            if enc and rows is not None:
+                valid = rows[0] * work["row_flops"] * P_launch / P + head
+                tiles = rows[1] * work["row_flops"] * P_launch / P + head
+            else:
+                valid = tiles = fixed
+            rate = lambda f: f / (avg * 1e-3) / 1e12
+            entry.update(bound="mfma", achieved=round(rate(valid), 2), peak=peak, unit="TFLOP/s",
+                         frac=round(rate(valid) / peak, 4),
+                         flops_basis=("encoder rows min(count, K) per object (the method's crop sets) + head on "
+                                      "every pair" if enc else "head on every pair"),
+                         fixed_2K_TFLOPs=round(rate(fixed), 2), fixed_2K_frac=round(rate(fixed) / peak, 4),
+                         tiles_run_TFLOPs=round(rate(tiles), 2), tiles_run_frac=round(rate(tiles) / peak, 4))
+            if name.startswith("fused"):  # crop inside: its HBM bytes too
+                gbps = (2 * 32 + 8 + 8 + work["contact_bytes"]) * P_launch / (avg * 1e-3) / 1e9
+                entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
         entry["traffic"] = counter_traffic(f"crop_{precision}" if name == "crop" else name, workload_name)
         kernels[name] = entry
     return kernels
+
+
+def encoder_rows(counts, K):
+    """(valid, tiles): encoder rows min(count, K) summed over the objects of the valid pairs, and the same
+    rounded up per object to the 32-row tiles the kernels run."""
+    import numpy as np
+    c = counts[counts[:, 0] >= 0]
+    c = np.clip(c, 0, K)
+    return int(c.sum()), int((((c + 31) // 32) * 32).sum())
 
 
 def time_path(args, scene, K, widths, w, precision, work, workload_name):
@@ -225,20 +277,25 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     torch.cuda.synchronize()
     print(f"[bench] {precision}: warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs",
           file=sys.stderr, flush=True)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ev[k][0].record(stream)
         ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
-        ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.profile(False)
     kt = ctx.profile_read()
+    # step latency percentiles from their own run of at least LATENCY_SAMPLES steps, each between two events
+    n_lat = max(LATENCY_SAMPLES, args.steps)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
+    for k in range(n_lat):
+        ev[k][0].record(stream)
+        ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    extra = {}
+    extra = {"latency_samples": n_lat}
     full = counts
     if counts is None:   # the same schedule with member counts requested (every point of both objects tested)
         full = torch.empty((P, 2), dtype=torch.int32, device="cuda")
@@ -251,12 +308,10 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
         extra["ms_per_step_with_member_counts"] = round(1000.0 * (time.perf_counter() - t1) / args.steps, 4)
     n_bad = ctx.device_errors()
     ctx.close()
-    c = full.cpu().numpy()
-    c = np.clip(c[c[:, 0] >= 0], 0, K)
-    exec_rows = int((((c + 31) // 32) * 32).sum())   # encoder rows in the row tiles the kernels run
+    rows = encoder_rows(full.cpu().numpy(), K)
     ms = 1000.0 * wall / args.steps
     kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision, full_scan=counts is not None,
-                             exec_rows=exec_rows)
+                             rows=rows)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
@@ -652,7 +707,11 @@ def run(args):
     w = I.flatten_weights(I.gaussian_weights(widths, seed=0))
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, w, widths, K, args.cpu_pairs)   # before the GPU is touched
+        small = None
+        if args.workload == "scale":
+            S = workload("small")
+            small = (S["scene"], I.flatten_weights(I.gaussian_weights(S["widths"], seed=0)), S["widths"], S["K"])
+        cpu = cpu_baseline(scene, w, widths, K, args.cpu_pairs, small=small)   # before the GPU is touched
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -673,6 +732,9 @@ def run(args):
     d = kernels[dominant]
     roofline = dict(kernel=dominant, bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
                     frac=d["frac"], traffic=d["traffic"])
+    for k in ("flops_basis", "fixed_2K_frac", "tiles_run_frac"):
+        if k in d:
+            roofline[k] = d[k]
     line = dict(
         metric=METRIC, value=main_path["value"], unit=UNIT, n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=main_path["ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -775,7 +837,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the library's default schedule")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving workload (0 = skip)")
-    ap.add_argument("--env-steps", type=int, default=40,
+    ap.add_argument("--env-steps", type=int, default=200,
                     help="simulation steps of the uneven-environment workload to time (0 = skip)")
     ap.add_argument("--cpu-pairs", type=int, default=16384)
     ap.add_argument("--no-voxel", action="store_true", help="skip the voxel-embedding variant's leg")

@@ -52,7 +52,8 @@ typedef enum {
   LOCC_ERR_HIP = -3,         /* a HIP runtime call failed (message has the HIP error) */
   LOCC_ERR_NOT_READY = -4,   /* detect before shapes and weights were uploaded */
   LOCC_ERR_RANGE = -5,       /* a size exceeds a library limit */
-  LOCC_ERR_BUSY = -6,        /* serving: request does not fit the memory budget now; retry */
+  LOCC_ERR_BUSY = -6,        /* serving: request does not fit the memory budget now (retry); or a captured
+                                graph still holds what the call would change (see locc_graph_capture) */
   LOCC_ERR_UNSUPPORTED = -7  /* widths / K / precision combination not compiled in */
 } locc_status;
 
@@ -132,7 +133,8 @@ LOCC_API void locc_destroy(locc_ctx* ctx);
  * n_floats must equal the total.  The encoder input row is
  * (x, y, z, nx, ny, nz) in a's frame; the head input is [f_a, f_b].
  * Low precisions quantise from these values (per-layer scales for FP8).
- * Errors: INVALID_ARG (null, wrong n_floats, non-finite value), OOM, HIP. */
+ * Errors: INVALID_ARG (null, wrong n_floats, non-finite value), BUSY (FP8
+ * context with a captured graph alive, see locc_graph_capture), OOM, HIP. */
 LOCC_API locc_status locc_upload_weights(locc_ctx* ctx, const float* h_weights, size_t n_floats);
 
 /* FP8 contexts: activation scales of the quantised encoder and head layers
@@ -152,7 +154,8 @@ LOCC_API locc_status locc_upload_weights(locc_ctx* ctx, const float* h_weights, 
  * >= 0; 0 means the activation is always 0).  locc_upload_weights clears
  * them: calibrate again after new weights.
  * Errors: INVALID_ARG (null, bad values), UNSUPPORTED (not an FP8 context),
- * NOT_READY (no shapes or weights), RANGE (during graph capture), OOM, HIP. */
+ * NOT_READY (no shapes or weights), RANGE (during graph capture), BUSY (a
+ * captured graph alive, see locc_graph_capture), OOM, HIP. */
 LOCC_API locc_status locc_calibrate(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs, const int32_t* d_pairs,
                            int32_t n_pairs, void* stream, float* h_amax_out);
 LOCC_API locc_status locc_set_activation_amax(locc_ctx* ctx, const float* h_amax);
@@ -164,7 +167,8 @@ LOCC_API locc_status locc_set_activation_amax(locc_ctx* ctx, const float* h_amax
  * every shape has at least one point; total < 2^31.  The per-shape
  * axis-aligned box is the min/max of the stored xyz.  Shape ids are 0..n-1.
  * Errors: INVALID_ARG (null, bad offsets, empty shape, non-finite value),
- * RANGE (too many points), OOM, HIP. */
+ * RANGE (too many points), BUSY (a captured graph alive, see
+ * locc_graph_capture), OOM, HIP. */
 LOCC_API locc_status locc_upload_shapes(locc_ctx* ctx, int32_t n_shapes, const int64_t* h_offsets,
                                const float* h_points);
 
@@ -268,7 +272,17 @@ LOCC_API locc_status locc_detect_device_count(locc_ctx* ctx, const locc_object* 
  * asynchronous copies on the launch stream before locc_graph_launch).
  * Capture uses a stream of the library's own, reserves the workspace first,
  * and records no memset node.  The schedule in force at capture time is the
- * one replayed.  Errors: INVALID_ARG, NOT_READY, OOM, HIP. */
+ * one replayed.
+ * Lifetime: a graph holds the context's workspace, broad-phase scratch,
+ * shape library and (FP8) scales as they were at capture.  While any graph
+ * of a context exists, calls that would move or change them are refused and
+ * touch nothing: a detect, broad phase, pose-gradient or training call that
+ * needs more workspace or scratch (RANGE: reserve enough before capturing),
+ * locc_upload_shapes, and on FP8 contexts locc_upload_weights,
+ * locc_set_activation_amax and locc_calibrate (BUSY).  FP32 and BF16 weights
+ * are rewritten in place, and replays after an upload use the new weights.
+ * Destroy every graph of a context before the context.
+ * Errors: INVALID_ARG, NOT_READY, OOM, HIP. */
 typedef struct locc_graph locc_graph;
 LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
                                         const int32_t* d_pairs, const int32_t* d_n_pairs, int32_t max_pairs,

@@ -1,4 +1,4 @@
-"""CPU model of the library's FP8 network arithmetic.  TEST INFRASTRUCTURE ONLY.
+"""CPU model of the library's BF16 and FP8 network arithmetic.  TEST INFRASTRUCTURE ONLY.
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this module; the product path never calls it and shares no code with
@@ -25,9 +25,19 @@ with a model written from the number formats, not from the kernel.
       e4m3(min(ReLU(h), 448)); encoder layer 2 e4m3 x e4m3, the max-pool on
       the unscaled sums, then scale s_x s_W2, bias and ReLU; head layers 1 and
       2 e4m3 x e4m3; head layer 2's output rounded to bf16; head layer 3 bf16
-      x bf16.  Every sum is float32 in the kernel; here sums are
-      float64 and the result is rounded to float32 where a quantisation
-      decision follows, so both sides take each decision in float32.
+      x bf16.  A head layer that is not e4m3 runs as in Q5 (its input and
+      weights bf16), so the variant with only encoder layer 2 in e4m3 has the
+      BF16 head.
+  Q5  the BF16 variant: every layer bf16 x bf16.  Encoder layer 1 on rows
+      rounded float64 -> float32 -> bf16 with bf16(W1) and bf16(b1) (the bias
+      enters the sum as a product with the constant input 1), output ReLU then
+      bf16; encoder layer 2 with bf16(W2), the max-pool on the raw sums, then
+      + b2 (float32) and ReLU, giving the pooled feature f in float32; the
+      head on bf16(f): g1 = bf16(ReLU(bf16(H1) . + c1)), g2 likewise with H2
+      and c2, y = bf16(H3) g2 + c3, biases c1..c3 float32.
+  Every sum is float32 in the kernels; here sums are float64 and the result is
+  rounded to float32 where a quantisation decision follows, so both sides
+  take each decision in float32.
 """
 
 from __future__ import annotations
@@ -105,11 +115,18 @@ def calibrate(geoms, weights_flat, widths):
     return np.array([m_h, m_z, m_g], np.float32)
 
 
-def fp8_forward(geoms, weights_flat, widths, amax, quantise=True):
+FP8_ALL = ("enc2", "head1", "head2")
+
+
+def fp8_forward(geoms, weights_flat, widths, amax, quantise=True, fp8_layers=FP8_ALL):
     """Q1-Q4: raw head outputs y [P, 8] (a's frame) and pooled features z
     [P, 2 h2] (float32 values before their quantisation); NaN for invalid
-    pairs.  quantise=False replaces every rounding by the identity (the
-    scales stay), which must give the full-precision network back."""
+    pairs.  fp8_layers names the layers run e4m3 x e4m3 (encoder layer 2 is
+    always one of them); the others run as in Q5.  quantise=False replaces
+    every rounding by the identity (the scales stay), which must give the
+    full-precision network back."""
+    if "enc2" not in fp8_layers:
+        raise ValueError("the FP8 variants all run encoder layer 2 in e4m3")
     h1w, h2w, hhw = widths
     W1, b1, W2, b2, H1, c1, H2, c2, H3, c3 = [f32(w) for w in O.unpack_weights(weights_flat, h1w, h2w, hhw)]
     qb = bf16 if quantise else f32
@@ -120,8 +137,9 @@ def fp8_forward(geoms, weights_flat, widths, amax, quantise=True):
     W1q, b1q = [qb(f32(w) * inv_x).astype(np.float64) for w in (W1, b1)]   # layer 1 in units of s_x
     H3q = qb(H3).astype(np.float64)
     W2q = q8(W2 / s_w2).astype(np.float64)
-    H1q = q8(H1 / s_h1).astype(np.float64)
-    H2q = q8(H2 / s_h2).astype(np.float64)
+    f8h1, f8h2 = "head1" in fp8_layers, "head2" in fp8_layers
+    H1q = (q8(H1 / s_h1) if f8h1 else qb(H1)).astype(np.float64)
+    H2q = (q8(H2 / s_h2) if f8h2 else qb(H2)).astype(np.float64)
     s_enc, s_hd1, s_hd2 = np.float32(s_x * s_w2), np.float32(s_z * s_h1), np.float32(s_g * s_h2)
     qa = quant_act if quantise else (lambda x, s: f32(x) * (np.float32(1.0) / np.float32(s)))
     P = len(geoms)
@@ -137,17 +155,61 @@ def fp8_forward(geoms, weights_flat, widths, amax, quantise=True):
             raw = acc.max(axis=0) if len(acc) else np.full(h2w, -np.inf)
             feats.append(np.maximum(f32(raw * np.float64(s_enc) + b2), 0))   # one rounding, as a fused multiply-add
         z[p] = np.concatenate(feats)
-        g1 = np.maximum(f32((qa(z[p], s_z).astype(np.float64) @ H1q.T) * np.float64(s_hd1) + c1), 0)
-        g2 = np.maximum(f32((qa(g1, s_g).astype(np.float64) @ H2q.T) * np.float64(s_hd2) + c2), 0)
+        if f8h1:
+            g1 = np.maximum(f32((qa(z[p], s_z).astype(np.float64) @ H1q.T) * np.float64(s_hd1) + c1), 0)
+        else:
+            g1 = np.maximum(f32(qb(z[p]).astype(np.float64) @ H1q.T) + c1, 0)
+        if f8h2:
+            g2 = np.maximum(f32((qa(g1, s_g).astype(np.float64) @ H2q.T) * np.float64(s_hd2) + c2), 0)
+        else:
+            g2 = np.maximum(f32(qb(g1).astype(np.float64) @ H2q.T) + c2, 0)
         y[p] = qb(g2).astype(np.float64) @ H3q.T + c3
     return y, z
 
 
-def fp8_detect(geoms, weights_flat, widths, amax, quantise=True):
-    """Contacts [P, 8] in the world frame (oracle O11 on the model's y), y and z."""
-    y, z = fp8_forward(geoms, weights_flat, widths, amax, quantise)
+def bf16_forward(geoms, weights_flat, widths, quantise=True):
+    """Q1, Q5: raw head outputs y [P, 8] (a's frame) and pooled features z
+    [P, 2 h2] (float32, before the bf16 rounding the head applies); NaN for
+    invalid pairs.  quantise=False replaces every bf16 rounding by the
+    identity, which must give the full-precision network back."""
+    h1w, h2w, hhw = widths
+    W1, b1, W2, b2, H1, c1, H2, c2, H3, c3 = [f32(w) for w in O.unpack_weights(weights_flat, h1w, h2w, hhw)]
+    qb = bf16 if quantise else f32
+    W1q, b1q, W2q, H1q, H2q, H3q = [qb(w).astype(np.float64) for w in (W1, b1, W2, H1, H2, H3)]
+    P = len(geoms)
+    z = np.full((P, 2 * h2w), np.nan, np.float32)
+    y = np.full((P, 8), np.nan)
+    for p in _valid(geoms):
+        g = geoms[p]
+        feats = []
+        for rows in (g.rows_a, g.rows_b):
+            r = qb(f32(rows)).astype(np.float64)
+            h = qb(np.maximum(f32(r @ W1q.T + b1q), 0)).astype(np.float64)
+            acc = f32(h @ W2q.T)
+            raw = acc.max(axis=0) if len(acc) else np.full(h2w, -np.inf, np.float32)
+            feats.append(np.maximum(raw + b2, np.float32(0)))
+        z[p] = np.concatenate(feats)
+        g1 = qb(np.maximum(f32(qb(z[p]).astype(np.float64) @ H1q.T) + c1, 0)).astype(np.float64)
+        g2 = qb(np.maximum(f32(g1 @ H2q.T) + c2, 0)).astype(np.float64)
+        y[p] = g2 @ H3q.T + c3
+    return y, z
+
+
+def _world(geoms, y):
     contacts = np.full((len(geoms), 8), np.nan)
     for p in _valid(geoms):
         g = geoms[p]
         contacts[p] = O.post(y[p], g.Ra, g.ta, g.sgn)
-    return dict(contacts=contacts, y=y, z=z)
+    return contacts
+
+
+def bf16_detect(geoms, weights_flat, widths, quantise=True):
+    """Contacts [P, 8] in the world frame (oracle O11 on the model's y), y and z of the BF16 variant."""
+    y, z = bf16_forward(geoms, weights_flat, widths, quantise)
+    return dict(contacts=_world(geoms, y), y=y, z=z)
+
+
+def fp8_detect(geoms, weights_flat, widths, amax, quantise=True, fp8_layers=FP8_ALL):
+    """Contacts [P, 8] in the world frame (oracle O11 on the model's y), y and z."""
+    y, z = fp8_forward(geoms, weights_flat, widths, amax, quantise, fp8_layers)
+    return dict(contacts=_world(geoms, y), y=y, z=z)

@@ -94,6 +94,9 @@ locc_status ensure_workspace(locc_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return LOCC_OK;
   if (c->capturing)
     return fail(LOCC_ERR_RANGE, "workspace of %zu bytes too small for %zu during graph capture", c->ws_bytes, bytes);
+  if (c->live_graphs > 0)
+    return fail(LOCC_ERR_RANGE, "workspace of %zu bytes too small for %zu while %d captured graph(s) use it: "
+                "reserve before capturing, or destroy the graphs first", c->ws_bytes, bytes, c->live_graphs);
   if (c->d_ws) HIP_TRY(hipFree(c->d_ws));  // implicit device synchronisation
   c->d_ws = nullptr;
   c->ws_bytes = 0;
@@ -480,6 +483,9 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   if (n != want) return fail(LOCC_ERR_INVALID_ARG, "weights: %zu floats given, %zu expected", n, want);
   for (size_t k = 0; k < n; ++k)
     if (!std::isfinite(h[k])) return fail(LOCC_ERR_INVALID_ARG, "weights: non-finite value at %zu", k);
+  if (c->cfg.precision == LOCC_FP8 && c->live_graphs > 0)
+    return fail(LOCC_ERR_BUSY, "FP8 weights: %d captured graph(s) hold the current scales; destroy them first",
+                c->live_graphs);
   const float* W1 = h;
   const float* b1 = W1 + (size_t)h1 * 6;
   const float* W2 = b1 + h1;
@@ -589,6 +595,9 @@ locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
       return fail(LOCC_ERR_INVALID_ARG, "activation maximum %d = %g: must be finite and >= 0", k, amax[k]);
   if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
   if (c->capturing) return fail(LOCC_ERR_RANGE, "activation maxima during graph capture");
+  if (c->live_graphs > 0)
+    return fail(LOCC_ERR_BUSY, "activation maxima: %d captured graph(s) hold the current scales; destroy them first",
+                c->live_graphs);
   return fp8_install_amax(c, amax);
 }
 
@@ -601,6 +610,9 @@ locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
   if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
   if (c->capturing) return fail(LOCC_ERR_RANGE, "calibration during graph capture");
+  if (c->live_graphs > 0)
+    return fail(LOCC_ERR_BUSY, "calibration: %d captured graph(s) hold the current scales; destroy them first",
+                c->live_graphs);
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(hipSetDevice(c->device));
   float amax[3] = {0.f, 0.f, 0.f};
@@ -640,6 +652,9 @@ locc_status locc_upload_shapes(locc_ctx* c, int32_t n_shapes, const int64_t* off
   }
   const int64_t total = off[n_shapes];
   if (total >= (int64_t)INT32_MAX) return fail(LOCC_ERR_RANGE, "%lld points in total", (long long)total);
+  if (c->live_graphs > 0)
+    return fail(LOCC_ERR_BUSY, "shape library: %d captured graph(s) read the current one; destroy them first",
+                c->live_graphs);
   std::vector<float> soa((size_t)total * 6);
   std::vector<ShapeDesc> desc(n_shapes);
   for (int s = 0; s < n_shapes; ++s) {
@@ -809,6 +824,7 @@ locc_status capture_graph(locc_ctx* c, locc_graph** graph, F&& body) {
   locc_graph* G = new locc_graph();
   G->ctx = c;
   G->graph = g;
+  ++c->live_graphs;  // counted down by locc_graph_destroy, on the failure path below too
   const hipError_t e2 = hipGraphInstantiate(&G->exec, g, nullptr, nullptr, 0);
   if (e2 != hipSuccess) {
     locc_graph_destroy(G);
@@ -824,6 +840,9 @@ locc_status ensure_broad_scratch(locc_ctx* c, int n_objs, int n_envs) {
   if (c->capturing)
     return fail(LOCC_ERR_RANGE, "broad-phase scratch of %zu bytes too small for %zu during graph capture",
                 c->bp_bytes, bytes);
+  if (c->live_graphs > 0)
+    return fail(LOCC_ERR_RANGE, "broad-phase scratch of %zu bytes too small for %zu while %d captured graph(s) "
+                "use it: reserve before capturing, or destroy the graphs first", c->bp_bytes, bytes, c->live_graphs);
   if (c->d_bp) HIP_TRY(hipFree(c->d_bp));
   c->d_bp = nullptr;
   c->bp_bytes = 0;
@@ -927,6 +946,7 @@ locc_status locc_graph_launch(locc_graph* G, void* stream) {
 
 void locc_graph_destroy(locc_graph* G) {
   if (!G) return;
+  if (G->ctx) --G->ctx->live_graphs;
   if (G->exec) (void)hipGraphExecDestroy(G->exec);
   if (G->graph) (void)hipGraphDestroy(G->graph);
   delete G;

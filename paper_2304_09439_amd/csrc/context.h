@@ -46,6 +46,10 @@ struct locc_ctx {
   hipEvent_t chunk_ev[kMaxChunks + 1] = {};
   hipStream_t capture_stream = nullptr;  // created on first graph capture
   bool capturing = false;
+  // graphs captured on this context and not yet destroyed: they hold raw pointers to the workspace, the
+  // broad-phase scratch, the shape library and (FP8) scales taken at capture, so nothing of these may move
+  // or change while any exists
+  int live_graphs = 0;
   // workspace
   void* d_ws = nullptr;
   size_t ws_bytes = 0;

@@ -30,19 +30,30 @@ def test_kernel_entries_rates_and_fractions():
     w = bench.per_pair_work(128, I.SCALE_WIDTHS, 2048)
     P, steps = 16384, 20
     kt = {"crop": (steps, 0.1 * steps), "encoder_head_bf16": (steps, 0.2 * steps)}
-    rows = P * 2 * 96   # 96 of the 128 rows of every object in the tiles run
-    k = bench.kernel_entries(kt, w, P, "scale", steps, "bf16", full_scan=False, exec_rows=rows)
+    valid, tiles = P * 2 * 90, P * 2 * 96   # 90 member rows per object, in 96 rows of tiles
+    k = bench.kernel_entries(kt, w, P, "scale", steps, "bf16", full_scan=False, rows=(valid, tiles))
     enc = k["encoder_head_bf16"]
-    flops = (w["enc_flops"] + w["head_flops"]) * P
-    assert enc["achieved"] == pytest.approx(flops / 0.2e-3 / 1e12, rel=1e-4)
+    t = 0.2e-3
+    method = valid * w["row_flops"] + w["head_flops"] * P
+    assert enc["achieved"] == pytest.approx(method / t / 1e12, rel=1e-4)
     assert enc["frac"] == pytest.approx(enc["achieved"] / 2500.0, rel=1e-3)
-    run = rows * w["row_flops"] + w["head_flops"] * P
-    assert enc["executed_TFLOPs"] == pytest.approx(run / 0.2e-3 / 1e12, rel=1e-4)
-    assert enc["executed_frac"] < enc["frac"]
+    fixed = (w["enc_flops"] + w["head_flops"]) * P
+    assert enc["fixed_2K_TFLOPs"] == pytest.approx(fixed / t / 1e12, rel=1e-4)
+    assert enc["tiles_run_TFLOPs"] == pytest.approx((tiles * w["row_flops"] + w["head_flops"] * P) / t / 1e12,
+                                                    rel=1e-4)
+    assert enc["frac"] < enc["tiles_run_frac"] < enc["fixed_2K_frac"]
     crop = k["crop"]
     assert crop["bound"] == "hbm"
-    assert crop["achieved"] == pytest.approx(w["crop_bytes"] * P / 0.1e-3 / 1e9, rel=1e-4)
     assert crop["hbm_bytes_per_pair"] == 2 * 32 + 8 + 8 + 2 * 128 * 16
-    assert crop["hbm_GBps"] == pytest.approx(crop["hbm_bytes_per_pair"] * P / 0.1e-3 / 1e9, rel=1e-4)
-    k32 = bench.kernel_entries({"crop": (1, 0.1)}, w, P, "scale", 1, "fp32")
+    assert crop["achieved"] == pytest.approx(crop["hbm_bytes_per_pair"] * P / 0.1e-3 / 1e9, rel=1e-4)
+    assert crop["frac"] == pytest.approx(crop["achieved"] / 8000.0, rel=1e-3) and crop["frac"] < 1
+    assert crop["scan_GBps"] == pytest.approx(w["crop_bytes"] * P / 0.1e-3 / 1e9, rel=1e-4)
+    k32 = bench.kernel_entries({"crop": (1, 0.1), "head_fp32": (1, 0.3)}, w, P, "scale", 1, "fp32")
     assert k32["crop"]["hbm_bytes_per_pair"] == 2 * 32 + 8 + 8 + 2 * 128 * 32
+    assert k32["head_fp32"]["achieved"] == pytest.approx(w["head_flops"] * P / 0.3e-3 / 1e12, rel=1e-4)
+
+
+def test_encoder_rows_counts_valid_and_tile_rows():
+    import numpy as np
+    counts = np.array([[0, 5], [200, 33], [-1, -1], [128, 64]], np.int32)
+    assert bench.encoder_rows(counts, 128) == (0 + 5 + 128 + 33 + 128 + 64, 0 + 32 + 128 + 64 + 128 + 64)

@@ -1,11 +1,15 @@
-"""GPU parity of the fused persistent BF16 kernel against the CPU FP64 oracle.
+"""GPU parity of the BF16 encoder + head kernels against the CPU FP64 oracle.
 
-Crop counts must match bit for bit.  Network outputs must match within 2e-2
-normwise relative error per field (||y_f - ref_f|| / ||ref_f|| over the
-pairs); the per-pair maximum error is reported beside it.  Collision-flag
-agreement must be >= 99.9% on pairs whose reference logit is not within
-2e-2 RMS of zero.  Results must not depend on the schedule or on the rest of
-the batch.
+Crop counts must match bit for bit.  Network outputs, per field, must match
+the FP64 oracle within 2e-2 normwise (||y_f - ref_f|| / ||ref_f|| over the
+pairs), and every pair within 1.5x the largest per-pair error of the CPU
+model of the same bf16 rounding decisions (oracle.quant_model, Q5) + 2e-3:
+the tail of the format's own error, measured without the kernel, bounds each
+pair.  The kernel must also stay within 5e-3 normwise of that model (it takes
+the same rounding decisions up to the order of its float32 sums).
+Collision-flag agreement must be >= 99.9% on pairs whose reference logit is
+not within 2e-2 RMS of zero.  Results must not depend on the schedule or on
+the rest of the batch.
 """
 
 import sys
@@ -14,10 +18,11 @@ import numpy as np
 import pytest
 
 from oracle import locc_oracle as O
+from oracle import quant_model as Q
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
 
-from helpers import field_errors, first_object_empty, flag_agreement, normwise_errors, with_first_object_empty
+from helpers import check_low_precision, first_object_empty, flag_agreement, with_first_object_empty
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +30,7 @@ SW, LW = I.SMALL_WIDTHS, I.SCALE_WIDTHS
 SMALL = (SW.h1, SW.h2, SW.hh)
 SCALE = (LW.h1, LW.h2, LW.hh)
 BF16_TOL = 2e-2
+MODEL_TOL = 5e-3
 
 
 def say(msg):
@@ -61,19 +67,21 @@ def _forward(torch, scene, K, widths, w, sched=None):
     return out.cpu().numpy(), counts.cpu().numpy(), z.cpu().numpy(), y.cpu().numpy(), n_bad
 
 
-def _check(out, counts, z, y, ref, label):
+def _check(out, counts, z, y, ref, label, w, widths):
     np.testing.assert_array_equal(counts, ref["counts"])
-    ez = float(np.linalg.norm(z - ref["z"]) / np.linalg.norm(ref["z"]))
-    ny = normwise_errors(y, ref["y"])
-    nc = normwise_errors(out, ref["contacts"])
-    my = field_errors(y, ref["y"])
-    fr = flag_agreement(out[:, 0], ref["contacts"][:, 0])
-    fb = flag_agreement(out[:, 0], ref["contacts"][:, 0], band=BF16_TOL)
-    fmt = lambda d: "{" + ", ".join(f"{k} {v:.2e}" for k, v in d.items()) + "}"
-    say(f"  {label}: z {ez:.2e}; normwise y {fmt(ny)} world {fmt(nc)}; per-pair max y {fmt(my)}; "
+    ok = ~np.isnan(ref["y"][:, 0])
+    assert np.array_equal(ok, ~np.isnan(y[:, 0]))
+    model = Q.bf16_detect(ref["geoms"], w, widths)
+    ez = float(np.linalg.norm(z[ok] - ref["z"][ok]) / np.linalg.norm(ref["z"][ok]))
+    ezm = float(np.linalg.norm(z[ok] - model["z"][ok]) / np.linalg.norm(model["z"][ok]))
+    fr = flag_agreement(out[ok, 0], ref["contacts"][ok, 0])
+    fb = flag_agreement(out[ok, 0], ref["contacts"][ok, 0], band=BF16_TOL)
+    say(f"  {label}: {int(ok.sum())} pairs; z normwise {ez:.2e} (vs model {ezm:.2e}); "
         f"flag raw {fr:.4f} banded {fb:.4f}")
-    assert ez < BF16_TOL
-    assert max(ny.values()) < BF16_TOL and max(nc.values()) < BF16_TOL
+    assert ez < BF16_TOL and ezm < 1e-3
+    check_low_precision(y[ok], model["y"][ok], ref["y"][ok], BF16_TOL, MODEL_TOL, label + " y", say)
+    check_low_precision(out[ok], model["contacts"][ok], ref["contacts"][ok], BF16_TOL, MODEL_TOL,
+                        label + " world", say)
     assert fb >= 0.999
 
 
@@ -83,7 +91,7 @@ def test_bf16_fused_matches_oracle_small(torch, small_scene, bias):
     say(f"bf16 fused parity: small workload, bias_std={bias}")
     out, counts, z, y, n_bad = _forward(torch, small_scene, 64, SMALL, w)
     assert n_bad == 0
-    _check(out, counts, z, y, O.detect_scene(small_scene, w, SMALL, 64), "small")
+    _check(out, counts, z, y, O.detect_scene(small_scene, w, SMALL, 64), "small", w, SMALL)
 
 
 def test_bf16_fused_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene):
@@ -94,7 +102,30 @@ def test_bf16_fused_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene)
     assert n_bad == 0
     rows = np.sort(np.random.default_rng(321).choice(sc.n_pairs, 192, replace=False))
     ref = O.detect_scene(sc, w, SCALE, 128, rows=rows)
-    _check(out[rows], counts[rows], z[rows], y[rows], ref, "scale sample")
+    _check(out[rows], counts[rows], z[rows], y[rows], ref, "scale sample", w, SCALE)
+
+
+def test_bf16_under_the_autotuned_schedule_matches_oracle(torch, scale_scene):
+    """The schedule the autotuner picks for the whole 16,384-pair workload (the one the benchmark times,
+    contacts only), checked against the oracle on pairs [0, 1024); the contacts of a plain detect under
+    that schedule equal the debug run's bit for bit."""
+    sc = scale_scene
+    w = _weights(LW, bias=0.0)
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision="bf16")
+    objs, pairs = B.scene_tensors(sc)
+    best, ms = ctx.autotune(objs, pairs, want_counts=False)
+    say(f"bf16 autotuned schedule on 16384 pairs: {best} ({ms:.4f} ms)")
+    plain, _ = ctx.detect(objs, pairs, want_counts=False)
+    out, counts, z, y = ctx.debug_forward(objs, pairs)
+    torch.cuda.synchronize()
+    assert ctx.get_schedule() == best
+    assert torch.equal(plain, out)
+    assert ctx.device_errors() == 0
+    ctx.close()
+    rows = np.arange(1024)
+    ref = O.detect_scene(sc, w, SCALE, 128, rows=rows)
+    o, c, zz, yy = (t.cpu().numpy()[rows] for t in (out, counts, z, y))
+    _check(o, c, zz, yy, ref, "autotuned schedule, pairs [0, 1024)", w, SCALE)
 
 
 SCHEDULES = [dict(wg_per_cu=2, claim=1, dynamic=True, split=False),
@@ -228,4 +259,4 @@ def test_bf16_first_object_empty(torch, one_sided_scene, split):
     out, counts, z, y, n_bad = _forward(torch, sc.subset(sample), 128, SCALE, w, sched)
     assert n_bad == 0
     ref = O.detect_scene(sc, w, SCALE, 128, rows=sample)
-    _check(out, counts, z, y, ref, "first object empty")
+    _check(out, counts, z, y, ref, "first object empty", w, SCALE)

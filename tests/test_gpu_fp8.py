@@ -42,6 +42,7 @@ SCALE = (LW.h1, LW.h2, LW.hh)
 Z_TOL = 1e-4     # pooled features vs the model
 Y_TOL = 1e-2     # raw outputs and contacts vs the model
 ORACLE_SLACK = 2e-3
+FP8_TOL = 6e-2   # the stated FP8 tolerance against the FP64 oracle
 
 
 def say(msg):
@@ -161,6 +162,24 @@ def test_fp8_error_against_the_oracle(torch, scale_case):
         f"banded(6e-2) {flag_agreement(y[rows, 0], ref_y[:, 0], band=6e-2):.4f}")
     for k in e_dev:
         assert e_dev[k] <= e_model[k] + ORACLE_SLACK, k
+    # the collision flag, banded at the FP8 tolerance (pairs whose reference logit lies within 6e-2 RMS of
+    # zero are left out, as the bar is stated for a flag the format can decide)
+    assert flag_agreement(y[rows, 0], ref_y[:, 0], band=FP8_TOL) >= 0.999
+
+
+@pytest.mark.xfail(strict=True, reason="e4m3 on encoder layer 2 and head layers 1-2: the format's own error on "
+                   "these untrained Gaussian weights is 0.037-0.12 normwise per field against the FP64 oracle "
+                   "(the CPU model of the roundings, with no kernel involved, gives the same figures)")
+def test_fp8_all_layers_within_the_fp8_tolerance_of_the_oracle(torch, scale_case):
+    c = scale_case
+    ctx = _ctx(c)
+    out, counts, z, y = _run(torch, ctx, c["scene"])
+    ctx.close()
+    rows = np.arange(1024)
+    rows = rows[~np.isnan(c["ref"]["y"][rows, 0])]
+    e = normwise_errors(y[rows], c["ref"]["y"][rows])
+    say(f"  FP8 (all layers) vs FP64 oracle normwise {e}")
+    assert max(e.values()) < FP8_TOL
 
 
 def test_fp8_needs_activation_scales(torch, small_case):
@@ -207,6 +226,9 @@ def test_fp8_results_do_not_depend_on_the_schedule_or_graph(torch, scale_case):
     n_dev = torch.tensor([P], dtype=torch.int32, device="cuda")
     out = torch.full((cap, 8), 7.0, dtype=torch.float32, device="cuda")
     g = ctx.capture_graph(objs, pbuf, n_dev, out)
+    with pytest.raises(B.LoccError) as e:       # the graph holds the current scales
+        ctx.set_activation_amax(c["amax"])
+    assert e.value.status == B.ERR_BUSY
     for n in (P, 100, P):
         out.fill_(7.0)
         n_dev.fill_(n)

@@ -13,7 +13,8 @@ from oracle import locc_oracle as O
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
 
-from helpers import field_errors, flag_agreement, sphere_case_scene, sphere_cases, sphere_probe_weights
+from helpers import (field_errors, flag_agreement, oracle_crop_all, sphere_case_scene, sphere_cases,
+                     sphere_probe_weights)
 
 pytestmark = pytest.mark.gpu
 
@@ -331,3 +332,15 @@ def test_fp32_at_scale_matches_oracle_on_sampled_pairs(torch, scale_scene):
     say(f"  world errors {e}")
     assert max(e.values()) < FP32_TOL
     assert flag_agreement(out[rows, 0], ref["contacts"][:, 0], band=1e-3) >= 0.999
+
+
+def test_crop_matches_oracle_on_every_pair_at_scale(torch, scale_scene):
+    """Every one of the 16,384 pairs: index sets and member counts of the crop (the oracle's O1-O7, run
+    over worker processes without the network) bit for bit."""
+    sc = scale_scene
+    say("scale crop: 16384 pairs, every pair against the oracle")
+    idx, counts = _run_crop(torch, sc, 128, SCALE)
+    ridx, rcounts = oracle_crop_all(sc, 128, workers=8)
+    np.testing.assert_array_equal(counts, rcounts)
+    np.testing.assert_array_equal(idx, ridx)
+    say(f"  objects with more than K members {np.mean(rcounts > 128):.3f}, empty {np.mean(rcounts == 0):.3f}")

@@ -12,8 +12,12 @@ import time
 import numpy as np
 import pytest
 
+from oracle import locc_oracle as O
+from oracle import quant_model as Q
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
+
+from helpers import check_low_precision
 
 pytestmark = pytest.mark.gpu
 
@@ -206,3 +210,40 @@ def test_waiting_requests_are_overtaken_only_on_disjoint_objects(torch, rs):
         np.testing.assert_array_equal(res[rid][0], ref_out)
         np.testing.assert_array_equal(res[rid][1], ref_counts)
     ctx.close()
+
+
+def test_served_results_match_the_oracle_on_the_serving_library(torch):
+    """The serving workload's own library (128 shapes x 4096 points, 4096 resident environments): a burst of
+    120 requests served with continuous batching; for 6 sampled requests (their first 150 pairs) the member
+    counts equal the FP64 oracle's bit for bit and the contacts are within the BF16 bounds of the oracle
+    on each request's own poses."""
+    rs = I.request_stream(n_requests=120)
+    say(f"serving library: {rs.lib.n_shapes} shapes x {int(rs.lib.offsets[1])} points, "
+        f"{len(rs.shape)} resident objects, 120 requests")
+    w = I.flatten_weights(I.gaussian_weights(LW, seed=0, bias_std=0.0))
+    ctx = B.Context(128, SCALE, precision="bf16")
+    ctx.upload_shapes(rs.lib.offsets, rs.lib.pts)
+    ctx.upload_weights(w)
+    srv = B.Server(ctx, _table(rs), batching=True, slots=3, max_batch_pairs=32768, max_batch_updates=65536,
+                   hbm_budget_bytes=4 << 30)
+    ids = [srv.submit(*_upd(rs, r)) for r in rs.requests]
+    res = _drain(srv, ids, timeout_s=120.0)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == len(ids) and st["batches"] < len(ids)
+    assert ctx.device_errors() == 0
+    ctx.close()
+    outs, refs, models = [], [], []
+    for k in np.random.default_rng(3).choice(len(ids), 6, replace=False):
+        upd_ids, pos, quat, pairs = rs.requests[k]
+        P = min(150, len(pairs))
+        gpos, gquat = rs.pos0.copy(), rs.quat0.copy()
+        gpos[upd_ids], gquat[upd_ids] = pos, quat
+        ref = O.detect(rs.lib.pts, rs.lib.offsets, gpos, gquat, rs.shape, pairs[:P], w, SCALE, 128)
+        out, counts, _ = res[ids[k]]
+        np.testing.assert_array_equal(counts[:P], ref["counts"])
+        outs.append(out[:P])
+        refs.append(ref["contacts"])
+        models.append(Q.bf16_detect(ref["geoms"], w, SCALE)["contacts"])
+    check_low_precision(np.concatenate(outs), np.concatenate(models), np.concatenate(refs), 2e-2, 5e-3,
+                        "served vs oracle (4096-point shapes)", say)

@@ -1,4 +1,4 @@
-"""Pins of the CPU model of the FP8 arithmetic (oracle.quant_model).
+"""Pins of the CPU model of the BF16 and FP8 arithmetic (oracle.quant_model).
 
 The number formats are pinned to PyTorch's own float8_e4m3fn / bfloat16
 conversions and to a brute-force nearest-value search over the enumerated
@@ -116,3 +116,50 @@ def test_quantised_model_is_close_but_not_equal(small):
     ok = ~np.isnan(ref["y"][:, 0])
     err = np.linalg.norm(out["y"][ok] - ref["y"][ok]) / np.linalg.norm(ref["y"][ok])
     assert 1e-3 < err < 0.3
+
+
+def test_bf16_model_without_rounding_is_the_full_precision_network(small):
+    sc, w, widths, ref = small
+    out = Q.bf16_detect(ref["geoms"], w, widths, quantise=False)
+    ok = ~np.isnan(ref["y"][:, 0])
+    assert ok.sum() > 0 and np.array_equal(ok, ~np.isnan(out["y"][:, 0]))
+    np.testing.assert_allclose(out["z"][ok], ref["z"][ok], rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(out["y"][ok], ref["y"][ok], rtol=1e-4, atol=1e-5)
+    np.testing.assert_allclose(out["contacts"][ok], ref["contacts"][ok], rtol=1e-4, atol=1e-5)
+
+
+def test_bf16_model_is_close_but_not_equal(small):
+    sc, w, widths, ref = small
+    out = Q.bf16_detect(ref["geoms"], w, widths)
+    ok = ~np.isnan(ref["y"][:, 0])
+    err = np.linalg.norm(out["y"][ok] - ref["y"][ok]) / np.linalg.norm(ref["y"][ok])
+    # eight significant bits per rounding: errors of order 2^-9 per value, far below the fp8 model's
+    assert 1e-4 < err < 2e-2
+    err8 = np.linalg.norm(Q.fp8_detect(ref["geoms"], w, widths, Q.calibrate(ref["geoms"], w, widths))["y"][ok]
+                          - ref["y"][ok]) / np.linalg.norm(ref["y"][ok])
+    assert err < err8 / 2
+
+
+def test_fp8_layer_sets(small):
+    """The variant with only encoder layer 2 in e4m3 has the BF16 model's head: without rounding every
+    variant is the full-precision network, and encoder layer 2 must be one of the e4m3 layers."""
+    sc, w, widths, ref = small
+    amax = Q.calibrate(ref["geoms"], w, widths)
+    ok = ~np.isnan(ref["y"][:, 0])
+    for layers in (("enc2",), ("enc2", "head2"), Q.FP8_ALL):
+        out = Q.fp8_detect(ref["geoms"], w, widths, amax, quantise=False, fp8_layers=layers)
+        np.testing.assert_allclose(out["y"][ok], ref["y"][ok], rtol=1e-4, atol=1e-5)
+    with pytest.raises(ValueError):
+        Q.fp8_forward(ref["geoms"], w, widths, amax, fp8_layers=("head1",))
+    # the same pooled features (encoder layer 2 is e4m3 in both), different heads
+    a = Q.fp8_detect(ref["geoms"], w, widths, amax, fp8_layers=("enc2",))
+    b = Q.fp8_detect(ref["geoms"], w, widths, amax)
+    np.testing.assert_array_equal(a["z"], b["z"])
+    assert not np.array_equal(a["y"][ok], b["y"][ok])
+    # the head of the encoder-only variant is exactly the BF16 model's head on those features
+    W1, b1, W2, b2, H1, c1, H2, c2, H3, c3 = [np.asarray(x, np.float32) for x in O.unpack_weights(w, *widths)]
+    z = a["z"][ok]
+    g1 = Q.bf16(np.maximum(np.float32(Q.bf16(z).astype(np.float64) @ Q.bf16(H1).astype(np.float64).T) + c1, 0))
+    g2 = Q.bf16(np.maximum(np.float32(g1.astype(np.float64) @ Q.bf16(H2).astype(np.float64).T) + c2, 0))
+    y = g2.astype(np.float64) @ Q.bf16(H3).astype(np.float64).T + c3
+    np.testing.assert_array_equal(a["y"][ok], y)
