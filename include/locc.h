@@ -290,6 +290,28 @@ LOCC_API locc_status locc_graph_capture(locc_ctx* ctx, const locc_object* d_objs
 LOCC_API locc_status locc_graph_launch(locc_graph* graph, void* stream);
 LOCC_API void locc_graph_destroy(locc_graph* graph);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the path of
+ * locc_detect (same arguments, same results bit for bit) with its workspace
+ * in a fixed 32 MiB device array of the library instead of the context's
+ * workspace.  The call allocates nothing and frees nothing; it runs one run
+ * of pairs in the static claim order and records no event timing, whatever
+ * the context's schedule says.  Largest batch: the workspace per pair is
+ * about 16 + 320 + 2K * 32 + 8 h2 bytes (FP32 contexts; 10.6 KB at K = 128,
+ * h2 = 256: about 3,100 pairs) or 16 + 320 + 2K * 16 (BF16 split schedule and
+ * FP8: 4.4 KB, about 7,500 pairs); the BF16 fused schedule needs none.
+ * Every context on a device shares that device's array, and it keeps the
+ * last call's contents: calls on one device whose GPU work overlaps in time
+ * (other streams, other contexts, other host threads) race on it.  The array
+ * is looked up when the context is created (locc_create fails with HIP if
+ * that fails).
+ * Errors: as locc_detect, and RANGE (more pairs than the array holds; the
+ * message gives the largest count for the context), NOT_READY (no array on
+ * the context's device). */
+LOCC_API locc_status locc_detect_noalloc(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
+                                         const int32_t* d_pairs, int32_t n_pairs, locc_contact* d_out,
+                                         int32_t* d_counts, void* stream);
+
 /* Pose gradients of the collision logit (Sec. II, collision resolution with
  * an object collision network: contact force and torque directions come from
  * the gradient of the network's output with respect to the poses).  FP32

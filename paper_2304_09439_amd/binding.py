@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_READY
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
-           "locc_upload_shapes", "locc_detect", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
+           "locc_upload_shapes", "locc_detect", "locc_detect_noalloc", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
            "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
            "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
@@ -96,6 +96,8 @@ def load() -> ctypes.CDLL:
     L.locc_upload_shapes.argtypes = [vp, i32, vp, vp]
     L.locc_detect.restype = ctypes.c_int
     L.locc_detect.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
+    L.locc_detect_noalloc.restype = ctypes.c_int
+    L.locc_detect_noalloc.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.locc_debug_crop.restype = ctypes.c_int
     L.locc_debug_crop.argtypes = [vp, vp, i32, vp, i32, vp, vp, vp]
     L.locc_debug_forward.restype = ctypes.c_int
@@ -269,6 +271,22 @@ class Context:
             counts = torch.empty((P, 2), dtype=torch.int32, device=dev)
         _check(load().locc_detect(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
                                   self._stream(stream)))
+        return out, counts
+
+    def detect_noalloc(self, objs, pairs, out, counts=None, stream=None):
+        """locc_detect_noalloc: the detect path with the library's fixed device array as its workspace.
+        The caller provides every output buffer (this call allocates nothing)."""
+        import torch
+        n_objs, P = self._inputs(objs, pairs)
+        self._check_dev("out", out, torch.float32, (8,))
+        if out.shape[0] < P:
+            raise ValueError(f"out: {out.shape[0]} rows for {P} pairs")
+        if counts is not None:
+            self._check_dev("counts", counts, torch.int32, (2,))
+            if counts.shape[0] < P:
+                raise ValueError(f"counts: {counts.shape[0]} rows for {P} pairs")
+        _check(load().locc_detect_noalloc(self._h, _ptr(objs), n_objs, _ptr(pairs), P, _ptr(out), _ptr(counts),
+                                          self._stream(stream)))
         return out, counts
 
     def debug_crop(self, objs, pairs, stream=None):

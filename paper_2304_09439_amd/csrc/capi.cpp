@@ -445,6 +445,11 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
     locc_destroy(c);
     return fail(LOCC_ERR_HIP, "error counter: %s", hipGetErrorString(e));
   }
+  const locc_status ns = noalloc_setup(device);   // this device's copy of the no-allocation scratch
+  if (ns != LOCC_OK) {
+    locc_destroy(c);
+    return ns;
+  }
   *out = c;
   return LOCC_OK;
 }

@@ -102,6 +102,11 @@ size_t workspace_bytes(const locc_ctx* c, int n_pairs);
 // Argument checks shared by the detect entry points.
 locc_status check_call(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs);
 
+// The no-allocation entry point's device array: looked up once per device
+// (that device current) at context creation; its size in bytes.
+locc_status noalloc_setup(int device);
+size_t noalloc_scratch_bytes();
+
 // One step of the path for n_pairs pairs (the capacity when n_dev is set),
 // enqueued on stream s.
 locc_status run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs, int32_t n_pairs,
