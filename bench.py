@@ -7,7 +7,7 @@ per-step latency percentiles, the roofline of the dominant kernel (timed with
 HIP events on its launch stream inside the library) and the CPU FP64 oracle
 timed on this host on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32,bf16,fp8]
+  python bench.py [--steps K] [--warmup W] [--workload scale|small] [--precision fp32,bf16,fp8,fp8_encoder]
 
 Counter post-processing (turns rocprofv3 --pmc CSV output into a summary):
   python bench.py --summarize-counters FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME
@@ -46,6 +46,15 @@ KERNEL_SOURCES = {
     "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
     "encoder_head_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
     "encoder_head_fp8": ["fused_fp8.hip", "fused.h", "post.h"],
+    "encoder_fp8_head_bf16": ["fused_fp8.hip", "fused.h", "head_bf16.h", "post.h"],
+    "crop_fp8_encoder": ["crop.hip", "geometry.h"],
+}
+# arithmetic of the encoder and of the head in each network kernel (None: not in that kernel)
+KERNEL_PREC = {
+    "encoder_fp32": ("fp32", None), "head_fp32": (None, "fp32"),
+    "fused_bf16": ("bf16", "bf16"), "encoder_head_bf16": ("bf16", "bf16"),
+    "encoder_head_fp8": ("fp8", "fp8"),              # encoder layer 1 and head layer 3 are bf16: charged at fp8
+    "encoder_fp8_head_bf16": ("fp8", "bf16"),        # encoder layer 1 bf16 charged at fp8 too
 }
 PATH_DESC = {
     "fp32": "per-step FP32: crop, encoder and head kernels on one stream",
@@ -53,6 +62,9 @@ PATH_DESC = {
     "fp8": "batched FP8: crop kernel, then one persistent encoder+head launch (encoder layer 2 and head "
            "layers 1-2 e4m3 x e4m3, encoder layer 1 and head layer 3 bf16; activation scales calibrated "
            "on the first 1,024 pairs)",
+    "fp8_encoder": "batched FP8, lower-error variant: crop kernel, then one persistent encoder+head launch "
+                   "(encoder layer 2 e4m3 x e4m3, encoder layer 1 and the whole head bf16; the activation scale "
+                   "calibrated on the first 1,024 pairs)",
 }
 
 
@@ -215,24 +227,31 @@ def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True,
                                     "read the shape library from L2" + (
                                         "" if full_scan else " and stop at K members without member counts"))
         else:
-            enc = name.startswith("encoder") or name.startswith("fused")
-            with_head = name.startswith("encoder_head") or name.startswith("fused")
-            prec = name.split("_")[-1]
-            peak = PEAK_TFLOPS[prec]
-            head = work["head_flops"] * P_launch if (with_head or name.startswith("head")) else 0.0
-            fixed = (work["enc_flops"] * P_launch if enc else 0.0) + head
+            enc_prec, head_prec = KERNEL_PREC[name]
+            enc = enc_prec is not None
+            head = work["head_flops"] * P_launch if head_prec else 0.0
+            fixed_enc = work["enc_flops"] * P_launch if enc else 0.0
             if enc and rows is not None:
-                valid = rows[0] * work["row_flops"] * P_launch / P + head
-                tiles = rows[1] * work["row_flops"] * P_launch / P + head
+                valid_enc = rows[0] * work["row_flops"] * P_launch / P
+                tiles_enc = rows[1] * work["row_flops"] * P_launch / P
             else:
-                valid = tiles = fixed
+                valid_enc = tiles_enc = fixed_enc
+
+            def peak_of(e):   # the rate at which the kernel's encoder and head work would take their peak time
+                t = (e / PEAK_TFLOPS[enc_prec] if enc else 0.0) + (head / PEAK_TFLOPS[head_prec] if head_prec else 0.0)
+                return (e + head) / t
+            peak = round(peak_of(valid_enc), 1)
+            valid, tiles, fixed = valid_enc + head, tiles_enc + head, fixed_enc + head
             rate = lambda f: f / (avg * 1e-3) / 1e12
             entry.update(bound="mfma", achieved=round(rate(valid), 2), peak=peak, unit="TFLOP/s",
                          frac=round(rate(valid) / peak, 4),
                          flops_basis=("encoder rows min(count, K) per object (the method's crop sets) + head on "
                                       "every pair" if enc else "head on every pair"),
-                         fixed_2K_TFLOPs=round(rate(fixed), 2), fixed_2K_frac=round(rate(fixed) / peak, 4),
-                         tiles_run_TFLOPs=round(rate(tiles), 2), tiles_run_frac=round(rate(tiles) / peak, 4))
+                         fixed_2K_TFLOPs=round(rate(fixed), 2), fixed_2K_frac=round(rate(fixed) / peak_of(fixed_enc), 4),
+                         tiles_run_TFLOPs=round(rate(tiles), 2), tiles_run_frac=round(rate(tiles) / peak_of(tiles_enc), 4))
+            if enc_prec != head_prec and head_prec:
+                entry["peak_basis"] = (f"encoder FLOPs at the {enc_prec} peak and head FLOPs at the {head_prec} peak "
+                                       "(the rate at which this work would take its time at those peaks)")
             if name.startswith("fused"):  # crop inside: its HBM bytes too
                 gbps = (2 * 32 + 8 + 8 + work["contact_bytes"]) * P_launch / (avg * 1e-3) / 1e9
                 entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
@@ -264,9 +283,9 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     counts = torch.empty((P, 2), dtype=torch.int32, device="cuda") if args.member_counts else None
     stream = torch.cuda.current_stream()
     schedule = None
-    if precision == "fp8":
+    if precision.startswith("fp8"):
         amax = ctx.calibrate(objs, pairs[:min(P, 1024)])
-        print(f"[bench] fp8: activation maxima {amax.tolist()}", file=sys.stderr, flush=True)
+        print(f"[bench] {precision}: activation maxima {amax.tolist()}", file=sys.stderr, flush=True)
     if precision != "fp32" and args.schedule.get(precision):
         ctx.set_schedule(**args.schedule[precision])   # a schedule given on the command line
         schedule = ctx.get_schedule()
@@ -316,7 +335,8 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
                 kernels=kernels, device_errors=int(n_bad), member_counts=bool(args.member_counts), **extra,
-                path={"fp32": PATH_DESC["fp32"], "fp8": PATH_DESC["fp8"] + f" (autotuned: {schedule})"}.get(
+                path={"fp32": PATH_DESC["fp32"], "fp8": PATH_DESC["fp8"] + f" (autotuned: {schedule})",
+                      "fp8_encoder": PATH_DESC["fp8_encoder"] + f" (autotuned: {schedule})"}.get(
                     precision, bf16_desc(schedule)))
 
 
@@ -829,7 +849,7 @@ def main():
     ap.add_argument("--schedule", action="append", default=[], metavar="PREC:WG,CLAIM,DYN,SPLIT,UNROLL,CHUNKS",
                     help="fix the schedule of a batched path instead of autotuning it, e.g. bf16:2,16,1,1,4,2 "
                          "(repeatable; used to profile the schedule a previous run picked)")
-    ap.add_argument("--precision", default="fp32,bf16,fp8",
+    ap.add_argument("--precision", default="fp32,bf16,fp8,fp8_encoder",
                     help="comma list of paths to time: fp32 (per-step), bf16 (batched, the headline), fp8 (batched)")
     ap.add_argument("--member-counts", action="store_true",
                     help="request the per-object member counts in the timed steps (full scans of both objects)")

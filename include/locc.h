@@ -57,7 +57,7 @@ typedef enum {
   LOCC_ERR_UNSUPPORTED = -7  /* widths / K / precision combination not compiled in */
 } locc_status;
 
-typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2 } locc_precision;
+typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2, LOCC_FP8_ENCODER = 3 } locc_precision;
 
 /* Network and crop configuration, fixed for the life of a context.
  *   K       crop cap per object, multiple of 32, 32..256
@@ -73,7 +73,11 @@ typedef enum { LOCC_FP32 = 0, LOCC_BF16 = 1, LOCC_FP8 = 2 } locc_precision;
  *              persistent network kernel whose encoder layer 2 and head
  *              layers 1-2 multiply OCP e4m3 operands (encoder layer 1 and
  *              head layer 3 stay bf16) and needs activation maxima
- *              (locc_calibrate or locc_set_activation_amax) first
+ *              (locc_calibrate or locc_set_activation_amax) first;
+ *              LOCC_FP8_ENCODER is LOCC_FP8 with e4m3 on encoder layer 2
+ *              only and the whole head in bf16 as in LOCC_BF16 (about
+ *              half of LOCC_FP8's error against full precision; the same
+ *              calls, of which only the first activation maximum is used)
  * Compiled width sets: (h1, h2, hh) = (64, 128, 256) and (128, 256, 512). */
 typedef struct {
   int32_t K;
@@ -137,13 +141,16 @@ LOCC_API void locc_destroy(locc_ctx* ctx);
  * context with a captured graph alive, see locc_graph_capture), OOM, HIP. */
 LOCC_API locc_status locc_upload_weights(locc_ctx* ctx, const float* h_weights, size_t n_floats);
 
-/* FP8 contexts: activation scales of the quantised encoder and head layers
+/* FP8 contexts (LOCC_FP8 and LOCC_FP8_ENCODER): activation scales of the
+ * quantised encoder and head layers
  * (Sec. III and appendix "Architecture Details" define the layers; the
  * quantisation is this library's).  Each e4m3 layer input x enters as
  * e4m3(min(x / s, 448)) with s = amax / 448, a static per-layer scale; the
  * weights carry their own per-layer scale (amax|W| / 448) set at upload.
  * amax[0]: encoder layer-1 output (after ReLU), amax[1]: pooled encoder
  * features [f_a, f_b], amax[2]: head layer-1 output (after ReLU).
+ * LOCC_FP8_ENCODER quantises only encoder layer 2's input and uses amax[0];
+ * the other two are measured and kept all the same.
  *
  * locc_calibrate measures them: it runs the crop step on the given workload
  * (valid input for locc_detect, device buffers as there) and a float32

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "liblocc.so")
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_NOT_READY, ERR_RANGE, ERR_BUSY, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "OOM", -3: "HIP", -4: "NOT_READY", -5: "RANGE", -6: "BUSY",
                 -7: "UNSUPPORTED"}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "fp8_encoder": 3}   # fp8_encoder: e4m3 on encoder layer 2 only
 
 EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "locc_upload_weights",
            "locc_upload_shapes", "locc_detect", "locc_detect_noalloc", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",

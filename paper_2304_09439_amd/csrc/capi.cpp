@@ -131,7 +131,7 @@ size_t locc::workspace_bytes(const locc_ctx* c, int n_pairs) {
   if (c->cfg.precision == LOCC_FP32)
     return meta + align256(P * 2 * c->cfg.K * kRowFloats * sizeof(float)) +
            align256(P * 2 * c->cfg.enc_h2 * sizeof(float)) + setup;
-  if (c->sched.split || c->cfg.precision == LOCC_FP8)
+  if (c->sched.split || c->fp8())
     return meta + align256(P * 2 * c->cfg.K * 8 * sizeof(unsigned short)) + setup;
   return 0;
 }
@@ -176,7 +176,7 @@ locc_status locc::check_call(locc_ctx* c, const locc_object* objs, int32_t n_obj
   if (n_pairs > 0 && (!objs || !pairs)) return fail(LOCC_ERR_INVALID_ARG, "null objects or pairs");
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");
   if (!c->have_weights) return fail(LOCC_ERR_NOT_READY, "no weights uploaded");
-  if (c->cfg.precision == LOCC_FP8 && !c->have_act_scales)
+  if (c->fp8() && !c->have_act_scales)
     return fail(LOCC_ERR_NOT_READY, "FP8: no activation scales (locc_calibrate or locc_set_activation_amax)");
   return LOCC_OK;
 }
@@ -216,7 +216,7 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
   }
   const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h;
   const int K = c->cfg.K;
-  if (c->cfg.precision == LOCC_FP8 || c->sched.split) {
+  if (c->fp8() || c->sched.split) {
     // Crop kernel, then the persistent encoder + head kernel.  With chunks > 1
     // the step is cut into that many runs of pairs: the crop of run k + 1 (on
     // the context's second stream) overlaps the network of run k (on s).
@@ -243,14 +243,14 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
         HIP_TRY(hipStreamWaitEvent(s, c->chunk_ev[k + 1], 0));
       }
       const int grid = fused_grid(c, len);
-      if (c->cfg.precision == LOCC_FP8) {
+      if (c->fp8()) {
         Fp8Args fa{};
         fa.objs = objs;
         fa.n_pairs = len;
         fa.n_pairs_dev = n_dev;
         fa.dev_base = s0;
         fa.K = K;
-        fp8_bind(fa, c->d_wfp8, h1, h2, hh);
+        fp8_bind(fa, c->d_wfp8, h1, h2, hh, c->fp8_head());
         fa.s_w2 = c->fp8_wscale[0];
         fa.s_h1 = c->fp8_wscale[1];
         fa.s_h2 = c->fp8_wscale[2];
@@ -265,7 +265,9 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
         fa.queue = own ? own->queue : c->d_queue;
         fa.claim = c->sched.claim;
         fa.dynamic = c->sched.dynamic;
-        HIP_TRY(timed(c, "encoder_head_fp8", s, [&] { return launch_encoder_head_fp8(fa, h1, h2, hh, grid, s); }));
+        const bool h8 = c->fp8_head();
+        HIP_TRY(timed(c, h8 ? "encoder_head_fp8" : "encoder_fp8_head_bf16", s,
+                      [&] { return launch_encoder_head_fp8(fa, h1, h2, hh, h8, grid, s); }));
       } else {
         FusedArgs fa{};
         fa.objs = objs;
@@ -386,7 +388,7 @@ std::vector<locc_schedule> tune_candidates(const locc_ctx* c) {
           for (int u : {4, 8})
             for (int chunks : {1, 2, 4}) {
               if (!split && (u != 8 || chunks != 1)) continue;  // the fused kernel: fixed scan unroll, no chunks
-              if (!split && c->cfg.precision == LOCC_FP8) continue;  // FP8 runs split only
+              if (!split && c->fp8()) continue;  // FP8 runs split only
               out.push_back(locc_schedule{wg, claim, dyn, split, u, chunks, {0, 0}});
             }
   return out;
@@ -414,7 +416,7 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (!(cfg->pad_m >= 0.0) || !std::isfinite(cfg->pad_m))
     return fail(LOCC_ERR_INVALID_ARG, "pad_m must be finite and >= 0");
   if (cfg->reserved != 0) return fail(LOCC_ERR_INVALID_ARG, "reserved field must be 0");
-  if (cfg->precision < LOCC_FP32 || cfg->precision > LOCC_FP8)
+  if (cfg->precision < LOCC_FP32 || cfg->precision > LOCC_FP8_ENCODER)
     return fail(LOCC_ERR_INVALID_ARG, "unknown precision %d", cfg->precision);
   if (!widths_supported(cfg->enc_h1, cfg->enc_h2, cfg->head_h))
     return fail(LOCC_ERR_UNSUPPORTED, "widths (%d, %d, %d) not compiled in", cfg->enc_h1, cfg->enc_h2,
@@ -434,7 +436,8 @@ locc_status locc_create(const locc_config* cfg, int device, locc_ctx** out) {
   if (e == hipSuccess) e = hipMemset(c->d_err, 0, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc(&c->d_queue, 2 * sizeof(unsigned int));
   if (e == hipSuccess) e = hipMemset(c->d_queue, 0, 2 * sizeof(unsigned int));
-  if (e == hipSuccess && cfg->precision == LOCC_FP8) e = hipMalloc(&c->d_amax, 3 * sizeof(unsigned int));
+  if (e == hipSuccess && (cfg->precision == LOCC_FP8 || cfg->precision == LOCC_FP8_ENCODER))
+    e = hipMalloc(&c->d_amax, 3 * sizeof(unsigned int));
   if (e == hipSuccess && cfg->precision != LOCC_FP32) {
     e = hipStreamCreateWithFlags(&c->crop_stream, hipStreamNonBlocking);
     for (int k = 0; e == hipSuccess && k <= locc_ctx::kMaxChunks; ++k)
@@ -488,7 +491,7 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   if (n != want) return fail(LOCC_ERR_INVALID_ARG, "weights: %zu floats given, %zu expected", n, want);
   for (size_t k = 0; k < n; ++k)
     if (!std::isfinite(h[k])) return fail(LOCC_ERR_INVALID_ARG, "weights: non-finite value at %zu", k);
-  if (c->cfg.precision == LOCC_FP8 && c->live_graphs > 0)
+  if (c->fp8() && c->live_graphs > 0)
     return fail(LOCC_ERR_BUSY, "FP8 weights: %d captured graph(s) hold the current scales; destroy them first",
                 c->live_graphs);
   const float* W1 = h;
@@ -555,11 +558,11 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     if (!c->d_wbf16) HIP_TRY(hipMalloc(&c->d_wbf16, L.total));
     HIP_TRY(hipMemcpy(c->d_wbf16, bpack.data(), L.total, hipMemcpyHostToDevice));
   }
-  if (c->cfg.precision == LOCC_FP8) {
-    const Fp8Layout L = fp8_layout(h1, h2, hh);
+  if (c->fp8()) {
+    const Fp8Layout L = fp8_layout(h1, h2, hh, c->fp8_head());
     std::vector<unsigned char> fpack(L.total);
     float sc[3];
-    fp8_pack(W1, b1, W2, b2, H1, c1, H2, c2, H3, c3, h1, h2, hh, fpack.data(), sc);
+    fp8_pack(W1, b1, W2, b2, H1, c1, H2, c2, H3, c3, h1, h2, hh, c->fp8_head(), fpack.data(), sc);
     if (!c->d_wfp8) HIP_TRY(hipMalloc(&c->d_wfp8, L.total));
     HIP_TRY(hipMemcpy(c->d_wfp8, fpack.data(), L.total, hipMemcpyHostToDevice));
     if (!c->d_wraw) HIP_TRY(hipMalloc(&c->d_wraw, n * sizeof(float)));
@@ -582,7 +585,7 @@ locc_status fp8_install_amax(locc_ctx* c, const float* amax) {
   const float inv = 1.f / fp8_scale(amax[0]);
   std::vector<unsigned short> w1((size_t)h1 * 8);
   fp8_pack_w1(c->h_w1b1.data(), c->h_w1b1.data() + (size_t)h1 * 6, h1, inv, w1.data());
-  const Fp8Layout L = fp8_layout(h1, c->cfg.enc_h2, c->cfg.head_h);
+  const Fp8Layout L = fp8_layout(h1, c->cfg.enc_h2, c->cfg.head_h, c->fp8_head());
   HIP_TRY(hipSetDevice(c->device));
   HIP_TRY(hipMemcpy(c->d_wfp8 + L.w1, w1.data(), w1.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
   for (int k = 0; k < 3; ++k) c->fp8_amax[k] = amax[k];
@@ -594,7 +597,7 @@ locc_status fp8_install_amax(locc_ctx* c, const float* amax) {
 
 locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
   if (!c || !amax) return fail(LOCC_ERR_INVALID_ARG, "null context or maxima");
-  if (c->cfg.precision != LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "activation maxima: not an FP8 context");
+  if (!c->fp8()) return fail(LOCC_ERR_UNSUPPORTED, "activation maxima: not an FP8 context");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(amax[k]) || amax[k] < 0.f)
       return fail(LOCC_ERR_INVALID_ARG, "activation maximum %d = %g: must be finite and >= 0", k, amax[k]);
@@ -609,7 +612,7 @@ locc_status locc_set_activation_amax(locc_ctx* c, const float* amax) {
 locc_status locc_calibrate(locc_ctx* c, const locc_object* objs, int32_t n_objs, const int32_t* pairs,
                            int32_t n_pairs, void* stream, float* amax_out) {
   if (!c) return fail(LOCC_ERR_INVALID_ARG, "null context");
-  if (c->cfg.precision != LOCC_FP8) return fail(LOCC_ERR_UNSUPPORTED, "calibration: not an FP8 context");
+  if (!c->fp8()) return fail(LOCC_ERR_UNSUPPORTED, "calibration: not an FP8 context");
   if (n_objs < 0 || n_pairs < 0) return fail(LOCC_ERR_INVALID_ARG, "negative count");
   if (n_pairs > 0 && (!objs || !pairs)) return fail(LOCC_ERR_INVALID_ARG, "null objects or pairs");
   if (!c->d_shapes) return fail(LOCC_ERR_NOT_READY, "no shape library uploaded");

@@ -67,6 +67,10 @@ struct locc_ctx {
   std::vector<hipEvent_t> event_pool;
   std::map<std::string, std::pair<int64_t, double>> totals;
 
+  // the FP8 network kernel: e4m3 on encoder layer 2 (both FP8 precisions), and on head layers 1-2 (LOCC_FP8)
+  bool fp8() const { return cfg.precision == LOCC_FP8 || cfg.precision == LOCC_FP8_ENCODER; }
+  bool fp8_head() const { return cfg.precision == LOCC_FP8; }
+
   locc::DeviceLibrary lib() const {
     const float* b = d_points;
     const size_t n = (size_t)n_points;

@@ -34,6 +34,7 @@
 // more resident workgroups than the encoder's register budget allows.
 #include "fused.h"
 #include "geometry.h"
+#include "head_bf16.h"
 #include "post.h"
 
 #include <cstring>
@@ -100,77 +101,16 @@ struct Smem {
   int32_t claim;
 };
 
-// One head layer on the tile: dst = ReLU(src W^T + bias), bf16 in / out.
-// Wave w computes output column tiles [w CTH, (w+1) CTH); B fragments stream
-// from global memory (L2) D k-steps ahead, in a ring of registers, so that
-// several L2 round trips are in flight behind the matrix cores.
-template <int KDIM, int SS, int DS, int CTH, int D>
-__device__ __forceinline__ void head_layer(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
-                                           const unsigned short* src, unsigned short* dst) {
-  constexpr int KS = KDIM / 16;
-  static_assert(KS % D == 0, "k-steps per head layer");
-  const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
-  const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
-  const unsigned short* arow = src + l32 * SS + 8 * g;
-  f32x16 acc[CTH];
-#pragma unroll
-  for (int c = 0; c < CTH; ++c) acc[c] = f32x16{};
-  u16x8 bq[D][CTH];
-#pragma unroll
-  for (int d = 0; d < D; ++d)
-#pragma unroll
-    for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + d) * 64];
-#pragma unroll 1
-  for (int s0 = 0; s0 < KS; s0 += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int s = s0 + d;
-      const u16x8 av = *reinterpret_cast<const u16x8*>(arow + 16 * s);
-#pragma unroll
-      for (int c = 0; c < CTH; ++c) acc[c] = mfma_k16(av, bq[d][c], acc[c]);
-      if (s + D < KS) {
-#pragma unroll
-        for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + s + D) * 64];
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < CTH; ++c) {
-    const int col = (wave * CTH + c) * 32 + l32;
-    const float bc = bias[col];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int row = 8 * (r >> 2) + 4 * g + (r & 3);
-      dst[row * DS + col] = bf16_bits(fmaxf(acc[c][r] + bc, 0.f));
-    }
-  }
-}
-
 // Head on the first n rows of the z tile, then the world-frame epilogue.
 // D: k-steps of weight fragments in flight (registers permitting)
 template <int H1, int H2, int HH, int D>
 __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& S, int n) {
   using S_t = Smem<H1, H2, HH>;
-  constexpr int T = S_t::T, ZS = S_t::ZS, GS = S_t::GS, CTH = HH / 128, KS3 = HH / 16;
-  const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
+  constexpr int T = S_t::T, ZS = S_t::ZS, GS = S_t::GS;
+  const int tid = threadIdx.x;
   for (int e = tid; e < (T - n) * ZS; e += 256) S.z[n * ZS + e] = 0;
   __syncthreads();
-  head_layer<2 * H2, ZS, GS, CTH, D>(A.h1p, A.c1, S.z, S.u.g);
-  __syncthreads();
-  head_layer<HH, GS, ZS, CTH, D>(A.h2p, A.c2, S.u.g, S.z);
-  __syncthreads();
-  // layer 3 (8 outputs, padded to 32 columns), reduction split over the 4 waves
-  {
-    f32x16 acc = f32x16{};
-    const u16x8* bp = reinterpret_cast<const u16x8*>(A.h3p) + lane;
-    const unsigned short* arow = S.z + l32 * ZS + 8 * g;
-#pragma unroll
-    for (int s = wave * (KS3 / 4); s < (wave + 1) * (KS3 / 4); ++s)
-      acc = mfma_k16(*reinterpret_cast<const u16x8*>(arow + 16 * s), bp[(size_t)s * 64], acc);
-    if (l32 < 8)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) S.y[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
-  }
+  head_bf16::layers<H2, HH, ZS, GS, D>(A.h1p, A.c1, A.h2p, A.c2, A.h3p, S.z, S.u.g, S.y);
   __syncthreads();
   for (int t = tid; t < T * 8; t += 256) {
     const int i = t >> 3, j = t & 7;
@@ -439,6 +379,20 @@ constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) 
 
 }  // namespace
 
+// B operand of 32x32x16: lane l of k-step s of column tile ct holds H[32 ct + l % 32][16 s + 8 (l / 32) + e]
+// (rows from out to out_pad zero)
+void bf16_pack_head(const float* H, int in, int out, int out_pad, unsigned short* dst) {
+  const int ks = in / 16;
+  for (int ct = 0; ct < out_pad / 32; ++ct)
+    for (int s = 0; s < ks; ++s)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int row = 32 * ct + l % 32;
+          const float v = row < out ? H[(size_t)row * in + 16 * s + 8 * (l / 32) + e] : 0.f;
+          dst[(((size_t)ct * ks + s) * 64 + l) * 8 + e] = host_bf16(v);
+        }
+}
+
 Bf16Layout bf16_layout(int h1, int h2, int hh) {
   Bf16Layout L{};
   size_t o = 0;
@@ -481,23 +435,11 @@ void bf16_pack(const float* W1, const float* b1, const float* W2, const float* b
             u16(L.w2)[(((size_t)(w * CT + ct) * KS2 + s) * 64 + l) * 8 + e] = host_bf16(W2[(size_t)col * h1 + f]);
           }
   std::memcpy(f32(L.b2), b2, sizeof(float) * h2);
-  // head layers, B operand of 32x32x16: lane l holds H[32 ct + l % 32][16 s + 8 (l / 32) + e]
-  auto pack_head = [&](const float* H, int in, int out, int out_pad, size_t at) {
-    const int ks = in / 16;
-    for (int ct = 0; ct < out_pad / 32; ++ct)
-      for (int s = 0; s < ks; ++s)
-        for (int l = 0; l < 64; ++l)
-          for (int e = 0; e < 8; ++e) {
-            const int row = 32 * ct + l % 32;
-            const float v = row < out ? H[(size_t)row * in + 16 * s + 8 * (l / 32) + e] : 0.f;
-            u16(at)[(((size_t)ct * ks + s) * 64 + l) * 8 + e] = host_bf16(v);
-          }
-  };
-  pack_head(H1, 2 * h2, hh, hh, L.h1);
+  bf16_pack_head(H1, 2 * h2, hh, hh, u16(L.h1));
   std::memcpy(f32(L.c1), c1, sizeof(float) * hh);
-  pack_head(H2, hh, hh, hh, L.h2);
+  bf16_pack_head(H2, hh, hh, hh, u16(L.h2));
   std::memcpy(f32(L.c2), c2, sizeof(float) * hh);
-  pack_head(H3, hh, 8, 32, L.h3);
+  bf16_pack_head(H3, hh, 8, 32, u16(L.h3));
   std::memcpy(f32(L.c3), c3, sizeof(float) * 8);
 }
 

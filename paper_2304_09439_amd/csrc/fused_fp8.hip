@@ -8,6 +8,8 @@
 //   encoder layer 2  fp8 x fp8, FP32 accumulation               32x32x64 f8f6f4
 //   head layers 1-2  fp8 x fp8, FP32 accumulation               32x32x64 f8f6f4
 //   head layer 3     bf16                                        32x32x16 bf16
+// or, with HEAD8 = false (the lower-error variant), the whole head in bf16 as
+// in the BF16 kernel (head_bf16.h), encoder layer 2 the only fp8 layer.
 // A weight matrix is stored as W / s_W in e4m3 with s_W = amax|W| / 448; an
 // activation x enters a layer as e4m3(min(x / s_x, 448)) with a static
 // s_x = amax / 448 from a calibration batch.  The product of the two scales
@@ -23,6 +25,7 @@
 // row holds, per k-step s and lane group g, those 32 bytes contiguously.
 #include "fused.h"
 #include "geometry.h"
+#include "head_bf16.h"
 #include "post.h"
 
 #include <cmath>
@@ -61,22 +64,25 @@ __device__ __forceinline__ int pack4_e4m3(float a, float b, float c, float d) {
   return __builtin_amdgcn_cvt_pk_fp8_f32(relu_clamp448(c), relu_clamp448(d), v, true);
 }
 
-template <int H1, int H2, int HH>
+// HEAD8: the fp8 head (z and g1 e4m3 tiles, g2 bf16); otherwise the bf16
+// head of head_bf16.h (z bf16, g1 in the union, g2 over z).
+template <int H1, int H2, int HH, bool HEAD8>
 struct Smem8 {
   static constexpr int T = kFusedTile;
   static constexpr int ZB = 2 * H2 + 16;  // bytes per row of the fp8 z tile
   static constexpr int GB = HH + 16;      // bytes per row of the fp8 g1 tile
-  static constexpr int G2 = HH + 8;       // bf16 elements per row of the g2 tile
+  static constexpr int G2 = HH + 8;       // bf16 elements per row of the g2 tile (the bf16 head's g1)
   static constexpr int HB = H1 + 16;      // bytes per row of the fp8 layer-1 tiles
+  static constexpr int ZS = (2 * H2 > HH ? 2 * H2 : HH) + 8;  // bf16 elements per row of the bf16 head's z tile
   union alignas(16) {
     struct {
       alignas(16) unsigned short rows[2 * kMaxK * 8];  // encoder rows of the current pair (bf16)
       alignas(16) unsigned char h1t[2][T * HB];        // layer-1 output of a 32-row tile (e4m3)
     } e;
-    unsigned short g2[T * G2];            // head layer-2 output (bf16)
+    unsigned short g2[T * G2];            // head layer-2 output (bf16), or the bf16 head's layer-1 output
   } u;
-  alignas(16) unsigned char z[T * ZB];
-  alignas(16) unsigned char g1[T * GB];
+  alignas(16) unsigned char z[HEAD8 ? T * ZB : 2 * T * ZS];
+  alignas(16) unsigned char g1[HEAD8 ? T * GB : 16];
   float y[4][T][8];
   int32_t pair[T];
   int32_t a[T];
@@ -136,18 +142,19 @@ __device__ __forceinline__ void head_layer8(const unsigned char* __restrict__ pa
   }
 }
 
-template <int H1, int H2, int HH>
-__device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH>& S, int n) {
-  using S_t = Smem8<H1, H2, HH>;
+// Head on the first n rows of the pooled-feature tile, then the world-frame epilogue.
+template <int H1, int H2, int HH, bool HEAD8>
+__device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH, HEAD8>& S, int n) {
+  using S_t = Smem8<H1, H2, HH, HEAD8>;
   constexpr int T = S_t::T, ZB = S_t::ZB, GB = S_t::GB, G2 = S_t::G2, CTH = HH / 128, KS3 = HH / 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
-  for (int e = tid; e < (T - n) * ZB; e += 256) S.z[n * ZB + e] = 0;
-  __syncthreads();
-  head_layer8<2 * H2, ZB, GB, CTH, false>(A.h1p, A.c1, A.s_z * A.s_h1, 1.f / A.s_g1, S.z, S.g1);
-  __syncthreads();
-  head_layer8<HH, GB, G2, CTH, true>(A.h2p, A.c2, A.s_g1 * A.s_h2, 0.f, S.g1, S.u.g2);
-  __syncthreads();
-  {
+  if constexpr (HEAD8) {
+    for (int e = tid; e < (T - n) * ZB; e += 256) S.z[n * ZB + e] = 0;
+    __syncthreads();
+    head_layer8<2 * H2, ZB, GB, CTH, false>(A.h1p, A.c1, A.s_z * A.s_h1, 1.f / A.s_g1, S.z, S.g1);
+    __syncthreads();
+    head_layer8<HH, GB, G2, CTH, true>(A.h2p, A.c2, A.s_g1 * A.s_h2, 0.f, S.g1, S.u.g2);
+    __syncthreads();
     f32x16 acc = f32x16{};
     const u16x8* bp = reinterpret_cast<const u16x8*>(A.h3p) + lane;
     const unsigned short* arow = S.u.g2 + l32 * G2 + 8 * g;
@@ -157,6 +164,14 @@ __device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH>& 
     if (l32 < 8)
 #pragma unroll
       for (int r = 0; r < 16; ++r) S.y[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
+  } else {
+    constexpr int ZS = S_t::ZS;
+    unsigned short* z16 = reinterpret_cast<unsigned short*>(S.z);
+    for (int e = tid; e < (T - n) * ZS; e += 256) z16[n * ZS + e] = 0;
+    __syncthreads();
+    head_bf16::layers<H2, HH, ZS, G2, 4>(reinterpret_cast<const unsigned short*>(A.h1p), A.c1,
+                                         reinterpret_cast<const unsigned short*>(A.h2p), A.c2, A.h3p, z16, S.u.g2,
+                                         S.y);
   }
   __syncthreads();
   for (int t = tid; t < T * 8; t += 256) {
@@ -168,9 +183,9 @@ __device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH>& 
   __syncthreads();
 }
 
-template <int H1, int H2, int HH>
+template <int H1, int H2, int HH, bool HEAD8>
 __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp8Args A) {
-  using S_t = Smem8<H1, H2, HH>;
+  using S_t = Smem8<H1, H2, HH, HEAD8>;
   constexpr int T = S_t::T, ZB = S_t::ZB;
   constexpr int FT = H1 / 32;    // layer-1 feature tiles
   constexpr int FW = (FT + 3) / 4;  // layer-1 feature tiles per wave (tiles wave, wave + 4, ...)
@@ -317,8 +332,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
           const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) * s_enc + bias2[ct], 0.f);
           if (lane < 32) {
             const int col = side * H2 + (wave * CT + ct) * 32 + lane;
-            const int q = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(f * inv_z, 448.f), 0.f, 0, false);
-            S.z[slot * ZB + col] = (unsigned char)(q & 0xff);
+            if constexpr (HEAD8) {
+              const int q = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(f * inv_z, 448.f), 0.f, 0, false);
+              S.z[slot * ZB + col] = (unsigned char)(q & 0xff);
+            } else {
+              reinterpret_cast<unsigned short*>(S.z)[slot * S_t::ZS + col] = head_bf16::bits(f);
+            }
             if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? f : __builtin_nanf("");
           }
         }
@@ -326,12 +345,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void encoder_head_fp8_kernel(Fp
       ++slot;
       __syncthreads();
       if (slot == T) {
-        head_tile8<H1, H2, HH>(A, S, T);
+        head_tile8<H1, H2, HH, HEAD8>(A, S, T);
         slot = 0;
       }
     }
   }
-  if (slot > 0) head_tile8<H1, H2, HH>(A, S, slot);
+  if (slot > 0) head_tile8<H1, H2, HH, HEAD8>(A, S, slot);
   if (A.dynamic && tid == 0) {
     __threadfence();
     if (atomicAdd(A.queue + 1, 1u) == gridDim.x - 1) {
@@ -465,15 +484,16 @@ void fp8_pack_w1(const float* W1, const float* b1, int h1, float inv, unsigned s
       }
 }
 
-Fp8Layout fp8_layout(int h1, int h2, int hh) {
+Fp8Layout fp8_layout(int h1, int h2, int hh, bool head8) {
   Fp8Layout L{};
+  const size_t hb = head8 ? 1 : 2;  // bytes per head weight
   size_t o = 0;
   L.w1 = o; o = align256(o + (size_t)h1 * 8 * 2);
   L.w2 = o; o = align256(o + (size_t)h2 * h1);
   L.b2 = o; o = align256(o + (size_t)h2 * 4);
-  L.h1 = o; o = align256(o + (size_t)hh * 2 * h2);
+  L.h1 = o; o = align256(o + (size_t)hh * 2 * h2 * hb);
   L.c1 = o; o = align256(o + (size_t)hh * 4);
-  L.h2 = o; o = align256(o + (size_t)hh * hh);
+  L.h2 = o; o = align256(o + (size_t)hh * hh * hb);
   L.c2 = o; o = align256(o + (size_t)hh * 4);
   L.h3 = o; o = align256(o + (size_t)32 * hh * 2);
   L.c3 = o; o = align256(o + 8 * 4);
@@ -482,17 +502,17 @@ Fp8Layout fp8_layout(int h1, int h2, int hh) {
 }
 
 void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1, const float* c1,
-              const float* H2, const float* c2, const float* H3, const float* c3, int h1, int h2, int hh,
+              const float* H2, const float* c2, const float* H3, const float* c3, int h1, int h2, int hh, bool head8,
               unsigned char* dst, float* weight_scales) {
-  const Fp8Layout L = fp8_layout(h1, h2, hh);
+  const Fp8Layout L = fp8_layout(h1, h2, hh, head8);
   std::memset(dst, 0, L.total);
   auto u16 = [&](size_t off) { return reinterpret_cast<unsigned short*>(dst + off); };
   auto f32 = [&](size_t off) { return reinterpret_cast<float*>(dst + off); };
   // encoder layer 1 (bf16): unscaled until the activation scale is known
   fp8_pack_w1(W1, b1, h1, 1.f, u16(L.w1));
   const float s_w2 = std::fmax(amax_of(W2, (size_t)h2 * h1), 1e-30f) / 448.f;
-  const float s_h1 = std::fmax(amax_of(H1, (size_t)hh * 2 * h2), 1e-30f) / 448.f;
-  const float s_h2 = std::fmax(amax_of(H2, (size_t)hh * hh), 1e-30f) / 448.f;
+  const float s_h1 = head8 ? std::fmax(amax_of(H1, (size_t)hh * 2 * h2), 1e-30f) / 448.f : 1.f;
+  const float s_h2 = head8 ? std::fmax(amax_of(H2, (size_t)hh * hh), 1e-30f) / 448.f : 1.f;
   weight_scales[0] = s_w2;
   weight_scales[1] = s_h1;
   weight_scales[2] = s_h2;
@@ -518,9 +538,14 @@ void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2
             dst[at + (((size_t)ct * ks + s) * 64 + l) * 32 + e] =
                 host_e4m3(H[(size_t)(32 * ct + l % 32) * in + 64 * s + 32 * (l / 32) + e] / sc);
   };
-  pack8(H1, 2 * h2, hh, s_h1, L.h1);
+  if (head8) {
+    pack8(H1, 2 * h2, hh, s_h1, L.h1);
+    pack8(H2, hh, hh, s_h2, L.h2);
+  } else {
+    bf16_pack_head(H1, 2 * h2, hh, hh, u16(L.h1));
+    bf16_pack_head(H2, hh, hh, hh, u16(L.h2));
+  }
   std::memcpy(f32(L.c1), c1, sizeof(float) * hh);
-  pack8(H2, hh, hh, s_h2, L.h2);
   std::memcpy(f32(L.c2), c2, sizeof(float) * hh);
   // head layer 3 (bf16, 8 outputs padded to 32 columns)
   for (int s = 0; s < hh / 16; ++s)
@@ -532,8 +557,8 @@ void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2
   std::memcpy(f32(L.c3), c3, sizeof(float) * 8);
 }
 
-void fp8_bind(Fp8Args& a, const unsigned char* base, int h1, int h2, int hh) {
-  const Fp8Layout L = fp8_layout(h1, h2, hh);
+void fp8_bind(Fp8Args& a, const unsigned char* base, int h1, int h2, int hh, bool head8) {
+  const Fp8Layout L = fp8_layout(h1, h2, hh, head8);
   a.w1p = reinterpret_cast<const unsigned short*>(base + L.w1);
   a.w2p = base + L.w2;
   a.b2 = reinterpret_cast<const float*>(base + L.b2);
@@ -545,12 +570,20 @@ void fp8_bind(Fp8Args& a, const unsigned char* base, int h1, int h2, int hh) {
   a.c3 = reinterpret_cast<const float*>(base + L.c3);
 }
 
-hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, int grid, hipStream_t s) {
+template <int H1, int H2, int HH>
+void launch_fp8(const Fp8Args& a, bool head8, int grid, hipStream_t s) {
+  if (head8)
+    hipLaunchKernelGGL((encoder_head_fp8_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((encoder_head_fp8_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
+}
+
+hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, bool head8, int grid, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   if (h1 == 64 && h2 == 128 && hh == 256)
-    hipLaunchKernelGGL((encoder_head_fp8_kernel<64, 128, 256>), dim3(grid), dim3(256), 0, s, a);
+    launch_fp8<64, 128, 256>(a, head8, grid, s);
   else if (h1 == 128 && h2 == 256 && hh == 512)
-    hipLaunchKernelGGL((encoder_head_fp8_kernel<128, 256, 512>), dim3(grid), dim3(256), 0, s, a);
+    launch_fp8<128, 256, 512>(a, head8, grid, s);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

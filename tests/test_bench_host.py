@@ -57,3 +57,20 @@ def test_encoder_rows_counts_valid_and_tile_rows():
     import numpy as np
     counts = np.array([[0, 5], [200, 33], [-1, -1], [128, 64]], np.int32)
     assert bench.encoder_rows(counts, 128) == (0 + 5 + 128 + 33 + 128 + 64, 0 + 32 + 128 + 64 + 128 + 64)
+
+
+def test_mixed_precision_kernel_peak():
+    """The FP8-encoder / BF16-head kernel is charged its encoder FLOPs at the FP8 peak and its head FLOPs at
+    the BF16 peak: its peak is the rate at which that work would take its time at those peaks."""
+    w = bench.per_pair_work(128, I.SCALE_WIDTHS, 2048)
+    P = 1000
+    rows = (P * 2 * 100, P * 2 * 128)
+    k = bench.kernel_entries({"encoder_fp8_head_bf16": (1, 0.5)}, w, P, "scale", 1, "fp8_encoder", rows=rows)
+    e = k["encoder_fp8_head_bf16"]
+    enc, head = rows[0] * w["row_flops"], w["head_flops"] * P
+    peak = (enc + head) / (enc / 5000.0 + head / 2500.0)
+    assert e["peak"] == pytest.approx(peak, abs=0.1) and 2500 < e["peak"] < 5000
+    assert e["frac"] == pytest.approx((enc + head) / 0.5e-3 / 1e12 / peak, abs=1e-4)
+    assert "peak_basis" in e
+    same = bench.kernel_entries({"encoder_head_fp8": (1, 0.5)}, w, P, "scale", 1, "fp8", rows=rows)
+    assert same["encoder_head_fp8"]["peak"] == 5000.0 and "peak_basis" not in same["encoder_head_fp8"]

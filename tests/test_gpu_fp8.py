@@ -20,6 +20,11 @@ Two comparisons on the same seeded inputs:
 Crop counts must match the oracle bit for bit.  Activation scales come from
 the model's calibration on a separate batch of pairs and are installed with
 locc_set_activation_amax, so both sides quantise with the same scales.
+
+The lower-error variant (precision "fp8_encoder": e4m3 on encoder layer 2
+only, the head in bf16) is held to the same bars against its own CPU model
+(fp8_layers = ("enc2",)) and against the oracle, where its logit, point and
+normal errors are also required below the FP8 tolerance of 6e-2.
 """
 
 import sys
@@ -43,6 +48,8 @@ Z_TOL = 1e-4     # pooled features vs the model
 Y_TOL = 1e-2     # raw outputs and contacts vs the model
 ORACLE_SLACK = 2e-3
 FP8_TOL = 6e-2   # the stated FP8 tolerance against the FP64 oracle
+ENC_ONLY = ("enc2",)   # the layers the fp8_encoder variant runs in e4m3
+VARIANTS = [("fp8", "model"), ("fp8_encoder", "model_enc")]
 
 
 def say(msg):
@@ -81,8 +88,9 @@ def scale_case():
     say(f"scale case: model calibration maxima {amax}")
     ref = O.detect_scene(ev, w, SCALE, 128)
     model = Q.fp8_detect(ref["geoms"], w, SCALE, amax)
+    model_enc = Q.fp8_detect(ref["geoms"], w, SCALE, amax, fp8_layers=ENC_ONLY)
     return dict(scene=ev, full=sc, w=w, K=128, widths=SCALE, amax=amax, ref=ref, model=model,
-                calib=calib_pairs)
+                model_enc=model_enc, calib=calib_pairs)
 
 
 @pytest.fixture(scope="module")
@@ -92,11 +100,13 @@ def small_case():
     ref = O.detect_scene(sc, w, SMALL, 64)
     amax = Q.calibrate(ref["geoms"], w, SMALL)
     model = Q.fp8_detect(ref["geoms"], w, SMALL, amax)
-    return dict(scene=sc, full=sc, w=w, K=64, widths=SMALL, amax=amax, ref=ref, model=model, calib=sc.pairs)
+    model_enc = Q.fp8_detect(ref["geoms"], w, SMALL, amax, fp8_layers=ENC_ONLY)
+    return dict(scene=sc, full=sc, w=w, K=64, widths=SMALL, amax=amax, ref=ref, model=model, model_enc=model_enc,
+                calib=sc.pairs)
 
 
-def _ctx(case, amax=True):
-    ctx = B.context_for_scene(case["scene"], case["K"], case["widths"], case["w"], precision="fp8")
+def _ctx(case, amax=True, precision="fp8"):
+    ctx = B.context_for_scene(case["scene"], case["K"], case["widths"], case["w"], precision=precision)
     if amax:
         ctx.set_activation_amax(case["amax"])
     return ctx
@@ -123,13 +133,14 @@ def test_calibration_matches_the_model(torch, scale_case):
     ctx.close()
 
 
+@pytest.mark.parametrize("precision,model_key", VARIANTS)
 @pytest.mark.parametrize("which", ["small", "scale"])
-def test_fp8_matches_the_quantised_model(torch, which, request):
+def test_fp8_matches_the_quantised_model(torch, which, precision, model_key, request):
     c = request.getfixturevalue(f"{which}_case")
-    say(f"FP8 vs quantised model, {which}: {c['scene'].n_pairs} pairs")
-    ctx = _ctx(c)
+    say(f"{precision} vs quantised model, {which}: {c['scene'].n_pairs} pairs")
+    ctx = _ctx(c, precision=precision)
     out, counts, z, y = _run(torch, ctx, c["scene"])
-    ref, model = c["ref"], c["model"]
+    ref, model = c["ref"], c[model_key]
     np.testing.assert_array_equal(counts, ref["counts"])
     bad = np.isnan(ref["y"][:, 0])
     assert np.array_equal(np.isnan(out).any(axis=1), bad) and np.isnan(y[bad]).all()
@@ -144,17 +155,18 @@ def test_fp8_matches_the_quantised_model(torch, which, request):
     ctx.close()
 
 
-def test_fp8_error_against_the_oracle(torch, scale_case):
+@pytest.mark.parametrize("precision,model_key", VARIANTS)
+def test_fp8_error_against_the_oracle(torch, scale_case, precision, model_key):
     c = scale_case
-    ctx = _ctx(c)
+    ctx = _ctx(c, precision=precision)
     out, counts, z, y = _run(torch, ctx, c["scene"])
     ctx.close()
     rows = np.arange(1024)
     rows = rows[~np.isnan(c["ref"]["y"][rows, 0])]
-    ref_y, model_y = c["ref"]["y"][rows], c["model"]["y"][rows]
+    ref_y, model_y = c["ref"]["y"][rows], c[model_key]["y"][rows]
     e_dev = normwise_errors(y[rows], ref_y)
     e_model = normwise_errors(model_y, ref_y)
-    say(f"  FP8 vs FP64 oracle on {len(rows)} pairs: normwise {e_dev}")
+    say(f"  {precision} vs FP64 oracle on {len(rows)} pairs: normwise {e_dev}")
     say(f"    per-pair max {field_errors(y[rows], ref_y)}")
     say(f"    CPU model of the format: normwise {e_model}")
     say(f"    flag agreement raw {flag_agreement(y[rows, 0], ref_y[:, 0]):.4f}, "
@@ -165,6 +177,11 @@ def test_fp8_error_against_the_oracle(torch, scale_case):
     # the collision flag, banded at the FP8 tolerance (pairs whose reference logit lies within 6e-2 RMS of
     # zero are left out, as the bar is stated for a flag the format can decide)
     assert flag_agreement(y[rows, 0], ref_y[:, 0], band=FP8_TOL) >= 0.999
+    if precision == "fp8_encoder":
+        # the lower-error variant meets the FP8 tolerance on the flag logit, the contact point and the normal;
+        # its depth error (0.088 in the CPU model of the roundings) is the format's own, on these untrained weights
+        for k in ("logit", "point", "normal"):
+            assert e_dev[k] < FP8_TOL, k
 
 
 @pytest.mark.xfail(strict=True, reason="e4m3 on encoder layer 2 and head layers 1-2: the format's own error on "
@@ -209,9 +226,10 @@ def test_fp8_needs_activation_scales(torch, small_case):
     bctx.close()
 
 
-def test_fp8_results_do_not_depend_on_the_schedule_or_graph(torch, scale_case):
+@pytest.mark.parametrize("precision", ["fp8", "fp8_encoder"])
+def test_fp8_results_do_not_depend_on_the_schedule_or_graph(torch, scale_case, precision):
     c = scale_case
-    ctx = _ctx(c)
+    ctx = _ctx(c, precision=precision)
     base = _run(torch, ctx, c["scene"])
     for sched in (dict(wg_per_cu=1, claim=1, dynamic=False, crop_unroll=4),
                   dict(wg_per_cu=2, claim=16, dynamic=True, crop_unroll=8)):

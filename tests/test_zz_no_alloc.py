@@ -37,13 +37,14 @@ def scene():
 
 
 @pytest.mark.parametrize("precision,split,first", [("fp32", None, 3000), ("bf16", True, 6000),
-                                                   ("bf16", False, 6000), ("fp8", None, 6000)])
+                                                   ("bf16", False, 6000), ("fp8", None, 6000),
+                                                   ("fp8_encoder", None, 6000)])
 def test_noalloc_equals_detect_on_two_calls(torch, scene, precision, split, first):
     say(f"no-allocation detect, {precision} split={split}: {first} pairs, then 700 others")
     w = I.flatten_weights(I.gaussian_weights(LW, seed=0, bias_std=0.1))
     ctx = B.context_for_scene(scene, 128, SCALE, w, precision=precision)
     objs, pairs = B.scene_tensors(scene)
-    if precision == "fp8":
+    if precision.startswith("fp8"):
         ctx.calibrate(objs, pairs[:1024])
     if split is not None:
         ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=split)
