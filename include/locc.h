@@ -490,6 +490,21 @@ LOCC_API locc_status locc_serve_start(locc_ctx* ctx, const locc_serve_config* cf
 LOCC_API locc_status locc_serve_submit(locc_server* srv, const int32_t* h_upd_ids, const locc_object* h_upd,
                                        int32_t n_upd, const int32_t* h_pairs, int32_t n_pairs, uint64_t* h_req_id);
 
+/* Queues n_req requests in order under one lock (host arrays, copied):
+ * request k holds the updates h_upd_offsets[k] .. h_upd_offsets[k + 1] - 1
+ * of h_upd_ids / h_upd and the pairs h_pair_offsets[k] .. h_pair_offsets[k +
+ * 1] - 1 of h_pairs (offsets [n_req + 1], non-decreasing, from 0); ids go to
+ * h_req_ids [n_req].  For callers that submit many requests at once (and
+ * for measuring the server without a per-request call): each request is
+ * checked as by locc_serve_submit, and the first one refused stops the call
+ * with its status; *h_n_accepted is the number queued before it.
+ * Errors: as locc_serve_submit; INVALID_ARG for negative or decreasing
+ * offsets. */
+LOCC_API locc_status locc_serve_submit_many(locc_server* srv, int32_t n_req, const int32_t* h_upd_offsets,
+                                            const int32_t* h_upd_ids, const locc_object* h_upd,
+                                            const int32_t* h_pair_offsets, const int32_t* h_pairs,
+                                            uint64_t* h_req_ids, int32_t* h_n_accepted);
+
 /* *h_done = 1 once the request has completed; then its contacts and counts
  * are copied to h_out [n_pairs] / h_counts [n_pairs][2] (either may be NULL),
  * *h_latency_ms (may be NULL) is completion minus submission on the host's
@@ -512,7 +527,9 @@ LOCC_API locc_status locc_serve_stop(locc_server* srv);
  * overhead).  locc_profile(ctx, 1) clears the totals and starts recording,
  * locc_profile(ctx, 0) stops.  Kernel names: "crop", "encoder_fp32",
  * "head_fp32" (FP32 per-step path), "fused_bf16" (BF16, one launch),
- * "crop" and "encoder_head_bf16" (BF16 split schedule). */
+ * "crop" and "encoder_head_bf16" (BF16 split schedule), "crop" and
+ * "encoder_head_fp8" (LOCC_FP8) or "encoder_fp8_head_bf16"
+ * (LOCC_FP8_ENCODER). */
 typedef struct {
   char name[32];
   int64_t launches;

@@ -25,7 +25,7 @@ EXPORTS = ("locc_version", "locc_last_error", "locc_create", "locc_destroy", "lo
            "locc_upload_shapes", "locc_detect", "locc_detect_noalloc", "locc_debug_crop", "locc_debug_forward", "locc_device_errors",
            "locc_profile", "locc_profile_read", "locc_set_schedule", "locc_get_schedule", "locc_autotune",
            "locc_reserve", "locc_detect_device_count", "locc_graph_capture", "locc_graph_launch",
-           "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_poll", "locc_serve_get_stats",
+           "locc_graph_destroy", "locc_serve_start", "locc_serve_submit", "locc_serve_submit_many", "locc_serve_poll", "locc_serve_get_stats",
            "locc_serve_stop", "locc_calibrate", "locc_set_activation_amax", "locc_broad_phase",
            "locc_reserve_broad_phase", "locc_step_graph_capture", "locc_voxel_weight_count", "locc_voxel_create",
            "locc_voxel_destroy", "locc_voxel_upload_weights", "locc_voxel_upload_shapes", "locc_voxel_embeddings",
@@ -129,6 +129,8 @@ def load() -> ctypes.CDLL:
     L.locc_serve_start.argtypes = [vp, ctypes.POINTER(ServeConfig), vp, i32, ctypes.POINTER(vp)]
     L.locc_serve_submit.restype = ctypes.c_int
     L.locc_serve_submit.argtypes = [vp, vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.locc_serve_submit_many.restype = ctypes.c_int
+    L.locc_serve_submit_many.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int32)]
     L.locc_serve_poll.restype = ctypes.c_int
     L.locc_serve_poll.argtypes = [vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_double)]
@@ -575,6 +577,46 @@ class Server:
                                         len(pr), ctypes.byref(rid)))
         self._n_pairs[rid.value] = len(pr)
         return rid.value
+
+    @staticmethod
+    def pack_requests(requests):
+        """[(upd_ids, upd_objects, pairs), ...] -> the flat arrays submit_many_arrays takes."""
+        n = len(requests)
+        uo = np.zeros(n + 1, np.int32)
+        po = np.zeros(n + 1, np.int32)
+        uo[1:] = np.cumsum([len(r[0]) for r in requests])
+        po[1:] = np.cumsum([len(r[2]) for r in requests])
+        ids = np.concatenate([np.asarray(r[0], np.int32).reshape(-1) for r in requests] + [np.zeros(0, np.int32)])
+        upd = np.concatenate([np.asarray(r[1], np.float32).reshape(-1, 8) for r in requests] +
+                             [np.zeros((0, 8), np.float32)])
+        pr = np.concatenate([np.asarray(r[2], np.int32).reshape(-1, 2) for r in requests] +
+                            [np.zeros((0, 2), np.int32)])
+        return tuple(np.ascontiguousarray(a) for a in (uo, ids, upd, po, pr))
+
+    def submit_many_arrays(self, upd_offsets, upd_ids, upd_objects, pair_offsets, pairs):
+        """locc_serve_submit_many on flat host arrays (see pack_requests); returns the ids of the requests
+        queued (all of them unless one was refused: then the call raises after queueing those before it, and
+        the exception carries their ids as .accepted_ids)."""
+        n = len(upd_offsets) - 1
+        out_ids = np.zeros(max(n, 1), np.uint64)
+        acc = ctypes.c_int32()
+        st = load().locc_serve_submit_many(self._h, n, upd_offsets.ctypes.data, upd_ids.ctypes.data,
+                                           upd_objects.ctypes.data, pair_offsets.ctypes.data, pairs.ctypes.data,
+                                           out_ids.ctypes.data, ctypes.byref(acc))
+        got = [int(x) for x in out_ids[:acc.value]]
+        for k, rid in enumerate(got):
+            self._n_pairs[rid] = int(pair_offsets[k + 1] - pair_offsets[k])
+        if st != OK:
+            try:
+                _check(st)
+            except LoccError as e:
+                e.accepted_ids = got
+                raise
+        return got
+
+    def submit_many(self, requests):
+        """Queues [(upd_ids, upd_objects, pairs), ...] in order with one call (see submit_many_arrays)."""
+        return self.submit_many_arrays(*self.pack_requests(requests))
 
     def poll(self, rid: int):
         """None while running; (contacts [P, 8], counts [P, 2], latency_ms) once done."""

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "locc_internal.h"
+#include "pack.h"
 
 namespace locc {
 
@@ -40,18 +41,7 @@ struct FusedArgs {
   int32_t dev_base;     // first pair of this launch within the step (device count mode)
 };
 
-// Byte offsets of the packed BF16 weights inside one device buffer.
-struct Bf16Layout {
-  size_t w1, w2, b2, h1, c1, h2, c2, h3, c3, total;
-};
-Bf16Layout bf16_layout(int h1, int h2, int hh);
-void bf16_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
-               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
-               int h2, int hh, unsigned char* dst);
 void bf16_bind(FusedArgs& a, const unsigned char* dev_base, int h1, int h2, int hh);
-// A head matrix H [out][in] (row-major) as the B operand fragments of the bf16
-// head (head_bf16.h); out_pad / 32 column tiles, rows past out zero.
-void bf16_pack_head(const float* H, int in, int out, int out_pad, unsigned short* dst);
 
 // Workgroups per CU the fused kernel is compiled for.
 constexpr int kFusedWgPerCu = 2;
@@ -99,20 +89,7 @@ struct Fp8Args {
   int32_t dev_base;  // first pair of this launch within the step (device count mode)
 };
 
-struct Fp8Layout {
-  size_t w1, w2, b2, h1, c1, h2, c2, h3, c3, total;
-};
-// head8: head layers 1-2 in e4m3 (else their bf16 fragments)
-Fp8Layout fp8_layout(int h1, int h2, int hh, bool head8);
-// weight_scales receives (s_w2, s_h1, s_h2); s_h1 = s_h2 = 1 without the fp8 head.
-void fp8_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1, const float* c1,
-              const float* H2, const float* c2, const float* H3, const float* c3, int h1, int h2, int hh, bool head8,
-              unsigned char* dst, float* weight_scales);
 void fp8_bind(Fp8Args& a, const unsigned char* dev_base, int h1, int h2, int hh, bool head8);
-// OCP e4m3 (E4M3FN) of x, round to nearest even, saturating at 448.
-unsigned char host_e4m3(float x);
-// Encoder layer-1 pack of the FP8 path, scaled by inv = 1 / s_x (h1 * 8 bf16 values).
-void fp8_pack_w1(const float* W1, const float* b1, int h1, float inv, unsigned short* dst);
 hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, bool head8, int grid, hipStream_t s);
 
 // Calibration: maxima over the valid pairs of the encoder layer-1 output, the

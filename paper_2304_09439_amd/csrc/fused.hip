@@ -366,82 +366,7 @@ hipError_t run_fused(const FusedArgs& a, int grid, bool pre, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------- host packing
-unsigned short host_bf16(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);  // quiet NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
-constexpr int perm_feature(int ft, int g, int r) { return 32 * ft + 8 * (r / 4) + 4 * g + r % 4; }
-
 }  // namespace
-
-// B operand of 32x32x16: lane l of k-step s of column tile ct holds H[32 ct + l % 32][16 s + 8 (l / 32) + e]
-// (rows from out to out_pad zero)
-void bf16_pack_head(const float* H, int in, int out, int out_pad, unsigned short* dst) {
-  const int ks = in / 16;
-  for (int ct = 0; ct < out_pad / 32; ++ct)
-    for (int s = 0; s < ks; ++s)
-      for (int l = 0; l < 64; ++l)
-        for (int e = 0; e < 8; ++e) {
-          const int row = 32 * ct + l % 32;
-          const float v = row < out ? H[(size_t)row * in + 16 * s + 8 * (l / 32) + e] : 0.f;
-          dst[(((size_t)ct * ks + s) * 64 + l) * 8 + e] = host_bf16(v);
-        }
-}
-
-Bf16Layout bf16_layout(int h1, int h2, int hh) {
-  Bf16Layout L{};
-  size_t o = 0;
-  L.w1 = o; o = align256(o + (size_t)h1 * 8 * 2);
-  L.w2 = o; o = align256(o + (size_t)h2 * h1 * 2);
-  L.b2 = o; o = align256(o + (size_t)h2 * 4);
-  L.h1 = o; o = align256(o + (size_t)hh * 2 * h2 * 2);
-  L.c1 = o; o = align256(o + (size_t)hh * 4);
-  L.h2 = o; o = align256(o + (size_t)hh * hh * 2);
-  L.c2 = o; o = align256(o + (size_t)hh * 4);
-  L.h3 = o; o = align256(o + (size_t)32 * hh * 2);
-  L.c3 = o; o = align256(o + 8 * 4);
-  L.total = o;
-  return L;
-}
-
-void bf16_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
-               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
-               int h2, int hh, unsigned char* dst) {
-  const Bf16Layout L = bf16_layout(h1, h2, hh);
-  std::memset(dst, 0, L.total);
-  auto u16 = [&](size_t off) { return reinterpret_cast<unsigned short*>(dst + off); };
-  auto f32 = [&](size_t off) { return reinterpret_cast<float*>(dst + off); };
-  // encoder layer 1, A operand of 32x32x8: [W1 | b1 | 0][32 ft + l % 32][4 (l / 32) + e]
-  for (int ft = 0; ft < h1 / 32; ++ft)
-    for (int l = 0; l < 64; ++l)
-      for (int e = 0; e < 4; ++e) {
-        const int f = 32 * ft + l % 32, c = 4 * (l / 32) + e;
-        u16(L.w1)[((size_t)ft * 64 + l) * 4 + e] = host_bf16(c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f));
-      }
-  // encoder layer 2, B operand of 32x32x16, reduction index permuted to layer 1's output layout
-  const int CT = h2 / 128, KS2 = h1 / 16;
-  for (int w = 0; w < 4; ++w)
-    for (int ct = 0; ct < CT; ++ct)
-      for (int s = 0; s < KS2; ++s)
-        for (int l = 0; l < 64; ++l)
-          for (int e = 0; e < 8; ++e) {
-            const int col = (w * CT + ct) * 32 + l % 32;
-            const int f = perm_feature(s / 2, l / 32, 8 * (s % 2) + e);
-            u16(L.w2)[(((size_t)(w * CT + ct) * KS2 + s) * 64 + l) * 8 + e] = host_bf16(W2[(size_t)col * h1 + f]);
-          }
-  std::memcpy(f32(L.b2), b2, sizeof(float) * h2);
-  bf16_pack_head(H1, 2 * h2, hh, hh, u16(L.h1));
-  std::memcpy(f32(L.c1), c1, sizeof(float) * hh);
-  bf16_pack_head(H2, hh, hh, hh, u16(L.h2));
-  std::memcpy(f32(L.c2), c2, sizeof(float) * hh);
-  bf16_pack_head(H3, hh, 8, 32, u16(L.h3));
-  std::memcpy(f32(L.c3), c3, sizeof(float) * 8);
-}
 
 void bf16_bind(FusedArgs& a, const unsigned char* base, int h1, int h2, int hh) {
   const Bf16Layout L = bf16_layout(h1, h2, hh);

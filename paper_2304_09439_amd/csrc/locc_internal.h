@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "locc.h"
+#include "pack.h"
 
 namespace locc {
 
@@ -146,11 +147,7 @@ struct NetArgs {
 hipError_t launch_encoder_fp32(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t s);
 hipError_t launch_head_fp32(const Fp32Net& w, const NetArgs& a, hipStream_t s);
 
-// Host-side packing of row-major FP32 weights into the fragment layouts above.
-size_t fp32_pack_floats(int h1, int h2, int hh);
-void fp32_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
-               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
-               int h2, int hh, float* dst);
+// Device views of the FP32 weights packed by fp32_pack (pack.h).
 Fp32Net fp32_view(const float* dev_base, int h1, int h2, int hh);
 
 }  // namespace locc

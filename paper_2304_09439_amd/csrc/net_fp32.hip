@@ -373,72 +373,8 @@ hipError_t launch_head_fp32(const Fp32Net& w, const NetArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-// ------------------------------------------------------------- host packing
-namespace {
-struct PackLayout {
-  size_t w1, w2, b2, h1, c1, h2, c2, h3, c3, total;
-};
-size_t align64(size_t n) { return (n + 63) & ~size_t(63); }
-PackLayout pack_layout(int h1, int h2, int hh) {
-  PackLayout L{};
-  size_t o = 0;
-  L.w1 = o; o = align64(o + (size_t)8 * h1);
-  L.w2 = o; o = align64(o + (size_t)h2 * h1);
-  L.b2 = o; o = align64(o + h2);
-  L.h1 = o; o = align64(o + (size_t)hh * 2 * h2);
-  L.c1 = o; o = align64(o + hh);
-  L.h2 = o; o = align64(o + (size_t)hh * hh);
-  L.c2 = o; o = align64(o + hh);
-  L.h3 = o; o = align64(o + (size_t)8 * hh);
-  L.c3 = o; o = align64(o + 8);
-  L.total = o;
-  return L;
-}
-}  // namespace
-
-size_t fp32_pack_floats(int h1, int h2, int hh) { return pack_layout(h1, h2, hh).total; }
-
-void fp32_pack(const float* W1, const float* b1, const float* W2, const float* b2, const float* H1,
-               const float* c1, const float* H2, const float* c2, const float* H3, const float* c3, int h1,
-               int h2, int hh, float* dst) {
-  const PackLayout L = pack_layout(h1, h2, hh);
-  std::memset(dst, 0, sizeof(float) * L.total);
-  // layer 1 A operand: [W1 | b1 | 0][f][c], f = 32 ft + l % 32, c = 2 s + l / 32
-  for (int ft = 0; ft < h1 / 32; ++ft)
-    for (int s = 0; s < 4; ++s)
-      for (int l = 0; l < 64; ++l) {
-        const int f = 32 * ft + l % 32, c = 2 * s + l / 32;
-        dst[L.w1 + (ft * 4 + s) * 64 + l] = c < 6 ? W1[f * 6 + c] : (c == 6 ? b1[f] : 0.f);
-      }
-  // layer 2 B operand, reduction index permuted to layer 1's output layout
-  const int CT = h2 / 128, KS = h1 / 2;
-  for (int w = 0; w < 4; ++w)
-    for (int ct = 0; ct < CT; ++ct)
-      for (int s = 0; s < KS; ++s)
-        for (int l = 0; l < 64; ++l) {
-          const int col = (w * CT + ct) * 32 + l % 32;
-          const int f = perm_feature(s / 16, l / 32, s % 16);
-          dst[L.w2 + ((size_t)(w * CT + ct) * KS + s) * 64 + l] = W2[(size_t)col * h1 + f];
-        }
-  std::memcpy(dst + L.b2, b2, sizeof(float) * h2);
-  // head layers: B[k][j] = H[j][k]; lane l holds H[32 ct + l % 32][2 s + l / 32]
-  auto pack_head = [&](const float* H, int in, int out, size_t at) {
-    const int ks = in / 2;
-    for (int ct = 0; ct < out / 32; ++ct)
-      for (int s = 0; s < ks; ++s)
-        for (int l = 0; l < 64; ++l)
-          dst[at + ((size_t)ct * ks + s) * 64 + l] = H[(size_t)(32 * ct + l % 32) * in + 2 * s + l / 32];
-  };
-  pack_head(H1, 2 * h2, hh, L.h1);
-  std::memcpy(dst + L.c1, c1, sizeof(float) * hh);
-  pack_head(H2, hh, hh, L.h2);
-  std::memcpy(dst + L.c2, c2, sizeof(float) * hh);
-  std::memcpy(dst + L.h3, H3, sizeof(float) * 8 * hh);
-  std::memcpy(dst + L.c3, c3, sizeof(float) * 8);
-}
-
 Fp32Net fp32_view(const float* base, int h1, int h2, int hh) {
-  const PackLayout L = pack_layout(h1, h2, hh);
+  const Fp32Layout L = fp32_layout(h1, h2, hh);
   return Fp32Net{h1, h2, hh, base + L.w1, base + L.w2, base + L.b2, base + L.h1,
                  base + L.c1, base + L.h2, base + L.c2, base + L.h3, base + L.c3};
 }

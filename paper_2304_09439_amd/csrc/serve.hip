@@ -1,32 +1,23 @@
-// Continuous-batching server over one context (locc_serve_* in locc.h).
-//
-// A worker thread owns the GPU side.  Its loop: (1) retire every slot whose
-// completion event has fired, copying each request's slice of the slot's
-// pinned output buffers into the request and stamping its completion time;
-// (2) for every free slot, scan the queue in submission order and take each
-// request that fits the slot (pairs, pose updates) and conflicts with
-// nothing in flight, in the batch, or left waiting ahead of it (a request
-// left behind blocks the objects it touches for the requests after it), copy
-// them into the slot's pinned staging buffers and enqueue on the slot's
-// stream: H2D copies, the pose scatter, the detect path with the slot's own
-// scratch and queue, D2H copies and the completion event; (3) sleep briefly
-// when idle.  Slots run on separate
-// streams, so a batch that forms while others are on the GPU starts as soon
-// as a slot frees up and overlaps with them on the device.
-#include <algorithm>
-#include <atomic>
+// Continuous-batching server over one context (locc_serve_* in locc.h): the
+// device side.  serve_core.h holds the host side (request checks, queue,
+// conflict-ordered batch formation, worker loop, statistics) and drives the
+// HipDevice below, which per slot stages a batch in pinned buffers and
+// enqueues on the slot's stream: H2D copies, the pose scatter, the detect
+// path with the slot's own scratch and queue, D2H copies and the completion
+// event.  Slots run on separate streams, so a batch that forms while others
+// are on the GPU starts as soon as a slot frees up and overlaps with them on
+// the device.
 #include <chrono>
-#include <condition_variable>
 #include <cstring>
-#include <list>
-#include <mutex>
+#include <memory>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "context.h"
+#include "serve_core.h"
 
 using namespace locc;
+using serve::Request;
 
 namespace {
 
@@ -34,24 +25,6 @@ __global__ void scatter_objects(locc_object* table, const int32_t* ids, const lo
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) table[ids[k]] = poses[k];
 }
-
-using Clock = std::chrono::steady_clock;
-
-double ms_since(Clock::time_point t0, Clock::time_point t1) {
-  return std::chrono::duration<double, std::milli>(t1 - t0).count();
-}
-
-struct Request {
-  uint64_t id = 0;
-  std::vector<int32_t> upd_ids;
-  std::vector<locc_object> upd;
-  std::vector<int32_t> pairs;
-  std::vector<int32_t> refs;  // distinct objects the pairs read
-  std::vector<locc_contact> out;
-  std::vector<int32_t> counts;
-  Clock::time_point t_submit, t_done;
-  bool done = false;
-};
 
 struct Slot {
   hipStream_t stream = nullptr;
@@ -67,212 +40,108 @@ struct Slot {
   locc_object* h_upd = nullptr;
   locc_contact* h_out = nullptr;
   int32_t* h_counts = nullptr;
-  std::vector<Request*> reqs;
-  std::vector<int> offs;
-  bool busy = false;
+};
+
+// The device side of the server: per slot, pinned staging buffers, device
+// buffers, a stream, a completion event and the detect path's own scratch.
+struct HipDevice {
+  locc_ctx* ctx = nullptr;
+  int32_t max_objects = 0;
+  locc_object* d_objs = nullptr;
+  std::vector<Slot> slot;
+  const std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  int slots() const { return (int)slot.size(); }
+
+  locc_status launch(int s, const std::vector<Request*>& batch) {
+    Slot& sl = slot[s];
+    int np = 0, nu = 0;
+    for (Request* r : batch) {
+      const int rp = r->n_pairs(), ru = r->n_upd();
+      std::memcpy(sl.h_pairs + 2 * np, r->pairs.data(), sizeof(int32_t) * 2 * rp);
+      std::memcpy(sl.h_upd_ids + nu, r->upd_ids.data(), sizeof(int32_t) * ru);
+      std::memcpy(sl.h_upd + nu, r->upd.data(), sizeof(locc_object) * ru);
+      np += rp;
+      nu += ru;
+    }
+    HIP_TRY(hipMemcpyAsync(sl.d_pairs, sl.h_pairs, sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, sl.stream));
+    if (nu > 0) {
+      HIP_TRY(hipMemcpyAsync(sl.d_upd_ids, sl.h_upd_ids, sizeof(int32_t) * nu, hipMemcpyHostToDevice, sl.stream));
+      HIP_TRY(hipMemcpyAsync(sl.d_upd, sl.h_upd, sizeof(locc_object) * nu, hipMemcpyHostToDevice, sl.stream));
+      hipLaunchKernelGGL(scatter_objects, dim3((nu + 255) / 256), dim3(256), 0, sl.stream, d_objs, sl.d_upd_ids,
+                         sl.d_upd, nu);
+      HIP_TRY(hipGetLastError());
+    }
+    const locc_status st = run_path(ctx, d_objs, max_objects, sl.d_pairs, np, nullptr, sl.d_out, sl.d_counts,
+                                    nullptr, nullptr, sl.stream, &sl.scratch);
+    if (st != LOCC_OK) return st;
+    HIP_TRY(hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(locc_contact) * np, hipMemcpyDeviceToHost, sl.stream));
+    HIP_TRY(hipMemcpyAsync(sl.h_counts, sl.d_counts, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, sl.stream));
+    HIP_TRY(hipEventRecord(sl.done, sl.stream));
+    return LOCC_OK;
+  }
+
+  bool finished(int s) { return hipEventQuery(slot[s].done) == hipSuccess; }
+
+  void collect(int s, const std::vector<Request*>& batch, const std::vector<int>& offs) {
+    const Slot& sl = slot[s];
+    for (size_t k = 0; k < batch.size(); ++k) {
+      const int o = offs[k], n = offs[k + 1] - o;
+      batch[k]->out.assign(sl.h_out + o, sl.h_out + o + n);
+      batch[k]->counts.assign(sl.h_counts + 2 * o, sl.h_counts + 2 * (o + n));
+    }
+  }
+
+  double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void worker_init() { (void)hipSetDevice(ctx->device); }
+  void idle_wait() { std::this_thread::sleep_for(std::chrono::microseconds(5)); }
+
+  void release() {
+    for (Slot& sl : slot) {
+      if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+      (void)hipFree(sl.d_pairs);
+      (void)hipFree(sl.d_upd_ids);
+      (void)hipFree(sl.d_upd);
+      (void)hipFree(sl.d_out);
+      (void)hipFree(sl.d_counts);
+      (void)hipFree(sl.scratch.base);
+      (void)hipFree(sl.scratch.queue);
+      (void)hipHostFree(sl.h_pairs);
+      (void)hipHostFree(sl.h_upd_ids);
+      (void)hipHostFree(sl.h_upd);
+      (void)hipHostFree(sl.h_out);
+      (void)hipHostFree(sl.h_counts);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+      if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    slot.clear();
+    (void)hipFree(d_objs);
+    d_objs = nullptr;
+  }
 };
 
 }  // namespace
 
 struct locc_server {
   locc_ctx* ctx = nullptr;
-  locc_serve_config cfg{};
-  int32_t batch_pairs = 0;
   bool was_profiling = false;
-  locc_object* d_objs = nullptr;
-  std::vector<Slot> slots;
-  // host state, guarded by mu
-  std::mutex mu;
-  std::list<Request*> queue;
-  std::unordered_map<uint64_t, Request*> reqs;
-  int64_t queued_pairs = 0;
-  uint64_t next_id = 1;
-  locc_serve_stats stats{};
-  bool stopping = false;
-  // worker-only state
-  std::vector<int32_t> upd_busy, ref_busy;  // in-flight / batched requests updating / reading each object
-  std::vector<uint8_t> upd_blocked, ref_blocked;  // objects a request left waiting during a scan updates / reads
-  std::vector<int32_t> blocked_ids;               // entries to clear after the scan
-  std::thread worker;
-  std::atomic<int> worker_status{LOCC_OK};
+  HipDevice dev;
+  std::unique_ptr<serve::Core<HipDevice>> core;
 };
 
 namespace {
 
-bool fits_and_free(locc_server* S, const Request* r, int pairs_used, int upd_used) {
-  if (pairs_used + (int)r->pairs.size() / 2 > S->batch_pairs) return false;
-  if (upd_used + (int)r->upd_ids.size() > S->cfg.max_batch_updates) return false;
-  for (int32_t id : r->upd_ids)
-    if (S->upd_busy[id] || S->ref_busy[id]) return false;
-  for (int32_t id : r->refs)
-    if (S->upd_busy[id]) return false;
-  return true;
+locc_status report(const serve::Check& ck) {
+  if (ck.st == LOCC_OK) return LOCC_OK;
+  return fail(ck.st, "%s", ck.msg.c_str());
 }
 
-// Whether r touches an object a request left waiting ahead of it in this scan
-// updates, or updates one it reads: r must not overtake that request.
-bool blocked(const locc_server* S, const Request* r) {
-  for (int32_t id : r->upd_ids)
-    if (S->upd_blocked[id] || S->ref_blocked[id]) return true;
-  for (int32_t id : r->refs)
-    if (S->upd_blocked[id]) return true;
-  return false;
-}
-
-void block(locc_server* S, const Request* r) {
-  for (int32_t id : r->upd_ids) {
-    S->upd_blocked[id] = 1;
-    S->blocked_ids.push_back(id);
-  }
-  for (int32_t id : r->refs) {
-    S->ref_blocked[id] = 1;
-    S->blocked_ids.push_back(id);
-  }
-}
-
-// Requests examined per batch at most (bounds the scan when the queue is long).
-constexpr int kMaxScan = 1024;
-
-void mark(locc_server* S, const Request* r, int d) {
-  for (int32_t id : r->upd_ids) S->upd_busy[id] += d;
-  for (int32_t id : r->refs) S->ref_busy[id] += d;
-}
-
-locc_status launch_slot(locc_server* S, Slot& sl) {
-  locc_ctx* c = S->ctx;
-  int np = 0, nu = 0;
-  sl.offs.clear();
-  for (Request* r : sl.reqs) {
-    sl.offs.push_back(np);
-    const int rp = (int)r->pairs.size() / 2, ru = (int)r->upd_ids.size();
-    std::memcpy(sl.h_pairs + 2 * np, r->pairs.data(), sizeof(int32_t) * 2 * rp);
-    std::memcpy(sl.h_upd_ids + nu, r->upd_ids.data(), sizeof(int32_t) * ru);
-    std::memcpy(sl.h_upd + nu, r->upd.data(), sizeof(locc_object) * ru);
-    np += rp;
-    nu += ru;
-  }
-  sl.offs.push_back(np);
-  HIP_TRY(hipMemcpyAsync(sl.d_pairs, sl.h_pairs, sizeof(int32_t) * 2 * np, hipMemcpyHostToDevice, sl.stream));
-  if (nu > 0) {
-    HIP_TRY(hipMemcpyAsync(sl.d_upd_ids, sl.h_upd_ids, sizeof(int32_t) * nu, hipMemcpyHostToDevice, sl.stream));
-    HIP_TRY(hipMemcpyAsync(sl.d_upd, sl.h_upd, sizeof(locc_object) * nu, hipMemcpyHostToDevice, sl.stream));
-    hipLaunchKernelGGL(scatter_objects, dim3((nu + 255) / 256), dim3(256), 0, sl.stream, S->d_objs, sl.d_upd_ids,
-                       sl.d_upd, nu);
-    HIP_TRY(hipGetLastError());
-  }
-  locc_status st = run_path(c, S->d_objs, S->cfg.max_objects, sl.d_pairs, np, nullptr, sl.d_out, sl.d_counts,
-                            nullptr, nullptr, sl.stream, &sl.scratch);
-  if (st != LOCC_OK) return st;
-  HIP_TRY(hipMemcpyAsync(sl.h_out, sl.d_out, sizeof(locc_contact) * np, hipMemcpyDeviceToHost, sl.stream));
-  HIP_TRY(hipMemcpyAsync(sl.h_counts, sl.d_counts, sizeof(int32_t) * 2 * np, hipMemcpyDeviceToHost, sl.stream));
-  HIP_TRY(hipEventRecord(sl.done, sl.stream));
-  sl.busy = true;
-  return LOCC_OK;
-}
-
-void retire_slot(locc_server* S, Slot& sl) {
-  const auto now = Clock::now();
-  std::lock_guard<std::mutex> lk(S->mu);
-  for (size_t k = 0; k < sl.reqs.size(); ++k) {
-    Request* r = sl.reqs[k];
-    const int o = sl.offs[k], n = sl.offs[k + 1] - o;
-    r->out.assign(sl.h_out + o, sl.h_out + o + n);
-    r->counts.assign(sl.h_counts + 2 * o, sl.h_counts + 2 * (o + n));
-    r->t_done = now;
-    r->done = true;
-    mark(S, r, -1);
-    S->stats.completed += 1;
-    S->stats.pairs_done += n;
-  }
-  sl.reqs.clear();
-  sl.busy = false;
-}
-
-void worker_loop(locc_server* S) {
-  (void)hipSetDevice(S->ctx->device);
-  Clock::time_point busy_since{};
-  bool any_busy = false;
-  for (;;) {
-    bool progressed = false;
-    for (Slot& sl : S->slots)
-      if (sl.busy && hipEventQuery(sl.done) == hipSuccess) {
-        retire_slot(S, sl);
-        progressed = true;
-      }
-    for (Slot& sl : S->slots) {
-      if (sl.busy) continue;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        int np = 0, nu = 0, scanned = 0;
-        for (auto it = S->queue.begin(); it != S->queue.end() && scanned < kMaxScan; ++scanned) {
-          Request* r = *it;
-          if (fits_and_free(S, r, np, nu) && !blocked(S, r)) {
-            it = S->queue.erase(it);
-            mark(S, r, +1);
-            np += (int)r->pairs.size() / 2;
-            nu += (int)r->upd_ids.size();
-            S->queued_pairs -= (int64_t)r->pairs.size() / 2;
-            sl.reqs.push_back(r);
-            if (!S->cfg.batching) break;
-            continue;
-          }
-          if (!S->cfg.batching) break;  // one request per launch, strictly in order
-          block(S, r);
-          ++it;
-        }
-        for (int32_t id : S->blocked_ids) S->upd_blocked[id] = S->ref_blocked[id] = 0;
-        S->blocked_ids.clear();
-      }
-      if (sl.reqs.empty()) continue;
-      const locc_status st = launch_slot(S, sl);
-      if (st != LOCC_OK) {
-        S->worker_status = st;
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stopping = true;
-        S->queue.clear();
-        return;
-      }
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->stats.batches += 1;
-      progressed = true;
-    }
-    bool busy_now = false;
-    for (const Slot& sl : S->slots) busy_now |= sl.busy;
-    const auto now = Clock::now();
-    if (busy_now && !any_busy) busy_since = now;
-    if (!busy_now && any_busy) {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->stats.busy_ms += ms_since(busy_since, now);
-    }
-    any_busy = busy_now;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      if (S->stopping && S->queue.empty() && !busy_now) return;
-    }
-    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(5));
-  }
-}
-
+// Joins the worker (if any), then frees the device side.
 void free_server(locc_server* S) {
-  for (Slot& sl : S->slots) {
-    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-    (void)hipFree(sl.d_pairs);
-    (void)hipFree(sl.d_upd_ids);
-    (void)hipFree(sl.d_upd);
-    (void)hipFree(sl.d_out);
-    (void)hipFree(sl.d_counts);
-    (void)hipFree(sl.scratch.base);
-    (void)hipFree(sl.scratch.queue);
-    (void)hipHostFree(sl.h_pairs);
-    (void)hipHostFree(sl.h_upd_ids);
-    (void)hipHostFree(sl.h_upd);
-    (void)hipHostFree(sl.h_out);
-    (void)hipHostFree(sl.h_counts);
-    if (sl.done) (void)hipEventDestroy(sl.done);
-    if (sl.stream) (void)hipStreamDestroy(sl.stream);
-  }
-  (void)hipFree(S->d_objs);
-  for (auto& kv : S->reqs) delete kv.second;
+  S->core.reset();
+  S->dev.release();
   S->ctx->profiling = S->was_profiling;
   delete S;
 }
@@ -301,37 +170,24 @@ locc_status locc_serve_start(locc_ctx* c, const locc_serve_config* cfg, const lo
            (size_t)cfg->max_batch_updates * per_update + workspace_bytes(c, pairs) + 8 * sizeof(unsigned int);
   };
   int pairs = cfg->max_batch_pairs;
-  if (pairs == 0) {  // as many as the budget allows
-    int lo = 0, hi = 1 << 24;
-    while (lo < hi) {
-      const int mid = lo + (hi - lo + 1) / 2;
-      if (table + slots * slot_bytes(mid) <= cfg->hbm_budget_bytes) lo = mid;
-      else hi = mid - 1;
-    }
-    pairs = lo;
-  }
+  if (pairs == 0) pairs = serve::pairs_for_budget(cfg->hbm_budget_bytes, table, slots, slot_bytes);  // all it allows
   if (pairs <= 0 || table + slots * slot_bytes(pairs) > cfg->hbm_budget_bytes)
     return fail(LOCC_ERR_OOM, "budget of %zu bytes does not hold the object table and %d slot(s) of %d pairs",
                 cfg->hbm_budget_bytes, slots, pairs);
   HIP_TRY(hipSetDevice(c->device));
   locc_server* S = new locc_server();
   S->ctx = c;
-  S->cfg = *cfg;
-  S->cfg.slots = slots;
-  S->batch_pairs = pairs;
-  S->stats.max_batch_pairs = pairs;
   S->was_profiling = c->profiling;
   c->profiling = false;  // the worker thread must not touch the profiling lists
-  S->upd_busy.assign(cfg->max_objects, 0);
-  S->ref_busy.assign(cfg->max_objects, 0);
-  S->upd_blocked.assign(cfg->max_objects, 0);
-  S->ref_blocked.assign(cfg->max_objects, 0);
-  S->slots.resize(slots);
-  hipError_t e = hipMalloc(&S->d_objs, table);
+  HipDevice& d = S->dev;
+  d.ctx = c;
+  d.max_objects = cfg->max_objects;
+  d.slot.resize(slots);
+  hipError_t e = hipMalloc(&d.d_objs, table);
   if (e == hipSuccess && n_objs > 0)
-    e = hipMemcpy(S->d_objs, objs, sizeof(locc_object) * n_objs, hipMemcpyHostToDevice);
+    e = hipMemcpy(d.d_objs, objs, sizeof(locc_object) * n_objs, hipMemcpyHostToDevice);
   const int U = cfg->max_batch_updates > 0 ? cfg->max_batch_updates : 1;
-  for (Slot& sl : S->slots) {
+  for (Slot& sl : d.slot) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc(&sl.d_pairs, sizeof(int32_t) * 2 * pairs);
@@ -354,93 +210,48 @@ locc_status locc_serve_start(locc_ctx* c, const locc_serve_config* cfg, const lo
     free_server(S);
     return fail(e == hipErrorOutOfMemory ? LOCC_ERR_OOM : LOCC_ERR_HIP, "server buffers: %s", hipGetErrorString(e));
   }
-  S->worker = std::thread(worker_loop, S);
+  serve::Limits L;
+  L.max_objects = cfg->max_objects;
+  L.batch_pairs = pairs;
+  L.max_batch_updates = cfg->max_batch_updates;
+  L.max_queued_pairs = cfg->max_queued_pairs;
+  L.batching = cfg->batching != 0;
+  S->core.reset(new serve::Core<HipDevice>(d, L));
+  S->core->start();
   *out = S;
   return LOCC_OK;
 }
 
 locc_status locc_serve_submit(locc_server* S, const int32_t* upd_ids, const locc_object* upd, int32_t n_upd,
                               const int32_t* pairs, int32_t n_pairs, uint64_t* req_id) {
-  if (!S || !req_id || n_upd < 0 || n_pairs < 0 || (n_upd > 0 && (!upd_ids || !upd)) || (n_pairs > 0 && !pairs))
-    return fail(LOCC_ERR_INVALID_ARG, "null or negative argument");
-  if (S->worker_status != LOCC_OK) return fail((locc_status)S->worker_status.load(), "server stopped after an error");
-  if (n_pairs > S->batch_pairs || n_upd > S->cfg.max_batch_updates)
-    return fail(LOCC_ERR_RANGE, "request of %d pairs / %d updates exceeds one batch (%d / %d)", n_pairs, n_upd,
-                S->batch_pairs, S->cfg.max_batch_updates);
-  const int32_t M = S->cfg.max_objects;
-  Request* r = new Request();
-  r->upd_ids.assign(upd_ids, upd_ids + n_upd);
-  r->upd.assign(upd, upd + n_upd);
-  r->pairs.assign(pairs, pairs + 2 * (size_t)n_pairs);
-  for (int32_t id : r->upd_ids)
-    if (id < 0 || id >= M) {
-      delete r;
-      return fail(LOCC_ERR_INVALID_ARG, "update of object %d outside the table of %d", id, M);
-    }
-  r->refs.reserve(r->pairs.size());
-  for (int32_t id : r->pairs)
-    if (id >= 0 && id < M) r->refs.push_back(id);  // out-of-range pairs are reported by the kernels
-  std::sort(r->refs.begin(), r->refs.end());
-  r->refs.erase(std::unique(r->refs.begin(), r->refs.end()), r->refs.end());
-  std::sort(r->upd_ids.begin(), r->upd_ids.end());
-  if (std::adjacent_find(r->upd_ids.begin(), r->upd_ids.end()) != r->upd_ids.end()) {
-    delete r;
-    return fail(LOCC_ERR_INVALID_ARG, "an object is updated twice in one request");
-  }
-  r->upd_ids.assign(upd_ids, upd_ids + n_upd);  // keep the caller's order, paired with upd
-  std::lock_guard<std::mutex> lk(S->mu);
-  if (S->stopping) {
-    delete r;
-    return fail(LOCC_ERR_INVALID_ARG, "server is stopping");
-  }
-  if (S->cfg.max_queued_pairs > 0 && S->queued_pairs + n_pairs > S->cfg.max_queued_pairs) {
-    delete r;
-    return fail(LOCC_ERR_BUSY, "queue holds %lld pairs", (long long)S->queued_pairs);
-  }
-  r->id = S->next_id++;
-  r->t_submit = Clock::now();
-  S->queue.push_back(r);
-  S->reqs[r->id] = r;
-  S->queued_pairs += n_pairs;
-  S->stats.submitted += 1;
-  *req_id = r->id;
-  return LOCC_OK;
+  if (!S || !req_id) return fail(LOCC_ERR_INVALID_ARG, "null server or id");
+  return report(S->core->submit(upd_ids, upd, n_upd, pairs, n_pairs, req_id));
+}
+
+locc_status locc_serve_submit_many(locc_server* S, int32_t n_req, const int32_t* upd_offsets, const int32_t* upd_ids,
+                                   const locc_object* upd, const int32_t* pair_offsets, const int32_t* pairs,
+                                   uint64_t* req_ids, int32_t* n_accepted) {
+  if (!S || !n_accepted) return fail(LOCC_ERR_INVALID_ARG, "null server or count");
+  return report(S->core->submit_many(n_req, upd_offsets, upd_ids, upd, pair_offsets, pairs, req_ids, n_accepted));
 }
 
 locc_status locc_serve_poll(locc_server* S, uint64_t id, locc_contact* out, int32_t* counts, int32_t* done,
                             double* latency_ms) {
-  if (!S || !done) return fail(LOCC_ERR_INVALID_ARG, "null server or output");
-  std::lock_guard<std::mutex> lk(S->mu);
-  auto it = S->reqs.find(id);
-  if (it == S->reqs.end()) return fail(LOCC_ERR_INVALID_ARG, "unknown request %llu", (unsigned long long)id);
-  Request* r = it->second;
-  *done = r->done ? 1 : 0;
-  if (!r->done) return LOCC_OK;
-  if (out) std::memcpy(out, r->out.data(), sizeof(locc_contact) * r->out.size());
-  if (counts) std::memcpy(counts, r->counts.data(), sizeof(int32_t) * r->counts.size());
-  if (latency_ms) *latency_ms = ms_since(r->t_submit, r->t_done);
-  delete r;
-  S->reqs.erase(it);
-  return LOCC_OK;
+  if (!S) return fail(LOCC_ERR_INVALID_ARG, "null server");
+  return report(S->core->poll(id, out, counts, done, latency_ms));
 }
 
 locc_status locc_serve_get_stats(locc_server* S, locc_serve_stats* st) {
   if (!S || !st) return fail(LOCC_ERR_INVALID_ARG, "null server or output");
-  std::lock_guard<std::mutex> lk(S->mu);
-  *st = S->stats;
+  *st = S->core->stats();
   return LOCC_OK;
 }
 
 locc_status locc_serve_stop(locc_server* S) {
   if (!S) return LOCC_OK;
-  {
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->stopping = true;
-  }
-  if (S->worker.joinable()) S->worker.join();
-  const int st = S->worker_status;
+  const locc_status st = S->core->stop();
   free_server(S);
-  if (st != LOCC_OK) return fail((locc_status)st, "server worker failed");
+  if (st != LOCC_OK) return fail(st, "server worker failed");
   return LOCC_OK;
 }
 

@@ -113,6 +113,46 @@ def test_served_results_equal_the_request_run_alone(torch, rs, precision, batchi
     ctx.close()
 
 
+def test_submit_many_queues_in_order_and_stops_at_the_first_refusal(torch, rs):
+    """locc_serve_submit_many: one call queues the requests in order (ids ascending), their results equal
+    the requests run alone; against a queue limit it queues the longest prefix that fits (the call holds
+    the queue's lock, so the worker cannot drain it meanwhile) and reports BUSY with the ids queued."""
+    n = 300
+    say(f"serving bf16: {n} requests in one submit_many call")
+    ctx = _ctx(rs, "bf16")
+    srv = B.Server(ctx, _table(rs), batching=True, slots=3, max_batch_pairs=4096, max_batch_updates=8192,
+                   hbm_budget_bytes=2 << 30)
+    reqs = [_upd(rs, rs.requests[k]) for k in range(n)]
+    ids = srv.submit_many(reqs)
+    assert len(ids) == n and ids == sorted(ids) and len(set(ids)) == n
+    res = _drain(srv, ids)
+    st = srv.stats()
+    srv.stop()
+    assert st["completed"] == n and st["batches"] < n
+    for k in np.random.default_rng(2).choice(n, 20, replace=False):
+        out, counts, _ = res[ids[k]]
+        ref_out, ref_counts = _alone(torch, ctx, rs, rs.requests[k])
+        np.testing.assert_array_equal(out, ref_out)
+        np.testing.assert_array_equal(counts, ref_counts)
+    limit = 1000
+    srv = B.Server(ctx, _table(rs), batching=True, slots=1, max_batch_pairs=4096, max_batch_updates=8192,
+                   max_queued_pairs=limit, hbm_budget_bytes=2 << 30)
+    sizes = np.cumsum([len(r[2]) for r in reqs])
+    fit = int(np.searchsorted(sizes, limit, side="right"))   # the longest prefix within the limit
+    assert 0 < fit < n
+    with pytest.raises(B.LoccError) as e:
+        srv.submit_many(reqs)
+    assert e.value.status == B.ERR_BUSY and len(e.value.accepted_ids) == fit
+    res = _drain(srv, e.value.accepted_ids)
+    srv.stop()
+    out, counts, _ = res[e.value.accepted_ids[-1]]
+    ref_out, ref_counts = _alone(torch, ctx, rs, rs.requests[fit - 1])
+    np.testing.assert_array_equal(out, ref_out)
+    np.testing.assert_array_equal(counts, ref_counts)
+    assert ctx.device_errors() == 0
+    ctx.close()
+
+
 def test_requests_on_the_same_environment_see_their_own_poses(torch, rs):
     ctx = _ctx(rs, "bf16")
     srv = B.Server(ctx, _table(rs), batching=True, slots=2, max_batch_pairs=4096, max_batch_updates=8192)
