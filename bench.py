@@ -11,6 +11,7 @@ timed on this host on a bounded sample of the same workload.
 
 Counter post-processing (turns rocprofv3 --pmc CSV output into a summary):
   python bench.py --summarize-counters FETCH_DIR WRITE_DIR --copy-mib M --kernel NAME
+  python bench.py --summarize-sq PASS1_DIR PASS2_DIR --kernel NAME --kernel-match STR
 """
 
 from __future__ import annotations
@@ -112,18 +113,7 @@ def source_hash(kernel: str) -> str:
 
 def counter_traffic(kernel: str, workload_name: str):
     """HBM bytes per launch from a committed counter summary, if it was taken on this kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_hbm_counters.txt")
-    if not os.path.exists(path):
-        return None
-    vals = {}
-    with open(path) as f:
-        for line in f:
-            parts = line.split()
-            if len(parts) >= 2 and parts[0] in ("source_sha256", "hbm_bytes_per_launch"):
-                vals[parts[0]] = parts[1]
-    if vals.get("source_sha256") != source_hash(kernel) or "hbm_bytes_per_launch" not in vals:
-        return None
-    return float(vals["hbm_bytes_per_launch"])
+    return counter_value(kernel, workload_name, "hbm", "hbm_bytes_per_launch")
 
 
 # ------------------------------------------------------------------ CPU baseline
@@ -249,13 +239,23 @@ def kernel_entries(kt, work, P, workload_name, steps, precision, full_scan=True,
                                       "every pair" if enc else "head on every pair"),
                          fixed_2K_TFLOPs=round(rate(fixed), 2), fixed_2K_frac=round(rate(fixed) / peak_of(fixed_enc), 4),
                          tiles_run_TFLOPs=round(rate(tiles), 2), tiles_run_frac=round(rate(tiles) / peak_of(tiles_enc), 4))
-            if enc_prec != head_prec and head_prec:
+            if enc_prec and head_prec and enc_prec != head_prec:
                 entry["peak_basis"] = (f"encoder FLOPs at the {enc_prec} peak and head FLOPs at the {head_prec} peak "
                                        "(the rate at which this work would take its time at those peaks)")
             if name.startswith("fused"):  # crop inside: its HBM bytes too
                 gbps = (2 * 32 + 8 + 8 + work["contact_bytes"]) * P_launch / (avg * 1e-3) / 1e9
                 entry.update(hbm_achieved_GBps=round(gbps, 1), hbm_frac=round(gbps / PEAK_HBM_GBPS, 4))
-        entry["traffic"] = counter_traffic(f"crop_{precision}" if name == "crop" else name, workload_name)
+        key = f"crop_{precision}" if name == "crop" else name
+        entry["traffic"] = counter_traffic(key, workload_name)
+        issue_ns = counter_value(key, workload_name, "sq", "valu_issue_bound_ns")
+        if name == "crop" and issue_ns is not None:
+            # the bound the crop can reach: its vector instructions issued back to back on every SIMD
+            entry["issue_bound"] = dict(bound_ms=round(issue_ns * 1e-6, 4), frac=round(issue_ns * 1e-6 / avg, 4),
+                                        basis="SQ_INSTS_VALU per launch x 4 cycles / (1024 SIMDs x 2.4 GHz), from "
+                                              "the committed SQ counter summary of this kernel source")
+        busy = counter_value(key, workload_name, "sq", "mfma_busy_frac")
+        if busy is not None and name != "crop":
+            entry["mfma_busy_frac"] = busy
         kernels[name] = entry
     return kernels
 
@@ -296,17 +296,26 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
     torch.cuda.synchronize()
     print(f"[bench] {precision}: warmup done ({args.warmup} steps), timing {args.steps} steps of {P} pairs",
           file=sys.stderr, flush=True)
-    ctx.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # per-kernel durations: the same number of steps again with the library's per-kernel events (start and
+    # stop events attached to the dispatches), kept out of the timed region above because they lengthen a
+    # step by about a tenth
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.detect(objs, pairs, out, counts, want_counts=counts is not None)
+    torch.cuda.synchronize()
+    wall_prof = time.perf_counter() - t1
     ctx.profile(False)
     kt = ctx.profile_read()
     # step latency percentiles from their own run of at least LATENCY_SAMPLES steps, each between two events
-    n_lat = max(LATENCY_SAMPLES, args.steps)
+    n_lat = 0 if args.profile_run else max(LATENCY_SAMPLES, args.steps)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_lat)]
     for k in range(n_lat):
         ev[k][0].record(stream)
@@ -314,9 +323,12 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    extra = {"latency_samples": n_lat}
+    extra = {"latency_samples": n_lat,
+             "kernel_timing": dict(steps=args.steps, ms_per_step=round(1000.0 * wall_prof / args.steps, 4),
+                                   note="kernel durations from a second run of the same steps with per-kernel "
+                                        "events, after the timed region")}
     full = counts
-    if counts is None:   # the same schedule with member counts requested (every point of both objects tested)
+    if counts is None and not args.profile_run:   # the same schedule with member counts (every point tested)
         full = torch.empty((P, 2), dtype=torch.int32, device="cuda")
         ctx.detect(objs, pairs, out, full)
         torch.cuda.synchronize()
@@ -325,19 +337,48 @@ def time_path(args, scene, K, widths, w, precision, work, workload_name):
             ctx.detect(objs, pairs, out, full)
         torch.cuda.synchronize()
         extra["ms_per_step_with_member_counts"] = round(1000.0 * (time.perf_counter() - t1) / args.steps, 4)
+    if precision == "bf16" and schedule and not args.profile_run:
+        extra["schedule_alternatives"] = schedule_alternatives(ctx, objs, pairs, out, counts, schedule, stream,
+                                                               args.steps)
     n_bad = ctx.device_errors()
     ctx.close()
-    rows = encoder_rows(full.cpu().numpy(), K)
+    rows = encoder_rows(full.cpu().numpy(), K) if full is not None else None
     ms = 1000.0 * wall / args.steps
     kernels = kernel_entries(kt, work, P, workload_name, args.steps, precision, full_scan=counts is not None,
                              rows=rows)
     return dict(value=round(P / (ms * 1e-3), 1), ms_per_step=round(ms, 4), schedule=schedule,
-                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
-                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+                p50_step_ms=round(float(np.percentile(step_ms, 50)), 4) if n_lat else None,
+                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4) if n_lat else None,
                 kernels=kernels, device_errors=int(n_bad), member_counts=bool(args.member_counts), **extra,
                 path={"fp32": PATH_DESC["fp32"], "fp8": PATH_DESC["fp8"] + f" (autotuned: {schedule})",
                       "fp8_encoder": PATH_DESC["fp8_encoder"] + f" (autotuned: {schedule})"}.get(
                     precision, bf16_desc(schedule)))
+
+
+def schedule_alternatives(ctx, objs, pairs, out, counts, best, stream, steps):
+    """ms per step of the chosen schedule and of the ones that would overlap or fuse the crop: one fused
+    launch (crop inside the network kernel), the split schedule cut into 2 and 4 runs whose crops overlap
+    the previous run's network (on the context's second stream), and the same at one network workgroup per
+    CU (leaving room on every CU for the next run's crop).  Same pairs, events on the launch stream."""
+    import torch
+    want = counts is not None
+    variants = {"chosen": dict(best), "one_fused_launch": dict(best, split=False, chunks=1, crop_unroll=8),
+                "split_2_runs": dict(best, chunks=2), "split_4_runs": dict(best, chunks=4),
+                "split_2_runs_1_wg_per_cu": dict(best, chunks=2, wg_per_cu=1)}
+    res = {}
+    for name, sc in variants.items():
+        ctx.set_schedule(**sc)
+        for _ in range(3):
+            ctx.detect(objs, pairs, out, counts, want_counts=want)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.detect(objs, pairs, out, counts, want_counts=want)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) / steps, 4)
+    ctx.set_schedule(**best)
+    return res
 
 
 def time_envs(args, envs, w, precision, gpu_broad=False):
@@ -392,7 +433,9 @@ def time_envs(args, envs, w, precision, gpu_broad=False):
         else:
             ctx.detect(objs, pairs[:P], out[:P], None if counts is None else counts[:P], want_counts=counts is not None)
 
-    for s in range(min(3, S)):
+    # one untimed pass over every step: each step has pinned host buffers of its own, and the first copy out of
+    # a pinned buffer pays for mapping it, which a simulation reusing one staging buffer per step would not
+    for s in range(S):
         step(s)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(S)]
@@ -619,7 +662,7 @@ def time_voxel(args, scene):
     ms = 1000.0 * wall / args.steps
     return dict(value=round(P / (ms * 1e-3), 1), unit=UNIT, ms_per_step=round(ms, 4),
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
-                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4),
+                max_step_ms=round(float(step_ms.max()), 4), step_samples=int(len(step_ms)),
                 kernel=dict(name="voxel select + mlp kernels (one step)", avg_ms=round(avg, 4), bound="alu",
                             achieved=round(achieved, 2), peak=PEAK_TFLOPS["fp32"], unit="TFLOP/s",
                             frac=round(achieved / PEAK_TFLOPS["fp32"], 4), flops_per_pair=voxel_pair_flops()),
@@ -652,21 +695,10 @@ def time_pose_grad(args, scene, K, widths, w):
         ctx.pose_gradients(objs, pairs, grad)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        ctx.pose_gradients(objs, pairs, grad)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.profile(False)
-    kt = ctx.profile_read()
+    wall, step_ms, kt, _ = timed_then_profiled(ctx, lambda: ctx.pose_gradients(objs, pairs, grad), args.steps,
+                                               stream)
     n_bad = ctx.device_errors()
     ctx.close()
-    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     kernels = {name: dict(avg_ms=round(tot / max(n, 1), 4), launches=int(n)) for name, (n, tot) in sorted(kt.items())}
     g = kernels.get("pose_grad")
     if g:
@@ -676,7 +708,7 @@ def time_pose_grad(args, scene, K, widths, w):
     ms = 1000.0 * wall / args.steps
     return dict(value=round(P / (ms * 1e-3), 1), unit="pair-gradients/s", ms_per_step=round(ms, 4),
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
-                p99_step_ms=round(float(np.percentile(step_ms, 99)), 4), kernels=kernels,
+                max_step_ms=round(float(step_ms.max()), 4), step_samples=int(len(step_ms)), kernels=kernels,
                 device_errors=int(n_bad),
                 path="FP32: crop (with index sets), encoder recording argmax rows, head backward (32 pairs per "
                      "workgroup), encoder backward at the argmax rows and float64 chain to the poses")
@@ -712,21 +744,10 @@ def time_train(args):
         ctx.train_step(objs, pairs, lab, loss=loss)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        ctx.train_step(objs, pairs, lab, loss=loss)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.profile(False)
-    kt = ctx.profile_read()
+    wall, step_ms, kt, _ = timed_then_profiled(ctx, lambda: ctx.train_step(objs, pairs, lab, loss=loss), args.steps,
+                                               stream)
     last = loss.cpu().numpy().tolist()
     ctx.close()
-    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     kernels = {name: dict(avg_ms=round(tot / max(n, 1), 4), launches=int(n)) for name, (n, tot) in sorted(kt.items())}
     P = sc.n_pairs
     t = kernels.get("train")
@@ -739,6 +760,31 @@ def time_train(args):
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4), kernels=kernels,
                 loss_after=last, path="FP32 training step: crop, encoder with argmax rows, head forward/backward "
                                       "on matrix cores, fixed-order weight-gradient reductions, Adam, repacking")
+
+
+def timed_then_profiled(ctx, step, steps, stream):
+    """steps calls of step() timed (wall clock and per-step events, no per-kernel events), then as many again
+    with the library's per-kernel events for the kernel durations.  Returns (wall s, step ms array, kernel
+    totals, wall s of the profiled run)."""
+    import numpy as np
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.profile(True)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall_prof = time.perf_counter() - t1
+    ctx.profile(False)
+    return wall, np.array([a.elapsed_time(b) for a, b in ev]), ctx.profile_read(), wall_prof
 
 
 def envs_widths():
@@ -839,6 +885,83 @@ def _counter_means(directory):
     return {k: sum(v.values()) / len(v) for k, v in acc.items()}
 
 
+N_SIMD = 1024          # 256 compute units x 4 SIMDs
+CLOCK_GHZ = 2.4        # published peak engine clock
+
+
+def _sq_means(directory, needle):
+    """(kernel name, {counter: mean per dispatch}, mean dispatch duration ns or None) of the dispatches whose
+    kernel name contains needle, from rocprofv3 counter CSV files."""
+    import csv
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *counter_collection.csv under {directory}")
+    acc, dur, name_seen = {}, {}, None
+    for f in files:
+        with open(f) as fh:
+            for row in csv.DictReader(fh):
+                name = row.get("Kernel_Name") or ""
+                if needle not in name:
+                    continue
+                name_seen = name
+                disp = row.get("Dispatch_Id") or str(len(dur))
+                acc.setdefault(row["Counter_Name"], {}).setdefault(disp, 0.0)
+                acc[row["Counter_Name"]][disp] += float(row["Counter_Value"])
+                t0, t1 = row.get("Start_Timestamp"), row.get("End_Timestamp")
+                if t0 and t1:
+                    dur[disp] = float(t1) - float(t0)
+    if not acc:
+        raise SystemExit(f"no dispatch of a kernel matching {needle!r} under {directory}")
+    means = {c: sum(v.values()) / len(v) for c, v in acc.items()}
+    n = max(len(v) for v in acc.values())
+    return name_seen, means, (sum(dur.values()) / len(dur) if dur else None), n
+
+
+def summarize_sq(args):
+    """SQ counters of one kernel from one or more rocprofv3 --pmc runs (one pass each), as means per dispatch,
+    with the derived vector-issue bound and matrix-core busy fraction."""
+    merged, name, dur, n = {}, None, None, 0
+    for d in args.summarize_sq:
+        nm, means, du, nd = _sq_means(d, args.kernel_match)
+        name = name or nm
+        dur = dur or du
+        n = max(n, nd)
+        merged.update(means)
+    print(f"kernel {args.kernel} ({name})")
+    print(f"source_sha256 {source_hash(args.kernel)}")
+    print(f"dispatches {n}")
+    if dur:
+        print(f"duration_ns_mean {dur:.0f}")
+    for c in sorted(merged):
+        print(f"{c} {merged[c]:.0f}")
+    if "SQ_INSTS_VALU" in merged:
+        # every wave64 vector instruction occupies its SIMD's vector unit for at least 4 cycles
+        print(f"valu_issue_bound_ns {merged['SQ_INSTS_VALU'] * 4 / (N_SIMD * CLOCK_GHZ):.0f}")
+    if "SQ_INSTS_VALU" in merged and "SQ_INSTS_MFMA" in merged and merged["SQ_INSTS_MFMA"] > 0:
+        print(f"valu_per_mfma {merged['SQ_INSTS_VALU'] / merged['SQ_INSTS_MFMA']:.2f}")
+    if dur and "SQ_VALU_MFMA_BUSY_CYCLES" in merged:
+        print(f"mfma_busy_frac {merged['SQ_VALU_MFMA_BUSY_CYCLES'] / (N_SIMD * CLOCK_GHZ * dur):.3f}")
+    if "SQ_WAIT_ANY" in merged and "SQ_WAVE_CYCLES" in merged:
+        print(f"wait_any_frac {merged['SQ_WAIT_ANY'] / merged['SQ_WAVE_CYCLES']:.3f}")
+
+
+def counter_value(kernel: str, workload_name: str, kind: str, key: str):
+    """A value from a committed counter summary (profiles/<kernel>_<workload>_<kind>_counters.txt), if it was
+    taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_name}_{kind}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_sha256") != source_hash(kernel) or key not in vals:
+        return None
+    return float(vals[key])
+
+
 def summarize_counters(args):
     fetch = _counter_means(args.summarize_counters[0])
     write = _counter_means(args.summarize_counters[1])
@@ -871,7 +994,7 @@ def summarize_counters(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="scale", choices=["scale", "small"])
     ap.add_argument("--schedule", action="append", default=[], metavar="PREC:WG,CLAIM,DYN,SPLIT,UNROLL,CHUNKS",
@@ -893,6 +1016,10 @@ def main():
     ap.add_argument("--no-train", action="store_true", help="skip the training leg")
     ap.add_argument("--copy-mib", type=int, default=0, help="also run a plain device copy of this size")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR", help="summarise SQ counter passes of --kernel")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="time only the warm-up and timed steps of each path (no latency samples, member-count "
+                         "leg or schedule alternatives), for runs under a profiler")
     ap.add_argument("--kernel", default="encoder_fp32")
     ap.add_argument("--kernel-match", default="encoder_fp32_kernel")
     ap.add_argument("--copy-kernel", default="neg_kernel")
@@ -906,6 +1033,8 @@ def main():
     args.schedule = sched
     if args.summarize_counters:
         return summarize_counters(args)
+    if args.summarize_sq:
+        return summarize_sq(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the LOCC path has no "
               f"multi-GPU mode in this build", file=sys.stderr)

@@ -188,15 +188,15 @@ hipError_t launch_broad_phase(const BroadArgs& a, hipStream_t s) {
   if (a.n_objs < 0 || a.n_envs < 0 || a.capacity < 0 || !a.count) return hipErrorInvalidValue;
   if (a.n_objs > 0) {
     if (!a.objs || !a.boxes) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(world_box_kernel, dim3((a.n_objs + kBoxThreads - 1) / kBoxThreads), dim3(kBoxThreads), 0, s,
+    kernel_launch(world_box_kernel, dim3((a.n_objs + kBoxThreads - 1) / kBoxThreads), dim3(kBoxThreads), 0, s,
                        a);
   }
   if (a.n_envs > 0) {
     if (!a.env_offsets || !a.env_count || !a.env_start || (a.capacity > 0 && !a.pairs)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(env_pairs_kernel<false>, dim3(a.n_envs), dim3(64), 0, s, a);
+    kernel_launch(env_pairs_kernel<false>, dim3(a.n_envs), dim3(64), 0, s, a);
   }
-  hipLaunchKernelGGL(env_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);  // also writes count when empty
-  if (a.n_envs > 0 && a.capacity > 0) hipLaunchKernelGGL(env_pairs_kernel<true>, dim3(a.n_envs), dim3(64), 0, s, a);
+  kernel_launch(env_scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a);  // also writes count when empty
+  if (a.n_envs > 0 && a.capacity > 0) kernel_launch(env_pairs_kernel<true>, dim3(a.n_envs), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

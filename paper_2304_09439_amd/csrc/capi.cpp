@@ -18,6 +18,7 @@ using namespace locc;
 namespace locc {
 
 thread_local std::string g_last_error;
+thread_local LaunchTiming g_launch_timing;
 
 locc_status fail(locc_status st, const char* fmt, ...) {
   char buf[512];
@@ -56,19 +57,25 @@ hipError_t take_event(locc_ctx* c, hipEvent_t* e) {
   return hipEventCreate(e);
 }
 
-// Launch `launch()` on stream s, bracketed by events while profiling is on.
+// Launch `launch()` on stream s; while profiling is on, its kernels carry a
+// start and a stop event (from the start of the first to the end of the last).
 template <class F>
 hipError_t timed(locc_ctx* c, const char* name, hipStream_t s, F&& launch) {
   if (!c->profiling) return launch();
   locc_ctx::Pending pd{name, nullptr, nullptr};
   hipError_t e = take_event(c, &pd.start);
   if (e == hipSuccess) e = take_event(c, &pd.stop);
-  if (e == hipSuccess) e = hipEventRecord(pd.start, s);
   if (e != hipSuccess) return e;
+  g_launch_timing = LaunchTiming{pd.start, pd.stop};
   e = launch();
+  const bool launched = g_launch_timing.start == nullptr;
+  g_launch_timing = LaunchTiming{};
   if (e != hipSuccess) return e;
-  e = hipEventRecord(pd.stop, s);
-  if (e != hipSuccess) return e;
+  if (!launched) {  // nothing to run: an empty interval
+    e = hipEventRecord(pd.start, s);
+    if (e == hipSuccess) e = hipEventRecord(pd.stop, s);
+    if (e != hipSuccess) return e;
+  }
   c->pending.push_back(pd);
   return hipSuccess;
 }

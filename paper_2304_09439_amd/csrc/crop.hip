@@ -257,13 +257,13 @@ __global__ __launch_bounds__(64 * W) void crop_kernel(CropArgs A) {
 hipError_t launch_crop(const CropArgs& a, hipStream_t s, int unroll) {
   if (a.n_pairs <= 0) return hipSuccess;
   if (!a.setup || (unroll != 2 && unroll != 4 && unroll != 8)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pair_setup_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
+  kernel_launch(pair_setup_kernel, dim3((a.n_pairs + kThreads - 1) / kThreads), dim3(kThreads), 0, s, a);
   constexpr int W = kCropWaves;
   const dim3 grid((2 * a.n_pairs + W - 1) / W), block(64 * W);
   switch (unroll) {
-    case 2: hipLaunchKernelGGL((crop_kernel<2, W>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((crop_kernel<4, W>), grid, block, 0, s, a); break;
-    case 8: hipLaunchKernelGGL((crop_kernel<8, W>), grid, block, 0, s, a); break;
+    case 2: kernel_launch((crop_kernel<2, W>), grid, block, 0, s, a); break;
+    case 4: kernel_launch((crop_kernel<4, W>), grid, block, 0, s, a); break;
+    case 8: kernel_launch((crop_kernel<8, W>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -360,9 +360,9 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
 template <int H1, int H2, int HH>
 hipError_t run_fused(const FusedArgs& a, int grid, bool pre, hipStream_t s) {
   if (pre)
-    hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
+    kernel_launch((fused_bf16_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((fused_bf16_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
+    kernel_launch((fused_bf16_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

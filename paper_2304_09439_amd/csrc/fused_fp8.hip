@@ -450,9 +450,9 @@ void fp8_bind(Fp8Args& a, const unsigned char* base, int h1, int h2, int hh, boo
 template <int H1, int H2, int HH>
 void launch_fp8(const Fp8Args& a, bool head8, int grid, hipStream_t s) {
   if (head8)
-    hipLaunchKernelGGL((encoder_head_fp8_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
+    kernel_launch((encoder_head_fp8_kernel<H1, H2, HH, true>), dim3(grid), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((encoder_head_fp8_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
+    kernel_launch((encoder_head_fp8_kernel<H1, H2, HH, false>), dim3(grid), dim3(256), 0, s, a);
 }
 
 hipError_t launch_encoder_head_fp8(const Fp8Args& a, int h1, int h2, int hh, bool head8, int grid, hipStream_t s) {
@@ -470,7 +470,7 @@ hipError_t launch_calibrate_fp8(const CalibArgs& a, int grid, hipStream_t s) {
   if (a.h1 > kCalibH1 || a.h2 > kCalibH2 || a.hh > kCalibHH || a.h1 > 256 || a.h2 > 256)
     return hipErrorInvalidValue;
   if (a.n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(calibrate_fp8_kernel, dim3(grid), dim3(256), 0, s, a);
+  kernel_launch(calibrate_fp8_kernel, dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -282,8 +282,8 @@ hipError_t run(const GradArgs& a, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&head_backward_kernel<2 * H2, HH>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((head_backward_kernel<2 * H2, HH>), dim3((a.n_pairs + kGT - 1) / kGT), dim3(256), smem, s, a);
-  hipLaunchKernelGGL((pose_kernel<H1, H2>), dim3(a.n_pairs), dim3(256), 0, s, a);
+  kernel_launch((head_backward_kernel<2 * H2, HH>), dim3((a.n_pairs + kGT - 1) / kGT), dim3(256), smem, s, a);
+  kernel_launch((pose_kernel<H1, H2>), dim3(a.n_pairs), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -723,25 +723,25 @@ hipError_t run_train(const TrainArgs& a, hipStream_t s) {
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int P = a.n_pairs;
-  hipLaunchKernelGGL((head_train_kernel<Z, HH>), dim3((P + kTT - 1) / kTT), dim3(256), smem, s, a, invB);
+  kernel_launch((head_train_kernel<Z, HH>), dim3((P + kTT - 1) / kTT), dim3(256), smem, s, a, invB);
   const GradOffsets& o = a.off;
   // dH3[0], dc3[0]; dH2, dc2; dH1, dc1: partial outer sums over pair ranges, then ordered reductions
   auto outer = [&](const float* X, int ldx, int NO, const float* Y, int ldy, int NK, float* D, float* Db) {
-    hipLaunchKernelGGL(outer_sum_kernel, dim3((NK + 1 + 63) / 64, (NO + 63) / 64, kOuterSplit), dim3(256), 0, s, X,
+    kernel_launch(outer_sum_kernel, dim3((NK + 1 + 63) / 64, (NO + 63) / 64, kOuterSplit), dim3(256), 0, s, X,
                        ldx, NO, Y, ldy, NK, P, a.opart);
-    hipLaunchKernelGGL(outer_reduce_kernel, dim3((NO * (NK + 1) + 255) / 256), dim3(256), 0, s,
+    kernel_launch(outer_reduce_kernel, dim3((NO * (NK + 1) + 255) / 256), dim3(256), 0, s,
                        (const float*)a.opart, NO, NK, D, NK, Db);
   };
   outer(a.dx, 1, 1, a.g2, HH, HH, a.grad + o.H3, a.grad + o.c3);
   outer(a.du2, HH, HH, a.g1, HH, HH, a.grad + o.H2, a.grad + o.c2);
   outer(a.du1, HH, HH, a.z, Z, Z, a.grad + o.H1, a.grad + o.c1);
-  hipLaunchKernelGGL((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((train_reduce_kernel<H1, H2>), dim3((H2 * (H1 + 1) + 255) / 256 + (H1 * 7 + 3) / 4 + 1),
+  kernel_launch((enc_grad_kernel<H1, H2>), dim3(H2, kEncSplit), dim3(256), 0, s, a);
+  kernel_launch((train_reduce_kernel<H1, H2>), dim3((H2 * (H1 + 1) + 255) / 256 + (H1 * 7 + 3) / 4 + 1),
                      dim3(256), 0, s, a, invB);
-  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
+  kernel_launch(adam_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  kernel_launch(gather_kernel, dim3((unsigned)((a.pack_n + 255) / 256)), dim3(256), 0, s, a.pack_dst,
                      a.pack_idx, a.pack_n, (const float*)a.raw);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((a.tr_n + 255) / 256)), dim3(256), 0, s, a.tr_dst, a.tr_idx,
+  kernel_launch(gather_kernel, dim3((unsigned)((a.tr_n + 255) / 256)), dim3(256), 0, s, a.tr_dst, a.tr_idx,
                      a.tr_n, (const float*)a.raw);
   return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 // Internal declarations shared by the library's translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -10,6 +11,29 @@
 #include "pack.h"
 
 namespace locc {
+
+// Per-kernel timing without marker packets: while a profiled step is being
+// enqueued on this host thread, its first kernel records `start` as its
+// dispatch begins and every kernel records `stop` as it ends (events attached
+// to the dispatches themselves, so the timing adds no work between kernels).
+struct LaunchTiming {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+extern thread_local LaunchTiming g_launch_timing;
+
+// Every kernel of the library is launched through this.
+template <class F, class... Args>
+inline void kernel_launch(F kernel, const dim3& grid, const dim3& block, uint32_t shmem, hipStream_t s,
+                          Args... args) {
+  LaunchTiming& t = g_launch_timing;
+  if (!t.stop) {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+    return;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, t.start, t.stop, 0u, args...);
+  t.start = nullptr;
+}
 
 // Per-shape descriptor in device memory: rows [off, off + n) of the SoA point
 // arrays, and the axis-aligned box of the stored xyz (min / max).  32 bytes.

@@ -340,9 +340,9 @@ hipError_t run_encoder(const Fp32Net& w, const NetArgs& a, int n_cu, hipStream_t
   const int slots = encoder_wg_per_cu<H1>() * n_cu;
   int grid = a.n_pairs < slots ? a.n_pairs : slots;
   if (a.amax)
-    hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2, true>), dim3(grid), dim3(256), 0, s, w, a);
+    kernel_launch((encoder_fp32_kernel<H1, H2, true>), dim3(grid), dim3(256), 0, s, w, a);
   else
-    hipLaunchKernelGGL((encoder_fp32_kernel<H1, H2, false>), dim3(grid), dim3(256), 0, s, w, a);
+    kernel_launch((encoder_fp32_kernel<H1, H2, false>), dim3(grid), dim3(256), 0, s, w, a);
   return hipGetLastError();
 }
 
@@ -353,7 +353,7 @@ hipError_t run_head(const Fp32Net& w, const NetArgs& a, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
   if (e != hipSuccess) return e;
   const int grid = (a.n_pairs + kHeadPairs - 1) / kHeadPairs;
-  hipLaunchKernelGGL((head_fp32_kernel<Z, HH>), dim3(grid), dim3(256), smem, s, w, a);
+  kernel_launch((head_fp32_kernel<Z, HH>), dim3(grid), dim3(256), smem, s, w, a);
   return hipGetLastError();
 }
 

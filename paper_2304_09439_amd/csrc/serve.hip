@@ -68,7 +68,7 @@ struct HipDevice {
     if (nu > 0) {
       HIP_TRY(hipMemcpyAsync(sl.d_upd_ids, sl.h_upd_ids, sizeof(int32_t) * nu, hipMemcpyHostToDevice, sl.stream));
       HIP_TRY(hipMemcpyAsync(sl.d_upd, sl.h_upd, sizeof(locc_object) * nu, hipMemcpyHostToDevice, sl.stream));
-      hipLaunchKernelGGL(scatter_objects, dim3((nu + 255) / 256), dim3(256), 0, sl.stream, d_objs, sl.d_upd_ids,
+      kernel_launch(scatter_objects, dim3((nu + 255) / 256), dim3(256), 0, sl.stream, d_objs, sl.d_upd_ids,
                          sl.d_upd, nu);
       HIP_TRY(hipGetLastError());
     }

@@ -599,7 +599,7 @@ hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float*
                 int D, int Do, int pad, int transposed, int n_shapes, hipStream_t s) {
   ConvArgs a{in1, c1, in2, c2, W, bias, out, kC, D, Do, pad, transposed, n_shapes};
   const long long n = (long long)n_shapes * kC * Do * Do * Do;
-  hipLaunchKernelGGL(conv_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  kernel_launch(conv_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -608,14 +608,14 @@ hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float*
 hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,
                           int64_t n_points, const EncoderBuffers& b, float* emb, double* consts, hipStream_t s) {
   if (n_shapes <= 0 || max_points <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(point_mlp_kernel, dim3((max_points + kPts - 1) / kPts, n_shapes), dim3(256), 0, s, w, shapes,
+  kernel_launch(point_mlp_kernel, dim3((max_points + kPts - 1) / kPts, n_shapes), dim3(256), 0, s, w, shapes,
                      xyz, n_points, b.grid);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = conv(b.grid, kH, nullptr, 0, w.C[0], w.k[0], b.c[0], kM, 4, 0, 0, n_shapes, s);
   for (int i = 1; i < 4 && e == hipSuccess; ++i)
     e = conv(b.c[i - 1], kC, nullptr, 0, w.C[i], w.k[i], b.c[i], 4, 4, 1, 0, n_shapes, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(global_kernel, dim3(n_shapes), dim3(kC), 0, s, b.c[3], b.glob);
+    kernel_launch(global_kernel, dim3(n_shapes), dim3(kC), 0, s, b.c[3], b.glob);
     e = hipGetLastError();
   }
   // transposed convs: on the bottleneck, then on [previous, matching conv output]
@@ -625,8 +625,8 @@ hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes,
   if (e == hipSuccess) e = conv(b.d[2], kC, b.c[0], kC, w.D[3], w.e[3], b.d4, 4, kM, 0, 1, n_shapes, s);
   if (e == hipSuccess) {
     const int n = n_shapes * kCells * kF;
-    hipLaunchKernelGGL(embed_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, b.d4, b.glob, emb, n_shapes);
-    hipLaunchKernelGGL(consts_kernel, dim3((n_shapes + 63) / 64), dim3(64), 0, s, shapes, n_shapes, consts);
+    kernel_launch(embed_kernel, dim3((n + 255) / 256), dim3(256), 0, s, w, b.d4, b.glob, emb, n_shapes);
+    kernel_launch(consts_kernel, dim3((n_shapes + 63) / 64), dim3(64), 0, s, shapes, n_shapes, consts);
     e = hipGetLastError();
   }
   return e;
@@ -646,8 +646,8 @@ void pair_workspace_carve(void* base, int n_pairs, PairArgs& a) {
 hipError_t launch_pairs(const PairArgs& a, hipStream_t s) {
   if (a.n_pairs <= 0) return hipSuccess;
   if (!a.z || !a.valid) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(select_kernel, dim3(a.n_pairs), dim3(64), 0, s, a);
-  hipLaunchKernelGGL(mlp_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(kThreads), 0, s, a);
+  kernel_launch(select_kernel, dim3(a.n_pairs), dim3(64), 0, s, a);
+  kernel_launch(mlp_kernel, dim3((a.n_pairs + kTP - 1) / kTP), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

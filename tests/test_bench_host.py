@@ -74,3 +74,29 @@ def test_mixed_precision_kernel_peak():
     assert "peak_basis" in e
     same = bench.kernel_entries({"encoder_head_fp8": (1, 0.5)}, w, P, "scale", 1, "fp8", rows=rows)
     assert same["encoder_head_fp8"]["peak"] == 5000.0 and "peak_basis" not in same["encoder_head_fp8"]
+
+
+def test_sq_summary_from_counter_csv(tmp_path, capsys):
+    """--summarize-sq: means per dispatch over two passes, the vector-issue bound and the matrix-core busy
+    fraction derived as stated."""
+    import argparse
+    header = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value,Start_Timestamp,End_Timestamp\n"
+    p1, p2 = tmp_path / "p1", tmp_path / "p2"
+    p1.mkdir()
+    p2.mkdir()
+    rows1 = [f'{d},"void locc::crop_kernel<4, 2>(x)",SQ_VALU_MFMA_BUSY_CYCLES,{v},1000,{1000 + 50000}\n'
+             for d, v in ((1, 1000.0), (2, 3000.0))]
+    rows1 += ["3,other_kernel,SQ_VALU_MFMA_BUSY_CYCLES,99,0,1\n"]
+    rows2 = [f'{d},"void locc::crop_kernel<4, 2>(x)",{c},{v},0,1\n'
+             for d, c, v in ((1, "SQ_INSTS_VALU", 1e6), (2, "SQ_INSTS_VALU", 3e6), (1, "SQ_INSTS_MFMA", 10.0),
+                             (2, "SQ_INSTS_MFMA", 30.0))]
+    (p1 / "a_counter_collection.csv").write_text(header + "".join(rows1))
+    (p2 / "b_counter_collection.csv").write_text(header + "".join(rows2))
+    args = argparse.Namespace(summarize_sq=[str(p1), str(p2)], kernel="crop_bf16", kernel_match="crop_kernel<4, 2>")
+    bench.summarize_sq(args)
+    out = dict(line.split()[:2] for line in capsys.readouterr().out.splitlines() if len(line.split()) >= 2)
+    assert float(out["SQ_INSTS_VALU"]) == 2e6 and float(out["SQ_INSTS_MFMA"]) == 20
+    assert float(out["valu_issue_bound_ns"]) == pytest.approx(2e6 * 4 / (1024 * 2.4), abs=1)
+    assert float(out["mfma_busy_frac"]) == pytest.approx(2000.0 / (1024 * 2.4 * 50000), abs=1e-3)
+    assert float(out["valu_per_mfma"]) == pytest.approx(1e5)
+    assert out["source_sha256"] == bench.source_hash("crop_bf16")
