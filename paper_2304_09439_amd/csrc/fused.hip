@@ -141,16 +141,20 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
   const int K = A.K;
   const int P = pair_count(A.n_pairs, A.n_pairs_dev, A.dev_base);
 
-  // this wave's W2 slice, layer-1 weights and layer-2 bias stay in registers
+  // this wave's W2 slice, layer-1 weights and layer-2 bias stay in registers (the W2 slice is reloaded after
+  // every head tile, so that its registers are free for the head's operands meanwhile)
   u16x8 w2f[CT][KS2];
   float bias2[CT];
+  auto load_w2 = [&]() __attribute__((always_inline)) {
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
+    for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-    for (int s = 0; s < KS2; ++s)
-      w2f[ct][s] = reinterpret_cast<const u16x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
-    bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
-  }
+      for (int s = 0; s < KS2; ++s)
+        w2f[ct][s] = reinterpret_cast<const u16x8*>(A.w2p)[(size_t)((wave * CT + ct) * KS2 + s) * 64 + lane];
+  };
+  load_w2();
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) bias2[ct] = A.b2[(wave * CT + ct) * 32 + l32];
   s16x4 w1f[FW];
 #pragma unroll
   for (int i = 0; i < FW; ++i)
@@ -343,6 +347,7 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
       if (slot == T) {
         head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, T);
         slot = 0;
+        load_w2();
       }
     }
   }
