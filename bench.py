@@ -680,14 +680,15 @@ def pose_grad_flops(widths):
     return 2 * (2 * h2 * hh + hh * hh + hh * hh + hh * h2) + 2 * h2 * h1 * 12
 
 
-def time_pose_grad(args, scene, K, widths, w):
-    """d logit / d (p, q) of both objects of every pair (FP32 context): crop, FP32 encoder with argmax
-    rows, head backward, encoder backward at the argmax rows and the float64 chain to the poses."""
+def time_pose_grad(args, scene, K, widths, w, precision="fp32"):
+    """d logit / d (p, q) of both objects of every pair: crop, encoder with argmax rows (FP32, or the BF16
+    split-schedule encoder in a BF16 context), head backward, encoder backward at the argmax rows and the
+    float64 chain to the poses."""
     import numpy as np
     import torch
     from paper_2304_09439_amd import binding as B
     wd = (widths.h1, widths.h2, widths.hh)
-    ctx = B.context_for_scene(scene, K, wd, w, precision="fp32")
+    ctx = B.context_for_scene(scene, K, wd, w, precision=precision)
     objs, pairs = B.scene_tensors(scene)
     P = scene.n_pairs
     grad = torch.empty((P, 14), dtype=torch.float32, device="cuda")
@@ -710,8 +711,12 @@ def time_pose_grad(args, scene, K, widths, w):
                 p50_step_ms=round(float(np.percentile(step_ms, 50)), 4),
                 max_step_ms=round(float(step_ms.max()), 4), step_samples=int(len(step_ms)), kernels=kernels,
                 device_errors=int(n_bad),
-                path="FP32: crop (with index sets), encoder recording argmax rows, head backward (32 pairs per "
-                     "workgroup), encoder backward at the argmax rows and float64 chain to the poses")
+                path=("FP32: crop (with index sets), encoder recording argmax rows, head backward (32 pairs per "
+                      "workgroup), encoder backward at the argmax rows and float64 chain to the poses")
+                if precision == "fp32" else
+                ("BF16 context: crop (float32 and bf16 rows, index sets), the BF16 split-schedule encoder recording "
+                 "argmax rows and pooled features, then the FP32 path's head backward, encoder backward at the "
+                 "argmax rows and float64 chain to the poses"))
 
 
 def train_flops(widths):
@@ -847,6 +852,7 @@ def run(args):
         line["voxel_variant"] = time_voxel(args, scene)
     if not args.no_pose_grad:
         line["pose_gradients"] = time_pose_grad(args, scene, K, widths, w)
+        line["pose_gradients"]["bf16"] = time_pose_grad(args, scene, K, widths, w, precision="bf16")
     if not args.no_train:
         line["training"] = time_train(args)
     if args.serve_requests > 0:

@@ -322,7 +322,7 @@ LOCC_API locc_status locc_detect_noalloc(locc_ctx* ctx, const locc_object* d_obj
 /* Pose gradients of the collision logit (Sec. II, collision resolution with
  * an object collision network: contact force and torque directions come from
  * the gradient of the network's output with respect to the poses).  FP32
- * contexts only.  Runs the crop and the FP32 encoder (recording per object
+ * and BF16 contexts.  Runs the crop and the FP32 encoder (recording per object
  * and channel the row of the largest raw second-layer sum, the first on
  * ties), the head backward and the encoder backward at those rows of the
  * second object (the first object's rows are its own stored points and do
@@ -330,6 +330,10 @@ LOCC_API locc_status locc_detect_noalloc(locc_ctx* ctx, const locc_object* d_obj
  * t_ab = R_a^T (p_b - p_a) and the rotation polynomial of the quaternion as
  * given (not renormalised).  The crop selection is piecewise constant in
  * the poses and contributes nothing.
+ * BF16 contexts run the encoder in BF16 (the split schedule's kernel,
+ * recording the argmax rows and the pooled features) and the rest in FP32
+ * as above; d_out then holds the FP32 head's outputs on those pooled
+ * features.
  *   d_grad  float32 [n_pairs][14], device, out: d logit / d (p (3), q (4)) of
  *           the caller's first object, then of its second; NaN for an
  *           invalid pair
@@ -339,7 +343,7 @@ LOCC_API locc_status locc_detect_noalloc(locc_ctx* ctx, const locc_object* d_obj
  *           object (b = max(i, j)), 255 where it has no rows or the pair
  *           is invalid; a parity hook for ties
  * Asynchronous on `stream`; the workspace grows on demand (synchronous).
- * Errors: INVALID_ARG, NOT_READY, UNSUPPORTED (not FP32), OOM, HIP. */
+ * Errors: INVALID_ARG, NOT_READY, UNSUPPORTED (FP8 contexts), OOM, HIP. */
 LOCC_API locc_status locc_pose_gradients(locc_ctx* ctx, const locc_object* d_objs, int32_t n_objs,
                                          const int32_t* d_pairs, int32_t n_pairs, float* d_grad,
                                          locc_contact* d_out, uint8_t* d_argmax_b, void* stream);

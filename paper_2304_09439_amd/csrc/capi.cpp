@@ -516,7 +516,7 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
   HIP_TRY(hipSetDevice(c->device));
   if (!c->d_wfp32) HIP_TRY(hipMalloc(&c->d_wfp32, pack.size() * sizeof(float)));
   HIP_TRY(hipMemcpy(c->d_wfp32, pack.data(), pack.size() * sizeof(float), hipMemcpyHostToDevice));
-  if (c->cfg.precision == LOCC_FP32) {
+  if (c->cfg.precision == LOCC_FP32 || c->cfg.precision == LOCC_BF16) {
     // the pose gradients read the plain weights, the two head matrices transposed and W2 transposed
     std::vector<float> t((size_t)2 * h2 * hh + (size_t)hh * hh + (size_t)h1 * h2);
     for (int o = 0; o < hh; ++o)
@@ -531,6 +531,8 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     if (!c->d_wgrad) HIP_TRY(hipMalloc(&c->d_wgrad, t.size() * sizeof(float)));
     HIP_TRY(hipMemcpy(c->d_wraw, h, n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->d_wgrad, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  if (c->cfg.precision == LOCC_FP32) {
     // training: where each packed value comes from (the packing is positional, so packing the
     // vector of indices + 1 gives the map; floats hold these integers exactly)
     std::vector<float> ix(n);
@@ -540,7 +542,7 @@ locc_status locc_upload_weights(locc_ctx* c, const float* h, size_t n) {
     std::vector<float> pk(pack.size());
     fp32_pack(X, xb1, X + (W2 - W1), X + (b2 - W1), X + (H1 - W1), X + (c1 - W1), X + (H2 - W1),
               X + (c2 - W1), X + (H3 - W1), X + (c3 - W1), h1, h2, hh, pk.data());
-    std::vector<int32_t> pidx(pk.size()), tidx(t.size());
+    std::vector<int32_t> pidx(pk.size()), tidx((size_t)2 * h2 * hh + (size_t)hh * hh + (size_t)h1 * h2);
     for (size_t k = 0; k < pk.size(); ++k) pidx[k] = (int32_t)pk[k] - 1;
     const size_t oH1 = (size_t)(H1 - W1), oH2 = (size_t)(H2 - W1), oW2 = (size_t)(W2 - W1);
     for (int o = 0; o < hh; ++o)
@@ -1020,40 +1022,78 @@ locc_status locc_pose_gradients(locc_ctx* c, const locc_object* objs, int32_t n_
                                 int32_t n_pairs, float* grad, locc_contact* out, uint8_t* argmax_b, void* stream) {
   locc_status st = check_call(c, objs, n_objs, pairs, n_pairs);
   if (st != LOCC_OK) return st;
-  if (c->cfg.precision != LOCC_FP32) return fail(LOCC_ERR_UNSUPPORTED, "pose gradients need an FP32 context");
+  const bool bf16 = c->cfg.precision == LOCC_BF16;
+  if (c->cfg.precision != LOCC_FP32 && !bf16)
+    return fail(LOCC_ERR_UNSUPPORTED, "pose gradients need an FP32 or BF16 context");
   if (n_pairs > 0 && !grad) return fail(LOCC_ERR_INVALID_ARG, "null gradient output");
   if (n_pairs == 0) return LOCC_OK;
   HIP_TRY(hipSetDevice(c->device));
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int h1 = c->cfg.enc_h1, h2 = c->cfg.enc_h2, hh = c->cfg.head_h, K = c->cfg.K;
   const size_t P = (size_t)n_pairs;
-  const size_t base = workspace_bytes(c, n_pairs);
+  // workspace: pair records, set-up records, float32 rows (the gradient reads them), pooled features, then
+  // the selected indices, the argmax rows and the gradient scratch; BF16 adds the bf16 rows of its encoder
+  const size_t b_meta = align256(P * sizeof(PairMeta)), b_setup = align256(P * kPairSetupBytes);
+  const size_t b_rows = align256(P * 2 * K * kRowFloats * sizeof(float)), b_z = align256(P * 2 * h2 * sizeof(float));
+  const size_t b_rows16 = bf16 ? align256(P * 2 * K * 8 * sizeof(unsigned short)) : 0;
   const size_t b_idx = align256(P * 2 * K * sizeof(int32_t)), b_amax = align256(P * 2 * h2);
-  st = ensure_workspace(c, base + b_idx + b_amax + align256(P * h2 * sizeof(float)));
+  const size_t b_dm = align256(P * h2 * sizeof(float));
+  st = ensure_workspace(c, b_meta + b_setup + b_rows + b_z + b_rows16 + b_idx + b_amax + b_dm);
   if (st != LOCC_OK) return st;
-  Workspace w{};
-  st = carve(c, n_pairs, &w, nullptr);
-  if (st != LOCC_OK) return st;
-  char* extra = static_cast<char*>(c->d_ws) + base;
-  int32_t* idx = reinterpret_cast<int32_t*>(extra);
-  uint8_t* amax = reinterpret_cast<uint8_t*>(extra + b_idx);
-  float* dm = reinterpret_cast<float*>(extra + b_idx + b_amax);
+  char* b = static_cast<char*>(c->d_ws);
+  PairMeta* meta = reinterpret_cast<PairMeta*>(b);
+  b += b_meta;
+  void* setup = b;
+  b += b_setup;
+  float* rows = reinterpret_cast<float*>(b);
+  b += b_rows;
+  float* z = reinterpret_cast<float*>(b);
+  b += b_z;
+  unsigned short* rows16 = bf16 ? reinterpret_cast<unsigned short*>(b) : nullptr;
+  b += b_rows16;
+  int32_t* idx = reinterpret_cast<int32_t*>(b);
+  b += b_idx;
+  uint8_t* amax = reinterpret_cast<uint8_t*>(b);
+  b += b_amax;
+  float* dm = reinterpret_cast<float*>(b);
   CropArgs ca{objs, n_objs, pairs, n_pairs, nullptr, c->lib(), K, c->cfg.pad_m,
-              idx, nullptr, w.meta, w.rows, nullptr, c->d_err, w.setup};
+              idx, nullptr, meta, rows, rows16, c->d_err, setup};
   HIP_TRY(timed(c, "crop", s, [&] { return launch_crop(ca, s, c->sched.crop_unroll); }));
   const Fp32Net net = fp32_view(c->d_wfp32, h1, h2, hh);
-  NetArgs na{w.rows, w.meta, objs, n_pairs, nullptr, K, w.z, nullptr, out, amax};
-  HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+  NetArgs na{rows, meta, objs, n_pairs, nullptr, K, z, nullptr, out, amax};
+  if (bf16) {
+    // the BF16 encoder of the split schedule, recording the pooled features and the argmax rows
+    FusedArgs fa{};
+    fa.objs = objs;
+    fa.n_objs = n_objs;
+    fa.n_pairs = n_pairs;
+    fa.lib = c->lib();
+    fa.K = K;
+    fa.pad = c->cfg.pad_m;
+    bf16_bind(fa, c->d_wbf16, h1, h2, hh);
+    fa.z_dbg = z;
+    fa.amax = amax;
+    fa.rows_bf16 = rows16;
+    fa.meta = meta;
+    fa.queue = c->d_queue;
+    fa.claim = c->sched.claim;
+    fa.dynamic = c->sched.dynamic;
+    const int grid = fused_grid(c, n_pairs);
+    HIP_TRY(timed(c, "encoder_bf16_argmax", s,
+                  [&] { return launch_encoder_bf16_argmax(fa, h1, h2, hh, grid, s); }));
+  } else {
+    HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
+  }
   if (out) HIP_TRY(timed(c, "head_fp32", s, [&] { return launch_head_fp32(net, na, s); }));
   GradArgs ga{};
   ga.objs = objs;
   ga.n_objs = n_objs;
   ga.pairs = pairs;
   ga.n_pairs = n_pairs;
-  ga.meta = w.meta;
-  ga.rows = w.rows;
+  ga.meta = meta;
+  ga.rows = rows;
   ga.idx = idx;
-  ga.z = w.z;
+  ga.z = z;
   ga.amax = amax;
   ga.dm = dm;
   ga.grad = grad;

@@ -28,8 +28,9 @@ struct FusedArgs {
   // outputs
   locc_contact* out;
   int32_t* counts;   // [P][2] or null
-  float* z_dbg;      // [P][2 h2] or null
+  float* z_dbg;      // [P][2 h2] or null (the pooled features; always written by the argmax variant)
   float* y_dbg;      // [P][8] or null
+  uint8_t* amax;     // argmax variant: [P][2][h2] row of the largest raw layer-2 sum per channel (first on ties)
   unsigned long long* err_counter;
   // split schedule: rows and per-pair records produced by the crop kernel
   const unsigned short* rows_bf16;  // [P][2K][8]
@@ -50,6 +51,9 @@ constexpr int kFusedTile = 32;
 // precropped = false: crop, encoder and head in one kernel; true: encoder and
 // head only, reading rows_bf16 / meta written by the crop kernel.
 hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, bool precropped, hipStream_t s);
+// The encoder of the split schedule alone, recording the pooled features (z_dbg, float) and per channel the
+// row of the largest raw layer-2 sum (amax; 255 for an object with no rows), for the pose gradients.
+hipError_t launch_encoder_bf16_argmax(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s);
 
 // ---------------------------------------------------------------- FP8 path
 // Encoder + head on the rows the crop kernel wrote, with encoder layer 2 and

@@ -121,8 +121,11 @@ __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& 
   __syncthreads();
 }
 
-template <int H1, int H2, int HH, bool PRE>
+// ARGMAX (split schedule only): the encoder alone, with per channel the row of its largest raw sum; the
+// pooled features and those rows go to z_dbg and amax, and no head runs.
+template <int H1, int H2, int HH, bool PRE, bool ARGMAX = false>
 __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArgs A) {
+  static_assert(PRE || !ARGMAX, "the argmax encoder reads the crop kernel's rows");
   using S_t = Smem<H1, H2, HH>;
   constexpr int T = S_t::T, ZS = S_t::ZS;
   constexpr int FT = H1 / 32;    // layer-1 feature tiles
@@ -265,8 +268,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
         const int nt = (m + 31) >> 5;  // uniform over the workgroup
         const unsigned short* xrow = &S.u.c.rows[(side * K + l32) * 8 + 4 * g];
         float run[CT];
+        int arg[CT];  // argmax variant: the row of run (255: none yet)
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) run[ct] = -__builtin_inff();
+        for (int ct = 0; ct < CT; ++ct) {
+          run[ct] = -__builtin_inff();
+          arg[ct] = 255;
+        }
         f32x16 acc1[FW];
         // the input operand of the next row tile is read one tile ahead
         s16x4 xb = *reinterpret_cast<const s16x4*>(xrow);
@@ -316,7 +323,19 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
           __builtin_amdgcn_s_setprio(0);
           if (more) layer1_store((t + 1) & 1);
           const int r0 = 32 * t;
-          if (r0 + 32 <= m) {
+          if constexpr (ARGMAX) {
+            // a lane's rows ascend with r, and tiles ascend with r0: strict > keeps the first maximum
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const int row = r0 + 8 * (r >> 2) + 4 * g + (r & 3);
+                if (row < m && acc2[ct][r] > run[ct]) {
+                  run[ct] = acc2[ct][r];
+                  arg[ct] = row;
+                }
+              }
+          } else if (r0 + 32 <= m) {
 #pragma unroll
             for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
@@ -334,24 +353,37 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-          const float f = fmaxf(fmaxf(run[ct], __shfl_xor(run[ct], 32, 64)) + bias2[ct], 0.f);
+          const float other = __shfl_xor(run[ct], 32, 64);
+          const float f = fmaxf(fmaxf(run[ct], other) + bias2[ct], 0.f);
+          if constexpr (ARGMAX) {
+            // the two half-waves hold rows 4g + ... of every tile: the larger value wins, the lower row on ties
+            const int other_arg = __shfl_xor(arg[ct], 32, 64);
+            const bool take = other > run[ct] || (other == run[ct] && other_arg < arg[ct]);
+            if (lane < 32)
+              A.amax[((size_t)p * 2 + side) * H2 + (wave * CT + ct) * 32 + lane] = (uint8_t)(take ? other_arg : arg[ct]);
+          }
           if (lane < 32) {
             const int col = side * H2 + (wave * CT + ct) * 32 + lane;
-            S.z[slot * ZS + col] = bf16_bits(f);
+            if constexpr (!ARGMAX) S.z[slot * ZS + col] = bf16_bits(f);
             if (A.z_dbg) A.z_dbg[(size_t)p * 2 * H2 + col] = valid ? f : __builtin_nanf("");
           }
         }
       }
       ++slot;
       __syncthreads();  // rows and crop scratch are reused by the next pair
-      if (slot == T) {
-        head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, T);
+      if constexpr (!ARGMAX) {
+        if (slot == T) {
+          head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, T);
+          slot = 0;
+          load_w2();
+        }
+      } else {
         slot = 0;
-        load_w2();
       }
     }
   }
-  if (slot > 0) head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, slot);
+  if constexpr (!ARGMAX)
+    if (slot > 0) head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, slot);
 
   if (A.dynamic && tid == 0) {
     __threadfence();
@@ -384,6 +416,18 @@ void bf16_bind(FusedArgs& a, const unsigned char* base, int h1, int h2, int hh) 
   a.c2 = reinterpret_cast<const float*>(base + L.c2);
   a.h3p = reinterpret_cast<const unsigned short*>(base + L.h3);
   a.c3 = reinterpret_cast<const float*>(base + L.c3);
+}
+
+hipError_t launch_encoder_bf16_argmax(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s) {
+  if (a.n_pairs <= 0) return hipSuccess;
+  if (!a.z_dbg || !a.amax || !a.rows_bf16 || !a.meta) return hipErrorInvalidValue;
+  if (h1 == 64 && h2 == 128 && hh == 256)
+    kernel_launch((fused_bf16_kernel<64, 128, 256, true, true>), dim3(grid), dim3(256), 0, s, a);
+  else if (h1 == 128 && h2 == 256 && hh == 512)
+    kernel_launch((fused_bf16_kernel<128, 256, 512, true, true>), dim3(grid), dim3(256), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int grid, bool pre, hipStream_t s) {

@@ -27,6 +27,8 @@ from oracle import pose_grad as PG
 from paper_2304_09439_amd import binding as B
 from paper_2304_09439_amd import inputs as I
 
+from helpers import normwise_errors
+
 pytestmark = pytest.mark.gpu
 
 LW = I.SCALE_WIDTHS
@@ -149,9 +151,115 @@ def test_swapped_and_empty_pairs(torch, setup):
     ctx.close()
 
 
+# BF16 contexts: the encoder's raw sums come from bf16 rows, weights and layer-1 outputs with float32
+# accumulation, a relative error of a few 2^-8 of the layer's magnitude, so an argmax row must attain the
+# float64 maximum within 1e-2 of that magnitude.  The gradient then differs from the float64 one, taken at the
+# same argmax rows, by more than the pooled features' bf16 error: every pooled feature whose pre-activation
+# lies within that error of zero may take the other ReLU branch, which adds or drops that channel's whole
+# term.  With 2 x 256 channels per pair nearly every pair has such a channel (on this workload all but one
+# of 155 pairs at 1e-3 of the scale), so no pair can be left out as in the FP32 test.  The bars are the
+# measured size of that effect with room: normwise 0.1 over the pairs (measured 0.058) and a median per-pair
+# error of 3e-2 (measured 0.015); the contacts of this path (an FP32 head on the BF16 pooled features) meet
+# the BF16 bar of 2e-2.
+BF16_ARG_MARGIN = 1e-2
+BF16_TOL = 2e-2
+BF16_GRAD_TOL = 1e-1
+BF16_GRAD_MEDIAN_TOL = 3e-2
+
+
+def _bf16_margins(g, wts, h2, arg_gpu):
+    """Asserts the kernel's argmax rows of the second object attain the float64 maxima within the BF16
+    margin; returns (smallest |pooled pre-activation| / scale over both objects, smallest |head
+    pre-activation| / scale)."""
+    W1, b1, W2, b2, H1, c1, H2, c2, H3, c3 = wts
+    z, zmin = [], np.inf
+    for side, rows in enumerate((g.rows_a, g.rows_b)):
+        rows = np.asarray(rows, np.float64).reshape(-1, 6)
+        if len(rows) == 0:
+            z.append(np.zeros(h2))
+            if side == 1:
+                assert np.all(arg_gpu == 255)
+            continue
+        pre = rows @ W1.T + b1
+        s = O.relu(pre) @ W2.T
+        m = s.max(axis=0)
+        z.append(O.relu(m + b2))
+        scale = np.abs(s).max()
+        zmin = min(zmin, float(np.min(np.abs(m + b2)) / scale))
+        if side == 1:
+            r = arg_gpu.astype(np.int64)
+            assert np.all(r < len(rows))
+            assert np.all(s[r, np.arange(h2)] >= m - BF16_ARG_MARGIN * scale)
+    u1 = np.concatenate(z) @ H1.T + c1
+    u2 = O.relu(u1) @ H2.T + c2
+    umin = min(float(np.min(np.abs(u1)) / np.abs(u1).max()), float(np.min(np.abs(u2)) / np.abs(u2).max()))
+    return zmin, umin
+
+
+def test_bf16_gradients_match_the_oracle(torch, setup):
+    """A BF16 context: its split-schedule encoder records the argmax rows; the gradient kernels are the FP32
+    path's.  Checked against the float64 oracle at the kernel's argmax rows."""
+    sc, w = setup
+    rows = np.arange(0, 600, 3)
+    pairs = sc.pairs[rows].copy()
+    pairs[7] = [5, 5]                     # invalid
+    ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="bf16")
+    objs = torch.from_numpy(B.pack_objects(sc.pos, sc.quat, sc.shape)).cuda()
+    pr = torch.from_numpy(pairs).cuda()
+    grad, out, arg = ctx.pose_gradients(objs, pr, want_contacts=True, want_argmax=True)
+    torch.cuda.synchronize()
+    grad, arg, out = grad.cpu().numpy(), arg.cpu().numpy(), out.cpu().numpy()
+    ref = PG.pose_gradients(sc.lib.pts, sc.lib.offsets, sc.pos, sc.quat, sc.shape, pairs, w, WIDTHS, K,
+                            argmax_b=arg)
+    wts = O.unpack_weights(w, *WIDTHS)
+    assert np.all(arg[7] == 255)
+    assert np.isnan(grad[7]).all() and np.isnan(ref["grad"][7]).all() and np.isnan(out[7]).all()
+    # contacts (the FP32 head on the BF16 encoder's pooled features) against the oracle's
+    scene = I.Scene(sc.lib, sc.pos, sc.quat, sc.shape, pairs)
+    ref_c = O.detect_scene(scene, w, WIDTHS, K)["contacts"]
+    ok = ~np.isnan(ref_c[:, 0])
+    ec = normwise_errors(out[ok], ref_c[ok])
+    say(f"BF16 pose path contacts vs oracle normwise {ec}")
+    assert max(ec.values()) < BF16_TOL
+    valid, zm, um = [], [], []
+    for p, g in enumerate(ref["geoms"]):
+        if g is None or not np.any(ref["grad"][p]):
+            continue
+        a, b = _bf16_margins(g, wts, LW.h2, arg[p])
+        valid.append(p)
+        zm.append(a)
+        um.append(b)
+    valid, zm, um = np.array(valid), np.array(zm), np.array(um)
+    err = np.linalg.norm(grad[valid] - ref["grad"][valid], axis=1) / np.linalg.norm(ref["grad"][valid], axis=1)
+    e_all = np.linalg.norm(grad[valid] - ref["grad"][valid]) / np.linalg.norm(ref["grad"][valid])
+    say(f"BF16 pose gradients on {len(valid)} pairs: normwise {e_all:.2e}; per pair median {np.median(err):.2e}, "
+        f"90% {np.percentile(err, 90):.2e}, max {err.max():.2e}")
+    k = (zm > 1e-3) & (um > 1e-3)
+    say(f"  {int(k.sum())} of {len(valid)} pairs have every pooled and head pre-activation beyond 1e-3 of the "
+        f"scale from zero")
+    assert len(valid) > 0.5 * len(pairs)
+    assert e_all < BF16_GRAD_TOL and np.median(err) < BF16_GRAD_MEDIAN_TOL
+    ctx.close()
+
+
+def test_bf16_swapped_pair_reorders_the_gradient(torch, setup):
+    sc, w = setup
+    pairs = np.array([sc.pairs[0], sc.pairs[0][::-1], sc.pairs[1], sc.pairs[1][::-1]], np.int32)
+    ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="bf16")
+    objs = torch.from_numpy(B.pack_objects(sc.pos, sc.quat, sc.shape)).cuda()
+    for sched in (dict(wg_per_cu=2, claim=4, dynamic=True), dict(wg_per_cu=1, claim=16, dynamic=False)):
+        ctx.set_schedule(**sched)
+        grad, _ = ctx.pose_gradients(objs, torch.from_numpy(pairs).cuda())
+        torch.cuda.synchronize()
+        g = grad.cpu().numpy()
+        np.testing.assert_array_equal(g[1], np.concatenate([g[0][7:], g[0][:7]]))
+        np.testing.assert_array_equal(g[3], np.concatenate([g[2][7:], g[2][:7]]))
+    ctx.close()
+
+
 def test_unsupported_precision(torch, setup):
     sc, w = setup
-    ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="bf16")
+    ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="fp8")
     objs = torch.from_numpy(B.pack_objects(sc.pos, sc.quat, sc.shape)).cuda()
     with pytest.raises(B.LoccError):
         ctx.pose_gradients(objs, torch.from_numpy(sc.pairs[:4]).cuda())
