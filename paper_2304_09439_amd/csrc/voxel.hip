@@ -5,8 +5,8 @@
 // points and keeps the channel-wise max per grid cell (atomic max on the bit
 // patterns, which order like the values for the non-negative ReLU outputs);
 // conv_kernel runs every convolution and transposed convolution of the
-// U-Net (one thread per output value, the skip concatenation read from two
-// inputs); global_kernel takes max and mean over the bottleneck cells;
+// U-Net as an implicit GEMM on the matrix cores (the skip concatenation read
+// from two inputs); global_kernel takes max and mean over the bottleneck cells;
 // embed_kernel maps [last layer, global feature] to the 16-float embedding;
 // consts_kernel writes the float64 cell size and margin of each shape.
 //
@@ -118,7 +118,17 @@ __global__ __launch_bounds__(256) void point_mlp_kernel(PackedNet w, const Shape
   for (int p = 0; p < np; ++p) atomicMax(g + cell[p], __float_as_uint(relu(acc[p])));
 }
 
-// One thread per output value.  conv: in[x + u - pad]; transposed: in[x - u + pad].
+// Convolutions and transposed convolutions of the U-Net as implicit GEMMs on
+// the matrix cores (v_mfma_f32_32x32x2f32): out[s][o][x] = ReLU(b[o] +
+// sum_k W[o][k] in(k, s, x)), k = c * 27 + u over the input channels c (the
+// skip concatenation read from two inputs) and the 27 taps u, in(k, s, x) =
+// input c of shape s at x + u - pad (conv) or x - u + pad (transposed), 0
+// outside the grid.  A workgroup owns 32 output channels x 32 output
+// positions; its eight waves take an eighth of k each (operands four k-steps
+// ahead), their 32 x 32 partial sums meet in LDS and are added in wave order
+// (a fixed order: a launch is reproducible bit for bit).  Lane layouts of 32x32x2: A[i][k] and B[k][j]
+// with i, j = l % 32 and k = l / 32; D[i][j] with j = l % 32 and
+// i = 8 (r / 4) + 4 (l / 32) + r % 4 for register r.
 struct ConvArgs {
   const float* in1;  // [S][c1][D^3]
   int c1;
@@ -130,40 +140,68 @@ struct ConvArgs {
   int O, D, Do, pad, transposed, n_shapes;
 };
 
-__global__ __launch_bounds__(256) void conv_kernel(ConvArgs A) {
-  const int D3 = A.D * A.D * A.D, Do3 = A.Do * A.Do * A.Do;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= (long long)A.n_shapes * A.O * Do3) return;
-  const int x = (int)(id % Do3);
-  const int o = (int)((id / Do3) % A.O);
-  const int s = (int)(id / ((long long)Do3 * A.O));
-  const int x0 = x / (A.Do * A.Do), x1 = (x / A.Do) % A.Do, x2 = x % A.Do;
-  const int C = A.c1 + A.c2;
-  float acc = A.b[o];
-  for (int c = 0; c < C; ++c) {
-    const float* src = c < A.c1 ? A.in1 + ((size_t)s * A.c1 + c) * D3 : A.in2 + ((size_t)s * A.c2 + (c - A.c1)) * D3;
-    const float* wk = A.W + ((size_t)o * C + c) * 27;
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kConvWaves = 8;
+
+__global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(ConvArgs A) {
+  __shared__ float part[kConvWaves][32][33];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
+  const int D = A.D, Do = A.Do, D3 = D * D * D, Do3 = Do * Do * Do;
+  const int N = A.n_shapes * Do3, C = A.c1 + A.c2, Kt = C * 27;
+  const int n0 = blockIdx.x * 32, o0 = blockIdx.y * 32;
+  // this lane's output position (B column) and output channel (A row)
+  const int n = n0 + l32;
+  const bool live = n < N;
+  const int sh = live ? n / Do3 : 0, x = live ? n % Do3 : 0;
+  const int x0 = x / (Do * Do), x1 = (x / Do) % Do, x2 = x % Do;
+  const float* wrow = A.W + (size_t)(o0 + l32) * Kt;
+  // this wave's share of k (Kt / kConvWaves is even: C x 27 with C a multiple of 16)
+  const int kq = Kt / kConvWaves, k_begin = wave * kq, k_end = k_begin + kq;
+  auto operand_b = [&](int k) -> float {
+    const int c = k / 27, u = k - 27 * c;
+    const int u0 = u / 9, u1 = (u / 3) % 3, u2 = u % 3;
+    const int y0 = A.transposed ? x0 - u0 + A.pad : x0 + u0 - A.pad;
+    const int y1 = A.transposed ? x1 - u1 + A.pad : x1 + u1 - A.pad;
+    const int y2 = A.transposed ? x2 - u2 + A.pad : x2 + u2 - A.pad;
+    if (!live || y0 < 0 || y0 >= D || y1 < 0 || y1 >= D || y2 < 0 || y2 >= D) return 0.f;
+    const float* src = c < A.c1 ? A.in1 + ((size_t)sh * A.c1 + c) * D3
+                                : A.in2 + ((size_t)sh * A.c2 + (c - A.c1)) * D3;
+    return src[(y0 * D + y1) * D + y2];
+  };
+  f32x16 acc = f32x16{};
+  // operands kAhead k-steps ahead, in a ring of registers
+  constexpr int kAhead = 4;
+  float ar[kAhead], br[kAhead];
 #pragma unroll
-    for (int u0 = 0; u0 < 3; ++u0) {
-      const int j0 = A.transposed ? x0 - u0 + A.pad : x0 + u0 - A.pad;
-      if (j0 < 0 || j0 >= A.D) continue;
+  for (int d = 0; d < kAhead; ++d) {
+    const int k = k_begin + 2 * d;
+    ar[d] = k < k_end ? wrow[k + g] : 0.f;
+    br[d] = k < k_end ? operand_b(k + g) : 0.f;
+  }
+  for (int k = k_begin; k < k_end; k += 2 * kAhead) {
 #pragma unroll
-      for (int u1 = 0; u1 < 3; ++u1) {
-        const int j1 = A.transposed ? x1 - u1 + A.pad : x1 + u1 - A.pad;
-        if (j1 < 0 || j1 >= A.D) continue;
-#pragma unroll
-        for (int u2 = 0; u2 < 3; ++u2) {
-          const int j2 = A.transposed ? x2 - u2 + A.pad : x2 + u2 - A.pad;
-          if (j2 < 0 || j2 >= A.D) continue;
-          acc = fmaf(wk[(u0 * 3 + u1) * 3 + u2], src[(j0 * A.D + j1) * A.D + j2], acc);
-        }
-      }
+    for (int d = 0; d < kAhead; ++d) {
+      if (k + 2 * d < k_end) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[d], br[d], acc, 0, 0, 0);
+      const int kn = k + 2 * (d + kAhead);
+      ar[d] = kn < k_end ? wrow[kn + g] : 0.f;
+      br[d] = kn < k_end ? operand_b(kn + g) : 0.f;
     }
   }
-  A.out[id] = relu(acc);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) part[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 32 * 32; e += 64 * kConvWaves) {
+    const int i = e >> 5, j = e & 31;   // output channel o0 + i, position n0 + j
+    const int nn = n0 + j;
+    if (nn >= N) continue;
+    float v = A.b[o0 + i];
+#pragma unroll
+    for (int w = 0; w < kConvWaves; ++w) v += part[w][i][j];
+    const int s2 = nn / Do3, xx = nn % Do3;
+    A.out[((size_t)s2 * A.O + o0 + i) * Do3 + xx] = relu(v);
+  }
 }
 
-// Global feature: [max, mean] over the bottleneck cells of each channel.
 __global__ __launch_bounds__(kC) void global_kernel(const float* c4, float* glob) {
   const int s = blockIdx.x, c = threadIdx.x;
   const float* src = c4 + ((size_t)s * kC + c) * kB;
@@ -597,9 +635,11 @@ namespace {
 
 hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float* W, const float* bias, float* out,
                 int D, int Do, int pad, int transposed, int n_shapes, hipStream_t s) {
+  static_assert(kC % 32 == 0, "output channels in tiles of 32");
+  if ((c1 + c2) % 16 != 0) return hipErrorInvalidValue;   // k split in even eighths
   ConvArgs a{in1, c1, in2, c2, W, bias, out, kC, D, Do, pad, transposed, n_shapes};
-  const long long n = (long long)n_shapes * kC * Do * Do * Do;
-  kernel_launch(conv_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  const int N = n_shapes * Do * Do * Do;
+  kernel_launch(conv_kernel, dim3((unsigned)((N + 31) / 32), kC / 32), dim3(64 * kConvWaves), 0, s, a);
   return hipGetLastError();
 }
 
