@@ -32,11 +32,12 @@ struct Shape {
 static_assert(sizeof(Shape) == 32, "Shape layout");
 
 // Device pointers to every weight array: the flat vector as uploaded, except
-// the point MLP's layers 2-3, which are used transposed to [in][out] (a
-// coalesced row of outputs per input) from a second, packed buffer.
+// the point MLP's layers 2-3, used transposed to [in][out] (a coalesced row
+// of outputs per input), and the U-Net's weights, used transposed to
+// [27 taps][in][out], both from a second, packed buffer.
 struct PackedNet {
   const float *P1, *p1, *P2t, *p2, *P3t, *p3;  // point MLP
-  const float *C[4], *k[4], *D[4], *e[4];      // U-Net convs, transposed convs
+  const float *C[4], *k[4], *D[4], *e[4];      // U-Net convs, transposed convs (C, D: [27][in][128])
   const float *L, *l;                          // embedding map [16][384]
   const float *A[3], *a[3];                    // per-object MLP [128][28], [128][128] x 2 (row-major)
   const float *Bw[3], *b[4], *B4;              // pair MLP [128][128] x 3, output row [128], b[3] = its bias

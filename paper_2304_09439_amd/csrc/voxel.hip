@@ -120,21 +120,26 @@ __global__ __launch_bounds__(256) void point_mlp_kernel(PackedNet w, const Shape
 
 // Convolutions and transposed convolutions of the U-Net as implicit GEMMs on
 // the matrix cores (v_mfma_f32_32x32x2f32): out[s][o][x] = ReLU(b[o] +
-// sum_k W[o][k] in(k, s, x)), k = c * 27 + u over the input channels c (the
-// skip concatenation read from two inputs) and the 27 taps u, in(k, s, x) =
+// sum_{u, c} W[o][c][u] in(c, u, s, x)) over the 27 taps u and the input
+// channels c (the skip concatenation read from two inputs), in(c, u, s, x) =
 // input c of shape s at x + u - pad (conv) or x - u + pad (transposed), 0
 // outside the grid.  A workgroup owns 32 output channels x 32 output
-// positions; its eight waves take an eighth of k each (operands four k-steps
-// ahead), their 32 x 32 partial sums meet in LDS and are added in wave order
-// (a fixed order: a launch is reproducible bit for bit).  Lane layouts of 32x32x2: A[i][k] and B[k][j]
-// with i, j = l % 32 and k = l / 32; D[i][j] with j = l % 32 and
-// i = 8 (r / 4) + 4 (l / 32) + r % 4 for register r.
+// positions; its eight waves take an eighth of the channels each, NP pairs
+// of them, over all 27 taps, tap-major: a tap's grid offset and bounds test
+// are formed once per lane and serve its NP steps, and the next tap's
+// operands load while the current tap's NP products issue.  The weights come
+// transposed, Wt[u][c][o], so that a step's A operand is two coalesced rows.
+// The waves' 32 x 32 partial sums meet in LDS and are added in wave order (a
+// fixed order: a launch is reproducible bit for bit).  Lane layouts of
+// 32x32x2: A[i][k] and B[k][j] with i, j = l % 32 and k = l / 32 (here the
+// channel parity); D[i][j] with j = l % 32 and i = 8 (r / 4) + 4 (l / 32) +
+// r % 4 for register r.
 struct ConvArgs {
   const float* in1;  // [S][c1][D^3]
   int c1;
   const float* in2;  // [S][c2][D^3] (the concatenated skip), or null with c2 = 0
   int c2;
-  const float* W;    // [O][c1 + c2][27]
+  const float* Wt;   // [27][c1 + c2][O]
   const float* b;    // [O]
   float* out;        // [S][O][Do^3]
   int O, D, Do, pad, transposed, n_shapes;
@@ -143,50 +148,60 @@ struct ConvArgs {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kConvWaves = 8;
 
+template <int NP>  // channel pairs per wave: (c1 + c2) = 16 NP
 __global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(ConvArgs A) {
   __shared__ float part[kConvWaves][32][33];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 5, l32 = lane & 31;
   const int D = A.D, Do = A.Do, D3 = D * D * D, Do3 = Do * Do * Do;
-  const int N = A.n_shapes * Do3, C = A.c1 + A.c2, Kt = C * 27;
+  const int N = A.n_shapes * Do3, C = A.c1 + A.c2, O = A.O;
   const int n0 = blockIdx.x * 32, o0 = blockIdx.y * 32;
-  // this lane's output position (B column) and output channel (A row)
+  // this lane's output position (B column)
   const int n = n0 + l32;
   const bool live = n < N;
   const int sh = live ? n / Do3 : 0, x = live ? n % Do3 : 0;
   const int x0 = x / (Do * Do), x1 = (x / Do) % Do, x2 = x % Do;
-  const float* wrow = A.W + (size_t)(o0 + l32) * Kt;
-  // this wave's share of k (Kt / kConvWaves is even: C x 27 with C a multiple of 16)
-  const int kq = Kt / kConvWaves, k_begin = wave * kq, k_end = k_begin + kq;
-  auto operand_b = [&](int k) -> float {
-    const int c = k / 27, u = k - 27 * c;
+  // this wave's channels c_begin + 2 j + g, all from one input (c1 is a multiple of 2 NP)
+  const int c_begin = wave * 2 * NP;
+  const float* src = c_begin < A.c1 ? A.in1 + ((size_t)sh * A.c1 + c_begin + g) * D3
+                                    : A.in2 + ((size_t)sh * A.c2 + (c_begin - A.c1) + g) * D3;
+  const float* wt = A.Wt + (size_t)(c_begin + g) * O + o0 + l32;
+  const size_t tap_stride = (size_t)C * O;
+  // The loads are unconditional (a tap outside the grid reads the channel's
+  // first value) and the bound test selects 0 at the product, so that no
+  // branch splits the loads of a tap and the waits stay per operand.
+  auto load = [&](int u, float (&a)[NP], float (&b)[NP]) -> bool {
     const int u0 = u / 9, u1 = (u / 3) % 3, u2 = u % 3;
     const int y0 = A.transposed ? x0 - u0 + A.pad : x0 + u0 - A.pad;
     const int y1 = A.transposed ? x1 - u1 + A.pad : x1 + u1 - A.pad;
     const int y2 = A.transposed ? x2 - u2 + A.pad : x2 + u2 - A.pad;
-    if (!live || y0 < 0 || y0 >= D || y1 < 0 || y1 >= D || y2 < 0 || y2 >= D) return 0.f;
-    const float* src = c < A.c1 ? A.in1 + ((size_t)sh * A.c1 + c) * D3
-                                : A.in2 + ((size_t)sh * A.c2 + (c - A.c1)) * D3;
-    return src[(y0 * D + y1) * D + y2];
+    const bool ok = live && y0 >= 0 && y0 < D && y1 >= 0 && y1 < D && y2 >= 0 && y2 < D;
+    const float* sp = src + (ok ? (y0 * D + y1) * D + y2 : 0);
+    const float* wp = wt + (size_t)u * tap_stride;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      a[j] = wp[(size_t)2 * j * O];
+      b[j] = sp[2 * j * D3];
+    }
+    return ok;
   };
   f32x16 acc = f32x16{};
-  // operands kAhead k-steps ahead, in a ring of registers
-  constexpr int kAhead = 4;
-  float ar[kAhead], br[kAhead];
+  float a0[NP], b0[NP], a1[NP], b1[NP];
+  // taps in pairs (u, u + 1) for u = 0, 2, ..., 24, then tap 26; no branch
+  // around a load, so each product waits only for its own operands
+  bool ok0 = load(0, a0, b0);
+  for (int u = 0; u < 26; u += 2) {
+    const bool ok1 = load(u + 1, a1, b1);
 #pragma unroll
-  for (int d = 0; d < kAhead; ++d) {
-    const int k = k_begin + 2 * d;
-    ar[d] = k < k_end ? wrow[k + g] : 0.f;
-    br[d] = k < k_end ? operand_b(k + g) : 0.f;
-  }
-  for (int k = k_begin; k < k_end; k += 2 * kAhead) {
+    for (int j = 0; j < NP; ++j)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], ok0 ? b0[j] : 0.f, acc, 0, 0, 0);
+    ok0 = load(u + 2, a0, b0);
 #pragma unroll
-    for (int d = 0; d < kAhead; ++d) {
-      if (k + 2 * d < k_end) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[d], br[d], acc, 0, 0, 0);
-      const int kn = k + 2 * (d + kAhead);
-      ar[d] = kn < k_end ? wrow[kn + g] : 0.f;
-      br[d] = kn < k_end ? operand_b(kn + g) : 0.f;
-    }
+    for (int j = 0; j < NP; ++j)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[j], ok1 ? b1[j] : 0.f, acc, 0, 0, 0);
   }
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[j], ok0 ? b0[j] : 0.f, acc, 0, 0, 0);
 #pragma unroll
   for (int r = 0; r < 16; ++r) part[wave][8 * (r >> 2) + 4 * g + (r & 3)][l32] = acc[r];
   __syncthreads();
@@ -198,7 +213,7 @@ __global__ __launch_bounds__(64 * kConvWaves) void conv_kernel(ConvArgs A) {
 #pragma unroll
     for (int w = 0; w < kConvWaves; ++w) v += part[w][i][j];
     const int s2 = nn / Do3, xx = nn % Do3;
-    A.out[((size_t)s2 * A.O + o0 + i) * Do3 + xx] = relu(v);
+    A.out[((size_t)s2 * O + o0 + i) * Do3 + xx] = relu(v);
   }
 }
 
@@ -553,8 +568,20 @@ void transpose(const float* src, int rows, int cols, float* dst) {
     for (int c = 0; c < cols; ++c) dst[(size_t)c * rows + r] = src[(size_t)r * cols + c];
 }
 
-// Packed buffer: P2t, P3t.
-constexpr size_t kPackSizes[] = {kH * kH, kH * kH};
+// Packed buffer: P2t, P3t, then the U-Net weights transposed to [27][in][out]:
+// C[0..3], D[0..3] (input channels 256, 128, 128, 128, 128, 256, 256, 256).
+constexpr int kConvIn[8] = {kH, kC, kC, kC, kC, 2 * kC, 2 * kC, 2 * kC};
+constexpr size_t kPackSizes[] = {kH * kH, kH * kH,
+                                 (size_t)27 * kH * kC, (size_t)27 * kC * kC, (size_t)27 * kC * kC,
+                                 (size_t)27 * kC * kC, (size_t)27 * kC * kC, (size_t)27 * 2 * kC * kC,
+                                 (size_t)27 * 2 * kC * kC, (size_t)27 * 2 * kC * kC};
+
+// [O][C][27] -> [27][C][O]
+void conv_transpose(const float* src, int C, float* dst) {
+  for (int o = 0; o < kC; ++o)
+    for (int c = 0; c < C; ++c)
+      for (int u = 0; u < 27; ++u) dst[((size_t)u * C + c) * kC + o] = src[((size_t)o * C + c) * 27 + u];
+}
 
 }  // namespace
 
@@ -571,6 +598,12 @@ void pack_transposed(const float* flat, float* dst) {
   transpose(flat + off[2], kH, kH, d);                 // P2
   d += kH * kH;
   transpose(flat + off[4], kH, kH, d);                 // P3
+  d += kH * kH;
+  for (int i = 0; i < 8; ++i) {                        // U-Net, in the order of kConvIn
+    const size_t o = i < 4 ? off[6 + 2 * i] : off[14 + 2 * (i - 4)];
+    conv_transpose(flat + o, kConvIn[i], d);
+    d += (size_t)27 * kConvIn[i] * kC;
+  }
 }
 
 PackedNet packed_view(const float* raw, const float* packed) {
@@ -582,9 +615,7 @@ PackedNet packed_view(const float* raw, const float* packed) {
   w.p2 = raw + off[3];
   w.p3 = raw + off[5];
   for (int i = 0; i < 4; ++i) {
-    w.C[i] = raw + off[6 + 2 * i];
     w.k[i] = raw + off[7 + 2 * i];
-    w.D[i] = raw + off[14 + 2 * i];
     w.e[i] = raw + off[15 + 2 * i];
   }
   w.L = raw + off[22];
@@ -599,6 +630,11 @@ PackedNet packed_view(const float* raw, const float* packed) {
   w.P2t = d;
   d += kH * kH;
   w.P3t = d;
+  d += kH * kH;
+  for (int i = 0; i < 8; ++i) {
+    (i < 4 ? w.C[i] : w.D[i - 4]) = d;
+    d += (size_t)27 * kConvIn[i] * kC;
+  }
   for (int i = 0; i < 3; ++i) {
     w.A[i] = raw + off[24 + 2 * i];
     w.Bw[i] = raw + off[30 + 2 * i];
@@ -633,13 +669,20 @@ EncoderBuffers encoder_carve(float* base, int n_shapes) {
 
 namespace {
 
-hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float* W, const float* bias, float* out,
+hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float* Wt, const float* bias, float* out,
                 int D, int Do, int pad, int transposed, int n_shapes, hipStream_t s) {
   static_assert(kC % 32 == 0, "output channels in tiles of 32");
-  if ((c1 + c2) % 16 != 0) return hipErrorInvalidValue;   // k split in even eighths
-  ConvArgs a{in1, c1, in2, c2, W, bias, out, kC, D, Do, pad, transposed, n_shapes};
+  const int C = c1 + c2;
+  // eight waves of C / 8 channels each, every wave's channels from one input
+  if (C % 16 != 0 || c1 % (C / 8) != 0) return hipErrorInvalidValue;
+  ConvArgs a{in1, c1, in2, c2, Wt, bias, out, kC, D, Do, pad, transposed, n_shapes};
   const int N = n_shapes * Do * Do * Do;
-  kernel_launch(conv_kernel, dim3((unsigned)((N + 31) / 32), kC / 32), dim3(64 * kConvWaves), 0, s, a);
+  const dim3 grid((unsigned)((N + 31) / 32), kC / 32), block(64 * kConvWaves);
+  switch (C / 16) {
+    case 8: kernel_launch(conv_kernel<8>, grid, block, 0, s, a); break;
+    case 16: kernel_launch(conv_kernel<16>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
