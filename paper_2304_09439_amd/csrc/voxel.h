@@ -48,14 +48,16 @@ void pack_transposed(const float* flat, float* dst);
 PackedNet packed_view(const float* d_raw, const float* d_packed);
 
 struct EncoderBuffers {
+  int32_t* order; // [n_points]: per shape, its point indices sorted by grid cell
+  uint8_t* cell;  // [n_points]: the grid cell of each entry of order
   float* grid;    // [S][256][216] (cell max of the point features, channel-major)
   float* c[4];    // [S][128][64]
   float* d[3];    // [S][128][64]
   float* d4;      // [S][128][216]
   float* glob;    // [S][256]
 };
-size_t encoder_scratch_floats(int n_shapes);
-EncoderBuffers encoder_carve(float* base, int n_shapes);
+size_t encoder_scratch_floats(int n_shapes, int64_t n_points);
+EncoderBuffers encoder_carve(float* base, int n_shapes, int64_t n_points);
 
 // Shape encoder over every shape; grid must be zero (the cell max starts at 0).
 hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,

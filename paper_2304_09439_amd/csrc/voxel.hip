@@ -1,9 +1,11 @@
 // Voxel-embedding LOCC variant (Sec. III, appendix "Architecture Details").
 //
 // Shape encoder (once per shape, at upload; float32 arithmetic, float64 grid
-// assignment): point_mlp_kernel runs the per-point MLP over chunks of 32
-// points and keeps the channel-wise max per grid cell (atomic max on the bit
-// patterns, which order like the values for the non-negative ReLU outputs);
+// assignment): cell_sort_kernel orders each shape's points by grid cell;
+// point_mlp_kernel runs the per-point MLP over chunks of 64 points in that
+// order (layers 2-3 on the matrix cores) and keeps the channel-wise max per
+// grid cell (an atomic max per run of equal cells, on the bit patterns, which
+// order like the values for the non-negative ReLU outputs);
 // conv_kernel runs every convolution and transposed convolution of the
 // U-Net as an implicit GEMM on the matrix cores (the skip concatenation read
 // from two inputs); global_kernel takes max and mean over the bottleneck cells;
@@ -53,28 +55,77 @@ __device__ __forceinline__ int cell_of(float x, float y, float z, const Shape& s
   return idx;
 }
 
-constexpr int kPts = 32;  // points per workgroup of the point MLP
+// Counting sort of each shape's points by grid cell (a workgroup per shape):
+// the cell histogram, its exclusive scan, then each point's slot from its
+// cell's cursor.  The order within a cell depends on the timing of the LDS
+// atomics; the cell max built from it does not.
+__global__ __launch_bounds__(1024) void cell_sort_kernel(const Shape* shapes, const float* xyz, int64_t n_points,
+                                                          int32_t* order, uint8_t* cells) {
+  __shared__ int hist[kCells];
+  const Shape sh = shapes[blockIdx.x];
+  const int t = threadIdx.x;
+  auto cell_at = [&](int i) {
+    const int64_t r = (int64_t)sh.off + i;
+    return cell_of(xyz[r], xyz[n_points + r], xyz[2 * n_points + r], sh);
+  };
+  for (int c = t; c < kCells; c += 1024) hist[c] = 0;
+  __syncthreads();
+  for (int i = t; i < sh.n; i += 1024) atomicAdd(&hist[cell_at(i)], 1);
+  __syncthreads();
+  if (t == 0) {  // exclusive scan: hist[c] becomes the first slot of cell c
+    int run = 0;
+    for (int c = 0; c < kCells; ++c) {
+      const int h = hist[c];
+      hist[c] = run;
+      run += h;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < sh.n; i += 1024) {
+    const int c = cell_at(i);
+    const int slot = atomicAdd(&hist[c], 1);
+    order[sh.off + slot] = i;
+    cells[sh.off + slot] = (uint8_t)c;
+  }
+}
 
+constexpr int kPts = 64;  // points per workgroup of the point MLP
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Per-point MLP 3 -> 256 -> 256 -> 256 over 64 points, taken in cell order,
+// and the cell max.
+// Layer 1 on the vector units (a wave per 64 channels, a lane per point);
+// layers 2 and 3 on the matrix cores (v_mfma_f32_32x32x2f32, bias as the
+// accumulator's start): wave w owns output channels [64 w, 64 w + 64), two
+// 32-channel tiles over the two 32-point tiles, its A operands the rows of
+// the transposed weights Wt[in][out] (coalesced, four steps ahead), its B
+// operands the activations, kept channel-major in LDS (HT[c][p]: a step
+// reads two rows of 32 points).  The last layer's outputs go to LDS too;
+// a thread per channel then walks the 64 points, whose cells come in runs,
+// and issues one atomic max per run.  Lane layouts as in conv_kernel below.
 __global__ __launch_bounds__(256) void point_mlp_kernel(PackedNet w, const Shape* shapes, const float* xyz,
-                                                         int64_t n_points, float* grid) {
+                                                         int64_t n_points, const int32_t* order,
+                                                         const uint8_t* cells, float* grid) {
   __shared__ float X[kPts][4];
   __shared__ int cell[kPts];
-  __shared__ __align__(16) float H[kPts][kH];
+  __shared__ float HT[kH][kPts + 1];  // padded: the pooling walk reads a column
   const int s = blockIdx.y;
   const Shape sh = shapes[s];
   const int base = blockIdx.x * kPts;
   if (base >= sh.n) return;  // uniform
   const int np = sh.n - base < kPts ? sh.n - base : kPts;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, g = lane >> 5, l32 = lane & 31;
   if (t < kPts) {
     float x = 0.f, y = 0.f, z = 0.f;
     int c = -1;
     if (t < np) {
-      const int64_t r = (int64_t)sh.off + base + t;
+      const int64_t q = (int64_t)sh.off + base + t;
+      const int64_t r = (int64_t)sh.off + order[q];
       x = xyz[r];
       y = xyz[n_points + r];
       z = xyz[2 * n_points + r];
-      c = cell_of(x, y, z, sh);
+      c = cells[q];
     }
     X[t][0] = x;
     X[t][1] = y;
@@ -82,40 +133,73 @@ __global__ __launch_bounds__(256) void point_mlp_kernel(PackedNet w, const Shape
     cell[t] = c;
   }
   __syncthreads();
-  const int o = t;  // output channel
-  {
-    const float w0 = w.P1[3 * o], w1 = w.P1[3 * o + 1], w2 = w.P1[3 * o + 2], b = w.p1[o];
-#pragma unroll 4
-    for (int p = 0; p < kPts; ++p) H[p][o] = relu(((w0 * X[p][0] + w1 * X[p][1]) + w2 * X[p][2]) + b);
+  {  // layer 1: lane = point, the wave's 64 channels in turn
+    const float x = X[lane][0], y = X[lane][1], z = X[lane][2];
+    for (int k = 0; k < 64; ++k) {
+      const int o = wave * 64 + k;
+      HT[o][lane] = relu(((w.P1[3 * o] * x + w.P1[3 * o + 1] * y) + w.P1[3 * o + 2] * z) + w.p1[o]);
+    }
   }
   __syncthreads();
-  float acc[kPts];
+  f32x16 acc[2][2];  // [channel tile][point tile]
   for (int layer = 0; layer < 2; ++layer) {
-    const float* Wt = layer ? w.P3t : w.P2t;
-    const float b = (layer ? w.p3 : w.p2)[o];
+    const float* Wt = (layer ? w.P3t : w.P2t) + (size_t)g * kH + wave * 64 + l32;
+    const float* bias = (layer ? w.p3 : w.p2) + wave * 64 + 4 * g;
 #pragma unroll
-    for (int p = 0; p < kPts; ++p) acc[p] = b;
-    for (int c = 0; c < kH; c += 4) {
-      const float w0 = Wt[(c + 0) * kH + o], w1 = Wt[(c + 1) * kH + o];
-      const float w2 = Wt[(c + 2) * kH + o], w3 = Wt[(c + 3) * kH + o];
+    for (int ot = 0; ot < 2; ++ot)
 #pragma unroll
-      for (int p = 0; p < kPts; ++p) {
-        const float4 h = *reinterpret_cast<const float4*>(&H[p][c]);
-        acc[p] = fmaf(h.x, w0, acc[p]);
-        acc[p] = fmaf(h.y, w1, acc[p]);
-        acc[p] = fmaf(h.z, w2, acc[p]);
-        acc[p] = fmaf(h.w, w3, acc[p]);
+      for (int r = 0; r < 16; ++r) {
+        const float b = bias[32 * ot + 8 * (r >> 2) + (r & 3)];
+        acc[ot][0][r] = b;
+        acc[ot][1][r] = b;
+      }
+    constexpr int kAhead = 4;
+    float ar[kAhead][2];
+#pragma unroll
+    for (int d = 0; d < kAhead; ++d)
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot) ar[d][ot] = Wt[(size_t)2 * d * kH + 32 * ot];
+    for (int k = 0; k < kH; k += 2 * kAhead) {
+#pragma unroll
+      for (int d = 0; d < kAhead; ++d) {
+        const int kk = k + 2 * d;
+        const float b0 = HT[kk + g][l32], b1 = HT[kk + g][32 + l32];
+#pragma unroll
+        for (int ot = 0; ot < 2; ++ot) {
+          acc[ot][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[d][ot], b0, acc[ot][0], 0, 0, 0);
+          acc[ot][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[d][ot], b1, acc[ot][1], 0, 0, 0);
+        }
+        const int kn = kk + 2 * kAhead;
+        if (kn < kH) {
+#pragma unroll
+          for (int ot = 0; ot < 2; ++ot) ar[d][ot] = Wt[(size_t)kn * kH + 32 * ot];
+        }
       }
     }
-    __syncthreads();  // every thread has read H
-    if (layer == 0) {
+    __syncthreads();  // every wave has read HT
 #pragma unroll
-      for (int p = 0; p < kPts; ++p) H[p][o] = relu(acc[p]);
-      __syncthreads();
-    }
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+      for (int pt = 0; pt < 2; ++pt)
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          HT[wave * 64 + 32 * ot + 8 * (r >> 2) + 4 * g + (r & 3)][32 * pt + l32] = relu(acc[ot][pt][r]);
+    __syncthreads();
   }
-  unsigned int* g = reinterpret_cast<unsigned int*>(grid) + ((size_t)s * kH + o) * kCells;
-  for (int p = 0; p < np; ++p) atomicMax(g + cell[p], __float_as_uint(relu(acc[p])));
+  // max over each run of equal cells (the grid starts at 0 and the outputs are >= 0)
+  unsigned int* gp = reinterpret_cast<unsigned int*>(grid) + ((size_t)s * kH + t) * kCells;
+  int cur = cell[0];
+  float m = 0.f;
+  for (int p = 0; p < np; ++p) {
+    const int c = cell[p];  // uniform
+    if (c != cur) {
+      atomicMax(gp + cur, __float_as_uint(m));
+      cur = c;
+      m = 0.f;
+    }
+    m = fmaxf(m, HT[t][p]);
+  }
+  atomicMax(gp + cur, __float_as_uint(m));
 }
 
 // Convolutions and transposed convolutions of the U-Net as implicit GEMMs on
@@ -145,7 +229,6 @@ struct ConvArgs {
   int O, D, Do, pad, transposed, n_shapes;
 };
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kConvWaves = 8;
 
 template <int NP>  // channel pairs per wave: (c1 + c2) = 16 NP
@@ -642,15 +725,19 @@ PackedNet packed_view(const float* raw, const float* packed) {
   return w;
 }
 
-size_t encoder_scratch_floats(int n_shapes) {
-  const size_t S = (size_t)n_shapes;
-  return S * kH * kCells + 7 * S * kC * kB + S * kC * kCells + S * 2 * kC;
+size_t encoder_scratch_floats(int n_shapes, int64_t n_points) {
+  const size_t S = (size_t)n_shapes, P = (size_t)n_points;
+  return P + (P + 3) / 4 + S * kH * kCells + 7 * S * kC * kB + S * kC * kCells + S * 2 * kC;
 }
 
-EncoderBuffers encoder_carve(float* base, int n_shapes) {
-  const size_t S = (size_t)n_shapes;
+EncoderBuffers encoder_carve(float* base, int n_shapes, int64_t n_points) {
+  const size_t S = (size_t)n_shapes, P = (size_t)n_points;
   EncoderBuffers b{};
   float* p = base;
+  b.order = reinterpret_cast<int32_t*>(p);
+  p += P;
+  b.cell = reinterpret_cast<uint8_t*>(p);
+  p += (P + 3) / 4;
   b.grid = p;
   p += S * kH * kCells;
   for (int i = 0; i < 4; ++i) {
@@ -691,8 +778,9 @@ hipError_t conv(const float* in1, int c1, const float* in2, int c2, const float*
 hipError_t launch_encoder(const PackedNet& w, const Shape* shapes, int n_shapes, int max_points, const float* xyz,
                           int64_t n_points, const EncoderBuffers& b, float* emb, double* consts, hipStream_t s) {
   if (n_shapes <= 0 || max_points <= 0) return hipErrorInvalidValue;
+  kernel_launch(cell_sort_kernel, dim3(n_shapes), dim3(1024), 0, s, shapes, xyz, n_points, b.order, b.cell);
   kernel_launch(point_mlp_kernel, dim3((max_points + kPts - 1) / kPts, n_shapes), dim3(256), 0, s, w, shapes,
-                     xyz, n_points, b.grid);
+                xyz, n_points, b.order, b.cell, b.grid);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = conv(b.grid, kH, nullptr, 0, w.C[0], w.k[0], b.c[0], kM, 4, 0, 0, n_shapes, s);
   for (int i = 1; i < 4 && e == hipSuccess; ++i)

@@ -54,9 +54,9 @@ locc_status encode(locc_voxel_ctx* c) {
   if (!c->have_weights || c->n_shapes == 0) return LOCC_OK;
   const int S = c->n_shapes;
   float* scratch = nullptr;
-  const size_t n = encoder_scratch_floats(S);
+  const size_t n = encoder_scratch_floats(S, c->n_points);
   HIP_TRY(hipMalloc(&scratch, n * sizeof(float)));
-  const EncoderBuffers b = encoder_carve(scratch, S);
+  const EncoderBuffers b = encoder_carve(scratch, S, c->n_points);
   hipError_t e = hipMemset(b.grid, 0, (size_t)S * kH * kCells * sizeof(float));
   if (e == hipSuccess)
     e = launch_encoder(packed_view(c->d_raw, c->d_packed), c->d_shapes, S, c->max_points, c->d_xyz, c->n_points, b,

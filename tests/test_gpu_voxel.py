@@ -76,6 +76,27 @@ def test_shape_embeddings_match_the_oracle(torch, setup):
     ctx2.close()
 
 
+def test_ragged_and_degenerate_shapes_match_the_oracle(torch, setup):
+    """Point counts off the encoder's 64-point tiles (1, 63, 64, 65, 130, 777, 2048) and a shape whose
+    points all coincide (zero extent: every point in cell 0), against the oracle's embeddings."""
+    lib, w, _ = setup
+    counts = [1, 63, 64, 65, 130, 777, 2048, 40]
+    clouds = [lib.pts[lib.offsets[s]:lib.offsets[s] + n] for s, n in enumerate(counts)]
+    clouds[-1] = np.repeat(lib.pts[lib.offsets[7]:lib.offsets[7] + 1], counts[-1], axis=0)
+    pts = np.concatenate(clouds).astype(np.float32)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    ref = V.library_embeddings(pts, offsets, w)
+    ctx = B.VoxelContext()
+    ctx.upload_weights(w)
+    ctx.upload_shapes(offsets, pts)
+    E = ctx.embeddings().cpu().numpy()
+    torch.cuda.synchronize()
+    errs = [_normwise(E[s], ref[s]) for s in range(len(counts))]
+    say(f"ragged embedding normwise errors {['%.2e' % e for e in errs]}")
+    assert max(errs) < TOL
+    ctx.close()
+
+
 def _scene(lib, n_objs=64, n_pairs=3000, seed=21, spread=0.06):
     rng = np.random.default_rng(seed)
     pos = (rng.standard_normal((n_objs, 3)) * spread).astype(np.float32)
