@@ -213,7 +213,11 @@ LOCC_API locc_status locc_debug_forward(locc_ctx* ctx, const locc_object* d_objs
 
 /* Work schedule of the BF16 path:
  *   wg_per_cu  workgroups per compute unit of the persistent network kernel
- *              (1 .. 2); grid = CUs x wg_per_cu
+ *              (1 .. 2); grid = CUs x wg_per_cu.  With split = 1 and
+ *              wg_per_cu = 1 the encoder+head kernel is a different one: a
+ *              workgroup of eight waves per CU with layer 2's weights in LDS,
+ *              taking groups of 64 pairs (w, w + CUs, ...), each wave
+ *              encoding whole objects; claim and dynamic do not apply to it
  *   claim      pairs a workgroup takes from the queue at a time (1 .. 64)
  *   dynamic    1: pairs are claimed from a device-side atomic queue;
  *              0: static round robin (workgroup w takes claims w, w + grid, ...)

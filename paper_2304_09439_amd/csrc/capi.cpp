@@ -294,7 +294,15 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
         fa.queue = own ? own->queue : c->d_queue;
         fa.claim = c->sched.claim;
         fa.dynamic = c->sched.dynamic;
-        HIP_TRY(timed(c, "encoder_head_bf16", s, [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, true, s); }));
+        if (c->sched.wg_per_cu == 1) {  // one workgroup of eight waves per CU, W2 in LDS
+          const int groups = (len + 63) / 64;
+          const int g8 = groups < c->n_cu ? groups : c->n_cu;
+          HIP_TRY(timed(c, "encoder_head_bf16", s,
+                        [&] { return launch_encoder_head_bf16_lds(fa, h1, h2, hh, g8, false, s); }));
+        } else {
+          HIP_TRY(timed(c, "encoder_head_bf16", s,
+                        [&] { return launch_fused_bf16(fa, h1, h2, hh, grid, true, s); }));
+        }
       }
     }
     return LOCC_OK;
@@ -1078,9 +1086,16 @@ locc_status locc_pose_gradients(locc_ctx* c, const locc_object* objs, int32_t n_
     fa.queue = c->d_queue;
     fa.claim = c->sched.claim;
     fa.dynamic = c->sched.dynamic;
-    const int grid = fused_grid(c, n_pairs);
-    HIP_TRY(timed(c, "encoder_bf16_argmax", s,
-                  [&] { return launch_encoder_bf16_argmax(fa, h1, h2, hh, grid, s); }));
+    if (c->sched.wg_per_cu == 1) {  // one workgroup of eight waves per CU, W2 in LDS
+      const int groups = (n_pairs + 63) / 64;
+      const int g8 = groups < c->n_cu ? groups : c->n_cu;
+      HIP_TRY(timed(c, "encoder_bf16_argmax", s,
+                    [&] { return launch_encoder_head_bf16_lds(fa, h1, h2, hh, g8, true, s); }));
+    } else {
+      const int grid = fused_grid(c, n_pairs);
+      HIP_TRY(timed(c, "encoder_bf16_argmax", s,
+                    [&] { return launch_encoder_bf16_argmax(fa, h1, h2, hh, grid, s); }));
+    }
   } else {
     HIP_TRY(timed(c, "encoder_fp32", s, [&] { return launch_encoder_fp32(net, na, c->n_cu, s); }));
   }

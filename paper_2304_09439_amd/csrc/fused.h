@@ -54,6 +54,10 @@ hipError_t launch_fused_bf16(const FusedArgs& a, int h1, int h2, int hh, int gri
 // The encoder of the split schedule alone, recording the pooled features (z_dbg, float) and per channel the
 // row of the largest raw layer-2 sum (amax; 255 for an object with no rows), for the pose gradients.
 hipError_t launch_encoder_bf16_argmax(const FusedArgs& a, int h1, int h2, int hh, int grid, hipStream_t s);
+// The split schedule's BF16 encoder + head with W2 in LDS (encoder_bf16.hip): one workgroup of eight waves
+// per CU, groups of 64 pairs; argmax: the encoder alone, writing z_dbg and amax as the argmax variant above.
+hipError_t launch_encoder_head_bf16_lds(const FusedArgs& a, int h1, int h2, int hh, int grid, bool argmax,
+                                        hipStream_t s);
 
 // ---------------------------------------------------------------- FP8 path
 // Encoder + head on the rows the crop kernel wrote, with encoder layer 2 and

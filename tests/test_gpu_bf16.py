@@ -149,6 +149,43 @@ def test_bf16_results_do_not_depend_on_the_schedule(torch, small_scene):
         np.testing.assert_array_equal(r[1], runs[0][1])
 
 
+# the split schedule's two encoder+head kernels: two workgroups per CU with W2 slices in registers, or one
+# workgroup of eight waves per CU with W2 in LDS (groups of 64 pairs)
+REG_SCHED = dict(wg_per_cu=2, claim=16, dynamic=False, split=True, crop_unroll=4)
+LDS_SCHED = dict(wg_per_cu=1, claim=16, dynamic=False, split=True, crop_unroll=4)
+
+
+def test_bf16_lds_kernel_matches_the_oracle_small(torch, small_scene):
+    w = _weights(SW)
+    say("bf16 split, W2 in LDS: small workload against the oracle")
+    out, counts, z, y, n_bad = _forward(torch, small_scene, 64, SMALL, w, LDS_SCHED)
+    assert n_bad == 0
+    _check(out, counts, z, y, O.detect_scene(small_scene, w, SMALL, 64), "small, W2 in LDS", w, SMALL)
+
+
+def test_bf16_lds_kernel_equals_the_register_kernel_at_scale(torch, scale_scene):
+    """Same products in the same order per output: the two kernels agree bit for bit on the 16,384 pairs
+    (contacts, pooled features, raw outputs), and on batches off the 64-pair groups."""
+    sc = scale_scene
+    w = _weights(LW)
+    say("bf16 split: W2 in LDS against W2 in registers, 16384 pairs")
+    a = _forward(torch, sc, 128, SCALE, w, REG_SCHED)
+    b = _forward(torch, sc, 128, SCALE, w, LDS_SCHED)
+    assert a[4] == 0 and b[4] == 0
+    for x, y in zip(a[:4], b[:4]):
+        np.testing.assert_array_equal(x, y)
+    ctx = B.context_for_scene(sc, 128, SCALE, w, precision="bf16")
+    ctx.set_schedule(**LDS_SCHED)
+    objs, pairs = B.scene_tensors(sc)
+    for n in (1, 63, 64, 65, 1000):
+        o, c = ctx.detect(objs, pairs[:n].contiguous())
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(o.cpu().numpy(), a[0][:n])
+        np.testing.assert_array_equal(c.cpu().numpy(), a[1][:n])
+    assert ctx.device_errors() == 0
+    ctx.close()
+
+
 def test_bf16_pair_results_are_the_same_alone_and_in_the_mix(torch, scale_scene):
     sc = scale_scene
     w = _weights(LW)

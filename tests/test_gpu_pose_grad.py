@@ -257,6 +257,24 @@ def test_bf16_swapped_pair_reorders_the_gradient(torch, setup):
     ctx.close()
 
 
+def test_bf16_gradients_do_not_depend_on_the_encoder_kernel(torch, setup):
+    """The argmax encoder of either split-schedule kernel (W2 slices in registers, two workgroups per CU; W2 in
+    LDS, one workgroup of eight waves per CU): the same argmax rows, contacts and gradients, bit for bit."""
+    sc, w = setup
+    pairs = torch.from_numpy(sc.pairs[:700].copy()).cuda()
+    ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="bf16")
+    objs = torch.from_numpy(B.pack_objects(sc.pos, sc.quat, sc.shape)).cuda()
+    res = []
+    for wg in (2, 1):
+        ctx.set_schedule(wg_per_cu=wg, claim=16, dynamic=False, split=True)
+        grad, out, arg = ctx.pose_gradients(objs, pairs, want_contacts=True, want_argmax=True)
+        torch.cuda.synchronize()
+        res.append([t.cpu().numpy() for t in (grad, out, arg)])
+    for x, y in zip(*res):
+        np.testing.assert_array_equal(x, y)
+    ctx.close()
+
+
 def test_unsupported_precision(torch, setup):
     sc, w = setup
     ctx = B.context_for_scene(sc, K, WIDTHS, w, precision="fp8")
