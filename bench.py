@@ -44,8 +44,9 @@ KERNEL_SOURCES = {
     "crop_fp8": ["crop.hip", "geometry.h"],    # ... bf16 rows (FP8 path)
     "encoder_fp32": ["net_fp32.hip"],
     "head_fp32": ["net_fp32.hip"],
-    "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
-    "encoder_head_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h"],
+    "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
+    # the split schedule's two encoder+head kernels (two workgroups per CU: fused.hip; one: encoder_bf16.hip)
+    "encoder_head_bf16": ["fused.hip", "encoder_bf16.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
     "encoder_head_fp8": ["fused_fp8.hip", "fused.h", "post.h"],
     "encoder_fp8_head_bf16": ["fused_fp8.hip", "fused.h", "head_bf16.h", "post.h"],
     "crop_fp8_encoder": ["crop.hip", "geometry.h"],
