@@ -19,9 +19,9 @@
 //     B fragment read once from LDS for both row tiles, and the raw sums
 //     max-pooled per column as soon as a column tile is done.
 // No barrier falls inside the encoder.  When the group's 128 sides are done,
-// the two halves of the workgroup (waves 0-3, 4-7) run the head on the
-// group's two 32-pair tiles at once (the head's first layer overwrites the
-// W2 fragments in LDS, which are reloaded from L2 afterwards).
+// the eight waves run the head on the group's two 32-pair tiles at once, each
+// head weight fragment streamed from L2 once for both (the head's first layer
+// overwrites the W2 fragments in LDS, which are reloaded from L2 afterwards).
 // Lane layouts (wave64): A[i][k]: i = l % 32, k = (K/2) (l / 32) + e;
 // B[k][j]: j = l % 32, same k; D[i][j]: j = l % 32, i = 8 (r / 4) + 4 (l / 32)
 // + r % 4 for register r.
@@ -44,7 +44,7 @@ typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;
-constexpr int kGroup = 2 * kFusedTile;  // pairs per group: one head tile per half-workgroup
+constexpr int kGroup = 2 * kFusedTile;  // pairs per group: two head tiles
 
 // ReLU(bf16(a)), ReLU(bf16(b)) in one word (round to nearest even).
 __device__ __forceinline__ unsigned bf16x2_relu(float a, float b) {
@@ -75,10 +75,10 @@ struct SmemL {
   static constexpr int NW2 = (H2 / 32) * (H1 / 16) * 64;      // W2 B fragments (u16x8 each)
   union {
     u16x8 w2[NW2];                 // layer-2 B fragments: [column tile][k-step][lane]
-    unsigned short g[2][T * GS];   // the head's layer-1 outputs, one tile per half-workgroup
+    unsigned short g[2][T * GS];   // the head's layer-1 outputs of the two tiles
   } u;
   unsigned short z[2][T * ZS];     // pooled features [f_a, f_b] of the group's pairs, bf16
-  float y[2][4][T][8];             // per half-workgroup: the four waves' parts of the raw outputs
+  float y[2][4][T][8];             // per tile: the four layer-3 waves' parts of the raw outputs
   int32_t m[kGroup][2];            // rows per object (0 for an invalid pair)
   int32_t a[kGroup];               // canonical first object, -1: invalid pair
   int32_t swapped[kGroup];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void encoder_bf16_kernel(FusedArgs 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int half = wave >> 2, w4 = wave & 3;
+  const int half = wave >> 2;  // head tile whose unused rows this half of the workgroup clears
   const int g = lane >> 5;
   const int l32 = lane & 31;
   const int K = A.K;
@@ -307,10 +307,11 @@ __global__ __launch_bounds__(64 * kWaves, 1) void encoder_bf16_kernel(FusedArgs 
       const int n_half = n_grp - T * half < 0 ? 0 : (n_grp - T * half < T ? n_grp - T * half : T);
       for (int e = tid - 256 * half; e < (T - n_half) * ZS; e += 256) S.z[half][n_half * ZS + e] = 0;
       __syncthreads();
-      head_bf16::layers<H2, HH, ZS, GS, 4>(A.h1p, A.c1, A.h2p, A.c2, A.h3p, S.z[half], S.u.g[half], S.y[half], w4);
+      head_bf16::layers2t<H2, HH, ZS, GS, 4>(A.h1p, A.c1, A.h2p, A.c2, A.h3p, S.z[0], S.z[1], S.u.g[0], S.u.g[1],
+                                             S.y[0], S.y[1], wave);
       __syncthreads();
       {
-        const int i = tid >> 3, j = tid & 7;  // 512 threads: row i of half i / 32
+        const int i = tid >> 3, j = tid & 7;  // 512 threads: row i % 32 of tile i / 32
         const int h = i >> 5, r = i & 31;
         S.y[h][0][r][j] = ((S.y[h][0][r][j] + S.y[h][1][r][j]) + S.y[h][2][r][j]) + S.y[h][3][r][j] + A.c3[j];
       }

@@ -106,5 +106,86 @@ __device__ __forceinline__ void layers(const unsigned short* h1p, const float* c
     for (int r = 0; r < 16; ++r) y[wave][8 * (r >> 2) + 4 * lg + (r & 3)][l32] = acc[r];
 }
 
+// Layers 1-3 on two 32-row tiles at once, by eight waves: each B fragment of
+// layers 1 and 2 is loaded once for both tiles (half the weight stream of
+// two separate tiles), wave w (0-7) computing output column tiles
+// [w CTH, (w+1) CTH) of both.  Layer 3 as in layers(): waves 0-3 on tile 0,
+// waves 4-7 on tile 1, each a quarter of the reduction.  Every output sees
+// the same products in the same order as layers() gives it.
+template <int KDIM, int SS, int DS, int CTH, int D>
+__device__ __forceinline__ void layer2t(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
+                                        const unsigned short* src0, const unsigned short* src1, unsigned short* dst0,
+                                        unsigned short* dst1, int wave) {
+  constexpr int KS = KDIM / 16;
+  static_assert(KS % D == 0, "k-steps per head layer");
+  const int lane = threadIdx.x & 63, g = lane >> 5, l32 = lane & 31;
+  const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
+  const unsigned short* arow0 = src0 + l32 * SS + 8 * g;
+  const unsigned short* arow1 = src1 + l32 * SS + 8 * g;
+  f32x16 acc0[CTH], acc1[CTH];
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) acc0[c] = acc1[c] = f32x16{};
+  u16x8 bq[D][CTH];
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + d) * 64];
+#pragma unroll 1
+  for (int s0 = 0; s0 < KS; s0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int s = s0 + d;
+      const u16x8 a0 = *reinterpret_cast<const u16x8*>(arow0 + 16 * s);
+      const u16x8 a1 = *reinterpret_cast<const u16x8*>(arow1 + 16 * s);
+#pragma unroll
+      for (int c = 0; c < CTH; ++c) {
+        acc0[c] = mfma(a0, bq[d][c], acc0[c]);
+        acc1[c] = mfma(a1, bq[d][c], acc1[c]);
+      }
+      if (s + D < KS) {
+#pragma unroll
+        for (int c = 0; c < CTH; ++c) bq[d][c] = bp[((size_t)c * KS + s + D) * 64];
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CTH; ++c) {
+    const int col = (wave * CTH + c) * 32 + l32;
+    const float bc = bias[col];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 8 * (r >> 2) + 4 * g + (r & 3);
+      dst0[row * DS + col] = bits(fmaxf(acc0[c][r] + bc, 0.f));
+      dst1[row * DS + col] = bits(fmaxf(acc1[c][r] + bc, 0.f));
+    }
+  }
+}
+
+template <int H2, int HH, int ZS, int GS, int D>
+__device__ __forceinline__ void layers2t(const unsigned short* h1p, const float* c1, const unsigned short* h2p,
+                                         const float* c2, const unsigned short* h3p, unsigned short* z0,
+                                         unsigned short* z1, unsigned short* g0, unsigned short* g1,
+                                         float (*y0)[32][8], float (*y1)[32][8], int wave) {
+  constexpr int CTH = HH / 256, KS3 = HH / 16;
+  static_assert(HH % 256 == 0 && ZS >= 2 * H2 && ZS >= HH && GS >= HH, "head tile strides");
+  const int lane = threadIdx.x & 63, lg = lane >> 5, l32 = lane & 31;
+  layer2t<2 * H2, ZS, GS, CTH, D>(h1p, c1, z0, z1, g0, g1, wave);
+  __syncthreads();
+  layer2t<HH, GS, ZS, CTH, D>(h2p, c2, g0, g1, z0, z1, wave);
+  __syncthreads();
+  const int t = wave >> 2, w4 = wave & 3;
+  unsigned short* z = t ? z1 : z0;
+  float(*y)[32][8] = t ? y1 : y0;
+  f32x16 acc = f32x16{};
+  const u16x8* bp = reinterpret_cast<const u16x8*>(h3p) + lane;
+  const unsigned short* arow = z + l32 * ZS + 8 * lg;
+#pragma unroll
+  for (int s = w4 * (KS3 / 4); s < (w4 + 1) * (KS3 / 4); ++s)
+    acc = mfma(*reinterpret_cast<const u16x8*>(arow + 16 * s), bp[(size_t)s * 64], acc);
+  if (l32 < 8)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) y[w4][8 * (r >> 2) + 4 * lg + (r & 3)][l32] = acc[r];
+}
+
 }  // namespace head_bf16
 }  // namespace locc
