@@ -46,7 +46,8 @@ KERNEL_SOURCES = {
     "head_fp32": ["net_fp32.hip"],
     "fused_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
     # the split schedule's two encoder+head kernels (two workgroups per CU: fused.hip; one: encoder_bf16.hip)
-    "encoder_head_bf16": ["fused.hip", "encoder_bf16.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
+    "encoder_head_bf16": ["fused.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
+    "encoder_head_bf16_lds": ["encoder_bf16.hip", "fused.h", "geometry.h", "post.h", "head_bf16.h"],
     "encoder_head_fp8": ["fused_fp8.hip", "fused.h", "post.h"],
     "encoder_fp8_head_bf16": ["fused_fp8.hip", "fused.h", "head_bf16.h", "post.h"],
     "crop_fp8_encoder": ["crop.hip", "geometry.h"],
@@ -54,7 +55,7 @@ KERNEL_SOURCES = {
 # arithmetic of the encoder and of the head in each network kernel (None: not in that kernel)
 KERNEL_PREC = {
     "encoder_fp32": ("fp32", None), "head_fp32": (None, "fp32"),
-    "fused_bf16": ("bf16", "bf16"), "encoder_head_bf16": ("bf16", "bf16"),
+    "fused_bf16": ("bf16", "bf16"), "encoder_head_bf16": ("bf16", "bf16"), "encoder_head_bf16_lds": ("bf16", "bf16"),
     "encoder_head_fp8": ("fp8", "fp8"),              # encoder layer 1 and head layer 3 are bf16: charged at fp8
     "encoder_fp8_head_bf16": ("fp8", "bf16"),        # encoder layer 1 bf16 charged at fp8 too
 }

@@ -535,7 +535,8 @@ LOCC_API locc_status locc_serve_stop(locc_server* srv);
  * overhead).  locc_profile(ctx, 1) clears the totals and starts recording,
  * locc_profile(ctx, 0) stops.  Kernel names: "crop", "encoder_fp32",
  * "head_fp32" (FP32 per-step path), "fused_bf16" (BF16, one launch),
- * "crop" and "encoder_head_bf16" (BF16 split schedule), "crop" and
+ * "crop" and "encoder_head_bf16" (BF16 split schedule; "encoder_head_bf16_lds"
+ * for its one-workgroup-per-CU kernel), "crop" and
  * "encoder_head_fp8" (LOCC_FP8) or "encoder_fp8_head_bf16"
  * (LOCC_FP8_ENCODER). */
 typedef struct {

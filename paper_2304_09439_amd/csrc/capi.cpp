@@ -297,7 +297,7 @@ locc_status locc::run_path(locc_ctx* c, const locc_object* objs, int32_t n_objs,
         if (c->sched.wg_per_cu == 1) {  // one workgroup of eight waves per CU, W2 in LDS
           const int groups = (len + 63) / 64;
           const int g8 = groups < c->n_cu ? groups : c->n_cu;
-          HIP_TRY(timed(c, "encoder_head_bf16", s,
+          HIP_TRY(timed(c, "encoder_head_bf16_lds", s,
                         [&] { return launch_encoder_head_bf16_lds(fa, h1, h2, hh, g8, false, s); }));
         } else {
           HIP_TRY(timed(c, "encoder_head_bf16", s,
