@@ -88,15 +88,17 @@ def test_device_count_is_clamped_to_the_capacity(torch, envs):
     objs, pairs = B.scene_tensors(sc)
     ctx.reserve(1100)
     ref, _ = ctx.detect(objs, pairs)
-    for chunks in (1, 2):   # two runs of 550 pairs: counts that end in either run
-        ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=True, crop_unroll=4, chunks=chunks)
+    # two runs of 550 pairs: counts that end in either run; both split-schedule kernels (W2 in registers at two
+    # workgroups per CU, W2 in LDS at one)
+    for wg, chunks in ((2, 1), (2, 2), (1, 1), (1, 2)):
+        ctx.set_schedule(wg_per_cu=wg, claim=4, dynamic=True, split=True, crop_unroll=4, chunks=chunks)
         for n, expect in ((10**6, 1100), (-5, 0), (0, 0), (123, 123), (600, 600)):
             out = torch.full((1100, 8), 7.0, dtype=torch.float32, device="cuda")
             n_dev = torch.tensor([n], dtype=torch.int32, device="cuda")
             ctx.detect_device_count(objs, pairs, n_dev, out)
             torch.cuda.synchronize()
-            assert torch.equal(out[:expect], ref[:expect]), (chunks, n)
-            assert torch.all(out[expect:] == 7.0), (chunks, n)
+            assert torch.equal(out[:expect], ref[:expect]), (wg, chunks, n)
+            assert torch.all(out[expect:] == 7.0), (wg, chunks, n)
     ctx.close()
 
 

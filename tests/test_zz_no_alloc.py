@@ -36,18 +36,19 @@ def scene():
     return I.scale_workload(n_pairs=6000)
 
 
-@pytest.mark.parametrize("precision,split,first", [("fp32", None, 3000), ("bf16", True, 6000),
-                                                   ("bf16", False, 6000), ("fp8", None, 6000),
-                                                   ("fp8_encoder", None, 6000)])
-def test_noalloc_equals_detect_on_two_calls(torch, scene, precision, split, first):
-    say(f"no-allocation detect, {precision} split={split}: {first} pairs, then 700 others")
+# wg: workgroups per CU of the BF16 schedule (at split, 1 selects the kernel with W2 in LDS)
+@pytest.mark.parametrize("precision,split,wg,first", [("fp32", None, 2, 3000), ("bf16", True, 2, 6000),
+                                                      ("bf16", True, 1, 6000), ("bf16", False, 2, 6000),
+                                                      ("fp8", None, 2, 6000), ("fp8_encoder", None, 2, 6000)])
+def test_noalloc_equals_detect_on_two_calls(torch, scene, precision, split, wg, first):
+    say(f"no-allocation detect, {precision} split={split} wg_per_cu={wg}: {first} pairs, then 700 others")
     w = I.flatten_weights(I.gaussian_weights(LW, seed=0, bias_std=0.1))
     ctx = B.context_for_scene(scene, 128, SCALE, w, precision=precision)
     objs, pairs = B.scene_tensors(scene)
     if precision.startswith("fp8"):
         ctx.calibrate(objs, pairs[:1024])
     if split is not None:
-        ctx.set_schedule(wg_per_cu=2, claim=4, dynamic=True, split=split)
+        ctx.set_schedule(wg_per_cu=wg, claim=4, dynamic=True, split=split)
     for rows in (np.arange(first), np.arange(5000 - 700, 5000)[::-1].copy()):
         pr = torch.from_numpy(np.ascontiguousarray(scene.pairs[rows])).cuda()
         P = len(rows)
