@@ -319,7 +319,7 @@ __global__ __launch_bounds__(64 * kWaves, 1) void encoder_bf16_kernel(FusedArgs 
       if (tid < n_grp)
         post_contact(A.objs, S.a[tid], S.swapped[tid], S.y[tid / T][0][tid % T], A.out, A.y_dbg, base + tid);
       __syncthreads();  // g (over the W2 fragments) is read no more
-      load_w2();
+      if (base + (int)gridDim.x * kGroup < P) load_w2();  // uniform: this workgroup has another group
     }
   }
 }
