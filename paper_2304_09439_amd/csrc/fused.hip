@@ -110,7 +110,7 @@ __device__ __forceinline__ void head_tile(const FusedArgs& A, Smem<H1, H2, HH>& 
   const int tid = threadIdx.x;
   for (int e = tid; e < (T - n) * ZS; e += 256) S.z[n * ZS + e] = 0;
   __syncthreads();
-  head_bf16::layers<H2, HH, ZS, GS, D>(A.h1p, A.c1, A.h2p, A.c2, A.h3p, S.z, S.u.g, S.y, wave_index());
+  head_bf16::layers<H2, HH, ZS, GS, D>(A.h1p, A.c1, A.h2p, A.c2, A.h3p, S.z, S.u.g, S.y);
   __syncthreads();
   for (int t = tid; t < T * 8; t += 256) {
     const int i = t >> 3, j = t & 7;

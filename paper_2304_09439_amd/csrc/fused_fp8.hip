@@ -171,7 +171,7 @@ __device__ __forceinline__ void head_tile8(const Fp8Args& A, Smem8<H1, H2, HH, H
     __syncthreads();
     head_bf16::layers<H2, HH, ZS, G2, 4>(reinterpret_cast<const unsigned short*>(A.h1p), A.c1,
                                          reinterpret_cast<const unsigned short*>(A.h2p), A.c2, A.h3p, z16, S.u.g2,
-                                         S.y, wave_index());
+                                         S.y);
   }
   __syncthreads();
   for (int t = tid; t < T * 8; t += 256) {

@@ -29,16 +29,16 @@ __device__ __forceinline__ unsigned short bits(float f) {
 }
 
 // One hidden layer on the tile: dst = bf16(ReLU(src W^T + bias)), src and dst
-// bf16 rows of stride SS and DS.  Wave w (0-3, the tile's four waves)
-// computes output column tiles [w CTH, (w+1) CTH); B fragments stream from
-// global memory (L2) D k-steps ahead, in a ring of registers, so that several
-// L2 round trips are in flight behind the matrix cores.
+// bf16 rows of stride SS and DS.  Wave w computes output column tiles
+// [w CTH, (w+1) CTH); B fragments stream from global memory (L2) D k-steps
+// ahead, in a ring of registers, so that several L2 round trips are in flight
+// behind the matrix cores.
 template <int KDIM, int SS, int DS, int CTH, int D>
 __device__ __forceinline__ void layer(const unsigned short* __restrict__ pack, const float* __restrict__ bias,
-                                      const unsigned short* src, unsigned short* dst, int wave) {
+                                      const unsigned short* src, unsigned short* dst) {
   constexpr int KS = KDIM / 16;
   static_assert(KS % D == 0, "k-steps per head layer");
-  const int lane = threadIdx.x & 63, g = lane >> 5, l32 = lane & 31;
+  const int lane = threadIdx.x & 63, wave = wave_index(), g = lane >> 5, l32 = lane & 31;
   const u16x8* bp = reinterpret_cast<const u16x8*>(pack) + (size_t)wave * CTH * KS * 64 + lane;
   const unsigned short* arow = src + l32 * SS + 8 * g;
   f32x16 acc[CTH];
@@ -80,19 +80,18 @@ __device__ __forceinline__ void layer(const unsigned short* __restrict__ pack, c
 // GS) -> z (layer 2, overwriting the features) -> y[w][row][j], the part of
 // the 8 raw outputs (without c3) that wave w's quarter of layer 3's
 // reduction contributes.  The caller adds the four parts in wave order and
-// c3.  wave: this wave's index among the tile's four.  Barriers (of the whole
-// workgroup, which may run two tiles at once, one per four waves): one
-// between layers; the caller synchronises before reading y.
+// c3.  Barriers: one between layers; the caller synchronises before reading
+// y.
 template <int H2, int HH, int ZS, int GS, int D>
 __device__ __forceinline__ void layers(const unsigned short* h1p, const float* c1, const unsigned short* h2p,
                                        const float* c2, const unsigned short* h3p, unsigned short* z,
-                                       unsigned short* g, float (*y)[32][8], int wave) {
+                                       unsigned short* g, float (*y)[32][8]) {
   constexpr int CTH = HH / 128, KS3 = HH / 16;
   static_assert(ZS >= 2 * H2 && ZS >= HH && GS >= HH, "head tile strides");
-  const int lane = threadIdx.x & 63, lg = lane >> 5, l32 = lane & 31;
-  layer<2 * H2, ZS, GS, CTH, D>(h1p, c1, z, g, wave);
+  const int lane = threadIdx.x & 63, wave = wave_index(), lg = lane >> 5, l32 = lane & 31;
+  layer<2 * H2, ZS, GS, CTH, D>(h1p, c1, z, g);
   __syncthreads();
-  layer<HH, GS, ZS, CTH, D>(h2p, c2, g, z, wave);
+  layer<HH, GS, ZS, CTH, D>(h2p, c2, g, z);
   __syncthreads();
   // layer 3 (8 outputs, padded to 32 columns), reduction split over the 4 waves
   f32x16 acc = f32x16{};
