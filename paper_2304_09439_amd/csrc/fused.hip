@@ -370,7 +370,12 @@ __global__ __launch_bounds__(256, kFusedWgPerCu) void fused_bf16_kernel(FusedArg
         }
       }
       ++slot;
-      __syncthreads();  // rows and crop scratch are reused by the next pair
+      // The crop scratch is reused by the next pair's crop.  The split schedule
+      // needs no barrier here: every read of this pair's rows and layer-1 tiles
+      // completed before the barrier ending its last row tile (a barrier waits
+      // for the wave's LDS accesses), the next pair writes another z slot, and
+      // the head begins with a barrier of its own.
+      if constexpr (!PRE) __syncthreads();
       if constexpr (!ARGMAX) {
         if (slot == T) {
           head_tile<H1, H2, HH, PRE ? 4 : 2>(A, S, T);
