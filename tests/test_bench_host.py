@@ -48,6 +48,12 @@ def test_kernel_entries_rates_and_fractions():
     assert crop["achieved"] == pytest.approx(crop["hbm_bytes_per_pair"] * P / 0.1e-3 / 1e9, rel=1e-4)
     assert crop["frac"] == pytest.approx(crop["achieved"] / 8000.0, rel=1e-3) and crop["frac"] < 1
     assert crop["scan_GBps"] == pytest.approx(w["crop_bytes"] * P / 0.1e-3 / 1e9, rel=1e-4)
+    # the one-workgroup-per-CU kernel of the split schedule is charged the same work at the same peak
+    kl = bench.kernel_entries({"crop": (steps, 0.1 * steps), "encoder_head_bf16_lds": (steps, 0.2 * steps)}, w, P,
+                              "scale", steps, "bf16", full_scan=False, rows=(valid, tiles))
+    lds = kl["encoder_head_bf16_lds"]
+    assert lds["bound"] == "mfma" and lds["peak"] == 2500.0
+    assert lds["achieved"] == pytest.approx(enc["achieved"], rel=1e-6)
     k32 = bench.kernel_entries({"crop": (1, 0.1), "head_fp32": (1, 0.3)}, w, P, "scale", 1, "fp32")
     assert k32["crop"]["hbm_bytes_per_pair"] == 2 * 32 + 8 + 8 + 2 * 128 * 32
     assert k32["head_fp32"]["achieved"] == pytest.approx(w["head_flops"] * P / 0.3e-3 / 1e12, rel=1e-4)
